@@ -1,0 +1,189 @@
+/*
+ * bkm.h -- C ABI of libbkm, balanced k-means geometric partitioning on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: M. von Looz, C. Tzovas, H. Meyerhenke, "Balanced k-means for
+ * Parallel Geometric Partitioning", arXiv:1805.01208.  Problem statement in
+ * Sec. 2 and Sec. 4 (points P, block count k, imbalance eps, optional node
+ * weights w: P -> R+); AssignAndBalance is Alg. 1, BalancedKMeans is Alg. 2.
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked [device] are device (HBM) pointers on the current HIP
+ *     device; [host] marks host memory.  The caller owns every buffer it
+ *     passes; the library never frees or keeps them.
+ *   - Points are structure-of-arrays: coords[j][i] is coordinate j of point
+ *     i, each array contiguous; d is 2 or 3.
+ *   - `stream` is a hipStream_t passed as void*, NULL for the default
+ *     stream.  Work is ordered on that stream; every call returns after the
+ *     stream has drained, so host outputs are valid on return.
+ *   - Scratch memory comes from the device's default memory pool on that
+ *     stream (hipMallocAsync) and is released before return.
+ *   - Return value: BKM_OK (0), a negative error code (the message is in
+ *     bkm_last_error()), or a positive warning.  No exception or abort ever
+ *     crosses the ABI.  On an error the outputs are unspecified.
+ */
+#ifndef BKM_H
+#define BKM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BKM_OK 0
+#define BKM_EINVAL (-1)      /* bad argument: NULL pointer, d not 2/3, k < 1 or k > n,
+                                eps < 0 or NaN, order out of range, ... */
+#define BKM_EDATA (-2)       /* non-finite coordinate, or weight <= 0 / non-finite */
+#define BKM_ENOMEM (-3)      /* device allocation failed */
+#define BKM_EHIP (-4)        /* a HIP runtime call failed (message names it) */
+#define BKM_WUNBALANCED 1    /* outputs valid, but the last AssignAndBalance call
+                                ran out of sweeps before meeting L_max */
+
+typedef enum { BKM_F32 = 0, BKM_F64 = 1 } bkm_dtype;
+
+/* Arithmetic of the assignment sweep.
+ *   BKM_PREC_F64          every effective distance in FP64, exactly the
+ *                         definition dist(p,c)/influence(c) (Sec. 4.2).
+ *   BKM_PREC_F32_RECHECK  FP32 screen on tile-local coordinate offsets; a
+ *                         point whose best and second-best FP32 values are
+ *                         closer than max(recheck_rel_gap, the proven FP32
+ *                         error) is decided again in FP64, so assignments are
+ *                         the FP64 ones. */
+typedef enum { BKM_PREC_F64 = 0, BKM_PREC_F32_RECHECK = 1 } bkm_precision;
+
+typedef struct {
+    int64_t n;               /* number of points, 1 <= n < 2^31 */
+    int32_t d;               /* 2 or 3 */
+    int32_t dtype;           /* bkm_dtype of the coordinate arrays */
+    const void* coords[3];   /* [device] d arrays of n values; coords[2] unused if d == 2 */
+    const double* weights;   /* [device] n node weights (> 0, finite), or NULL for unit weights */
+} bkm_points;
+
+typedef struct {
+    int32_t k;                /* number of blocks, 1 <= k <= n */
+    int32_t max_iter;         /* AssignAndBalance calls (Alg. 2 loop), >= 1; default 50 */
+    int32_t max_balance_iter; /* sweeps per AssignAndBalance call (Alg. 1 loop), >= 1; default 20 */
+    int32_t hilbert_order;    /* bits per axis of the Hilbert index: 1..31 (2D), 1..21 (3D); default 16 */
+    int32_t precision;        /* bkm_precision; default BKM_PREC_F32_RECHECK */
+    int32_t use_bounds;       /* 1: Hamerly upper/lower bounds skip points (Sec. 4.3); default 1 */
+    int32_t tile_points;      /* points per tile of the sweep: 256, 512 or 1024; 0 = default */
+    int32_t super_tiles;      /* tiles per candidate super-tile, >= 1; 0 = default */
+    double epsilon;           /* imbalance eps >= 0 (may be +inf); default 0.03 */
+    double delta_threshold;   /* absolute; < 0 selects 1e-5 * largest bounding-box extent */
+    double recheck_rel_gap;   /* FP64 recheck window, relative, >= 0; default 1e-5 */
+} bkm_params;
+
+/* Counters of one bkm_balanced_kmeans call (host struct). */
+typedef struct {
+    int32_t rounds;           /* AssignAndBalance calls made */
+    int32_t sweeps;           /* assignment sweeps made over all calls */
+    int32_t balanced;         /* last call ended with every block <= L_max */
+    int32_t converged;        /* max center movement fell below delta_threshold */
+    double imbalance;         /* max block weight / (W/k) - 1 of the returned assignment */
+    double max_block_weight;
+    double l_max;             /* (1+eps)*ceil(n/k), or (1+eps)*W/k with node weights */
+    int64_t evaluated;        /* point visits that evaluated candidate centers */
+    int64_t skipped;          /* point visits skipped by the bounds (Sec. 4.3) */
+    int64_t rechecked;        /* evaluated visits decided again in FP64 */
+    int64_t changed;          /* point visits whose block changed */
+    int64_t candidate_evals;  /* (point, center) effective distances evaluated */
+    double bootstrap_ms;      /* device time of the SFC bootstrap */
+    double total_ms;          /* device time of the whole call */
+} bkm_info;
+
+typedef struct {
+    double imbalance;         /* max block weight / (W/k) - 1 */
+    double objective;         /* sum_p w(p) * dist(p, weighted mean of its block)^2 */
+    double l_max;
+    int32_t empty_blocks;
+    int32_t overloaded_blocks; /* blocks with weight > L_max (Sec. 2) */
+} bkm_stats;
+
+/* Fill *p with the defaults listed above for k blocks. */
+void bkm_default_params(bkm_params* p, int32_t k);
+
+/* Hilbert space-filling-curve bootstrap (Alg. 2, lines computing sfcIndex,
+ * sorting by it and picking the initial centers; Sec. 4.1).
+ *   Key of point i: with lo/hi the global bounding box and ext its largest
+ *   extent, cell q_j = min(2^m-1, floor((x_j - lo_j) * (2^m / ext))), then the
+ *   order-m Hilbert index of (q_0..q_{d-1}) (Skilling's transpose algorithm,
+ *   levels most significant first, axis 0 first within a level).  ext == 0
+ *   gives key 0 for every point.
+ *   Points are stably sorted by key (ties keep input order) and center c is
+ *   the sorted point floor(c*n/k) + floor(n/(2k)).
+ * Outputs:
+ *   centers_out [device] k*d doubles, row-major [k][d] (FP32 input widened).
+ *   perm_out    [device] n int32, sorted position -> input index, or NULL.
+ *   keys_out    [device] n uint64, key of each point in input order, or NULL.
+ * Errors: BKM_EINVAL, BKM_EDATA (non-finite coordinate), BKM_ENOMEM, BKM_EHIP. */
+int bkm_init_centers_sfc(const bkm_points* pts, int32_t k, int32_t hilbert_order,
+                         double* centers_out, int32_t* perm_out, uint64_t* keys_out,
+                         void* stream);
+
+/* Balanced k-means (Alg. 2 around Alg. 1).
+ *   Effective distance dist(p,c)/influence(c), Euclidean, not squared
+ *   (Sec. 4.2); each sweep assigns every point the argmin (ties to the lowest
+ *   center index), sums block weights, and stops the AssignAndBalance call when
+ *   max weight <= L_max, else multiplies influence(c) by
+ *   clamp((W/k / weight(c))^(1/d), 0.95, 1.05) (Eq. 1 read so that oversized
+ *   blocks lose influence, 5% step limit; an empty block gets 1.05).  After each
+ *   call the centers move to the weighted means of their blocks (an empty block
+ *   keeps its center); the run stops when the largest move is below
+ *   delta_threshold, else the influence is eroded (Sec. 4.2:
+ *   alpha = 2/(1+exp(-delta/beta)) - 1, influence <- influence^(1-alpha), beta
+ *   the mean bounding-box diagonal of the non-empty blocks) and the next call
+ *   starts.  Points are processed in Hilbert order; the Hamerly bounds
+ *   (Sec. 4.3) and box pruning (Sec. 4.4) are exact, so the assignment is the
+ *   argmin itself.
+ * Inputs:
+ *   centers_init [device] k*d doubles [k][d], or NULL for the SFC bootstrap.
+ * Outputs (device, caller-allocated; NULL skips an optional one):
+ *   assignment_out    n int32 block ids in input order (required).
+ *   centers_out       k*d doubles [k][d] (required): the final centers.
+ *   influence_out     k doubles, or NULL.
+ *   block_weights_out k doubles (exact integers for unit weights), or NULL.
+ *   info              [host] counters, or NULL.
+ * Returns BKM_OK, BKM_WUNBALANCED, or an error code. */
+int bkm_balanced_kmeans(const bkm_points* pts, const bkm_params* prm,
+                        const double* centers_init, int32_t* assignment_out,
+                        double* centers_out, double* influence_out,
+                        double* block_weights_out, bkm_info* info, void* stream);
+
+/* A sequence of `steps` assignment sweeps with caller-given centers and
+ * influence (the Alg. 1 inner loop with the bound relaxation of Alg. 2
+ * between steps).  Step s uses centers[s] and influence[s]; the Hamerly
+ * bounds carry over from step to step, relaxed by how far each center moved
+ * and how its influence changed, exactly as in bkm_balanced_kmeans.
+ *   centers    [device] steps*k*d doubles, [steps][k][d].
+ *   influence  [device] steps*k doubles, > 0.
+ *   assignment_out [device] steps*n int32, [steps][n], input order.
+ *   block_weights_out [device] steps*k doubles, or NULL.
+ *   info [host] counters summed over the steps, or NULL.
+ * Errors as bkm_balanced_kmeans. */
+int bkm_assign_sweeps(const bkm_points* pts, int32_t k, int32_t steps,
+                      const double* centers, const double* influence,
+                      int32_t precision, int32_t use_bounds, int32_t tile_points,
+                      int32_t* assignment_out, double* block_weights_out,
+                      bkm_info* info, void* stream);
+
+/* Statistics of a given assignment (Sec. 2): block weights, weighted block
+ * means (NaN for an empty block), imbalance, k-means objective, empty and
+ * overloaded block counts.
+ *   assignment [device] n int32 in [0, k).
+ *   block_weights_out, centers_out [device] k and k*d doubles, or NULL.
+ *   out [host] required.
+ * Errors: BKM_EINVAL (also for an assignment outside [0,k)), BKM_EDATA,
+ * BKM_ENOMEM, BKM_EHIP. */
+int bkm_partition_stats(const bkm_points* pts, const int32_t* assignment, int32_t k,
+                        double epsilon, double* block_weights_out, double* centers_out,
+                        bkm_stats* out, void* stream);
+
+/* Message of the last nonzero return on the calling thread ("" if none). */
+const char* bkm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BKM_H */

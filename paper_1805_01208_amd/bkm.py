@@ -1,0 +1,213 @@
+"""Thin ctypes binding of libbkm (include/bkm.h).
+
+Argument marshalling only: every step runs in the HIP kernels of libbkm.so.
+Points are a list of d contiguous CUDA tensors (float32 or float64, same dtype,
+input order); weights a float64 CUDA tensor or None.  Work is enqueued on
+torch's current stream.  There is no CPU fallback: a missing library raises.
+"""
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbkm.so")
+
+BKM_OK, BKM_EINVAL, BKM_EDATA, BKM_ENOMEM, BKM_EHIP = 0, -1, -2, -3, -4
+BKM_WUNBALANCED = 1
+BKM_F32, BKM_F64 = 0, 1
+PREC_F64, PREC_F32_RECHECK = 0, 1
+PRECISIONS = {"f64": PREC_F64, "f32_recheck": PREC_F32_RECHECK}
+
+
+class Points(C.Structure):
+    _fields_ = [("n", C.c_int64), ("d", C.c_int32), ("dtype", C.c_int32),
+                ("coords", C.c_void_p * 3), ("weights", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("k", C.c_int32), ("max_iter", C.c_int32), ("max_balance_iter", C.c_int32),
+                ("hilbert_order", C.c_int32), ("precision", C.c_int32),
+                ("use_bounds", C.c_int32), ("tile_points", C.c_int32),
+                ("super_tiles", C.c_int32), ("epsilon", C.c_double),
+                ("delta_threshold", C.c_double), ("recheck_rel_gap", C.c_double)]
+
+
+class Info(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("sweeps", C.c_int32), ("balanced", C.c_int32),
+                ("converged", C.c_int32), ("imbalance", C.c_double),
+                ("max_block_weight", C.c_double), ("l_max", C.c_double),
+                ("evaluated", C.c_int64), ("skipped", C.c_int64), ("rechecked", C.c_int64),
+                ("changed", C.c_int64), ("candidate_evals", C.c_int64),
+                ("bootstrap_ms", C.c_double), ("total_ms", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("imbalance", C.c_double), ("objective", C.c_double), ("l_max", C.c_double),
+                ("empty_blocks", C.c_int32), ("overloaded_blocks", C.c_int32)]
+
+
+class BkmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libbkm error {code}: {msg}")
+        self.code = code
+
+
+_LIB = None
+FUNCTIONS = ("bkm_default_params", "bkm_init_centers_sfc", "bkm_balanced_kmeans",
+             "bkm_assign_sweeps", "bkm_partition_stats", "bkm_last_error")
+
+
+def lib():
+    """Load libbkm.so (built by paper_1805_01208_amd/build.py)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing; build it with "
+                               "python -m paper_1805_01208_amd.build")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.bkm_default_params.argtypes = [C.POINTER(Params), C.c_int32]
+        L.bkm_default_params.restype = None
+        L.bkm_init_centers_sfc.argtypes = [C.POINTER(Points), C.c_int32, C.c_int32, P, P, P, P]
+        L.bkm_balanced_kmeans.argtypes = [C.POINTER(Points), C.POINTER(Params), P, P, P, P, P,
+                                          C.POINTER(Info), P]
+        L.bkm_assign_sweeps.argtypes = [C.POINTER(Points), C.c_int32, C.c_int32, P, P, C.c_int32,
+                                        C.c_int32, C.c_int32, P, P, C.POINTER(Info), P]
+        L.bkm_partition_stats.argtypes = [C.POINTER(Points), P, C.c_int32, C.c_double, P, P,
+                                          C.POINTER(Stats), P]
+        L.bkm_last_error.argtypes = []
+        L.bkm_last_error.restype = C.c_char_p
+        for f in ("bkm_init_centers_sfc", "bkm_balanced_kmeans", "bkm_assign_sweeps",
+                  "bkm_partition_stats"):
+            getattr(L, f).restype = C.c_int
+        _LIB = L
+    return _LIB
+
+
+def _check(rc):
+    if rc < 0:
+        raise BkmError(rc, lib().bkm_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_points(X, W=None):
+    """Points struct over caller tensors (kept alive by the caller)."""
+    X = list(X)
+    d = len(X)
+    if d not in (2, 3):
+        raise ValueError("points need 2 or 3 coordinate arrays")
+    dt = X[0].dtype
+    for x in X:
+        if x.dtype != dt or not x.is_cuda or not x.is_contiguous() or x.dim() != 1:
+            raise ValueError("coordinates must be contiguous 1-D CUDA tensors of one dtype")
+    if dt not in (torch.float32, torch.float64):
+        raise ValueError("coordinates must be float32 or float64")
+    if W is not None and (W.dtype != torch.float64 or not W.is_cuda or not W.is_contiguous()):
+        raise ValueError("weights must be a contiguous float64 CUDA tensor")
+    p = Points()
+    p.n = X[0].numel()
+    p.d = d
+    p.dtype = BKM_F32 if dt == torch.float32 else BKM_F64
+    for j in range(3):
+        p.coords[j] = X[j].data_ptr() if j < d else None
+    p.weights = None if W is None else W.data_ptr()
+    return p
+
+
+def default_params(k):
+    p = Params()
+    lib().bkm_default_params(C.byref(p), int(k))
+    return p
+
+
+def info_dict(info):
+    return {f: getattr(info, f) for f, _ in Info._fields_}
+
+
+def init_centers_sfc(X, k, hilbert_order=16):
+    """(centers [k,d] float64, perm int32 sorted->input, keys int64 bit pattern of uint64)."""
+    dev = X[0].device
+    pts = make_points(X)
+    cen = torch.empty((k, pts.d), dtype=torch.float64, device=dev)
+    perm = torch.empty(pts.n, dtype=torch.int32, device=dev)
+    keys = torch.empty(pts.n, dtype=torch.int64, device=dev)
+    _check(lib().bkm_init_centers_sfc(C.byref(pts), int(k), int(hilbert_order), _ptr(cen),
+                                      _ptr(perm), _ptr(keys), _stream()))
+    return cen, perm, keys
+
+
+def balanced_kmeans(X, k, W=None, eps=0.03, max_iter=50, max_balance_iter=20,
+                    delta_threshold=-1.0, hilbert_order=16, precision="f32_recheck",
+                    use_bounds=True, tile_points=0, super_tiles=0, recheck_rel_gap=1e-5,
+                    centers_init=None, out=None):
+    """Balanced k-means; returns dict(A, centers, influence, block_weights, info, code)."""
+    dev = X[0].device
+    pts = make_points(X, W)
+    prm = default_params(k)
+    prm.epsilon = float(eps)
+    prm.max_iter = int(max_iter)
+    prm.max_balance_iter = int(max_balance_iter)
+    prm.delta_threshold = float(delta_threshold)
+    prm.hilbert_order = int(hilbert_order)
+    prm.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    prm.use_bounds = 1 if use_bounds else 0
+    prm.tile_points = int(tile_points)
+    prm.super_tiles = int(super_tiles)
+    prm.recheck_rel_gap = float(recheck_rel_gap)
+    if out is None:
+        out = dict(A=torch.empty(pts.n, dtype=torch.int32, device=dev),
+                   centers=torch.empty((k, pts.d), dtype=torch.float64, device=dev),
+                   influence=torch.empty(k, dtype=torch.float64, device=dev),
+                   block_weights=torch.empty(k, dtype=torch.float64, device=dev))
+    ci = None
+    if centers_init is not None:
+        ci = centers_init.to(device=dev, dtype=torch.float64).contiguous()
+    info = Info()
+    rc = _check(lib().bkm_balanced_kmeans(C.byref(pts), C.byref(prm), _ptr(ci), _ptr(out["A"]),
+                                          _ptr(out["centers"]), _ptr(out["influence"]),
+                                          _ptr(out["block_weights"]), C.byref(info), _stream()))
+    res = dict(out)
+    res["info"] = info_dict(info)
+    res["code"] = rc
+    return res
+
+
+def assign_sweeps(X, centers_seq, influence_seq, precision="f32_recheck", use_bounds=True,
+                  tile_points=0):
+    """Successive sweeps with given (centers [S,k,d], influence [S,k]); returns
+    (A [S,n] int32, block weights [S,k] float64, info)."""
+    dev = X[0].device
+    pts = make_points(X)
+    cs = centers_seq.to(device=dev, dtype=torch.float64).contiguous()
+    ins = influence_seq.to(device=dev, dtype=torch.float64).contiguous()
+    S, k = ins.shape
+    A = torch.empty((S, pts.n), dtype=torch.int32, device=dev)
+    bw = torch.empty((S, k), dtype=torch.float64, device=dev)
+    info = Info()
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(lib().bkm_assign_sweeps(C.byref(pts), int(k), int(S), _ptr(cs), _ptr(ins), prec,
+                                   1 if use_bounds else 0, int(tile_points), _ptr(A), _ptr(bw),
+                                   C.byref(info), _stream()))
+    return A, bw, info_dict(info)
+
+
+def partition_stats(X, A, k, eps=0.03, W=None):
+    dev = X[0].device
+    pts = make_points(X, W)
+    bw = torch.empty(k, dtype=torch.float64, device=dev)
+    cen = torch.empty((k, pts.d), dtype=torch.float64, device=dev)
+    st = Stats()
+    _check(lib().bkm_partition_stats(C.byref(pts), _ptr(A.contiguous()), int(k), float(eps),
+                                     _ptr(bw), _ptr(cen), C.byref(st), _stream()))
+    res = {f: getattr(st, f) for f, _ in Stats._fields_}
+    res.update(block_weights=bw, centers=cen)
+    return res

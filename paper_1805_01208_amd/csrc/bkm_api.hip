@@ -1,0 +1,479 @@
+// C ABI of libbkm (include/bkm.h): argument checks, device workspace, and the
+// host driver of the SFC bootstrap and the round loop of balanced k-means
+// (Alg. 2 around Alg. 1).
+//
+// The round loop keeps the host out of the per-sweep decision: sweeps,
+// balance tests and the round-end kernels read the run's device state and turn
+// into no-ops once their AssignAndBalance call (or the run) is over, so the
+// host enqueues a batch of sweeps plus the round end and synchronises once per
+// batch.  A batch starts at one sweep (most calls balance at once) and doubles
+// while a call keeps running.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "bkm_internal.h"
+
+using namespace bkm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(e_ == hipErrorOutOfMemory ? BKM_ENOMEM : BKM_EHIP, "%s: %s", #expr, \
+                        hipGetErrorString(e_));                                         \
+    } while (0)
+
+// Device workspace carved from one stream-ordered allocation.
+struct Arena {
+    char* base = nullptr;
+    size_t off = 0;
+    size_t cap = 0;
+    hipStream_t s = nullptr;
+
+    template <typename T>
+    T* take(size_t count)
+    {
+        size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+        T* p = (T*)(base + off);
+        off += bytes;
+        return p;
+    }
+    ~Arena()
+    {
+        if (base) {
+            (void)hipFreeAsync(base, s);
+            (void)hipStreamSynchronize(s);
+        }
+    }
+};
+
+struct Sizes {
+    size_t total = 0;
+    template <typename T>
+    void add(size_t count) { total += (count * sizeof(T) + 255) & ~size_t(255); }
+};
+
+void keep_pool_memory()
+{
+    static bool done = false;
+    if (done) return;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    done = true;
+}
+
+// Small pinned host buffer for per-round state reads.
+DevState* host_state()
+{
+    thread_local DevState* h = nullptr;
+    if (!h) {
+        if (hipHostMalloc((void**)&h, sizeof(DevState), hipHostMallocDefault) != hipSuccess)
+            h = nullptr;
+    }
+    return h;
+}
+
+int check_points(const bkm_points* pts)
+{
+    if (!pts) return fail(BKM_EINVAL, "points is NULL");
+    if (pts->n < 1 || pts->n >= (int64_t(1) << 31))
+        return fail(BKM_EINVAL, "n = %lld outside [1, 2^31)", (long long)pts->n);
+    if (pts->d != 2 && pts->d != 3) return fail(BKM_EINVAL, "d = %d is not 2 or 3", pts->d);
+    if (pts->dtype != BKM_F32 && pts->dtype != BKM_F64)
+        return fail(BKM_EINVAL, "dtype = %d unknown", pts->dtype);
+    for (int j = 0; j < pts->d; ++j)
+        if (!pts->coords[j]) return fail(BKM_EINVAL, "coords[%d] is NULL", j);
+    return BKM_OK;
+}
+
+int check_order(int d, int m)
+{
+    const int mmax = d == 2 ? 31 : 21;
+    if (m < 1 || m > mmax)
+        return fail(BKM_EINVAL, "hilbert_order %d outside [1, %d] for d = %d", m, mmax, d);
+    return BKM_OK;
+}
+
+// Fill the sizes of a run and lay its arrays out in the arena.
+void plan(RunDev& r, const bkm_points* pts, int k, int T, int ST, int precision, int use_bounds,
+          double gap)
+{
+    std::memset(&r, 0, sizeof(r));
+    r.n = pts->n;
+    r.d = pts->d;
+    r.k = k;
+    r.in_f32 = pts->dtype == BKM_F32;
+    r.weighted = pts->weights != nullptr;
+    r.T = T;
+    r.ppt = T / kBlock;
+    r.ntiles = (int)((r.n + T - 1) / T);
+    r.npad = (int64_t)r.ntiles * T;
+    r.super_tiles = ST;
+    r.nsuper = (r.ntiles + ST - 1) / ST;
+    r.ngroups = (int)(r.npad / kWave);
+    r.precision = precision;
+    r.use_bounds = use_bounds;
+    r.recheck_gap = gap;
+    for (int j = 0; j < r.d; ++j) r.in_x[j] = pts->coords[j];
+    r.in_w = pts->weights;
+}
+
+size_t layout(RunDev& r, Arena* a, bool full)
+{
+    Sizes z;
+    const int64_t n = r.n, np = r.npad;
+    const int d = r.d, k = r.k;
+    const int nblk = (int)((n + 4095) / 4096);
+    const int64_t hlen = (int64_t)256 * nblk;
+    const int nseg = (int)((hlen + 1023) / 1024);
+    auto both = [&](auto* tag, size_t count, auto*& ptr) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        if (a)
+            ptr = a->take<T>(count);
+        else
+            z.add<T>(count);
+    };
+    both((DevState*)nullptr, 1, r.st);
+    both((double*)nullptr, std::max<int64_t>(8192, k), r.red);
+    both((uint64_t*)nullptr, n, r.keys);
+    both((uint64_t*)nullptr, n, r.keys2);
+    both((int32_t*)nullptr, n, r.perm);
+    both((int32_t*)nullptr, n, r.vals2);
+    both((uint32_t*)nullptr, hlen, r.hist);
+    both((uint32_t*)nullptr, nseg + 1, r.part);
+    for (int j = 0; j < d; ++j) {
+        if (r.in_f32)
+            both((float*)nullptr, np, r.xs32[j]);
+        else
+            both((double*)nullptr, np, r.xs64[j]);
+    }
+    both((double*)nullptr, (size_t)d * k, r.C);
+    if (full) {
+        if (r.precision == BKM_PREC_F32_RECHECK)
+            for (int j = 0; j < d; ++j) both((float*)nullptr, np, r.ofs[j]);
+        if (r.weighted) both((double*)nullptr, np, r.ws);
+        both((int32_t*)nullptr, np, r.A);
+        both((float*)nullptr, np, r.ubt);
+        both((float*)nullptr, np, r.lbt);
+        both((double*)nullptr, (size_t)r.ntiles * 2 * d, r.tbox);
+        both((double*)nullptr, (size_t)r.ngroups * 2 * d, r.gbox);
+        both((double*)nullptr, (size_t)r.nsuper * 2 * d, r.sbox);
+        both((int32_t*)nullptr, (size_t)r.nsuper * k, r.slist);
+        both((int32_t*)nullptr, (size_t)r.nsuper, r.scount);
+        both((double*)nullptr, (size_t)k, r.I);
+        both((double2*)nullptr, (size_t)k, r.clus);
+        both((long long*)nullptr, (size_t)k * kAcc, r.acc);
+        both((unsigned long long*)nullptr, (size_t)k * 2 * d, r.bb);
+    }
+    return z.total;
+}
+
+int alloc_run(RunDev& r, Arena& a, hipStream_t s, bool full)
+{
+    size_t bytes = layout(r, nullptr, full);
+    a.s = s;
+    hipError_t e = hipMallocAsync((void**)&a.base, bytes, s);
+    if (e != hipSuccess) {
+        a.base = nullptr;
+        return fail(e == hipErrorOutOfMemory ? BKM_ENOMEM : BKM_EHIP,
+                    "hipMallocAsync(%zu bytes): %s", bytes, hipGetErrorString(e));
+    }
+    a.cap = bytes;
+    layout(r, &a, full);
+    HIPCHK(hipMemsetAsync(r.st, 0, sizeof(DevState), s));
+    return BKM_OK;
+}
+
+int read_state(const RunDev& r, hipStream_t s, DevState* out)
+{
+    DevState* h = host_state();
+    if (!h) return fail(BKM_ENOMEM, "pinned host buffer unavailable");
+    HIPCHK(hipMemcpyAsync(h, r.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *out = *h;
+    return BKM_OK;
+}
+
+// SFC bootstrap: bounding box (+ data checks), keys, sort, permutation.
+int bootstrap(RunDev& r, int order, hipStream_t s, bool tiles)
+{
+    HIPCHK(launch_bbox(r, order, s));
+    DevState h;
+    int rc = read_state(r, s, &h);
+    if (rc) return rc;
+    if (h.bad_data)
+        return fail(BKM_EDATA, r.weighted ? "non-finite coordinate or weight <= 0 / non-finite"
+                                          : "non-finite coordinate");
+    HIPCHK(launch_keys(r, order, r.perm, s));
+    HIPCHK(radix_sort_pairs(r, r.keys, r.perm, r.d * order, s));
+    HIPCHK(launch_permute(r, r.perm, s));
+    if (tiles) HIPCHK(launch_tile_prep(r, s));
+    return BKM_OK;
+}
+
+int check_tile(int T) { return T == 0 || T == 256 || T == 512 || T == 1024; }
+
+}  // namespace
+
+extern "C" {
+
+void bkm_default_params(bkm_params* p, int32_t k)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->k = k;
+    p->max_iter = 50;
+    p->max_balance_iter = 20;
+    p->hilbert_order = 16;
+    p->precision = BKM_PREC_F32_RECHECK;
+    p->use_bounds = 1;
+    p->tile_points = 0;
+    p->super_tiles = 0;
+    p->epsilon = 0.03;
+    p->delta_threshold = -1.0;
+    p->recheck_rel_gap = 1e-5;
+}
+
+const char* bkm_last_error(void) { return g_err.c_str(); }
+
+int bkm_init_centers_sfc(const bkm_points* pts, int32_t k, int32_t hilbert_order,
+                         double* centers_out, int32_t* perm_out, uint64_t* keys_out,
+                         void* stream)
+{
+    g_err.clear();
+    int rc = check_points(pts);
+    if (rc) return rc;
+    if (k < 1 || k > pts->n) return fail(BKM_EINVAL, "k = %d outside [1, n]", k);
+    if ((rc = check_order(pts->d, hilbert_order))) return rc;
+    if (!centers_out) return fail(BKM_EINVAL, "centers_out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    keep_pool_memory();
+    RunDev r;
+    plan(r, pts, k, 1024, 16, BKM_PREC_F64, 0, 0.0);
+    Arena a;
+    if ((rc = alloc_run(r, a, s, false))) return rc;
+    HIPCHK(launch_bbox(r, hilbert_order, s));
+    DevState h;
+    if ((rc = read_state(r, s, &h))) return rc;
+    if (h.bad_data) return fail(BKM_EDATA, "non-finite coordinate");
+    HIPCHK(launch_keys(r, hilbert_order, r.perm, s));
+    if (keys_out)
+        HIPCHK(hipMemcpyAsync(keys_out, r.keys, r.n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    HIPCHK(radix_sort_pairs(r, r.keys, r.perm, r.d * hilbert_order, s));
+    HIPCHK(launch_permute(r, r.perm, s));
+    HIPCHK(launch_centers_from_sorted(r, centers_out, 1, s));
+    if (perm_out)
+        HIPCHK(hipMemcpyAsync(perm_out, r.perm, r.n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return BKM_OK;
+}
+
+int bkm_balanced_kmeans(const bkm_points* pts, const bkm_params* prm, const double* centers_init,
+                        int32_t* assignment_out, double* centers_out, double* influence_out,
+                        double* block_weights_out, bkm_info* info, void* stream)
+{
+    g_err.clear();
+    int rc = check_points(pts);
+    if (rc) return rc;
+    if (!prm) return fail(BKM_EINVAL, "params is NULL");
+    const bkm_params p = *prm;
+    if (p.k < 1 || p.k > pts->n) return fail(BKM_EINVAL, "k = %d outside [1, n]", p.k);
+    if (!(p.epsilon >= 0.0)) return fail(BKM_EINVAL, "epsilon must be >= 0");
+    if (p.max_iter < 1 || p.max_balance_iter < 1)
+        return fail(BKM_EINVAL, "max_iter and max_balance_iter must be >= 1");
+    if ((rc = check_order(pts->d, p.hilbert_order))) return rc;
+    if (p.precision != BKM_PREC_F64 && p.precision != BKM_PREC_F32_RECHECK)
+        return fail(BKM_EINVAL, "precision %d unknown", p.precision);
+    if (!check_tile(p.tile_points)) return fail(BKM_EINVAL, "tile_points %d not 0/256/512/1024", p.tile_points);
+    if (p.super_tiles < 0) return fail(BKM_EINVAL, "super_tiles must be >= 0");
+    if (!(p.recheck_rel_gap >= 0.0) || !std::isfinite(p.recheck_rel_gap))
+        return fail(BKM_EINVAL, "recheck_rel_gap must be finite and >= 0");
+    if (std::isnan(p.delta_threshold)) return fail(BKM_EINVAL, "delta_threshold is NaN");
+    if (!assignment_out || !centers_out) return fail(BKM_EINVAL, "assignment_out/centers_out is NULL");
+
+    hipStream_t s = (hipStream_t)stream;
+    keep_pool_memory();
+    const int T = p.tile_points ? p.tile_points : 1024;
+    const int ST = p.super_tiles ? p.super_tiles : 16;
+    RunDev r;
+    plan(r, pts, p.k, T, ST, p.precision, p.use_bounds ? 1 : 0, p.recheck_rel_gap);
+    Arena a;
+    if ((rc = alloc_run(r, a, s, true))) return rc;
+
+    hipEvent_t ev[3];
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    struct EvFree { hipEvent_t* e; ~EvFree() { for (int i = 0; i < 3; ++i) (void)hipEventDestroy(e[i]); } } evf{ev};
+    HIPCHK(hipEventRecord(ev[0], s));
+
+    if ((rc = bootstrap(r, p.hilbert_order, s, true))) return rc;
+    if (!centers_init) HIPCHK(launch_centers_from_sorted(r, r.C, 0, s));
+    HIPCHK(launch_init_run(r, centers_init, p.max_iter, p.max_balance_iter, p.epsilon,
+                           p.delta_threshold, s));
+    HIPCHK(hipEventRecord(ev[1], s));
+
+    DevState h;
+    int prev_rounds = 0;
+    int batch = 1;
+    // every batch ends a call or adds a sweep to it, so the loop is bounded
+    const int64_t max_batches = (int64_t)p.max_iter * (p.max_balance_iter + 2) + 8;
+    for (int64_t nb = 0;; ++nb) {
+        if (nb >= max_batches) return fail(BKM_EHIP, "round loop made no progress");
+        for (int i = 0; i < batch; ++i) {
+            HIPCHK(launch_supercand(r, s));
+            HIPCHK(launch_sweep(r, s));
+            HIPCHK(launch_balance(r, s));
+        }
+        HIPCHK(launch_block_boxes(r, s));
+        HIPCHK(launch_move(r, s));
+        if ((rc = read_state(r, s, &h))) return rc;
+        if (h.done) break;
+        if (h.rounds > prev_rounds) {
+            prev_rounds = h.rounds;
+            batch = 1;
+        } else {
+            batch = std::min(batch * 2, std::max(1, p.max_balance_iter - h.sweep_in_round));
+        }
+    }
+    HIPCHK(launch_finish(r, assignment_out, centers_out, influence_out, block_weights_out, s));
+    HIPCHK(hipEventRecord(ev[2], s));
+    if ((rc = read_state(r, s, &h))) return rc;
+
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->rounds = h.rounds;
+        info->sweeps = h.sweeps;
+        info->balanced = h.balanced;
+        info->converged = h.converged;
+        info->l_max = h.lmax;
+        info->max_block_weight = h.max_weight;
+        info->imbalance = h.max_weight / h.target - 1.0;
+        info->evaluated = (int64_t)h.evaluated;
+        info->skipped = (int64_t)h.skipped;
+        info->rechecked = (int64_t)h.rechecked;
+        info->changed = (int64_t)h.changed;
+        info->candidate_evals = (int64_t)h.cand_evals;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) info->bootstrap_ms = ms;
+        if (hipEventElapsedTime(&ms, ev[0], ev[2]) == hipSuccess) info->total_ms = ms;
+    }
+    return h.balanced ? BKM_OK : BKM_WUNBALANCED;
+}
+
+int bkm_assign_sweeps(const bkm_points* pts, int32_t k, int32_t steps, const double* centers,
+                      const double* influence, int32_t precision, int32_t use_bounds,
+                      int32_t tile_points, int32_t* assignment_out, double* block_weights_out,
+                      bkm_info* info, void* stream)
+{
+    g_err.clear();
+    int rc = check_points(pts);
+    if (rc) return rc;
+    if (k < 1 || k > pts->n) return fail(BKM_EINVAL, "k = %d outside [1, n]", k);
+    if (steps < 1) return fail(BKM_EINVAL, "steps must be >= 1");
+    if (!centers || !influence || !assignment_out)
+        return fail(BKM_EINVAL, "centers/influence/assignment_out is NULL");
+    if (precision != BKM_PREC_F64 && precision != BKM_PREC_F32_RECHECK)
+        return fail(BKM_EINVAL, "precision %d unknown", precision);
+    if (!check_tile(tile_points)) return fail(BKM_EINVAL, "tile_points %d not 0/256/512/1024", tile_points);
+    hipStream_t s = (hipStream_t)stream;
+    keep_pool_memory();
+    RunDev r;
+    plan(r, pts, k, tile_points ? tile_points : 1024, 16, precision, use_bounds ? 1 : 0, 1e-5);
+    Arena a;
+    if ((rc = alloc_run(r, a, s, true))) return rc;
+    if ((rc = bootstrap(r, 16, s, true))) return rc;
+    HIPCHK(launch_init_run(r, nullptr, 1, 1, 0.0, -1.0, s));
+    for (int t = 0; t < steps; ++t) {
+        HIPCHK(launch_set_step(r, centers + (int64_t)t * k * r.d, influence + (int64_t)t * k,
+                               t == 0, s));
+        HIPCHK(launch_supercand(r, s));
+        HIPCHK(launch_sweep(r, s));
+        HIPCHK(launch_finish(r, assignment_out + (int64_t)t * r.n, nullptr, nullptr,
+                             block_weights_out ? block_weights_out + (int64_t)t * k : nullptr, s));
+    }
+    DevState h;
+    if ((rc = read_state(r, s, &h))) return rc;
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->sweeps = steps;
+        info->evaluated = (int64_t)h.evaluated;
+        info->skipped = (int64_t)h.skipped;
+        info->rechecked = (int64_t)h.rechecked;
+        info->changed = (int64_t)h.changed;
+        info->candidate_evals = (int64_t)h.cand_evals;
+    }
+    return BKM_OK;
+}
+
+int bkm_partition_stats(const bkm_points* pts, const int32_t* assignment, int32_t k,
+                        double epsilon, double* block_weights_out, double* centers_out,
+                        bkm_stats* out, void* stream)
+{
+    g_err.clear();
+    int rc = check_points(pts);
+    if (rc) return rc;
+    if (k < 1) return fail(BKM_EINVAL, "k = %d < 1", k);
+    if (!assignment || !out) return fail(BKM_EINVAL, "assignment/out is NULL");
+    if (!(epsilon >= 0.0)) return fail(BKM_EINVAL, "epsilon must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    keep_pool_memory();
+    RunDev r;
+    plan(r, pts, k, 1024, 16, BKM_PREC_F64, 0, 0.0);
+    // statistics need only the state, the reduction buffer, centers and sums
+    Sizes z;
+    z.add<DevState>(1);
+    z.add<double>(std::max<int64_t>(8192, k));
+    z.add<double>((size_t)k * r.d);
+    z.add<long long>((size_t)k * kAcc);
+    z.add<double>(8);
+    Arena a;
+    a.s = s;
+    HIPCHK(hipMallocAsync((void**)&a.base, z.total, s));
+    r.st = a.take<DevState>(1);
+    r.red = a.take<double>(std::max<int64_t>(8192, k));
+    r.C = a.take<double>((size_t)k * r.d);
+    r.acc = a.take<long long>((size_t)k * kAcc);
+    double* out6 = a.take<double>(8);
+    HIPCHK(hipMemsetAsync(r.st, 0, sizeof(DevState), s));
+    HIPCHK(hipMemsetAsync(r.acc, 0, (size_t)k * kAcc * sizeof(long long), s));
+    HIPCHK(launch_bbox(r, 16, s));
+    HIPCHK(launch_stats(r, assignment, epsilon, block_weights_out, centers_out, out6, s));
+    double h6[8];
+    HIPCHK(hipMemcpyAsync(h6, out6, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    DevState h;
+    if ((rc = read_state(r, s, &h))) return rc;
+    if (h.bad_data & 2) return fail(BKM_EINVAL, "assignment outside [0, k)");
+    if (h.bad_data & 1) return fail(BKM_EDATA, "non-finite coordinate or bad weight");
+    out->imbalance = h6[0];
+    out->objective = h6[1];
+    out->l_max = h6[2];
+    out->empty_blocks = (int32_t)h6[3];
+    out->overloaded_blocks = (int32_t)h6[4];
+    return BKM_OK;
+}
+
+}  // extern "C"

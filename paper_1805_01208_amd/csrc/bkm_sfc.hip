@@ -1,0 +1,535 @@
+// Hilbert space-filling-curve bootstrap of balanced k-means (Alg. 2: the SFC
+// index of every point, the stable sort by it, the redistribution into
+// sorted order and the initial centers; Sec. 4.1).  On one GPU the global sort
+// and redistribution become an LSD radix sort of (key, index) followed by one
+// gather into a structure-of-arrays copy in curve order, cut into tiles of
+// consecutive points whose bounding boxes drive the candidate pruning of the
+// sweep.
+#include <math.h>
+
+#include "bkm_internal.h"
+
+namespace bkm {
+
+namespace {
+
+template <typename T>
+__device__ inline double ld(const void* p, int64_t i)
+{
+    return (double)((const T*)p)[i];
+}
+
+// ---------------------------------------------------------------- bbox
+// Per-block partial min/max of every axis, the largest weight and finiteness
+// checks; a single block then folds the partials into the run state.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bbox_partial(RunDev r)
+{
+    double mn[3] = {INFINITY, INFINITY, INFINITY};
+    double mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double wmax = 0.0, wsum = 0.0;
+    int bad = 0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < r.n; i += stride) {
+        for (int j = 0; j < r.d; ++j) {
+            double v = ld<T>(r.in_x[j], i);
+            if (!isfinite(v)) bad = 1;
+            mn[j] = fmin(mn[j], v);
+            mx[j] = fmax(mx[j], v);
+        }
+        if (r.in_w) {
+            double w = r.in_w[i];
+            if (!(w > 0.0) || !isfinite(w)) bad = 1;
+            wmax = fmax(wmax, w);
+            wsum += w;
+        }
+    }
+    __shared__ double sh[kBlock / kWave][8];
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    for (int j = 0; j < 3; ++j) {
+        mn[j] = wave_min_d(mn[j]);
+        mx[j] = wave_max_d(mx[j]);
+    }
+    wmax = wave_max_d(wmax);
+    wsum = wave_sum_d(wsum);
+    unsigned long long anybad = __ballot(bad);
+    if (lane == 0) {
+        for (int j = 0; j < 3; ++j) {
+            sh[wv][j] = mn[j];
+            sh[wv][3 + j] = mx[j];
+        }
+        sh[wv][6] = wmax;
+        sh[wv][7] = wsum;
+        if (anybad) atomicOr(&r.st->bad_data, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double o[8];
+        for (int q = 0; q < 8; ++q) o[q] = sh[0][q];
+        for (int w = 1; w < kBlock / kWave; ++w) {
+            for (int j = 0; j < 3; ++j) {
+                o[j] = fmin(o[j], sh[w][j]);
+                o[3 + j] = fmax(o[3 + j], sh[w][3 + j]);
+            }
+            o[6] = fmax(o[6], sh[w][6]);
+            o[7] += sh[w][7];
+        }
+        for (int q = 0; q < 8; ++q) r.red[(int64_t)blockIdx.x * 8 + q] = o[q];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bbox_final(RunDev r, int nparts, int m)
+{
+    __shared__ double o[8];
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 8; ++q) o[q] = r.red[q];
+        for (int b = 1; b < nparts; ++b) {
+            const double* p = r.red + (int64_t)b * 8;
+            for (int j = 0; j < 3; ++j) {
+                o[j] = fmin(o[j], p[j]);
+                o[3 + j] = fmax(o[3 + j], p[3 + j]);
+            }
+            o[6] = fmax(o[6], p[6]);
+            o[7] += p[7];
+        }
+        DevState* st = r.st;
+        double ext = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            st->lo[j] = j < r.d ? o[j] : 0.0;
+            st->hi[j] = j < r.d ? o[3 + j] : 0.0;
+            if (j < r.d && o[3 + j] - o[j] > ext) ext = o[3 + j] - o[j];
+        }
+        st->ext = ext;
+        st->key_scale = ext > 0.0 ? ldexp(1.0, m) / ext : 0.0;
+        // fixed-point scales: every coordinate term w*(x-lo)*sx_scale and
+        // weight term w*w_scale stays below 2^61 (power-of-two scales, so
+        // scaling is exact and only the final rounding to an integer is not)
+        double wmax = r.in_w ? o[6] : 1.0;
+        double span = ext > 0.0 ? ext * wmax : wmax;
+        st->sx_scale = ldexp(1.0, 60 - ilogb(span));
+        st->w_scale = r.in_w ? ldexp(1.0, 60 - ilogb(wmax)) : 1.0;
+        st->wmax = wmax;
+        st->total_weight = r.in_w ? o[7] : (double)r.n;
+    }
+}
+
+// ---------------------------------------------------------------- Hilbert
+// Hilbert index of cell (q0..q_{d-1}) at order m (Skilling, "Programming the
+// Hilbert curve", 2004): axes -> transposed index by walking levels from the
+// top (set bit in axis i: invert the lower bits of axis 0; clear bit:
+// exchange the lower bits of axes 0 and i), Gray code across axes, then
+// remove the accumulated rotation; finally interleave the transposed bits,
+// top level first, axis 0 first.
+template <int D>
+__device__ inline uint64_t hilbert_key(uint32_t* q, int m)
+{
+    for (int lvl = m - 1; lvl >= 1; --lvl) {
+        const uint32_t hb = 1u << lvl;
+        const uint32_t below = hb - 1u;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            if (q[a] & hb) {
+                q[0] ^= below;
+            } else {
+                const uint32_t sw = (q[0] ^ q[a]) & below;
+                q[0] ^= sw;
+                q[a] ^= sw;
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 1; a < D; ++a) q[a] ^= q[a - 1];
+    uint32_t rot = 0;
+    for (int lvl = m - 1; lvl >= 1; --lvl)
+        if (q[D - 1] & (1u << lvl)) rot ^= (1u << lvl) - 1u;
+#pragma unroll
+    for (int a = 0; a < D; ++a) q[a] ^= rot;
+    uint64_t key = 0;
+    for (int lvl = m - 1; lvl >= 0; --lvl) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) key = (key << 1) | (uint64_t)((q[a] >> lvl) & 1u);
+    }
+    return key;
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_keys(RunDev r, int m, uint64_t* keys,
+                                                 int32_t* vals)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= r.n) return;
+    const DevState* st = r.st;
+    uint64_t key = 0;
+    if (st->ext > 0.0) {
+        const double scale = st->key_scale;
+        const double top = ldexp(1.0, m) - 1.0;
+        uint32_t q[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            double c = floor((ld<T>(r.in_x[a], i) - st->lo[a]) * scale);
+            q[a] = (uint32_t)fmin(c, top);
+        }
+        key = hilbert_key<D>(q, m);
+    }
+    keys[i] = key;
+    vals[i] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------- radix sort
+// Stable LSD radix sort of (64-bit key, int32 value), 8-bit digits.  Per pass:
+// block histograms (digit-major), one exclusive scan, then a stable scatter in
+// which every block ranks its items in input order with wave ballots.
+constexpr int kIpt = 16;                       // items per thread per pass
+constexpr int kChunk = kBlock * kIpt;          // items per block per pass
+constexpr int kScanSeg = 1024;
+
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t* keys, int64_t n,
+                                                      int shift, uint32_t* hist, int nblk)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    for (int it = 0; it < kIpt; ++it) {
+        int64_t i = base + (int64_t)it * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of `len` counts, three kernels: segment sums, a scan of the
+// segment sums in one block, then the scan inside each segment.
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* in, int64_t len,
+                                                       uint32_t* part)
+{
+    __shared__ uint32_t sh[kBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanSeg;
+    uint32_t s = 0;
+    for (int q = threadIdx.x; q < kScanSeg; q += kBlock)
+        if (base + q < len) s += in[base + q];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(uint32_t* part, int nseg)
+{
+    __shared__ uint32_t sh[1024];
+    const int per = (nseg + 1023) / 1024;
+    const int b = threadIdx.x * per;
+    uint32_t s = 0;
+    for (int q = 0; q < per; ++q)
+        if (b + q < nseg) s += part[b + q];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = sh[threadIdx.x] - s;  // exclusive
+    for (int q = 0; q < per; ++q)
+        if (b + q < nseg) {
+            uint32_t v = part[b + q];
+            part[b + q] = run;
+            run += v;
+        }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t* data, int64_t len,
+                                                     const uint32_t* part)
+{
+    __shared__ uint32_t sh[kBlock];
+    const int64_t base = (int64_t)blockIdx.x * kScanSeg;
+    constexpr int per = kScanSeg / kBlock;
+    uint32_t v[per];
+    uint32_t s = 0;
+    for (int q = 0; q < per; ++q) {
+        int64_t i = base + (int64_t)threadIdx.x * per + q;
+        v[q] = i < len ? data[i] : 0;
+        s += v[q];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        uint32_t t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    uint32_t run = part[blockIdx.x] + sh[threadIdx.x] - s;
+    for (int q = 0; q < per; ++q) {
+        int64_t i = base + (int64_t)threadIdx.x * per + q;
+        if (i < len) data[i] = run;
+        run += v[q];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t* kin,
+                                                         const int32_t* vin, uint64_t* kout,
+                                                         int32_t* vout, int64_t n, int shift,
+                                                         const uint32_t* offs, int nblk)
+{
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wc[kBlock / kWave][256];
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    run[threadIdx.x] = offs[(int64_t)threadIdx.x * nblk + blockIdx.x];
+    for (int w = 0; w < kBlock / kWave; ++w) wc[w][threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    const unsigned long long below = (1ULL << lane) - 1ULL;
+    for (int it = 0; it < kIpt; ++it) {
+        const int64_t i = base + (int64_t)it * kBlock + threadIdx.x;
+        const bool valid = i < n;
+        uint64_t key = valid ? kin[i] : 0;
+        int32_t val = valid ? vin[i] : 0;
+        const uint32_t dig = (uint32_t)((key >> shift) & 255u);
+        unsigned long long same = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            unsigned long long bal = __ballot((dig >> b) & 1u);
+            same &= ((dig >> b) & 1u) ? bal : ~bal;
+        }
+        const uint32_t rank = (uint32_t)__popcll(same & below);
+        if (valid && rank == 0) wc[wv][dig] = (uint32_t)__popcll(same);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[dig] + rank;
+            for (int w = 0; w < wv; ++w) pos += wc[w][dig];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        uint32_t tot = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) {
+            tot += wc[w][threadIdx.x];
+            wc[w][threadIdx.x] = 0;
+        }
+        run[threadIdx.x] += tot;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- permute
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_permute(RunDev r, const int32_t* src)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= r.n) return;
+    const int32_t s = src[i];
+    r.perm[i] = s;
+    for (int j = 0; j < r.d; ++j) {
+        if (r.in_f32)
+            r.xs32[j][i] = ((const float*)r.in_x[j])[s];
+        else
+            r.xs64[j][i] = ((const double*)r.in_x[j])[s];
+    }
+    if (r.ws) r.ws[i] = r.in_w[s];
+}
+
+__device__ inline double xs_at(const RunDev& r, int j, int64_t i)
+{
+    return r.in_f32 ? (double)r.xs32[j][i] : r.xs64[j][i];
+}
+
+// Per tile (one block of T sorted points): exact FP64 box, boxes of its
+// 64-point groups, and the FP32 offsets of its points from the box center.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_tile_prep(RunDev r)
+{
+    __shared__ double sh[kBlock / kWave][2 * D];
+    __shared__ double box[2 * D];
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    const int64_t base = (int64_t)blockIdx.x * r.T;
+    double tmn[D], tmx[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        tmn[j] = INFINITY;
+        tmx[j] = -INFINITY;
+    }
+    for (int q = 0; q < r.ppt; ++q) {
+        const int64_t g0 = base + (int64_t)q * kBlock + wv * kWave;  // group start
+        const int64_t i = g0 + lane;
+        double gmn[D], gmx[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            double v = i < r.n ? xs_at(r, j, i) : INFINITY;
+            double w = i < r.n ? v : -INFINITY;
+            gmn[j] = wave_min_d(v);
+            gmx[j] = wave_max_d(w);
+            tmn[j] = fmin(tmn[j], gmn[j]);
+            tmx[j] = fmax(tmx[j], gmx[j]);
+        }
+        if (lane == 0 && g0 < r.n) {
+            double* gb = r.gbox + (g0 / kWave) * 2 * D;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                gb[j] = gmn[j];
+                gb[D + j] = gmx[j];
+            }
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            sh[wv][j] = tmn[j];
+            sh[wv][D + j] = tmx[j];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * D) {
+        const int j = threadIdx.x;
+        double v = sh[0][j];
+        for (int w = 1; w < kBlock / kWave; ++w) v = j < D ? fmin(v, sh[w][j]) : fmax(v, sh[w][j]);
+        box[j] = v;
+        r.tbox[(int64_t)blockIdx.x * 2 * D + j] = v;
+    }
+    __syncthreads();
+    if (r.precision == BKM_PREC_F32_RECHECK) {
+        double X[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) X[j] = 0.5 * (box[j] + box[D + j]);
+        for (int q = 0; q < r.ppt; ++q) {
+            const int64_t i = base + (int64_t)q * kBlock + threadIdx.x;
+            if (i < r.n) {
+#pragma unroll
+                for (int j = 0; j < D; ++j) r.ofs[j][i] = (float)(xs_at(r, j, i) - X[j]);
+            }
+        }
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_super_boxes(RunDev r)
+{
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= r.nsuper) return;
+    const int t0 = s * r.super_tiles;
+    const int t1 = min(r.ntiles, t0 + r.super_tiles);
+    double b[2 * D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        b[j] = INFINITY;
+        b[D + j] = -INFINITY;
+    }
+    for (int t = t0; t < t1; ++t) {
+        const double* tb = r.tbox + (int64_t)t * 2 * D;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            b[j] = fmin(b[j], tb[j]);
+            b[D + j] = fmax(b[D + j], tb[D + j]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 2 * D; ++j) r.sbox[(int64_t)s * 2 * D + j] = b[j];
+}
+
+// Initial centers: center c is the sorted point floor(c*n/k) + floor(n/(2k)).
+__global__ __launch_bounds__(kBlock) void k_centers_from_sorted(RunDev r, double* out,
+                                                               int row_major)
+{
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= r.k) return;
+    const int64_t pos = ((int64_t)c * r.n) / r.k + r.n / (2 * (int64_t)r.k);
+    for (int j = 0; j < r.d; ++j) {
+        double v = xs_at(r, j, pos);
+        if (row_major)
+            out[(int64_t)c * r.d + j] = v;
+        else
+            out[(int64_t)j * r.k + c] = v;
+    }
+}
+
+inline unsigned nblocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_bbox(const RunDev& r, int hilbert_order, hipStream_t s)
+{
+    int nparts = (int)std::min<int64_t>(1024, (r.n + kBlock - 1) / kBlock);
+    if (r.in_f32)
+        k_bbox_partial<float><<<nparts, kBlock, 0, s>>>(r);
+    else
+        k_bbox_partial<double><<<nparts, kBlock, 0, s>>>(r);
+    k_bbox_final<<<1, kBlock, 0, s>>>(r, nparts, hilbert_order);
+    return hipGetLastError();
+}
+
+hipError_t launch_keys(const RunDev& r, int hilbert_order, int32_t* vals, hipStream_t s)
+{
+    unsigned g = nblocks(r.n, kBlock);
+    if (r.d == 2) {
+        if (r.in_f32) k_keys<float, 2><<<g, kBlock, 0, s>>>(r, hilbert_order, r.keys, vals);
+        else k_keys<double, 2><<<g, kBlock, 0, s>>>(r, hilbert_order, r.keys, vals);
+    } else {
+        if (r.in_f32) k_keys<float, 3><<<g, kBlock, 0, s>>>(r, hilbert_order, r.keys, vals);
+        else k_keys<double, 3><<<g, kBlock, 0, s>>>(r, hilbert_order, r.keys, vals);
+    }
+    return hipGetLastError();
+}
+
+// Sorts (keys, vals) on their low `nbits` bits; the result ends in keys/vals.
+hipError_t radix_sort_pairs(const RunDev& r, uint64_t* keys, int32_t* vals, int nbits,
+                            hipStream_t s)
+{
+    const int64_t n = r.n;
+    const int nblk = (int)nblocks(n, kChunk);
+    const int64_t len = (int64_t)256 * nblk;
+    const int nseg = (int)((len + kScanSeg - 1) / kScanSeg);
+    uint64_t* ka = keys;
+    int32_t* va = vals;
+    uint64_t* kb = r.keys2;
+    int32_t* vb = r.vals2;
+    int passes = (nbits + 7) / 8;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        k_radix_hist<<<nblk, kBlock, 0, s>>>(ka, n, shift, r.hist, nblk);
+        k_scan_reduce<<<nseg, kBlock, 0, s>>>(r.hist, len, r.part);
+        k_scan_top<<<1, 1024, 0, s>>>(r.part, nseg);
+        k_scan_down<<<nseg, kBlock, 0, s>>>(r.hist, len, r.part);
+        k_radix_scatter<<<nblk, kBlock, 0, s>>>(ka, va, kb, vb, n, shift, r.hist, nblk);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    if (ka != keys) {
+        hipError_t e = hipMemcpyAsync(keys, ka, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(vals, va, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_permute(const RunDev& r, const int32_t* perm_sorted, hipStream_t s)
+{
+    unsigned g = nblocks(r.n, kBlock);
+    k_permute<double><<<g, kBlock, 0, s>>>(r, perm_sorted);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_prep(const RunDev& r, hipStream_t s)
+{
+    if (r.d == 2) {
+        k_tile_prep<2><<<r.ntiles, kBlock, 0, s>>>(r);
+        k_super_boxes<2><<<nblocks(r.nsuper, kBlock), kBlock, 0, s>>>(r);
+    } else {
+        k_tile_prep<3><<<r.ntiles, kBlock, 0, s>>>(r);
+        k_super_boxes<3><<<nblocks(r.nsuper, kBlock), kBlock, 0, s>>>(r);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_centers_from_sorted(const RunDev& r, double* out, int row_major,
+                                      hipStream_t s)
+{
+    k_centers_from_sorted<<<nblocks(r.k, kBlock), kBlock, 0, s>>>(r, out, row_major);
+    return hipGetLastError();
+}
+
+}  // namespace bkm

@@ -1,0 +1,585 @@
+// k-length updates of balanced k-means and the per-round passes:
+//   * balance test and influence adaptation after every sweep (Alg. 1 after
+//     the block sizes; Eq. 1 read so that oversized blocks lose influence,
+//     clamped to a 5% change per step, Sec. 4.2);
+//   * exact per-block bounding boxes of each round's final assignment, for
+//     beta, the average cluster diameter of the erosion (Sec. 4.2);
+//   * center movement to the weighted block means, the convergence test and
+//     the influence erosion (Alg. 2; Sec. 4.2), and the bound relaxation of
+//     Eqs. (2)-(3) folded into the lazy bound frames;
+//   * run initialisation, outputs, and partition statistics.
+#include <math.h>
+
+#include "bkm_internal.h"
+
+namespace bkm {
+
+namespace {
+
+constexpr double kUp = 1.0 + 0x1p-50;     // conservative rounding of bound frames
+constexpr double kDown = 1.0 - 0x1p-50;
+
+__device__ inline double block_weight(const RunDev& r, int c)
+{
+    const long long* a = r.acc + (int64_t)c * kAcc;
+    if (!r.weighted) return (double)a[6];
+    return fix_value(a[6], a[7]) / r.st->w_scale;
+}
+
+// Block-wide reductions for 1024-thread single-block kernels.
+template <typename F>
+__device__ inline double block_reduce_1024(double v, double* sh, F op)
+{
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    for (int m = kWave / 2; m > 0; m >>= 1) v = op(v, __shfl_xor(v, m, kWave));
+    __syncthreads();
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double r = sh[0];
+    for (int w = 1; w < 1024 / kWave; ++w) r = op(r, sh[w]);
+    return r;
+}
+
+struct OpMax { __device__ double operator()(double a, double b) const { return fmax(a, b); } };
+struct OpMin { __device__ double operator()(double a, double b) const { return fmin(a, b); } };
+struct OpAdd { __device__ double operator()(double a, double b) const { return a + b; } };
+
+template <int D>
+__global__ __launch_bounds__(1024) void k_balance(RunDev r)
+{
+    DevState* st = r.st;
+    if (st->done || st->round_done) return;
+    __shared__ double sh[1024 / kWave];
+    const int k = r.k;
+    double mx = -INFINITY;
+    for (int c = threadIdx.x; c < k; c += 1024) mx = fmax(mx, block_weight(r, c));
+    mx = block_reduce_1024(mx, sh, OpMax());
+    const bool bal = mx <= st->lmax;
+    const int sweep_no = st->sweep_in_round + 1;
+    double mu = 1.0;
+    if (!bal) {
+        const double target = st->target;
+        double m = INFINITY;
+        for (int c = threadIdx.x; c < k; c += 1024) {
+            const double s = block_weight(r, c);
+            double f;
+            if (s > 0.0) {
+                const double g = target / s;
+                f = D == 2 ? sqrt(g) : cbrt(g);
+                if (f > 1.05) f = 1.05;
+                if (f < 0.95) f = 0.95;
+            } else {
+                f = 1.05;
+            }
+            const double io = r.I[c];
+            const double in = io * f;
+            r.I[c] = in;
+            r.clus[c].y = 1.0 / in;
+            m = fmin(m, io / in);
+        }
+        mu = block_reduce_1024(m, sh, OpMin());
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->sweep_in_round = sweep_no;
+        st->sweeps += 1;
+        st->balanced = bal ? 1 : 0;
+        st->max_weight = mx;
+        if (bal) {
+            st->round_done = 1;
+        } else {
+            // lower bounds shrink with the largest relative influence growth
+            st->M = st->M * mu * kDown;
+            st->E = st->E * mu * kUp;
+            if (sweep_no >= st->max_balance_iter) st->round_done = 1;
+        }
+    }
+}
+
+// Exact bounding box of every block under the round's final assignment.  A
+// 64-point group whose points all sit in one block contributes its stored
+// group box; a mixed group reads its coordinates.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_block_boxes(RunDev r)
+{
+    const DevState* st = r.st;
+    if (st->done || !st->round_done) return;
+    const int lane = threadIdx.x % kWave;
+    const int64_t gstride = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t g = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+         g * kWave < r.n; g += gstride) {
+        const int64_t p = g * kWave + lane;
+        const bool valid = p < r.n;
+        const int a = valid ? r.A[p] : -1;
+        const int a0 = __shfl(a, 0, kWave);
+        const bool uniform = __ballot(valid && a != a0) == 0ULL;
+        if (uniform) {
+            if (lane < 2 * D && a0 >= 0) {
+                const double v = r.gbox[g * 2 * D + lane];
+                unsigned long long* dst = r.bb + (int64_t)a0 * 2 * D + lane;
+                if (lane < D)
+                    atomicMin(dst, enc_ord(v));
+                else
+                    atomicMax(dst, enc_ord(v));
+            }
+            continue;
+        }
+        double xv[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            xv[j] = valid ? (r.in_f32 ? (double)r.xs32[j][p] : r.xs64[j][p]) : 0.0;
+        unsigned long long pend = __ballot(valid);
+        while (pend) {
+            const int leader = __builtin_ctzll(pend);
+            const int key = __shfl(a, leader, kWave);
+            const bool mine = valid && a == key;
+            double mn[D], mx[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                mn[j] = wave_min_d(mine ? xv[j] : INFINITY);
+                mx[j] = wave_max_d(mine ? xv[j] : -INFINITY);
+            }
+            if (lane == leader && key >= 0) {
+                unsigned long long* dst = r.bb + (int64_t)key * 2 * D;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    atomicMin(dst + j, enc_ord(mn[j]));
+                    atomicMax(dst + D + j, enc_ord(mx[j]));
+                }
+            }
+            pend &= ~__ballot(mine);
+        }
+    }
+}
+
+// Center movement, convergence, erosion and bound-frame update of one round.
+template <int D>
+__global__ __launch_bounds__(1024) void k_move(RunDev r, double* delta)
+{
+    DevState* st = r.st;
+    if (st->done || !st->round_done) return;
+    __shared__ double sh[1024 / kWave];
+    const int k = r.k;
+    const double sxs = st->sx_scale;
+    double dmax = 0.0, dsum = 0.0, cnt = 0.0;
+    for (int c = threadIdx.x; c < k; c += 1024) {
+        const long long* a = r.acc + (int64_t)c * kAcc;
+        const double W = block_weight(r, c);
+        double dd = 0.0;
+        if (W > 0.0) {
+            double cn[D], dv[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                cn[j] = st->lo[j] + (fix_value(a[2 * j], a[2 * j + 1]) / sxs) / W;
+                dv[j] = cn[j] - r.C[(int64_t)j * k + c];
+            }
+            double s = dv[0] * dv[0] + dv[1] * dv[1];
+            if (D == 3) s = s + dv[D - 1] * dv[D - 1];
+            dd = sqrt(s);
+#pragma unroll
+            for (int j = 0; j < D; ++j) r.C[(int64_t)j * k + c] = cn[j];
+            const unsigned long long* b = r.bb + (int64_t)c * 2 * D;
+            double e[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) e[j] = dec_ord(b[D + j]) - dec_ord(b[j]);
+            double q = e[0] * e[0] + e[1] * e[1];
+            if (D == 3) q = q + e[D - 1] * e[D - 1];
+            dsum += sqrt(q);
+            cnt += 1.0;
+        }
+        delta[c] = dd;
+        dmax = fmax(dmax, dd);
+    }
+    dmax = block_reduce_1024(dmax, sh, OpMax());
+    dsum = block_reduce_1024(dsum, sh, OpAdd());
+    cnt = block_reduce_1024(cnt, sh, OpAdd());
+    const bool conv = dmax < st->delta_threshold;
+    const double beta = dsum / cnt;
+    double mu = 1.0, emax = 0.0;
+    if (!conv) {
+        double m = INFINITY, e = 0.0;
+        for (int c = threadIdx.x; c < k; c += 1024) {
+            const double dl = delta[c];
+            const double io = r.I[c];
+            double in = io;
+            if (dl != 0.0) {
+                double t = -dl / beta;
+                if (t > 0.0) t = 0.0;
+                const double alpha = 2.0 / (1.0 + exp(t)) - 1.0;
+                in = exp((1.0 - alpha) * log(io));
+            }
+            r.I[c] = in;
+            const double dacc = (r.clus[c].x + dl) * kUp;
+            r.clus[c] = make_double2(dacc, 1.0 / in);
+            m = fmin(m, io / in);
+            e = fmax(e, dl / in);
+        }
+        mu = block_reduce_1024(m, sh, OpMin());
+        emax = block_reduce_1024(e, sh, OpMax());
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->max_delta = dmax;
+        st->beta = beta;
+        st->nonempty = (int)cnt;
+        st->rounds += 1;
+        if (conv) {
+            st->converged = 1;
+            st->done = 1;
+        } else {
+            st->M = st->M * mu * kDown;
+            st->E = (st->E * mu + emax) * kUp;
+        }
+        if (st->rounds >= st->max_iter) st->done = 1;
+        st->round_done = 0;
+        st->sweep_in_round = 0;
+    }
+    for (int i = threadIdx.x; i < k * 2 * D; i += 1024)
+        r.bb[i] = (i % (2 * D)) < D ? ~0ULL : 0ULL;
+}
+
+// Fresh run state: influence 1, no assignment, empty sums, open bounds.
+__global__ __launch_bounds__(kBlock) void k_init_points(RunDev r)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= r.npad) return;
+    r.A[i] = -1;
+    r.ubt[i] = INFINITY;
+    r.lbt[i] = 0.0f;
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_clusters(RunDev r, const double* cinit,
+                                                          int max_iter, int max_bal,
+                                                          double eps, double dthr)
+{
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    const int D = r.d;
+    if (c < r.k) {
+        if (cinit)
+            for (int j = 0; j < D; ++j) r.C[(int64_t)j * r.k + c] = cinit[(int64_t)c * D + j];
+        r.I[c] = 1.0;
+        r.clus[c] = make_double2(0.0, 1.0);
+        for (int a = 0; a < kAcc; ++a) r.acc[(int64_t)c * kAcc + a] = 0;
+        for (int j = 0; j < 2 * D; ++j) r.bb[(int64_t)c * 2 * D + j] = j < D ? ~0ULL : 0ULL;
+    }
+    if (c == 0) {
+        DevState* st = r.st;
+        st->done = 0;
+        st->round_done = 0;
+        st->balanced = 0;
+        st->converged = 0;
+        st->rounds = 0;
+        st->sweep_in_round = 0;
+        st->sweeps = 0;
+        st->max_iter = max_iter;
+        st->max_balance_iter = max_bal;
+        st->M = 1.0;
+        st->E = 0.0;
+        const double W = st->total_weight;
+        if (r.weighted) {
+            st->lmax = (1.0 + eps) * (W / (double)r.k);
+        } else {
+            const int64_t ck = (r.n + r.k - 1) / r.k;
+            st->lmax = (1.0 + eps) * (double)ck;
+        }
+        st->target = W / (double)r.k;
+        st->delta_threshold = dthr < 0.0 ? 1e-5 * st->ext : dthr;
+        st->evaluated = st->skipped = st->rechecked = st->changed = 0;
+        st->cand_evals = st->overflow_tiles = 0;
+    }
+}
+
+// Caller-given centers/influence of one step of bkm_assign_sweeps, with the
+// bound relaxation the change implies (movement delta, influence ratios).
+template <int D>
+__global__ __launch_bounds__(1024) void k_set_step(RunDev r, const double* crm,
+                                                   const double* infl, int first)
+{
+    DevState* st = r.st;
+    __shared__ double sh[1024 / kWave];
+    const int k = r.k;
+    double m = INFINITY, e = 0.0;
+    for (int c = threadIdx.x; c < k; c += 1024) {
+        double dv[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const double v = crm[(int64_t)c * D + j];
+            dv[j] = v - r.C[(int64_t)j * k + c];
+            r.C[(int64_t)j * k + c] = v;
+        }
+        double s = dv[0] * dv[0] + dv[1] * dv[1];
+        if (D == 3) s = s + dv[D - 1] * dv[D - 1];
+        const double dl = first ? 0.0 : sqrt(s);
+        const double io = r.I[c];
+        const double in = infl[c];
+        r.I[c] = in;
+        const double dacc = first ? 0.0 : (r.clus[c].x + dl) * kUp;
+        r.clus[c] = make_double2(dacc, 1.0 / in);
+        m = fmin(m, io / in);
+        e = fmax(e, dl / in);
+    }
+    m = block_reduce_1024(m, sh, OpMin());
+    e = block_reduce_1024(e, sh, OpMax());
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (first) {
+            st->M = 1.0;
+            st->E = 0.0;
+        } else {
+            st->M = st->M * m * kDown;
+            st->E = (st->E * m + e) * kUp;
+        }
+        st->done = 0;
+        st->round_done = 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter_back(RunDev r, int32_t* out)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < r.n) out[r.perm[i]] = r.A[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_cluster_out(RunDev r, double* cout, double* iout,
+                                                        double* bwout)
+{
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= r.k) return;
+    if (cout)
+        for (int j = 0; j < r.d; ++j) cout[(int64_t)c * r.d + j] = r.C[(int64_t)j * r.k + c];
+    if (iout) iout[c] = r.I[c];
+    if (bwout) bwout[c] = block_weight(r, c);
+}
+
+// ---------------------------------------------------------------- statistics
+// partition_stats works on the caller's points in input order.
+template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_stats_sums(RunDev r, const int32_t* asg)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x % kWave;
+    const bool valid = i < r.n;
+    int a = valid ? asg[i] : 0;
+    if (valid && (a < 0 || a >= r.k)) {
+        atomicOr(&r.st->bad_data, 2);
+        a = 0;
+    }
+    const DevState* st = r.st;
+    long long th[D], tl[D], wh = 1, wl = 0;
+    const double w = (valid && r.in_w) ? r.in_w[i] : 1.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        double v = valid ? (double)((const T*)r.in_x[j])[i] - st->lo[j] : 0.0;
+        if (r.in_w) v = w * v;
+        fix_split(v * st->sx_scale, th[j], tl[j]);
+    }
+    if (r.in_w) fix_split(w * st->w_scale, wh, wl);
+    unsigned long long pend = __ballot(valid);
+    while (pend) {
+        const int leader = __builtin_ctzll(pend);
+        const int key = __shfl(a, leader, kWave);
+        const bool mine = valid && a == key;
+        const unsigned long long mm = __ballot(mine);
+        long long v[kAcc];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            v[2 * j] = wave_sum_ll(mine ? th[j] : 0);
+            v[2 * j + 1] = wave_sum_ll(mine ? tl[j] : 0);
+        }
+        v[6] = r.in_w ? wave_sum_ll(mine ? wh : 0) : (long long)__popcll(mm);
+        v[7] = r.in_w ? wave_sum_ll(mine ? wl : 0) : 0;
+        if (lane == leader) {
+            unsigned long long* dst = (unsigned long long*)(r.acc + (int64_t)key * kAcc);
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                atomicAdd(dst + 2 * j, (unsigned long long)v[2 * j]);
+                atomicAdd(dst + 2 * j + 1, (unsigned long long)v[2 * j + 1]);
+            }
+            atomicAdd(dst + 6, (unsigned long long)v[6]);
+            atomicAdd(dst + 7, (unsigned long long)v[7]);
+        }
+        pend &= ~mm;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_stats_centers(RunDev r, double* bwout,
+                                                          double* cout)
+{
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= r.k) return;
+    const long long* a = r.acc + (int64_t)c * kAcc;
+    const double W = block_weight(r, c);
+    if (bwout) bwout[c] = W;
+    for (int j = 0; j < D; ++j) {
+        const double v = W > 0.0 ? r.st->lo[j] + (fix_value(a[2 * j], a[2 * j + 1]) / r.st->sx_scale) / W
+                                 : NAN;
+        r.C[(int64_t)j * r.k + c] = v;
+        if (cout) cout[(int64_t)c * D + j] = v;
+    }
+}
+
+// Per-block partial objective sums in a fixed order (deterministic).
+template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_stats_objective(RunDev r, const int32_t* asg)
+{
+    __shared__ double sh[kBlock / kWave];
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < r.n; i += stride) {
+        int a = asg[i];
+        if (a < 0 || a >= r.k) continue;
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const double dv = (double)((const T*)r.in_x[j])[i] - r.C[(int64_t)j * r.k + a];
+            s = s + dv * dv;
+        }
+        acc += (r.in_w ? r.in_w[i] : 1.0) * s;
+    }
+    acc = wave_sum_d(acc);
+    if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / kWave; ++w) t += sh[w];
+        r.red[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_stats_final(RunDev r, int nparts, double eps,
+                                                        double* out6)
+{
+    __shared__ double sh[kBlock / kWave];
+    double mx = 0.0, empty = 0.0, over = 0.0;
+    const DevState* st = r.st;
+    const double W = st->total_weight;
+    double lmax;
+    if (r.weighted) {
+        lmax = (1.0 + eps) * (W / (double)r.k);
+    } else {
+        const int64_t ck = (r.n + r.k - 1) / r.k;
+        lmax = (1.0 + eps) * (double)ck;
+    }
+    for (int c = threadIdx.x; c < r.k; c += kBlock) {
+        const double b = block_weight(r, c);
+        mx = fmax(mx, b);
+        if (b == 0.0) empty += 1.0;
+        if (b > lmax) over += 1.0;
+    }
+    mx = wave_max_d(mx);
+    empty = wave_sum_d(empty);
+    over = wave_sum_d(over);
+    if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = sh[0];
+        for (int w = 1; w < kBlock / kWave; ++w) m = fmax(m, sh[w]);
+        out6[0] = m / (W / (double)r.k) - 1.0;
+        double obj = 0.0;
+        for (int b = 0; b < nparts; ++b) obj += r.red[b];
+        out6[1] = obj;
+        out6[2] = lmax;
+    }
+    __syncthreads();
+    if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = empty;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double e = 0.0;
+        for (int w = 0; w < kBlock / kWave; ++w) e += sh[w];
+        out6[3] = e;
+    }
+    __syncthreads();
+    if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = over;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double e = 0.0;
+        for (int w = 0; w < kBlock / kWave; ++w) e += sh[w];
+        out6[4] = e;
+        out6[5] = (double)st->bad_data;
+    }
+}
+
+inline unsigned nblocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_init_run(const RunDev& r, const double* cinit, int max_iter,
+                           int max_balance_iter, double eps, double dthr, hipStream_t s)
+{
+    k_init_points<<<nblocks(r.npad, kBlock), kBlock, 0, s>>>(r);
+    k_init_clusters<<<nblocks(r.k, kBlock), kBlock, 0, s>>>(r, cinit, max_iter,
+                                                            max_balance_iter, eps, dthr);
+    return hipGetLastError();
+}
+
+hipError_t launch_balance(const RunDev& r, hipStream_t s)
+{
+    if (r.d == 2)
+        k_balance<2><<<1, 1024, 0, s>>>(r);
+    else
+        k_balance<3><<<1, 1024, 0, s>>>(r);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_boxes(const RunDev& r, hipStream_t s)
+{
+    const int64_t groups = (r.n + kWave - 1) / kWave;
+    const unsigned g = (unsigned)std::min<int64_t>((groups + 3) / 4, 8192);
+    if (r.d == 2)
+        k_block_boxes<2><<<g, kBlock, 0, s>>>(r);
+    else
+        k_block_boxes<3><<<g, kBlock, 0, s>>>(r);
+    return hipGetLastError();
+}
+
+hipError_t launch_move(const RunDev& r, hipStream_t s)
+{
+    if (r.d == 2)
+        k_move<2><<<1, 1024, 0, s>>>(r, r.red);
+    else
+        k_move<3><<<1, 1024, 0, s>>>(r, r.red);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_step(const RunDev& r, const double* crm, const double* infl, int first,
+                           hipStream_t s)
+{
+    if (r.d == 2)
+        k_set_step<2><<<1, 1024, 0, s>>>(r, crm, infl, first);
+    else
+        k_set_step<3><<<1, 1024, 0, s>>>(r, crm, infl, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const RunDev& r, int32_t* asg, double* cout, double* iout,
+                         double* bwout, hipStream_t s)
+{
+    if (asg) k_scatter_back<<<nblocks(r.n, kBlock), kBlock, 0, s>>>(r, asg);
+    k_cluster_out<<<nblocks(r.k, kBlock), kBlock, 0, s>>>(r, cout, iout, bwout);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats(const RunDev& r, const int32_t* asg, double eps, double* bwout,
+                        double* cout, double* out6, hipStream_t s)
+{
+    const unsigned g = nblocks(r.n, kBlock);
+    const int nparts = (int)std::min<int64_t>(1024, g);
+    if (r.d == 2) {
+        if (r.in_f32) k_stats_sums<float, 2><<<g, kBlock, 0, s>>>(r, asg);
+        else k_stats_sums<double, 2><<<g, kBlock, 0, s>>>(r, asg);
+        k_stats_centers<2><<<nblocks(r.k, kBlock), kBlock, 0, s>>>(r, bwout, cout);
+        if (r.in_f32) k_stats_objective<float, 2><<<nparts, kBlock, 0, s>>>(r, asg);
+        else k_stats_objective<double, 2><<<nparts, kBlock, 0, s>>>(r, asg);
+    } else {
+        if (r.in_f32) k_stats_sums<float, 3><<<g, kBlock, 0, s>>>(r, asg);
+        else k_stats_sums<double, 3><<<g, kBlock, 0, s>>>(r, asg);
+        k_stats_centers<3><<<nblocks(r.k, kBlock), kBlock, 0, s>>>(r, bwout, cout);
+        if (r.in_f32) k_stats_objective<float, 3><<<nparts, kBlock, 0, s>>>(r, asg);
+        else k_stats_objective<double, 3><<<nparts, kBlock, 0, s>>>(r, asg);
+    }
+    k_stats_final<<<1, kBlock, 0, s>>>(r, nparts, eps, out6);
+    return hipGetLastError();
+}
+
+}  // namespace bkm

@@ -1,0 +1,111 @@
+"""The C-ABI library loads and exports every entry point include/bkm.h
+declares; argument errors are reported without touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bkm.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bkm_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def bkm():
+    from paper_1805_01208_amd import bkm as b
+    if not os.path.exists(b.LIB_PATH):
+        from paper_1805_01208_amd import build
+        build.build()
+    return b
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for f in ("bkm_init_centers_sfc", "bkm_balanced_kmeans", "bkm_partition_stats",
+              "bkm_last_error"):
+        assert f in names
+
+
+def test_every_declared_symbol_is_exported(bkm):
+    L = bkm.lib()
+    for name in declared():
+        assert hasattr(L, name), name
+    assert set(bkm.FUNCTIONS) == set(declared())
+
+
+def test_struct_layouts_match_header(bkm):
+    assert C.sizeof(bkm.Points) == 48
+    assert C.sizeof(bkm.Params) == 56
+    assert C.sizeof(bkm.Info) == 96
+    assert C.sizeof(bkm.Stats) == 32
+
+
+def test_default_params(bkm):
+    p = bkm.default_params(16)
+    assert (p.k, p.max_iter, p.max_balance_iter, p.hilbert_order) == (16, 50, 20, 16)
+    assert p.precision == bkm.PREC_F32_RECHECK and p.use_bounds == 1
+    assert p.epsilon == 0.03 and p.delta_threshold < 0 and p.recheck_rel_gap == 1e-5
+
+
+def _pts(bkm, n=100, d=2, dtype=1):
+    p = bkm.Points()
+    p.n, p.d, p.dtype = n, d, dtype
+    for j in range(3):
+        p.coords[j] = 0x1000 if j < d else None  # never dereferenced: rejected first
+    p.weights = None
+    return p
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda p, q: setattr(p, "d", 4), "d = 4"),
+    (lambda p, q: setattr(p, "n", 0), "n = 0"),
+    (lambda p, q: setattr(p, "dtype", 7), "dtype"),
+    (lambda p, q: setattr(q, "k", 0), "k = 0"),
+    (lambda p, q: setattr(q, "k", 101), "k = 101"),
+    (lambda p, q: setattr(q, "epsilon", -0.5), "epsilon"),
+    (lambda p, q: setattr(q, "epsilon", float("nan")), "epsilon"),
+    (lambda p, q: setattr(q, "max_iter", 0), "max_iter"),
+    (lambda p, q: setattr(q, "hilbert_order", 32), "hilbert_order"),
+    (lambda p, q: setattr(q, "precision", 5), "precision"),
+    (lambda p, q: setattr(q, "tile_points", 300), "tile_points"),
+    (lambda p, q: setattr(q, "recheck_rel_gap", -1.0), "recheck_rel_gap"),
+])
+def test_invalid_arguments(bkm, mutate, needle):
+    L = bkm.lib()
+    p = _pts(bkm)
+    q = bkm.default_params(10)
+    mutate(p, q)
+    rc = L.bkm_balanced_kmeans(C.byref(p), C.byref(q), None, C.c_void_p(0x2000),
+                               C.c_void_p(0x3000), None, None, None, None)
+    assert rc == bkm.BKM_EINVAL
+    assert needle in L.bkm_last_error().decode()
+
+
+def test_3d_order_limit_and_null_outputs(bkm):
+    L = bkm.lib()
+    p = _pts(bkm, d=3)
+    rc = L.bkm_init_centers_sfc(C.byref(p), 4, 22, C.c_void_p(0x2000), None, None, None)
+    assert rc == bkm.BKM_EINVAL and "hilbert_order" in L.bkm_last_error().decode()
+    rc = L.bkm_init_centers_sfc(C.byref(p), 4, 16, None, None, None, None)
+    assert rc == bkm.BKM_EINVAL
+    q = bkm.default_params(4)
+    rc = L.bkm_balanced_kmeans(C.byref(p), C.byref(q), None, None, None, None, None, None, None)
+    assert rc == bkm.BKM_EINVAL
+    rc = L.bkm_partition_stats(None, None, 4, 0.03, None, None, None, None)
+    assert rc == bkm.BKM_EINVAL
+    rc = L.bkm_assign_sweeps(C.byref(p), 4, 0, None, None, 0, 1, 0, None, None, None, None)
+    assert rc == bkm.BKM_EINVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    from paper_1805_01208_amd import bkm as b
+    monkeypatch.setattr(b, "_LIB", None)
+    monkeypatch.setattr(b, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        b.lib()

@@ -1,0 +1,109 @@
+"""GPU assignment sweeps against the oracle's brute-force argmin, with the
+state (centers, influence) injected step by step so that the Hamerly bounds
+carried between steps (Sec. 4.3; Eqs. 2-3 read as relaxations) and the box
+pruning (Sec. 4.4) are exercised, in both arithmetic modes."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import assert_assignment_parity, cuda, torch, widened
+
+pytestmark = pytest.mark.gpu
+
+
+def state_sequence(X, k, steps, seed, big_move_at=3):
+    """SFC centers and unit influence, then small random moves and influence
+    changes, one large move, and one step that repeats the previous state."""
+    rng = np.random.default_rng(seed)
+    d = len(X)
+    C0, _, _ = oracle.init_centers_sfc(widened(X), k, 16)
+    ext = max(float(np.ptp(x)) for x in X)
+    Cs, Is = [C0], [np.ones(k)]
+    for s in range(1, steps):
+        C = Cs[-1].copy()
+        I = Is[-1].copy()
+        if s == steps - 1:
+            pass  # unchanged state: everything should be skipped
+        elif s == big_move_at:
+            C += rng.normal(0.0, 0.05 * ext, C.shape)
+            I *= rng.uniform(0.8, 1.25, k)
+        else:
+            C += rng.normal(0.0, 0.002 * ext, C.shape)
+            I *= rng.uniform(0.95, 1.05, k)
+        Cs.append(C)
+        Is.append(I)
+    return np.stack(Cs), np.stack(Is)
+
+
+def run_and_compare(X, k, precision, use_bounds, tile, steps=6, seed=0):
+    from paper_1805_01208_amd import bkm
+    Cs, Is = state_sequence(X, k, steps, seed)
+    print(f"case d={len(X)} n={len(X[0])} k={k} {precision} bounds={use_bounds} tile={tile}",
+          flush=True)
+    A, bw, info = bkm.assign_sweeps(cuda(X), torch.from_numpy(Cs), torch.from_numpy(Is),
+                                    precision=precision, use_bounds=use_bounds,
+                                    tile_points=tile)
+    A = A.cpu().numpy()
+    bw = bw.cpu().numpy()
+    Xw = widened(X)
+    for s in range(steps):
+        Ao, best, second = oracle.assign(Xw, Cs[s], Is[s])
+        assert_assignment_parity(A[s], Ao, best, second, f"step {s}")
+        assert np.array_equal(bw[s], np.bincount(A[s], minlength=k).astype(np.float64))
+    return info
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("precision", ["f64", "f32_recheck"])
+@pytest.mark.parametrize("use_bounds", [True, False])
+def test_sweep_sequence(d, precision, use_bounds):
+    rng = np.random.default_rng(d)
+    n = 60007
+    X = [rng.random(n) for _ in range(d)]
+    info = run_and_compare(X, 40, precision, use_bounds, 256)
+    assert info["evaluated"] + info["skipped"] == 6 * n
+    if use_bounds:
+        assert info["skipped"] > n  # at least the repeated last step skips nearly everything
+    else:
+        assert info["skipped"] == 0
+
+
+@pytest.mark.parametrize("tile", [256, 512, 1024])
+def test_sweep_tiles_and_float32_input(tile):
+    rng = np.random.default_rng(tile)
+    n = 77777
+    X = [rng.random(n).astype(np.float32) for _ in range(2)]
+    run_and_compare(X, 97, "f32_recheck", True, tile)
+
+
+def test_sweep_clustered_3d():
+    from paper_1805_01208_amd import workloads
+    X = workloads.gauss3d(80000, 5)
+    run_and_compare(X, 200, "f32_recheck", True, 1024)
+
+
+@pytest.mark.parametrize("n,k", [(5, 1), (5, 5), (300, 300), (1025, 2)])
+def test_sweep_degenerate_sizes(n, k):
+    rng = np.random.default_rng(n * 7 + k)
+    X = [rng.random(n), rng.random(n)]
+    for prec in ("f64", "f32_recheck"):
+        run_and_compare(X, k, prec, True, 256, steps=4, seed=n)
+
+
+def test_sweep_duplicate_points_and_centers():
+    """Exact ties: duplicated points and two centers at one place; the lower
+    index must win in both modes (Sec. 4.2 argmin, ties to the lowest index)."""
+    from paper_1805_01208_amd import bkm
+    rng = np.random.default_rng(9)
+    base = [rng.random(2000), rng.random(2000)]
+    X = [np.repeat(b, 3) for b in base]
+    k = 12
+    C = np.stack([rng.random(k), rng.random(k)], axis=1)
+    C[7] = C[3]
+    Is = np.ones((1, k))
+    for prec in ("f64", "f32_recheck"):
+        A, _, _ = bkm.assign_sweeps(cuda(X), torch.from_numpy(C[None]), torch.from_numpy(Is),
+                                    precision=prec)
+        Ao, _, _ = oracle.assign(X, C, Is[0])
+        assert np.array_equal(A[0].cpu().numpy(), Ao)
+        assert not np.any(A[0].cpu().numpy() == 7)
