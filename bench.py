@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Balanced k-means on one MI355X: points assigned per second per sweep.
+
+One step = one whole bkm_balanced_kmeans call on the resident synthetic cloud:
+Hilbert bootstrap (bounding box, keys, radix sort, permutation, tiles,
+initial centers) and every AssignAndBalance round until convergence or
+max_iter (sweeps with their balance tests, block boxes, center moves).
+value = n * (sweeps made in the step) / (step wall time), averaged over the
+timed steps, with the FP32-screen + FP64-recheck sweep.  The plain FP64 sweep
+on the same cloud is timed beside it.
+
+The roofline figure is for the dominant kernel, the assignment sweep: its
+device time comes from HIP events the library records around every sweep
+launch on the call's stream; its algorithmic bytes come from the run's
+visit counters (see algorithmic_bytes).  The CPU baseline is the plain FP64
+oracle timed on a bounded random sample of the same cloud.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "points assigned/s per balanced k-means sweep, FP32+recheck vs FP64, ε=0.03"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(info, d, precision, weighted):
+    """Bytes a sweep must move, from the run's visit counters.
+
+    every visit: block id (4) + stored upper and lower bound (4 + 4), read;
+    evaluated:   working coordinates (FP32: 4d, FP64: 8d) read, both bounds written (8);
+    changed:     block id written (4); FP64 coordinates (8d, FP32 mode) and the
+                 weight (8, weighted) read for the fixed-point block sums;
+    rechecked:   FP64 coordinates read (8d)."""
+    visits = info["evaluated"] + info["skipped"]
+    f32 = precision == "f32_recheck"
+    b = 12 * visits
+    b += info["evaluated"] * ((4 * d if f32 else 8 * d) + 8)
+    b += info["changed"] * (4 + (8 * d if f32 else 0) + (8 if weighted else 0))
+    if f32:
+        b += info["rechecked"] * 8 * d
+    return b
+
+
+def make_workload(name, n=None):
+    from paper_1805_01208_amd import workloads
+    kw = {} if n is None else {"n": n}
+    return workloads.CONFIGS[name](**kw)
+
+
+def cpu_baseline(cfg, budget_s):
+    """The oracle's sweep (brute-force argmin over all k centers, block
+    weights, balance test) on a random sample of the workload."""
+    import numpy as np
+    import oracle
+    X = cfg["X"]
+    W = cfg["W"]
+    n = len(X[0])
+    k = cfg["k"]
+    rng = np.random.default_rng(12345)
+
+    def sweep(m):
+        idx = np.sort(rng.choice(n, size=m, replace=False))
+        Xs = [np.asarray(x[idx], dtype=np.float64) for x in X]
+        Ws = None if W is None else np.asarray(W[idx])
+        kk = min(k, m)
+        C, _, _ = oracle.init_centers_sfc(Xs, kk, 16)
+        I = np.ones(kk)
+        t0 = time.perf_counter()
+        A, _, _ = oracle.assign(Xs, C, I)
+        bw = oracle.block_weights(A, Ws, kk)
+        tw = oracle.total_weight(m, Ws)
+        oracle.balance_step(bw, len(X), oracle.lmax(m, kk, cfg["eps"], Ws), tw / kk, I)
+        return time.perf_counter() - t0
+
+    m0 = min(n, 4096)
+    t0 = sweep(m0)
+    m = int(min(n, max(m0, m0 * budget_s / max(t0, 1e-6))))
+    t = sweep(m)
+    return dict(value=m / t, unit="points/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"{m} random points of the workload, k={min(k, m)} SFC centers of the "
+                       f"sample, one oracle sweep (FP64 brute-force argmin over all centers, "
+                       f"block weights, balance test): {t:.2f} s")
+
+
+def run_steps(bkm, torch, X, W, cfg, precision, steps, warmup, max_iter):
+    n = X[0].numel()
+    k = cfg["k"]
+    dev = X[0].device
+    out = dict(A=torch.empty(n, dtype=torch.int32, device=dev),
+               centers=torch.empty((k, len(X)), dtype=torch.float64, device=dev),
+               influence=torch.empty(k, dtype=torch.float64, device=dev),
+               block_weights=torch.empty(k, dtype=torch.float64, device=dev))
+
+    def one():
+        return bkm.balanced_kmeans(X, k, W=W, eps=cfg["eps"], max_iter=max_iter,
+                                   precision=precision, timing=True, out=out)
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos.append(one()["info"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tot = {key: sum(i[key] for i in infos) for key in infos[0]}
+    return wall, tot, infos[-1]
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c5"])
+    ap.add_argument("--n", type=int, default=None, help="override the workload size")
+    ap.add_argument("--max-iter", type=int, default=50)
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design, not part of this build).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1805_01208_amd import bkm
+
+    t_gen = time.perf_counter()
+    cfg = make_workload(args.config, args.n)
+    gen_s = time.perf_counter() - t_gen
+    Xh = cfg["X"]
+    d = len(Xh)
+    n = len(Xh[0])
+    print(f"[bench] {cfg['name']} n={n} d={d} k={cfg['k']} generated in {gen_s:.1f} s",
+          file=sys.stderr, flush=True)
+    X = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in Xh]
+    W = None if cfg["W"] is None else torch.from_numpy(cfg["W"]).cuda()
+    weighted = W is not None
+    torch.cuda.synchronize()
+
+    wall, tot, last = run_steps(bkm, torch, X, W, cfg, "f32_recheck", args.steps, args.warmup,
+                                args.max_iter)
+    sweeps = tot["sweeps"]
+    value = n * sweeps / wall
+    ms_per_step = 1e3 * wall / args.steps
+    print(f"[bench] f32_recheck: {ms_per_step:.2f} ms/step, {sweeps / args.steps:.1f} sweeps/step",
+          file=sys.stderr, flush=True)
+
+    wall64, tot64, _ = run_steps(bkm, torch, X, W, cfg, "f64", args.fp64_steps, 1, args.max_iter)
+    value64 = n * tot64["sweeps"] / wall64
+    print(f"[bench] f64: {1e3 * wall64 / args.fp64_steps:.2f} ms/step", file=sys.stderr, flush=True)
+
+    sweep_s = tot["sweep_ms"] / 1e3 / sweeps
+    algo = algorithmic_bytes(tot, d, "f32_recheck", weighted) / sweeps
+    achieved = algo / sweep_s / 1e9
+    sweep64_s = tot64["sweep_ms"] / 1e3 / tot64["sweeps"]
+    algo64 = algorithmic_bytes(tot64, d, "f64", weighted) / tot64["sweeps"]
+
+    visits = tot["evaluated"] + tot["skipped"]
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "n": n, "d": d, "k": cfg["k"], "eps": cfg["eps"],
+                   "weighted": weighted, "precision": "f32_recheck", "max_iter": args.max_iter,
+                   "max_balance_iter": 20, "hilbert_order": 16},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_sweep", "avg_sweep_us": sweep_s * 1e6,
+                     "algorithmic_bytes_per_sweep": algo},
+        "sweeps_per_step": sweeps / args.steps,
+        "rounds_per_step": tot["rounds"] / args.steps,
+        "skip_frac": tot["skipped"] / visits,
+        "recheck_frac_of_evaluated": tot["rechecked"] / max(1, tot["evaluated"]),
+        "candidates_per_evaluated": tot["candidate_evals"] / max(1, tot["evaluated"]),
+        "kernel_ms_per_step": {kk: tot[kk] / args.steps for kk in
+                               ("cand_ms", "sweep_ms", "balance_ms", "boxes_ms", "move_ms",
+                                "bootstrap_ms", "total_ms")},
+        "balanced": last["balanced"],
+        "imbalance": last["imbalance"],
+        "fp64_plain": {"value": value64, "ms_per_step": 1e3 * wall64 / args.fp64_steps,
+                       "sweeps_per_step": tot64["sweeps"] / args.fp64_steps,
+                       "avg_sweep_us": sweep64_s * 1e6,
+                       "sweep_gbs": algo64 / sweep64_s / 1e9},
+        "speedup_vs_fp64": value / value64,
+        "sweep_speedup_vs_fp64": sweep64_s / sweep_s,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

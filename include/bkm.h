@@ -69,6 +69,8 @@ typedef struct {
     int32_t use_bounds;       /* 1: Hamerly upper/lower bounds skip points (Sec. 4.3); default 1 */
     int32_t tile_points;      /* points per tile of the sweep: 256, 512 or 1024; 0 = default */
     int32_t super_tiles;      /* tiles per candidate super-tile, >= 1; 0 = default */
+    int32_t timing;           /* 1: time every kernel of the round loop with HIP events on
+                                 `stream` and report the sums in bkm_info; default 0 */
     double epsilon;           /* imbalance eps >= 0 (may be +inf); default 0.03 */
     double delta_threshold;   /* absolute; < 0 selects 1e-5 * largest bounding-box extent */
     double recheck_rel_gap;   /* FP64 recheck window, relative, >= 0; default 1e-5 */
@@ -90,6 +92,13 @@ typedef struct {
     int64_t candidate_evals;  /* (point, center) effective distances evaluated */
     double bootstrap_ms;      /* device time of the SFC bootstrap */
     double total_ms;          /* device time of the whole call */
+    /* with params.timing: summed device time of each kernel of the round loop
+       (only launches that did work are counted) */
+    double cand_ms;           /* super-tile candidate lists, one per sweep */
+    double sweep_ms;          /* assignment sweeps */
+    double balance_ms;        /* balance test + influence update, one per sweep */
+    double boxes_ms;          /* block bounding boxes, one per round */
+    double move_ms;           /* center move + erosion, one per round */
 } bkm_info;
 
 typedef struct {

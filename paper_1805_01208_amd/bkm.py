@@ -29,7 +29,7 @@ class Params(C.Structure):
     _fields_ = [("k", C.c_int32), ("max_iter", C.c_int32), ("max_balance_iter", C.c_int32),
                 ("hilbert_order", C.c_int32), ("precision", C.c_int32),
                 ("use_bounds", C.c_int32), ("tile_points", C.c_int32),
-                ("super_tiles", C.c_int32), ("epsilon", C.c_double),
+                ("super_tiles", C.c_int32), ("timing", C.c_int32), ("epsilon", C.c_double),
                 ("delta_threshold", C.c_double), ("recheck_rel_gap", C.c_double)]
 
 
@@ -39,7 +39,9 @@ class Info(C.Structure):
                 ("max_block_weight", C.c_double), ("l_max", C.c_double),
                 ("evaluated", C.c_int64), ("skipped", C.c_int64), ("rechecked", C.c_int64),
                 ("changed", C.c_int64), ("candidate_evals", C.c_int64),
-                ("bootstrap_ms", C.c_double), ("total_ms", C.c_double)]
+                ("bootstrap_ms", C.c_double), ("total_ms", C.c_double),
+                ("cand_ms", C.c_double), ("sweep_ms", C.c_double), ("balance_ms", C.c_double),
+                ("boxes_ms", C.c_double), ("move_ms", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -148,7 +150,7 @@ def init_centers_sfc(X, k, hilbert_order=16):
 def balanced_kmeans(X, k, W=None, eps=0.03, max_iter=50, max_balance_iter=20,
                     delta_threshold=-1.0, hilbert_order=16, precision="f32_recheck",
                     use_bounds=True, tile_points=0, super_tiles=0, recheck_rel_gap=1e-5,
-                    centers_init=None, out=None):
+                    centers_init=None, timing=False, out=None):
     """Balanced k-means; returns dict(A, centers, influence, block_weights, info, code)."""
     dev = X[0].device
     pts = make_points(X, W)
@@ -163,6 +165,7 @@ def balanced_kmeans(X, k, W=None, eps=0.03, max_iter=50, max_balance_iter=20,
     prm.tile_points = int(tile_points)
     prm.super_tiles = int(super_tiles)
     prm.recheck_rel_gap = float(recheck_rel_gap)
+    prm.timing = 1 if timing else 0
     if out is None:
         out = dict(A=torch.empty(pts.n, dtype=torch.int32, device=dev),
                    centers=torch.empty((k, pts.d), dtype=torch.float64, device=dev),

@@ -5,9 +5,8 @@
 // The round loop keeps the host out of the per-sweep decision: sweeps,
 // balance tests and the round-end kernels read the run's device state and turn
 // into no-ops once their AssignAndBalance call (or the run) is over, so the
-// host enqueues a batch of sweeps plus the round end and synchronises once per
-// batch.  A batch starts at one sweep (most calls balance at once) and doubles
-// while a call keeps running.
+// host enqueues a batch (one sweep, its balance test and the round end) and
+// synchronises once per batch.
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -253,6 +252,7 @@ void bkm_default_params(bkm_params* p, int32_t k)
     p->use_bounds = 1;
     p->tile_points = 0;
     p->super_tiles = 0;
+    p->timing = 0;
     p->epsilon = 0.03;
     p->delta_threshold = -1.0;
     p->recheck_rel_gap = 1e-5;
@@ -335,28 +335,49 @@ int bkm_balanced_kmeans(const bkm_points* pts, const bkm_params* prm, const doub
                            p.delta_threshold, s));
     HIPCHK(hipEventRecord(ev[1], s));
 
+    // One sweep per batch: most AssignAndBalance calls balance after their
+    // first sweep, and a batch of one never launches a sweep that has nothing
+    // to do.  Every batch ends a call or adds a sweep to it, so the loop is
+    // bounded.
     DevState h;
     int prev_rounds = 0;
-    int batch = 1;
-    // every batch ends a call or adds a sweep to it, so the loop is bounded
-    const int64_t max_batches = (int64_t)p.max_iter * (p.max_balance_iter + 2) + 8;
+    const bool timing = p.timing != 0;
+    hipEvent_t tev[6];
+    int ntev = 0;
+    struct TevFree {
+        hipEvent_t* e; int* n;
+        ~TevFree() { for (int i = 0; i < *n; ++i) (void)hipEventDestroy(e[i]); }
+    } tevf{tev, &ntev};
+    if (timing)
+        for (; ntev < 6; ++ntev) HIPCHK(hipEventCreate(&tev[ntev]));
+    double tk[5] = {0, 0, 0, 0, 0};
+    auto mark = [&](int i) -> hipError_t { return timing ? hipEventRecord(tev[i], s) : hipSuccess; };
+    const int64_t max_batches = (int64_t)p.max_iter * (p.max_balance_iter + 1) + 8;
     for (int64_t nb = 0;; ++nb) {
         if (nb >= max_batches) return fail(BKM_EHIP, "round loop made no progress");
-        for (int i = 0; i < batch; ++i) {
-            HIPCHK(launch_supercand(r, s));
-            HIPCHK(launch_sweep(r, s));
-            HIPCHK(launch_balance(r, s));
-        }
+        HIPCHK(mark(0));
+        HIPCHK(launch_supercand(r, s));
+        HIPCHK(mark(1));
+        HIPCHK(launch_sweep(r, s));
+        HIPCHK(mark(2));
+        HIPCHK(launch_balance(r, s));
+        HIPCHK(mark(3));
         HIPCHK(launch_block_boxes(r, s));
+        HIPCHK(mark(4));
         HIPCHK(launch_move(r, s));
+        HIPCHK(mark(5));
         if ((rc = read_state(r, s, &h))) return rc;
-        if (h.done) break;
-        if (h.rounds > prev_rounds) {
-            prev_rounds = h.rounds;
-            batch = 1;
-        } else {
-            batch = std::min(batch * 2, std::max(1, p.max_balance_iter - h.sweep_in_round));
+        const bool round_ended = h.rounds > prev_rounds;
+        if (timing) {
+            for (int i = 0; i < 5; ++i) {
+                if (i >= 3 && !round_ended) continue;
+                float ms = 0.0f;
+                HIPCHK(hipEventElapsedTime(&ms, tev[i], tev[i + 1]));
+                tk[i] += ms;
+            }
         }
+        prev_rounds = h.rounds;
+        if (h.done) break;
     }
     HIPCHK(launch_finish(r, assignment_out, centers_out, influence_out, block_weights_out, s));
     HIPCHK(hipEventRecord(ev[2], s));
@@ -379,6 +400,11 @@ int bkm_balanced_kmeans(const bkm_points* pts, const bkm_params* prm, const doub
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) info->bootstrap_ms = ms;
         if (hipEventElapsedTime(&ms, ev[0], ev[2]) == hipSuccess) info->total_ms = ms;
+        info->cand_ms = tk[0];
+        info->sweep_ms = tk[1];
+        info->balance_ms = tk[2];
+        info->boxes_ms = tk[3];
+        info->move_ms = tk[4];
     }
     return h.balanced ? BKM_OK : BKM_WUNBALANCED;
 }
