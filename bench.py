@@ -89,7 +89,7 @@ def cpu_baseline(cfg, budget_s):
                        f"block weights, balance test): {t:.2f} s")
 
 
-def run_steps(bkm, torch, X, W, cfg, precision, steps, warmup, max_iter):
+def run_steps(bkm, torch, X, W, cfg, precision, steps, warmup, max_iter, tile=0, sup=0):
     n = X[0].numel()
     k = cfg["k"]
     dev = X[0].device
@@ -100,7 +100,8 @@ def run_steps(bkm, torch, X, W, cfg, precision, steps, warmup, max_iter):
 
     def one():
         return bkm.balanced_kmeans(X, k, W=W, eps=cfg["eps"], max_iter=max_iter,
-                                   precision=precision, timing=True, out=out)
+                                   precision=precision, tile_points=tile, super_tiles=sup,
+                                   timing=True, out=out)
 
     for _ in range(warmup):
         one()
@@ -123,6 +124,8 @@ def main():
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c5"])
     ap.add_argument("--n", type=int, default=None, help="override the workload size")
     ap.add_argument("--max-iter", type=int, default=50)
+    ap.add_argument("--tile", type=int, default=0, help="points per tile (0: library default)")
+    ap.add_argument("--super", type=int, default=0, help="tiles per super-tile (0: default)")
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -150,14 +153,15 @@ def main():
     torch.cuda.synchronize()
 
     wall, tot, last = run_steps(bkm, torch, X, W, cfg, "f32_recheck", args.steps, args.warmup,
-                                args.max_iter)
+                                args.max_iter, args.tile, args.super)
     sweeps = tot["sweeps"]
     value = n * sweeps / wall
     ms_per_step = 1e3 * wall / args.steps
     print(f"[bench] f32_recheck: {ms_per_step:.2f} ms/step, {sweeps / args.steps:.1f} sweeps/step",
           file=sys.stderr, flush=True)
 
-    wall64, tot64, _ = run_steps(bkm, torch, X, W, cfg, "f64", args.fp64_steps, 1, args.max_iter)
+    wall64, tot64, _ = run_steps(bkm, torch, X, W, cfg, "f64", args.fp64_steps, 1, args.max_iter,
+                                 args.tile, args.super)
     value64 = n * tot64["sweeps"] / wall64
     print(f"[bench] f64: {1e3 * wall64 / args.fp64_steps:.2f} ms/step", file=sys.stderr, flush=True)
 
@@ -183,7 +187,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["name"], "n": n, "d": d, "k": cfg["k"], "eps": cfg["eps"],
                    "weighted": weighted, "precision": "f32_recheck", "max_iter": args.max_iter,
-                   "max_balance_iter": 20, "hilbert_order": 16},
+                   "max_balance_iter": 20, "hilbert_order": 16, "tile_points": args.tile or 1024,
+                   "super_tiles": args.super or 16},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_sweep", "avg_sweep_us": sweep_s * 1e6,

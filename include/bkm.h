@@ -90,11 +90,12 @@ typedef struct {
     int64_t rechecked;        /* evaluated visits decided again in FP64 */
     int64_t changed;          /* point visits whose block changed */
     int64_t candidate_evals;  /* (point, center) effective distances evaluated */
+    int64_t overflow_tiles;   /* tile sweeps whose candidate list overflowed */
     double bootstrap_ms;      /* device time of the SFC bootstrap */
     double total_ms;          /* device time of the whole call */
     /* with params.timing: summed device time of each kernel of the round loop
        (only launches that did work are counted) */
-    double cand_ms;           /* super-tile candidate lists, one per sweep */
+    double cand_ms;           /* super-tile and tile candidate lists, once per sweep */
     double sweep_ms;          /* assignment sweeps */
     double balance_ms;        /* balance test + influence update, one per sweep */
     double boxes_ms;          /* block bounding boxes, one per round */

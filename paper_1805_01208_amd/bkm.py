@@ -39,6 +39,7 @@ class Info(C.Structure):
                 ("max_block_weight", C.c_double), ("l_max", C.c_double),
                 ("evaluated", C.c_int64), ("skipped", C.c_int64), ("rechecked", C.c_int64),
                 ("changed", C.c_int64), ("candidate_evals", C.c_int64),
+                ("overflow_tiles", C.c_int64),
                 ("bootstrap_ms", C.c_double), ("total_ms", C.c_double),
                 ("cand_ms", C.c_double), ("sweep_ms", C.c_double), ("balance_ms", C.c_double),
                 ("boxes_ms", C.c_double), ("move_ms", C.c_double)]

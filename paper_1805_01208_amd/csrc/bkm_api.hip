@@ -117,6 +117,15 @@ int check_order(int d, int m)
     return BKM_OK;
 }
 
+// Tile, super-tile and group counts of a padded layout of npad points.
+void set_layout_size(RunDev& r, int64_t npad)
+{
+    r.npad = npad;
+    r.ntiles = (int)(npad / r.T);
+    r.nsuper = (r.ntiles + r.super_tiles - 1) / r.super_tiles;
+    r.ngroups = (int)(npad / kWave);
+}
+
 // Fill the sizes of a run and lay its arrays out in the arena.
 void plan(RunDev& r, const bkm_points* pts, int k, int T, int ST, int precision, int use_bounds,
           double gap)
@@ -129,11 +138,11 @@ void plan(RunDev& r, const bkm_points* pts, int k, int T, int ST, int precision,
     r.weighted = pts->weights != nullptr;
     r.T = T;
     r.ppt = T / kBlock;
-    r.ntiles = (int)((r.n + T - 1) / T);
-    r.npad = (int64_t)r.ntiles * T;
+    // capacity of the padded layout: at most maxjumps realigned jumps
+    r.maxjumps = (int)std::min<int64_t>(kMaxJumps, std::max<int64_t>(1, r.n / (4 * (int64_t)T)));
+    r.npad_cap = (r.n + (int64_t)r.maxjumps * (T - 1) + T - 1) / T * T;
     r.super_tiles = ST;
-    r.nsuper = (r.ntiles + ST - 1) / ST;
-    r.ngroups = (int)(r.npad / kWave);
+    set_layout_size(r, (r.n + T - 1) / T * T);
     r.precision = precision;
     r.use_bounds = use_bounds;
     r.recheck_gap = gap;
@@ -144,7 +153,9 @@ void plan(RunDev& r, const bkm_points* pts, int k, int T, int ST, int precision,
 size_t layout(RunDev& r, Arena* a, bool full)
 {
     Sizes z;
-    const int64_t n = r.n, np = r.npad;
+    const int64_t n = r.n, np = r.npad_cap;
+    const int64_t ntiles = np / r.T;
+    const int64_t nsuper = (ntiles + r.super_tiles - 1) / r.super_tiles;
     const int d = r.d, k = r.k;
     const int nblk = (int)((n + 4095) / 4096);
     const int64_t hlen = (int64_t)256 * nblk;
@@ -157,34 +168,49 @@ size_t layout(RunDev& r, Arena* a, bool full)
             z.add<T>(count);
     };
     both((DevState*)nullptr, 1, r.st);
+    both((unsigned long long*)nullptr, kCntSlots * kCntWords, r.cnt);
     both((double*)nullptr, std::max<int64_t>(8192, k), r.red);
     both((uint64_t*)nullptr, n, r.keys);
     both((uint64_t*)nullptr, n, r.keys2);
-    both((int32_t*)nullptr, n, r.perm);
+    both((int32_t*)nullptr, n, r.sperm);
     both((int32_t*)nullptr, n, r.vals2);
     both((uint32_t*)nullptr, hlen, r.hist);
     both((uint32_t*)nullptr, nseg + 1, r.part);
     for (int j = 0; j < d; ++j) {
         if (r.in_f32)
-            both((float*)nullptr, np, r.xs32[j]);
+            both((float*)nullptr, n, r.tx32[j]);
         else
-            both((double*)nullptr, np, r.xs64[j]);
+            both((double*)nullptr, n, r.tx64[j]);
     }
     both((double*)nullptr, (size_t)d * k, r.C);
     if (full) {
+        both((unsigned int*)nullptr, kGapBins, r.ghist);
+        both((int32_t*)nullptr, r.maxjumps, r.jumps);
+        both((int64_t*)nullptr, r.maxjumps, r.jshift);
+        both((int32_t*)nullptr, np, r.perm);
+        for (int j = 0; j < d; ++j) {
+            if (r.in_f32)
+                both((float*)nullptr, np, r.xs32[j]);
+            else
+                both((double*)nullptr, np, r.xs64[j]);
+        }
         if (r.precision == BKM_PREC_F32_RECHECK)
             for (int j = 0; j < d; ++j) both((float*)nullptr, np, r.ofs[j]);
         if (r.weighted) both((double*)nullptr, np, r.ws);
         both((int32_t*)nullptr, np, r.A);
         both((float*)nullptr, np, r.ubt);
         both((float*)nullptr, np, r.lbt);
-        both((double*)nullptr, (size_t)r.ntiles * 2 * d, r.tbox);
-        both((double*)nullptr, (size_t)r.ngroups * 2 * d, r.gbox);
-        both((double*)nullptr, (size_t)r.nsuper * 2 * d, r.sbox);
-        both((int32_t*)nullptr, (size_t)r.nsuper * k, r.slist);
-        both((int32_t*)nullptr, (size_t)r.nsuper, r.scount);
+        both((double*)nullptr, (size_t)ntiles * 2 * d, r.tbox);
+        both((double*)nullptr, (size_t)(np / kWave) * 2 * d, r.gbox);
+        both((double*)nullptr, (size_t)nsuper * 2 * d, r.sbox);
+        both((int32_t*)nullptr, (size_t)nsuper * k, r.slist);
+        both((int32_t*)nullptr, (size_t)nsuper, r.scount);
+        both((TileHead*)nullptr, (size_t)ntiles, r.thead);
+        both((CandRec*)nullptr, (size_t)ntiles * kTileCap, r.tcand);
         both((double*)nullptr, (size_t)k, r.I);
         both((double2*)nullptr, (size_t)k, r.clus);
+        both((float2*)nullptr, (size_t)k, r.clus32);
+        both((long long*)nullptr, (size_t)(np / kWave) * 2 * d, r.gsum);
         both((long long*)nullptr, (size_t)k * kAcc, r.acc);
         both((unsigned long long*)nullptr, (size_t)k * 2 * d, r.bb);
     }
@@ -217,7 +243,21 @@ int read_state(const RunDev& r, hipStream_t s, DevState* out)
     return BKM_OK;
 }
 
-// SFC bootstrap: bounding box (+ data checks), keys, sort, permutation.
+int read_counters(const RunDev& r, hipStream_t s, unsigned long long out[kCntWords])
+{
+    unsigned long long h[kCntSlots * kCntWords];
+    HIPCHK(hipMemcpyAsync(h, r.cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int j = 0; j < kCntWords; ++j) {
+        out[j] = 0;
+        for (int q = 0; q < kCntSlots; ++q) out[j] += h[q * kCntWords + j];
+    }
+    return BKM_OK;
+}
+
+// SFC bootstrap: bounding box (+ data checks), keys, sort, coordinates in
+// Hilbert order; with `tiles`, also the jump-aligned padded layout and the
+// tile, group and super-tile boxes.
 int bootstrap(RunDev& r, int order, hipStream_t s, bool tiles)
 {
     HIPCHK(launch_bbox(r, order, s));
@@ -227,10 +267,18 @@ int bootstrap(RunDev& r, int order, hipStream_t s, bool tiles)
     if (h.bad_data)
         return fail(BKM_EDATA, r.weighted ? "non-finite coordinate or weight <= 0 / non-finite"
                                           : "non-finite coordinate");
-    HIPCHK(launch_keys(r, order, r.perm, s));
-    HIPCHK(radix_sort_pairs(r, r.keys, r.perm, r.d * order, s));
-    HIPCHK(launch_permute(r, r.perm, s));
-    if (tiles) HIPCHK(launch_tile_prep(r, s));
+    HIPCHK(launch_keys(r, order, r.sperm, s));
+    HIPCHK(radix_sort_pairs(r, r.keys, r.sperm, r.d * order, s));
+    HIPCHK(launch_permute(r, s));
+    if (!tiles) return BKM_OK;
+    HIPCHK(launch_jump_plan(r, s));
+    if ((rc = read_state(r, s, &h))) return rc;
+    if (h.npad < r.n || h.npad > r.npad_cap)
+        return fail(BKM_EHIP, "padded layout of %lld points outside [n, %lld]", (long long)h.npad,
+                    (long long)r.npad_cap);
+    set_layout_size(r, h.npad);
+    HIPCHK(launch_place(r, s));
+    HIPCHK(launch_tile_prep(r, s));
     return BKM_OK;
 }
 
@@ -280,14 +328,14 @@ int bkm_init_centers_sfc(const bkm_points* pts, int32_t k, int32_t hilbert_order
     DevState h;
     if ((rc = read_state(r, s, &h))) return rc;
     if (h.bad_data) return fail(BKM_EDATA, "non-finite coordinate");
-    HIPCHK(launch_keys(r, hilbert_order, r.perm, s));
+    HIPCHK(launch_keys(r, hilbert_order, r.sperm, s));
     if (keys_out)
         HIPCHK(hipMemcpyAsync(keys_out, r.keys, r.n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
-    HIPCHK(radix_sort_pairs(r, r.keys, r.perm, r.d * hilbert_order, s));
-    HIPCHK(launch_permute(r, r.perm, s));
+    HIPCHK(radix_sort_pairs(r, r.keys, r.sperm, r.d * hilbert_order, s));
+    HIPCHK(launch_permute(r, s));
     HIPCHK(launch_centers_from_sorted(r, centers_out, 1, s));
     if (perm_out)
-        HIPCHK(hipMemcpyAsync(perm_out, r.perm, r.n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(perm_out, r.sperm, r.n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     return BKM_OK;
 }
@@ -357,6 +405,7 @@ int bkm_balanced_kmeans(const bkm_points* pts, const bkm_params* prm, const doub
         if (nb >= max_batches) return fail(BKM_EHIP, "round loop made no progress");
         HIPCHK(mark(0));
         HIPCHK(launch_supercand(r, s));
+        HIPCHK(launch_tilecand(r, s));
         HIPCHK(mark(1));
         HIPCHK(launch_sweep(r, s));
         HIPCHK(mark(2));
@@ -382,6 +431,8 @@ int bkm_balanced_kmeans(const bkm_points* pts, const bkm_params* prm, const doub
     HIPCHK(launch_finish(r, assignment_out, centers_out, influence_out, block_weights_out, s));
     HIPCHK(hipEventRecord(ev[2], s));
     if ((rc = read_state(r, s, &h))) return rc;
+    unsigned long long cnt[kCntWords];
+    if ((rc = read_counters(r, s, cnt))) return rc;
 
     if (info) {
         std::memset(info, 0, sizeof(*info));
@@ -392,11 +443,12 @@ int bkm_balanced_kmeans(const bkm_points* pts, const bkm_params* prm, const doub
         info->l_max = h.lmax;
         info->max_block_weight = h.max_weight;
         info->imbalance = h.max_weight / h.target - 1.0;
-        info->evaluated = (int64_t)h.evaluated;
-        info->skipped = (int64_t)h.skipped;
-        info->rechecked = (int64_t)h.rechecked;
-        info->changed = (int64_t)h.changed;
-        info->candidate_evals = (int64_t)h.cand_evals;
+        info->evaluated = (int64_t)cnt[kCntEvaluated];
+        info->skipped = (int64_t)cnt[kCntSkipped];
+        info->rechecked = (int64_t)cnt[kCntRechecked];
+        info->changed = (int64_t)cnt[kCntChanged];
+        info->candidate_evals = (int64_t)cnt[kCntCandEvals];
+        info->overflow_tiles = (int64_t)cnt[kCntOverflow];
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) info->bootstrap_ms = ms;
         if (hipEventElapsedTime(&ms, ev[0], ev[2]) == hipSuccess) info->total_ms = ms;
@@ -436,20 +488,22 @@ int bkm_assign_sweeps(const bkm_points* pts, int32_t k, int32_t steps, const dou
         HIPCHK(launch_set_step(r, centers + (int64_t)t * k * r.d, influence + (int64_t)t * k,
                                t == 0, s));
         HIPCHK(launch_supercand(r, s));
+        HIPCHK(launch_tilecand(r, s));
         HIPCHK(launch_sweep(r, s));
         HIPCHK(launch_finish(r, assignment_out + (int64_t)t * r.n, nullptr, nullptr,
                              block_weights_out ? block_weights_out + (int64_t)t * k : nullptr, s));
     }
-    DevState h;
-    if ((rc = read_state(r, s, &h))) return rc;
+    unsigned long long cnt[kCntWords];
+    if ((rc = read_counters(r, s, cnt))) return rc;
     if (info) {
         std::memset(info, 0, sizeof(*info));
         info->sweeps = steps;
-        info->evaluated = (int64_t)h.evaluated;
-        info->skipped = (int64_t)h.skipped;
-        info->rechecked = (int64_t)h.rechecked;
-        info->changed = (int64_t)h.changed;
-        info->candidate_evals = (int64_t)h.cand_evals;
+        info->evaluated = (int64_t)cnt[kCntEvaluated];
+        info->skipped = (int64_t)cnt[kCntSkipped];
+        info->rechecked = (int64_t)cnt[kCntRechecked];
+        info->changed = (int64_t)cnt[kCntChanged];
+        info->candidate_evals = (int64_t)cnt[kCntCandEvals];
+        info->overflow_tiles = (int64_t)cnt[kCntOverflow];
     }
     return BKM_OK;
 }

@@ -11,10 +11,14 @@ namespace bkm {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;          // threads per block of the point kernels
-constexpr int kLcap = 1024;          // super-tile candidates a tile can stage
-constexpr int kMaxc = 256;           // tile candidates held in LDS per chunk
+constexpr int kTileCap = 128;        // candidate records kept per tile
 constexpr int kFixShift = 30;        // fixed-point sums: term = hi * 2^30 + lo
 constexpr long long kFixLoMask = (1LL << kFixShift) - 1;
+constexpr int kPad = -2;             // block id of a padding point (never evaluated)
+constexpr int kMaxJumps = 8192;      // jumps between Hilbert-consecutive points realigned to tiles
+constexpr int kGapBins = 128;        // log2 histogram of gaps between consecutive points
+constexpr int kCntSlots = 64;        // sweep counters spread over this many cache lines
+constexpr int kCntWords = 8;         // counters per slot (one 64-byte line)
 
 // Control and scalar state of one run, resident in device memory.  Kernels
 // of a round read it to decide whether they still have work (a finished
@@ -32,7 +36,8 @@ struct DevState {
     int32_t max_balance_iter;
     int32_t bad_data;         // a non-finite coordinate or a bad weight was seen
     int32_t nonempty;         // non-empty blocks seen by the last center update
-    int32_t pad;
+    int32_t njumps;           // jumps found (before the kMaxJumps / capacity cap)
+    int64_t npad;             // padded point count of the tiled layout
     // Hamerly lower bounds are stored in a lazy frame: the bound at the current
     // time is M * stored - E (both conservatively rounded).
     double M, E;
@@ -44,14 +49,36 @@ struct DevState {
     double w_scale;           // power of two: weight term = rint(w*w_scale) (1 for unit weights)
     double wmax;
     double beta, max_delta, max_weight, total_weight;
-    unsigned long long evaluated, skipped, rechecked, changed, cand_evals, overflow_tiles;
+};
+
+// Sweep counters, summed over the kCntSlots slots by the host.
+enum { kCntEvaluated = 0, kCntSkipped, kCntRechecked, kCntChanged, kCntCandEvals, kCntOverflow };
+
+// Candidates of one tile for the current sweep, written by k_tilecand.
+struct TileHead {
+    int32_t n;                // records in use
+    int32_t overflow;         // 1: more than kTileCap candidates; sweep the super-tile list
+    int32_t pad0, pad1;
+    double tau;               // bound on |FP32 effective distance - exact| over the candidates
+    double dmax;              // bound on |FP32 distance - exact| over the candidates
+    double lb_out;            // lower bound on the effective distance of every center left out
+    double pad2;
+};
+
+// One candidate center of a tile: FP32 offset of the center from the tile
+// anchor and squared FP32 inverse influence, for the FP32 screen.
+struct alignas(32) CandRec {
+    float qx, qy, qz, w2;
+    int32_t id;
+    int32_t pad0, pad1, pad2;
 };
 
 // Everything a run keeps on the device.  Point arrays are in Hilbert (sorted)
 // order and padded to whole tiles.
 struct RunDev {
-    int64_t n, npad;
+    int64_t n, npad, npad_cap;  // points, padded layout size, its capacity
     int d, k, in_f32, weighted;
+    int maxjumps;
     int T, ppt, ntiles, super_tiles, nsuper, ngroups;
     int precision, use_bounds;
     double recheck_gap;
@@ -63,7 +90,13 @@ struct RunDev {
     float* xs32[3];           // sorted master coordinates (FP32 input)
     float* ofs[3];            // FP32 offsets from the tile anchor (FP32 sweep)
     double* ws;               // sorted weights or null
-    int32_t* perm;            // sorted position -> input index
+    int32_t* sperm;           // Hilbert order -> input index (n entries, no padding)
+    int32_t* perm;            // padded layout position -> input index, -1 for padding
+    double* tx64[3];          // coordinates in Hilbert order before padding (FP64 input)
+    float* tx32[3];           // same for FP32 input
+    unsigned int* ghist;      // [kGapBins]
+    int32_t* jumps;           // [maxjumps] first point after each jump, sorted by the plan
+    int64_t* jshift;          // [maxjumps] layout shift of the points from jumps[j] on
     int32_t* A;               // current block of each sorted point (-1: none yet)
     float* ubt;               // stored upper bounds (distance frame)
     float* lbt;               // stored lower bounds (lazy frame)
@@ -72,12 +105,17 @@ struct RunDev {
     double* sbox;             // [nsuper][2d]
     int32_t* slist;           // [nsuper][k] candidate centers of each super-tile
     int32_t* scount;          // [nsuper]
+    TileHead* thead;          // [ntiles]
+    CandRec* tcand;           // [ntiles][kTileCap]
     double* C;                // [d][k] centers (SoA)
     double* I;                // [k] influence
     double2* clus;            // [k] (accumulated movement, 1/influence)
+    float2* clus32;           // [k] the same rounded up to FP32, for the Hamerly test
+    long long* gsum;          // [ngroups][2d] fixed-point coordinate sums of each 64-point group
     long long* acc;           // [k][kAcc] fixed-point block sums
     unsigned long long* bb;   // [k][2d] encoded block boxes (min..., max...)
     DevState* st;
+    unsigned long long* cnt;  // [kCntSlots][kCntWords]
     // bootstrap scratch
     uint64_t* keys;
     uint64_t* keys2;
@@ -88,8 +126,30 @@ struct RunDev {
 };
 
 // Number of fixed-point accumulators per block: coordinate hi/lo per axis and
-// weight hi/lo (count in the hi word for unit weights).
+// weight hi/lo (count in the hi word for unit weights).  The weights follow
+// every sweep incrementally; the coordinate sums are rebuilt at the end of
+// each AssignAndBalance call.
 constexpr int kAcc = 8;
+constexpr int kAccW = 6;
+
+// Fixed-point coordinate terms of one point: hi/lo words of
+// rint(w * (x_j - lo_j) * sx_scale) per axis (w = 1 for unit weights).
+template <int D>
+__device__ inline void coord_terms(const double* x, const double* lo, double w, bool weighted,
+                                   double sxs, long long* t)
+{
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        double v = x[j] - lo[j];
+        if (weighted) v = w * v;
+        long long h, l;
+        const long long q = __double2ll_rn(v * sxs);
+        h = q >> kFixShift;
+        l = q & kFixLoMask;
+        t[2 * j] = h;
+        t[2 * j + 1] = l;
+    }
+}
 
 // ------------------------------------------------------------------ helpers
 __device__ inline double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, kWave); }
@@ -182,7 +242,9 @@ hipError_t launch_bbox(const RunDev& r, int hilbert_order, hipStream_t s);
 hipError_t launch_keys(const RunDev& r, int hilbert_order, int32_t* vals, hipStream_t s);
 hipError_t radix_sort_pairs(const RunDev& r, uint64_t* keys, int32_t* vals, int nbits,
                             hipStream_t s);
-hipError_t launch_permute(const RunDev& r, const int32_t* perm_sorted, hipStream_t s);
+hipError_t launch_permute(const RunDev& r, hipStream_t s);
+hipError_t launch_jump_plan(const RunDev& r, hipStream_t s);
+hipError_t launch_place(const RunDev& r, hipStream_t s);
 hipError_t launch_tile_prep(const RunDev& r, hipStream_t s);
 hipError_t launch_centers_from_sorted(const RunDev& r, double* out, int row_major,
                                       hipStream_t s);
@@ -190,6 +252,7 @@ hipError_t launch_init_run(const RunDev& r, const double* centers_init_rowmajor,
                            int max_iter, int max_balance_iter, double eps,
                            double delta_threshold, hipStream_t s);
 hipError_t launch_supercand(const RunDev& r, hipStream_t s);
+hipError_t launch_tilecand(const RunDev& r, hipStream_t s);
 hipError_t launch_sweep(const RunDev& r, hipStream_t s);
 hipError_t launch_balance(const RunDev& r, hipStream_t s);
 hipError_t launch_block_boxes(const RunDev& r, hipStream_t s);

@@ -317,20 +317,176 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t* kin,
 }
 
 // ---------------------------------------------------------------- permute
+// Coordinates in Hilbert order (no padding yet).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_permute(RunDev r, const int32_t* src)
+__global__ __launch_bounds__(kBlock) void k_permute(RunDev r)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= r.n) return;
-    const int32_t s = src[i];
-    r.perm[i] = s;
+    const int32_t s = r.sperm[i];
     for (int j = 0; j < r.d; ++j) {
         if (r.in_f32)
-            r.xs32[j][i] = ((const float*)r.in_x[j])[s];
+            r.tx32[j][i] = ((const float*)r.in_x[j])[s];
         else
-            r.xs64[j][i] = ((const double*)r.in_x[j])[s];
+            r.tx64[j][i] = ((const double*)r.in_x[j])[s];
     }
-    if (r.ws) r.ws[i] = r.in_w[s];
+}
+
+__device__ inline double tx_at(const RunDev& r, int j, int64_t i)
+{
+    return r.in_f32 ? (double)r.tx32[j][i] : r.tx64[j][i];
+}
+
+// ---------------------------------------------------------------- jumps
+// The Hilbert order keeps consecutive points close, except where the curve
+// leaves the data and re-enters elsewhere (empty parts of the curve's cube).
+// A tile straddling such a jump gets a huge box and a huge candidate list, so
+// the layout is padded to start a new tile after every jump.  A jump is a gap
+// between consecutive points larger than 64 times the median gap (median from
+// a log2 histogram, so the threshold is exact and order-independent).
+__device__ inline int gap_bin(double g)
+{
+    if (!(g > 0.0)) return 0;
+    const int e = ilogb(g) + 64;
+    return e < 1 ? 1 : (e >= kGapBins ? kGapBins - 1 : e);
+}
+
+__device__ inline double gap_at(const RunDev& r, int64_t i)
+{
+    double s = 0.0;
+    for (int j = 0; j < r.d; ++j) {
+        const double v = tx_at(r, j, i + 1) - tx_at(r, j, i);
+        s += v * v;
+    }
+    return sqrt(s);
+}
+
+__global__ __launch_bounds__(kBlock) void k_gap_hist(RunDev r)
+{
+    __shared__ unsigned int h[kGapBins];
+    if (threadIdx.x < kGapBins) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i + 1 < r.n; i += stride)
+        atomicAdd(&h[gap_bin(gap_at(r, i))], 1u);
+    __syncthreads();
+    if (threadIdx.x < kGapBins && h[threadIdx.x]) atomicAdd(&r.ghist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_jump_find(RunDev r)
+{
+    __shared__ double thr;
+    if (threadIdx.x == 0) {
+        // upper edge of the median bin, times 64
+        unsigned long long tot = 0, acc = 0;
+        for (int b = 0; b < kGapBins; ++b) tot += r.ghist[b];
+        int med = 0;
+        for (int b = 0; b < kGapBins; ++b) {
+            acc += r.ghist[b];
+            if (2 * acc >= tot) { med = b; break; }
+        }
+        thr = med == 0 ? 0.0 : ldexp(1.0, med - 64 + 1 + 6);
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i + 1 >= r.n || !(thr > 0.0)) return;
+    if (gap_at(r, i) > thr) {
+        const int slot = atomicAdd(&r.st->njumps, 1);
+        if (slot < r.maxjumps) r.jumps[slot] = (int32_t)(i + 1);
+    }
+}
+
+// One block: sort the jump starts, then walk them to give every run its
+// layout shift (the padding that moves its first point to a tile boundary).
+__global__ __launch_bounds__(1024) void k_jump_plan(RunDev r)
+{
+    __shared__ int32_t sj[kMaxJumps];
+    DevState* st = r.st;
+    const int nj = min(st->njumps, r.maxjumps);
+    int m = 1;
+    while (m < nj) m <<= 1;
+    for (int i = threadIdx.x; i < m; i += 1024) sj[i] = i < nj ? r.jumps[i] : 0x7fffffff;
+    __syncthreads();
+    for (int size = 2; size <= m; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < m; i += 1024) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool up = (i & size) == 0;
+                    const int32_t a = sj[i], b = sj[j];
+                    if ((a > b) == up) {
+                        sj[i] = b;
+                        sj[j] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) {
+        int64_t shift = 0;
+        for (int q = 0; q < nj; ++q) {
+            const int64_t pos = (int64_t)sj[q] + shift;
+            shift += (r.T - pos % r.T) % r.T;
+            r.jumps[q] = sj[q];
+            r.jshift[q] = shift;
+        }
+        const int64_t used = r.n + shift;
+        st->npad = (used + r.T - 1) / r.T * r.T;
+        st->njumps = nj;
+    }
+}
+
+// Layout shift of Hilbert position i: that of the last jump at or before i.
+__device__ inline int64_t shift_of(const RunDev& r, int nj, int64_t i)
+{
+    int lo = 0, hi = nj;  // first jump start > i
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)r.jumps[mid] <= i) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo > 0 ? r.jshift[lo - 1] : 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_layout(RunDev r)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= r.npad) return;
+    r.perm[p] = -1;
+    r.A[p] = kPad;
+}
+
+// Points into the padded layout; the last point before each gap in the
+// layout also fills the gap with copies of itself, so tile and group boxes
+// are those of the real points.
+__global__ __launch_bounds__(kBlock) void k_place(RunDev r)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= r.n) return;
+    const int nj = r.st->njumps;
+    const int64_t pos = i + shift_of(r, nj, i);
+    const int32_t src = r.sperm[i];
+    r.perm[pos] = src;
+    r.A[pos] = -1;
+    if (r.ws) r.ws[pos] = r.in_w[src];
+    double x[3];
+    for (int j = 0; j < r.d; ++j) {
+        x[j] = tx_at(r, j, i);
+        if (r.in_f32)
+            r.xs32[j][pos] = r.tx32[j][i];
+        else
+            r.xs64[j][pos] = x[j];
+    }
+    const int64_t next = (i + 1 < r.n) ? i + 1 + shift_of(r, nj, i + 1) : r.npad;
+    for (int64_t q = pos + 1; q < next; ++q) {
+        for (int j = 0; j < r.d; ++j) {
+            if (r.in_f32)
+                r.xs32[j][q] = r.tx32[j][i];
+            else
+                r.xs64[j][q] = x[j];
+        }
+    }
 }
 
 __device__ inline double xs_at(const RunDev& r, int j, int64_t i)
@@ -359,20 +515,38 @@ __global__ __launch_bounds__(kBlock) void k_tile_prep(RunDev r)
         double gmn[D], gmx[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            double v = i < r.n ? xs_at(r, j, i) : INFINITY;
-            double w = i < r.n ? v : -INFINITY;
+            const double v = xs_at(r, j, i);
+            const double w = v;
             gmn[j] = wave_min_d(v);
             gmx[j] = wave_max_d(w);
             tmn[j] = fmin(tmn[j], gmn[j]);
             tmx[j] = fmax(tmx[j], gmx[j]);
         }
-        if (lane == 0 && g0 < r.n) {
+        // fixed-point coordinate sums of the group's real points
+        long long t[2 * D];
+        {
+            double xv[D], lov[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                xv[j] = xs_at(r, j, i);
+                lov[j] = r.st->lo[j];
+            }
+            const bool real = r.perm[i] >= 0;
+            const double w = (r.ws && real) ? r.ws[i] : 1.0;
+            coord_terms<D>(xv, lov, w, r.ws != nullptr, r.st->sx_scale, t);
+#pragma unroll
+            for (int j = 0; j < 2 * D; ++j) t[j] = wave_sum_ll(real ? t[j] : 0);
+        }
+        if (lane == 0) {
             double* gb = r.gbox + (g0 / kWave) * 2 * D;
+            long long* gs = r.gsum + (g0 / kWave) * 2 * D;
 #pragma unroll
             for (int j = 0; j < D; ++j) {
                 gb[j] = gmn[j];
                 gb[D + j] = gmx[j];
             }
+#pragma unroll
+            for (int j = 0; j < 2 * D; ++j) gs[j] = t[j];
         }
     }
     if (lane == 0) {
@@ -397,10 +571,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_prep(RunDev r)
         for (int j = 0; j < D; ++j) X[j] = 0.5 * (box[j] + box[D + j]);
         for (int q = 0; q < r.ppt; ++q) {
             const int64_t i = base + (int64_t)q * kBlock + threadIdx.x;
-            if (i < r.n) {
 #pragma unroll
-                for (int j = 0; j < D; ++j) r.ofs[j][i] = (float)(xs_at(r, j, i) - X[j]);
-            }
+            for (int j = 0; j < D; ++j) r.ofs[j][i] = (float)(xs_at(r, j, i) - X[j]);
         }
     }
 }
@@ -438,7 +610,7 @@ __global__ __launch_bounds__(kBlock) void k_centers_from_sorted(RunDev r, double
     if (c >= r.k) return;
     const int64_t pos = ((int64_t)c * r.n) / r.k + r.n / (2 * (int64_t)r.k);
     for (int j = 0; j < r.d; ++j) {
-        double v = xs_at(r, j, pos);
+        double v = tx_at(r, j, pos);
         if (row_major)
             out[(int64_t)c * r.d + j] = v;
         else
@@ -506,10 +678,29 @@ hipError_t radix_sort_pairs(const RunDev& r, uint64_t* keys, int32_t* vals, int 
     return hipGetLastError();
 }
 
-hipError_t launch_permute(const RunDev& r, const int32_t* perm_sorted, hipStream_t s)
+hipError_t launch_permute(const RunDev& r, hipStream_t s)
 {
     unsigned g = nblocks(r.n, kBlock);
-    k_permute<double><<<g, kBlock, 0, s>>>(r, perm_sorted);
+    k_permute<double><<<g, kBlock, 0, s>>>(r);
+    return hipGetLastError();
+}
+
+// Gap histogram, jump search and plan; the padded size lands in st->npad.
+hipError_t launch_jump_plan(const RunDev& r, hipStream_t s)
+{
+    hipError_t e = hipMemsetAsync(r.ghist, 0, kGapBins * sizeof(unsigned int), s);
+    if (e != hipSuccess) return e;
+    const unsigned g = (unsigned)std::min<int64_t>(2048, nblocks(r.n, kBlock));
+    k_gap_hist<<<g, kBlock, 0, s>>>(r);
+    k_jump_find<<<nblocks(r.n, kBlock), kBlock, 0, s>>>(r);
+    k_jump_plan<<<1, 1024, 0, s>>>(r);
+    return hipGetLastError();
+}
+
+hipError_t launch_place(const RunDev& r, hipStream_t s)
+{
+    k_init_layout<<<nblocks(r.npad, kBlock), kBlock, 0, s>>>(r);
+    k_place<<<nblocks(r.n, kBlock), kBlock, 0, s>>>(r);
     return hipGetLastError();
 }
 

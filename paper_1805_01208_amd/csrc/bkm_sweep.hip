@@ -7,20 +7,24 @@
 //     possible effective distance to B exceeds the second-smallest largest
 //     effective distance of any center to B can be neither the best nor the
 //     second-best center of any point in B.  The filter runs at two levels:
-//     super-tiles against all k centers (k_supercand), then each tile of
-//     consecutive Hilbert-ordered points against its super-tile's list, inside
-//     the sweep block, into LDS.
+//     super-tiles against all k centers (k_supercand, one block each), then
+//     every tile of consecutive Hilbert-ordered points against its
+//     super-tile's list (k_tilecand, one wave each), which writes the
+//     surviving centers as compact records: FP32 offset from the tile anchor
+//     and squared FP32 inverse influence.
 //   * points (Sec. 4.3, Hamerly): a point whose upper bound on the effective
 //     distance to its own center is below its lower bound on the second-best
 //     effective distance keeps its block without evaluating anything.  The
 //     bounds are stored lazily -- the upper bound as a distance relative to the
 //     accumulated movement of its center, the lower bound in a global affine
 //     frame (M, E) -- so a point that is skipped is never written.
-// Block weights and the weighted coordinate sums of the center update are
-// maintained incrementally: a point that changes block moves its exact
-// fixed-point terms from the old to the new block with integer atomics, so the
-// sums equal the from-scratch sums bit for bit and do not depend on
-// scheduling order.
+// The sweep itself (k_sweep) streams the points' block ids and bounds; points
+// the bounds settle stop there, the others are compacted into a per-tile work
+// list in LDS and each gets a full lane to scan the tile's records (staged in
+// LDS).  Block weights are maintained incrementally: a point that changes
+// block moves its exact fixed-point weight (a count for unit weights) from
+// the old to the new block with integer atomics, so the weights equal the
+// from-scratch sums bit for bit whatever the scheduling order.
 #include <math.h>
 
 #include "bkm_internal.h"
@@ -34,10 +38,11 @@ constexpr double kCandSlack = 1e-9;               // relative slack of the cente
 constexpr double kTiny = 1e-12;                   // relative slack of FP64 bound arithmetic
 constexpr double kInf = INFINITY;
 
-// Smallest and largest effective distance from center c to the box [lo, hi].
+// Squared smallest and largest effective distance from center c to the box
+// [lo, hi]; iv = 1 / influence(c).
 template <int D>
-__device__ inline void box_eff(const double* lo, const double* hi, const double* C, int k,
-                               int c, double infl, double& lo_eff, double& hi_eff)
+__device__ inline void box_eff2(const double* lo, const double* hi, const double* C, int k,
+                                int c, double iv, double& lo2, double& hi2)
 {
     double mn = 0.0, mx = 0.0;
 #pragma unroll
@@ -48,8 +53,9 @@ __device__ inline void box_eff(const double* lo, const double* hi, const double*
         mn += g * g;
         mx += f * f;
     }
-    lo_eff = sqrt(mn) / infl;
-    hi_eff = sqrt(mx) / infl;
+    const double iv2 = iv * iv;
+    lo2 = mn * iv2;
+    hi2 = mx * iv2;
 }
 
 // Effective distance in FP64, evaluated exactly as defined:
@@ -75,6 +81,7 @@ __device__ inline double sorted_coord(const RunDev& r, int j, int64_t p)
     return r.in_f32 ? (double)r.xs32[j][p] : r.xs64[j][p];
 }
 
+// ------------------------------------------------------------ super-tiles
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_supercand(RunDev r)
 {
@@ -92,9 +99,9 @@ __global__ __launch_bounds__(kBlock) void k_supercand(RunDev r)
     }
     Two t{kInf, kInf};
     for (int c = tid; c < k; c += kBlock) {
-        double le, he;
-        box_eff<D>(lo, hi, r.C, k, c, r.I[c], le, he);
-        t = merge_two(t, Two{he, kInf});
+        double lo2, hi2;
+        box_eff2<D>(lo, hi, r.C, k, c, r.clus[c].y, lo2, hi2);
+        t = merge_two(t, Two{hi2, kInf});
     }
     t = wave_two(t);
     if (lane == 0) {
@@ -105,16 +112,16 @@ __global__ __launch_bounds__(kBlock) void k_supercand(RunDev r)
     __syncthreads();
     Two all{sa[0], sb[0]};
     for (int w = 1; w < kBlock / kWave; ++w) all = merge_two(all, Two{sa[w], sb[w]});
-    const double thr = all.b * (1.0 + kCandSlack);
+    const double thr2 = all.b * (1.0 + 2.0 * kCandSlack);
     int* out = r.slist + (int64_t)s * k;
     const unsigned long long below = (1ULL << lane) - 1ULL;
     for (int c0 = 0; c0 < k; c0 += kBlock) {
         const int c = c0 + tid;
         bool keep = false;
         if (c < k) {
-            double le, he;
-            box_eff<D>(lo, hi, r.C, k, c, r.I[c], le, he);
-            keep = le <= thr;
+            double lo2, hi2;
+            box_eff2<D>(lo, hi, r.C, k, c, r.clus[c].y, lo2, hi2);
+            keep = lo2 <= thr2;
         }
         const unsigned long long b = __ballot(keep);
         int off = 0;
@@ -126,35 +133,30 @@ __global__ __launch_bounds__(kBlock) void k_supercand(RunDev r)
     if (tid == 0) r.scount[s] = cnt;
 }
 
-// One sweep.  Block = one tile of T = 256 * PPT consecutive Hilbert-ordered
-// points; thread t handles points base + t + 256 q, so each wave covers
-// 64-point groups and every global access is coalesced.
-template <int D, int PREC, int PPT, bool WEIGHTED>
-__global__ __launch_bounds__(kBlock) void k_sweep(RunDev r)
+// ------------------------------------------------------------------ tiles
+// One wave per tile: filter the super-tile list against the tile box and
+// write the survivors' records plus the FP32 error bounds of the tile.
+//
+// FP32 error bound.  With anchor X (tile box center), half-extent norm Rn and
+// a candidate c at distance r_c from X, the FP32 offsets of point and center
+// are each within 1.0001*u*(Rn + r_c) of exact (u = 2^-24), their difference
+// within 2.001*u*(Rn + r_c), and the FP32 norm (two fused multiply-adds and a
+// square root) within 3.6*u*(Rn + r_c) of the exact distance; dmax uses
+// 8*u*(Rn + r_c), and tau that times 1/influence(c), maximised over the
+// candidates.
+template <int D, int PREC>
+__global__ __launch_bounds__(kBlock) void k_tilecand(RunDev r)
 {
-    DevState* st = r.st;
+    const DevState* st = r.st;
     if (st->done || st->round_done) return;
     constexpr bool F32 = PREC == BKM_PREC_F32_RECHECK;
-
-    __shared__ double s_lo[kLcap];
-    __shared__ int s_id[kMaxc];
-    __shared__ int s_cid[kMaxc];
-    __shared__ float s_q[D][kMaxc];
-    __shared__ float s_w2[kMaxc];
-    __shared__ double s_c[F32 ? 1 : D][F32 ? 1 : kMaxc];
-    __shared__ double s_I[F32 ? 1 : kMaxc];
-    __shared__ double s_red[2 * (kBlock / kWave)];
-    __shared__ int s_nc;
-    __shared__ unsigned long long s_cnt[5];
-
-    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
-    const int tile = blockIdx.x;
-    const int64_t base = (int64_t)tile * r.T;
+    constexpr int kCpl = 4;   // candidates a lane keeps in registers between passes
+    const int lane = threadIdx.x % kWave;
+    const int tile = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (tile >= r.ntiles) return;
     const int k = r.k;
     const double* __restrict__ C = r.C;
-    const double* __restrict__ I = r.I;
 
-    // tile geometry: exact box, anchor X (box center), half-extent norm
     double blo[D], bhi[D], X[D];
     double rn2 = 0.0;
 #pragma unroll
@@ -166,56 +168,96 @@ __global__ __launch_bounds__(kBlock) void k_sweep(RunDev r)
         rn2 += h * h;
     }
     const double Rn = sqrt(rn2) * (1.0 + kTiny);
-
-    // tile-level center filter over the super-tile's candidates
     const int sidx = tile / r.super_tiles;
     const int L = r.scount[sidx];
-    const int* sl = r.slist + (int64_t)sidx * k;
+    const int* __restrict__ sl = r.slist + (int64_t)sidx * k;
+    CandRec* __restrict__ out = r.tcand + (int64_t)tile * kTileCap;
+    const unsigned long long below = (1ULL << lane) - 1ULL;
+
+    int cnt = 0;
+    double tau = 0.0, dmax = 0.0;
+    // error bounds of one candidate; the record itself when it fits
+    auto emit = [&](bool keep, int c) {
+        const unsigned long long b = __ballot(keep);
+        const int pos = cnt + (int)__popcll(b & below);
+        if (keep) {
+            const double iv = r.clus[c].y;
+            double dd = 0.0, q[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                q[j] = C[(int64_t)j * k + c] - X[j];
+                dd += q[j] * q[j];
+            }
+            const double delta = 8.0 * kU32 * (Rn + sqrt(dd) * (1.0 + kTiny));
+            dmax = fmax(dmax, delta);
+            tau = fmax(tau, delta * iv);
+            if (pos < kTileCap) {
+                CandRec rec;
+                rec.qx = (float)q[0];
+                rec.qy = (float)q[1];
+                rec.qz = D == 3 ? (float)q[D - 1] : 0.0f;
+                const float fi = (float)iv;
+                rec.w2 = fi * fi;
+                rec.id = c;
+                rec.pad0 = rec.pad1 = rec.pad2 = 0;
+                out[pos] = rec;
+            }
+        }
+        cnt += (int)__popcll(b);
+    };
+
     Two t{kInf, kInf};
-    for (int i = tid; i < L; i += kBlock) {
-        const int c = sl[i];
-        double le, he;
-        box_eff<D>(blo, bhi, C, k, c, I[c], le, he);
-        if (i < kLcap) s_lo[i] = le;
-        t = merge_two(t, Two{he, kInf});
-    }
-    t = wave_two(t);
-    if (lane == 0) {
-        s_red[wv] = t.a;
-        s_red[kBlock / kWave + wv] = t.b;
-    }
-    if (tid < 5) s_cnt[tid] = 0;
-    if (tid == 0) s_nc = 0;
-    __syncthreads();
-    Two all{s_red[0], s_red[kBlock / kWave]};
-    for (int w = 1; w < kBlock / kWave; ++w) all = merge_two(all, Two{s_red[w], s_red[kBlock / kWave + w]});
-    const double thr = all.b * (1.0 + kCandSlack);
-    bool overflow = L > kLcap;
-    if (!overflow) {
-        const unsigned long long below = (1ULL << lane) - 1ULL;
-        for (int i0 = 0; i0 < L; i0 += kBlock) {
-            const int i = i0 + tid;
-            const bool keep = i < L && s_lo[i] <= thr;
-            const unsigned long long b = __ballot(keep);
-            int off = 0;
-            if (lane == 0 && b) off = atomicAdd(&s_nc, (int)__popcll(b));
-            off = __shfl(off, 0, kWave);
-            const int pos = off + (int)__popcll(b & below);
-            if (keep && pos < kMaxc) s_id[pos] = sl[i];
+    double thr2;
+    if (L <= kCpl * kWave) {
+        int cc[kCpl];
+        double clo[kCpl];
+#pragma unroll
+        for (int u = 0; u < kCpl; ++u) {
+            const int i = lane + u * kWave;
+            cc[u] = -1;
+            clo[u] = kInf;
+            if (i < L) {
+                const int c = sl[i];
+                double lo2, hi2;
+                box_eff2<D>(blo, bhi, C, k, c, r.clus[c].y, lo2, hi2);
+                cc[u] = c;
+                clo[u] = lo2;
+                t = merge_two(t, Two{hi2, kInf});
+            }
+        }
+        t = wave_two(t);
+        thr2 = t.b * (1.0 + 2.0 * kCandSlack);
+#pragma unroll
+        for (int u = 0; u < kCpl; ++u) emit(cc[u] >= 0 && clo[u] <= thr2, cc[u]);
+    } else {
+        for (int i = lane; i < L; i += kWave) {
+            const int c = sl[i];
+            double lo2, hi2;
+            box_eff2<D>(blo, bhi, C, k, c, r.clus[c].y, lo2, hi2);
+            t = merge_two(t, Two{hi2, kInf});
+        }
+        t = wave_two(t);
+        thr2 = t.b * (1.0 + 2.0 * kCandSlack);
+        for (int i0 = 0; i0 < L; i0 += kWave) {
+            const int i = i0 + lane;
+            int c = 0;
+            bool keep = false;
+            if (i < L) {
+                c = sl[i];
+                double lo2, hi2;
+                box_eff2<D>(blo, bhi, C, k, c, r.clus[c].y, lo2, hi2);
+                keep = lo2 <= thr2;
+            }
+            emit(keep, c);
         }
     }
-    __syncthreads();
-    if (!overflow && s_nc > kMaxc) overflow = true;
-    const int* src = overflow ? sl : s_id;
-    const int ncand = overflow ? L : s_nc;
-    // a lower bound on the effective distance of every center left out
-    const double lb_out = thr * (1.0 - kTiny);
-
-    // FP32 error constants of this tile (see the sweep notes below)
-    double tau = 0.0, dmax = 0.0;
-    if (F32) {
-        for (int i = tid; i < ncand; i += kBlock) {
-            const int c = src[i];
+    const bool overflow = cnt > kTileCap;
+    if (overflow && F32) {
+        // the sweep will scan the whole super-tile list: bound its error
+        tau = 0.0;
+        dmax = 0.0;
+        for (int i = lane; i < L; i += kWave) {
+            const int c = sl[i];
             double dd = 0.0;
 #pragma unroll
             for (int j = 0; j < D; ++j) {
@@ -224,181 +266,242 @@ __global__ __launch_bounds__(kBlock) void k_sweep(RunDev r)
             }
             const double delta = 8.0 * kU32 * (Rn + sqrt(dd) * (1.0 + kTiny));
             dmax = fmax(dmax, delta);
-            tau = fmax(tau, delta / I[c]);
+            tau = fmax(tau, delta * r.clus[c].y);
         }
-        tau = wave_max_d(tau);
-        dmax = wave_max_d(dmax);
-        if (lane == 0) {
-            s_red[wv] = tau;
-            s_red[kBlock / kWave + wv] = dmax;
-        }
-        __syncthreads();
-        tau = s_red[0];
-        dmax = s_red[kBlock / kWave];
-        for (int w = 1; w < kBlock / kWave; ++w) {
-            tau = fmax(tau, s_red[w]);
-            dmax = fmax(dmax, s_red[kBlock / kWave + w]);
-        }
-        tau *= 1.0 + kTiny;
-        dmax *= 1.0 + kTiny;
     }
+    tau = wave_max_d(tau);
+    dmax = wave_max_d(dmax);
+    if (lane == 0) {
+        TileHead h;
+        h.n = overflow ? 0 : cnt;
+        h.overflow = overflow ? 1 : 0;
+        h.pad0 = h.pad1 = 0;
+        h.tau = tau * (1.0 + kTiny);
+        h.dmax = dmax * (1.0 + kTiny);
+        h.lb_out = sqrt(t.b) * (1.0 - kTiny);
+        h.pad2 = 0.0;
+        r.thead[tile] = h;
+    }
+}
 
-    // load points, Hamerly test
-    const double M = st->M, E = st->E;
+// ------------------------------------------------------------------ sweep
+// Block = one tile of T = 256 * PPT consecutive Hilbert-ordered points.
+// Phase 1 streams every point of the tile (thread t, points base + t + 256 q,
+// so each wave reads 64 consecutive points and every access is coalesced):
+// block id, stored bounds, Hamerly test.  The points the bounds cannot
+// decide are compacted into an LDS work list, and phase 2 gives each of them
+// a full lane for the candidate scan (records staged in LDS), the decision
+// and the block-weight bookkeeping, so skipped points cost no candidate
+// arithmetic.  The coordinate sums of the center update are not touched
+// here: the round-end pass rebuilds them from the final assignment.
+template <int D, int PREC, int PPT, bool WEIGHTED>
+__global__ __launch_bounds__(kBlock) void k_sweep(RunDev r)
+{
+    DevState* st = r.st;
+    if (st->done || st->round_done) return;
+    constexpr bool F32 = PREC == BKM_PREC_F32_RECHECK;
+    constexpr int T = kBlock * PPT;
+    __shared__ int s_off[T];      // tile offsets of the points to evaluate
+    __shared__ int s_aold[T];     // and their current block
+    __shared__ float4 s_q[kTileCap];
+    __shared__ int s_cid[kTileCap];
+    __shared__ double s_c64[F32 ? 1 : 4][F32 ? 1 : kTileCap];
+    __shared__ int s_nl;
+    __shared__ unsigned long long s_cnt[5];
+
+    const int tid = threadIdx.x, lane = tid % kWave;
+    const int tile = blockIdx.x;
+    const int64_t base = (int64_t)tile * T;
+    const int k = r.k;
+    const double* __restrict__ C = r.C;
+    const double* __restrict__ I = r.I;
+    if (tid < 5) s_cnt[tid] = 0;
+    if (tid == 0) s_nl = 0;
+
+    // ---- phase 1: block ids and stored bounds (arrays are padded to whole tiles)
     int aold[PPT];
-    bool ev[PPT];
-    float o[PPT][D];
-    double x[PPT][D];
-    float b2[PPT], s2[PPT], bd2[PPT];
-    int bi[PPT];
-    double be[PPT], se[PPT], bs2[PPT];
-    int bc[PPT];
-    unsigned n_eval = 0, n_skip = 0;
+    float ut[PPT], lt[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
         const int64_t p = base + (int64_t)q * kBlock + tid;
-        const bool valid = p < r.n;
-        aold[q] = valid ? r.A[p] : -1;
-        ev[q] = valid;
-        if (valid && r.use_bounds && aold[q] >= 0) {
-            const double2 cl = r.clus[aold[q]];
-            const double ub = ((double)r.ubt[p] + cl.x) * cl.y * (1.0 + kTiny);
-            const double lt = (double)r.lbt[p];
-            const double lb = (M * lt - E) - kTiny * (M * lt + E);
+        aold[q] = r.A[p];
+        ut[q] = r.use_bounds ? r.ubt[p] : 0.0f;
+        lt[q] = r.use_bounds ? r.lbt[p] : 0.0f;
+    }
+    const TileHead hd = r.thead[tile];
+    const int sidx = tile / r.super_tiles;
+    const int* __restrict__ sl = r.slist + (int64_t)sidx * k;
+    const CandRec* __restrict__ cr = r.tcand + (int64_t)tile * kTileCap;
+    const int ncand = hd.overflow ? r.scount[sidx] : hd.n;
+    // the tile's candidate records into LDS
+    if (!hd.overflow && tid < hd.n) {
+        const CandRec rec = cr[tid];
+        s_cid[tid] = rec.id;
+        if (F32) {
+            s_q[tid] = make_float4(rec.qx, rec.qy, rec.qz, rec.w2);
+        } else {
+            s_c64[0][F32 ? 0 : tid] = C[rec.id];
+            s_c64[F32 ? 0 : 1][F32 ? 0 : tid] = C[(int64_t)k + rec.id];
+            s_c64[F32 ? 0 : 2][F32 ? 0 : tid] = D == 3 ? C[(int64_t)(D - 1) * k + rec.id] : 0.0;
+            s_c64[F32 ? 0 : 3][F32 ? 0 : tid] = I[rec.id];
+        }
+    }
+    float2 cl[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) cl[q] = r.clus32[aold[q] > 0 ? aold[q] : 0];
+    // lower-bound frame in FP32, rounded so that every bound stays valid
+    const float Mf = f32_down(st->M), Ef = f32_up(st->E);
+    const double M = st->M, E = st->E;
+    unsigned n_eval = 0, n_skip = 0;
+    __syncthreads();   // s_nl initialised
+    const unsigned long long below = (1ULL << lane) - 1ULL;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        bool ev = aold[q] != kPad && ncand > 0;
+        if (ev && r.use_bounds && aold[q] >= 0) {
+            // Hamerly test (Sec. 4.3): upper bound on the own effective
+            // distance below the lower bound on the second-best one.  FP32
+            // with absolute slack covering every rounding.
+            float sub = ut[q] + cl[q].x;
+            sub += 0x1p-21f * (fabsf(ut[q]) + cl[q].x);
+            const float ub = sub * cl[q].y * (1.0f + 0x1p-20f);
+            const float m = Mf * lt[q];
+            const float lb = (m - Ef) - 0x1p-20f * (m + Ef);
             if (ub < lb) {
-                ev[q] = false;
+                ev = false;
                 ++n_skip;
             }
         }
-        if (ncand == 0) ev[q] = false;  // no candidate (cannot happen for finite data)
-        if (ev[q]) ++n_eval;
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            o[q][j] = 0.0f;
-            x[q][j] = 0.0;
-            if (ev[q]) {
-                if (F32)
-                    o[q][j] = r.ofs[j][p];
-                else
-                    x[q][j] = sorted_coord(r, j, p);
-            }
-        }
-        b2[q] = s2[q] = bd2[q] = INFINITY;
-        bi[q] = 0;
-        be[q] = se[q] = bs2[q] = kInf;
-        bc[q] = 0x7fffffff;
-    }
-    bool anyev = false;
-#pragma unroll
-    for (int q = 0; q < PPT; ++q) anyev |= ev[q];
-    const bool wave_busy = __ballot(anyev) != 0ULL;
-
-    // evaluate the candidates, chunk by chunk through LDS
-    for (int cs = 0; cs < ncand; cs += kMaxc) {
-        const int cn = min(kMaxc, ncand - cs);
-        __syncthreads();
-        for (int i = tid; i < cn; i += kBlock) {
-            const int c = src[cs + i];
-            s_cid[i] = c;
-            if (F32) {
-#pragma unroll
-                for (int j = 0; j < D; ++j) s_q[j][i] = (float)(C[(int64_t)j * k + c] - X[j]);
-                const float iv = (float)(1.0 / I[c]);
-                s_w2[i] = iv * iv;
-            } else {
-#pragma unroll
-                for (int j = 0; j < D; ++j) s_c[F32 ? 0 : j][F32 ? 0 : i] = C[(int64_t)j * k + c];
-                s_I[F32 ? 0 : i] = I[c];
-            }
-        }
-        __syncthreads();
-        if (!wave_busy) continue;
-        for (int i = 0; i < cn; ++i) {
-            if (F32) {
-                const float q0 = s_q[0][i], q1 = s_q[1][i], q2 = D == 3 ? s_q[D - 1][i] : 0.0f;
-                const float w2 = s_w2[i];
-#pragma unroll
-                for (int q = 0; q < PPT; ++q) {
-                    const float dx = o[q][0] - q0;
-                    const float dy = o[q][1] - q1;
-                    float d2 = dx * dx;
-                    d2 = __builtin_fmaf(dy, dy, d2);
-                    if (D == 3) {
-                        const float dz = o[q][D - 1] - q2;
-                        d2 = __builtin_fmaf(dz, dz, d2);
-                    }
-                    const float e2 = d2 * w2;
-                    if (e2 < b2[q]) {
-                        s2[q] = b2[q];
-                        b2[q] = e2;
-                        bd2[q] = d2;
-                        bi[q] = cs + i;
-                    } else if (e2 < s2[q]) {
-                        s2[q] = e2;
-                    }
-                }
-            } else {
-                const int c = s_cid[i];
-                const double cx = s_c[0][F32 ? 0 : i], cy = s_c[F32 ? 0 : 1][F32 ? 0 : i];
-                const double cz = D == 3 ? s_c[F32 ? 0 : D - 1][F32 ? 0 : i] : 0.0;
-                const double ic = s_I[F32 ? 0 : i];
-#pragma unroll
-                for (int q = 0; q < PPT; ++q) {
-                    double sq;
-                    const double e = eff64<D>(x[q], cx, cy, cz, ic, sq);
-                    if (e < be[q] || (e == be[q] && c < bc[q])) {
-                        se[q] = be[q];
-                        be[q] = e;
-                        bc[q] = c;
-                        bs2[q] = sq;
-                    } else if (e < se[q]) {
-                        se[q] = e;
-                    }
-                }
-            }
+        const unsigned long long b = __ballot(ev);
+        int pos = 0;
+        if (lane == 0 && b) pos = atomicAdd(&s_nl, (int)__popcll(b));
+        pos = __shfl(pos, 0, kWave) + (int)__popcll(b & below);
+        if (ev) {
+            s_off[pos] = q * kBlock + tid;
+            s_aold[pos] = aold[q];
+            ++n_eval;
         }
     }
+    __syncthreads();
+    const int nl = s_nl;
 
-    // decide, store bounds, move fixed-point terms of points that changed block
+    // ---- phase 2: one lane per undecided point
     unsigned n_rechk = 0, n_chg = 0;
     const double gap_rel = r.recheck_gap;
-    const double lo0 = st->lo[0], lo1 = st->lo[1], lo2 = st->lo[D - 1];
-    const double sxs = st->sx_scale, wsc = st->w_scale;
+    const double wsc = st->w_scale;
+    double X[D];
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-        const int64_t p = base + (int64_t)q * kBlock + tid;
-        int cbest = aold[q];
+    for (int j = 0; j < D; ++j) X[j] = 0.0;
+    if (hd.overflow) {
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            X[j] = 0.5 * (r.tbox[(int64_t)tile * 2 * D + j] + r.tbox[(int64_t)tile * 2 * D + D + j]);
+    }
+    for (int i0 = 0; i0 < nl; i0 += kBlock) {
+        const int i = i0 + tid;
+        const bool act = i < nl;
+        const int off = act ? s_off[i] : 0;
+        const int ao = act ? s_aold[i] : -1;
+        const int64_t p = base + off;
+        float o[D];
+        double x[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            o[j] = 0.0f;
+            x[j] = 0.0;
+            if (act) {
+                if (F32)
+                    o[j] = r.ofs[j][p];
+                else
+                    x[j] = sorted_coord(r, j, p);
+            }
+        }
+        // best and second-best over the tile's candidates
+        float b2 = INFINITY, s2 = INFINITY, bd2 = INFINITY;
+        double be = kInf, se = kInf, bs2 = kInf;
+        int bc = 0x7fffffff;
+        auto consider32 = [&](int c, float qx, float qy, float qz, float w2) {
+            const float dx = o[0] - qx;
+            const float dy = o[1] - qy;
+            float d2 = dx * dx;
+            d2 = __builtin_fmaf(dy, dy, d2);
+            if (D == 3) {
+                const float dz = o[D - 1] - qz;
+                d2 = __builtin_fmaf(dz, dz, d2);
+            }
+            const float e2 = d2 * w2;
+            const bool better = e2 < b2;
+            s2 = better ? b2 : fminf(s2, e2);
+            bd2 = better ? d2 : bd2;
+            bc = better ? c : bc;
+            b2 = better ? e2 : b2;
+        };
+        auto consider64 = [&](int c, double cx, double cy, double cz, double ic) {
+            double sq;
+            const double e = eff64<D>(x, cx, cy, cz, ic, sq);
+            const bool better = e < be || (e == be && c < bc);
+            se = better ? be : fmin(se, e);
+            bs2 = better ? sq : bs2;
+            bc = better ? c : bc;
+            be = better ? e : be;
+        };
+        if (__ballot(act) != 0ULL) {
+            if (!hd.overflow) {
+                for (int c0 = 0; c0 < ncand; ++c0) {
+                    const int c = s_cid[c0];
+                    if (F32) {
+                        const float4 qv = s_q[c0];
+                        consider32(c, qv.x, qv.y, qv.z, qv.w);
+                    } else {
+                        consider64(c, s_c64[0][F32 ? 0 : c0], s_c64[F32 ? 0 : 1][F32 ? 0 : c0],
+                                   s_c64[F32 ? 0 : 2][F32 ? 0 : c0], s_c64[F32 ? 0 : 3][F32 ? 0 : c0]);
+                    }
+                }
+            } else {
+                for (int c0 = 0; c0 < ncand; ++c0) {
+                    const int c = sl[c0];
+                    if (F32) {
+                        const float fi = (float)r.clus[c].y;
+                        consider32(c, (float)(C[c] - X[0]), (float)(C[(int64_t)k + c] - X[1]),
+                                   D == 3 ? (float)(C[(int64_t)(D - 1) * k + c] - X[D - 1]) : 0.0f,
+                                   fi * fi);
+                    } else {
+                        consider64(c, C[c], C[(int64_t)k + c],
+                                   D == 3 ? C[(int64_t)(D - 1) * k + c] : 0.0, I[c]);
+                    }
+                }
+            }
+        }
+        int cbest = ao;
         bool chg = false;
-        long long th[D], tl[D], wh = 1, wl = 0;
-        if (ev[q]) {
+        long long wh = 1, wl = 0;
+        if (act) {
             double ubd, lb;
-            bool have64 = !F32;
             if (F32) {
-                const float eb = __builtin_sqrtf(b2[q]);
-                const float es = __builtin_sqrtf(s2[q]);
-                // single candidate: certain; an overflowed FP32 value: decide in FP64
+                const float eb = __builtin_sqrtf(b2);
+                const float es = __builtin_sqrtf(s2);
+                // one candidate: certain; an overflowed FP32 value: decide in FP64
                 const bool sure =
-                    b2[q] < INFINITY &&
+                    b2 < INFINITY &&
                     (ncand == 1 ||
-                     (s2[q] < INFINITY &&
-                      (double)es * (1.0 - 8.0 * kU32) - (double)eb * (1.0 + 8.0 * kU32) > 2.0 * tau &&
+                     (s2 < INFINITY &&
+                      (double)es * (1.0 - 8.0 * kU32) - (double)eb * (1.0 + 8.0 * kU32) > 2.0 * hd.tau &&
                       (double)es - (double)eb > gap_rel * (double)es));
                 if (sure) {
-                    cbest = src[bi[q]];
-                    ubd = (double)__builtin_sqrtf(bd2[q]) * (1.0 + 4.0 * kU32) + dmax;
-                    lb = (double)es * (1.0 - 8.0 * kU32) - tau;
+                    cbest = bc;
+                    ubd = (double)__builtin_sqrtf(bd2) * (1.0 + 4.0 * kU32) + hd.dmax;
+                    lb = (double)es * (1.0 - 8.0 * kU32) - hd.tau;
                 } else {
                     // FP64 recheck over every candidate of the tile
                     ++n_rechk;
 #pragma unroll
-                    for (int j = 0; j < D; ++j) x[q][j] = sorted_coord(r, j, p);
-                    have64 = true;
+                    for (int j = 0; j < D; ++j) x[j] = sorted_coord(r, j, p);
                     double b = kInf, s = kInf, bsq = kInf;
                     int bcc = 0x7fffffff;
-                    for (int i = 0; i < ncand; ++i) {
-                        const int c = src[i];
+                    for (int c0 = 0; c0 < ncand; ++c0) {
+                        const int c = hd.overflow ? sl[c0] : s_cid[c0];
                         double sq;
-                        const double e = eff64<D>(x[q], C[c], C[(int64_t)k + c],
+                        const double e = eff64<D>(x, C[c], C[(int64_t)k + c],
                                                   D == 3 ? C[(int64_t)(D - 1) * k + c] : 0.0, I[c], sq);
                         if (e < b || (e == b && c < bcc)) {
                             s = b;
@@ -414,12 +517,12 @@ __global__ __launch_bounds__(kBlock) void k_sweep(RunDev r)
                     lb = s * (1.0 - kTiny);
                 }
             } else {
-                cbest = bc[q];
-                ubd = sqrt(bs2[q]) * (1.0 + kTiny);
-                lb = se[q] * (1.0 - kTiny);
+                cbest = bc;
+                ubd = sqrt(bs2) * (1.0 + kTiny);
+                lb = se * (1.0 - kTiny);
             }
-            if (cbest < 0 || cbest >= k) cbest = aold[q] >= 0 ? aold[q] : src[0];
-            lb = fmin(lb, lb_out);
+            if (cbest < 0 || cbest >= k) cbest = ao >= 0 ? ao : (hd.overflow ? sl[0] : s_cid[0]);
+            lb = fmin(lb, hd.lb_out);
             if (r.use_bounds) {
                 const double Db = r.clus[cbest].x;
                 double uv = ubd - Db;
@@ -429,84 +532,60 @@ __global__ __launch_bounds__(kBlock) void k_sweep(RunDev r)
                 lv -= kTiny * fabs(lv);
                 r.lbt[p] = (lv > 0.0) ? f32_down(lv) : 0.0f;
             }
-            if (cbest != aold[q]) {
+            if (cbest != ao) {
                 chg = true;
                 ++n_chg;
                 r.A[p] = cbest;
-                if (!have64) {
-#pragma unroll
-                    for (int j = 0; j < D; ++j) x[q][j] = sorted_coord(r, j, p);
-                }
-                const double w = WEIGHTED ? r.ws[p] : 1.0;
-                const double lov[3] = {lo0, lo1, lo2};
-#pragma unroll
-                for (int j = 0; j < D; ++j) {
-                    double v = x[q][j] - lov[j];
-                    if (WEIGHTED) v = w * v;
-                    fix_split(v * sxs, th[j], tl[j]);
-                }
-                if (WEIGHTED) fix_split(w * wsc, wh, wl);
+                if (WEIGHTED) fix_split(r.ws[p] * wsc, wh, wl);
             }
         }
-        // wave-aggregated transfer of the terms from the old to the new block
+        // wave-aggregated transfer of the point's weight from the old to the new block
         unsigned long long pend = __ballot(chg);
         while (pend) {
-            const int leader = (int)__ffsll((long long)pend) - 1;
-            const int ka = __shfl(aold[q], leader, kWave);
+            const int leader = __builtin_ctzll(pend);
+            const int ka = __shfl(ao, leader, kWave);
             const int kb = __shfl(cbest, leader, kWave);
-            const bool mine = chg && aold[q] == ka && cbest == kb;
+            const bool mine = chg && ao == ka && cbest == kb;
             const unsigned long long mm = __ballot(mine);
-            long long v[kAcc];
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                v[2 * j] = wave_sum_ll(mine ? th[j] : 0);
-                v[2 * j + 1] = wave_sum_ll(mine ? tl[j] : 0);
-            }
+            long long vh, vl = 0;
             if (WEIGHTED) {
-                v[6] = wave_sum_ll(mine ? wh : 0);
-                v[7] = wave_sum_ll(mine ? wl : 0);
+                vh = wave_sum_ll(mine ? wh : 0);
+                vl = wave_sum_ll(mine ? wl : 0);
             } else {
-                v[6] = (long long)__popcll(mm);
-                v[7] = 0;
+                vh = (long long)__popcll(mm);
             }
             if (lane == leader) {
-                unsigned long long* nb = (unsigned long long*)(r.acc + (int64_t)kb * kAcc);
-                unsigned long long* ob = (unsigned long long*)(r.acc + (int64_t)ka * kAcc);
-#pragma unroll
-                for (int j = 0; j < D; ++j) {
-                    atomicAdd(nb + 2 * j, (unsigned long long)v[2 * j]);
-                    atomicAdd(nb + 2 * j + 1, (unsigned long long)v[2 * j + 1]);
-                    if (ka >= 0) {
-                        atomicAdd(ob + 2 * j, (unsigned long long)(-v[2 * j]));
-                        atomicAdd(ob + 2 * j + 1, (unsigned long long)(-v[2 * j + 1]));
-                    }
-                }
-                atomicAdd(nb + 6, (unsigned long long)v[6]);
-                if (ka >= 0) atomicAdd(ob + 6, (unsigned long long)(-v[6]));
-                if (WEIGHTED) {
-                    atomicAdd(nb + 7, (unsigned long long)v[7]);
-                    if (ka >= 0) atomicAdd(ob + 7, (unsigned long long)(-v[7]));
+                unsigned long long* nb = (unsigned long long*)(r.acc + (int64_t)kb * kAcc + kAccW);
+                atomicAdd(nb, (unsigned long long)vh);
+                if (WEIGHTED) atomicAdd(nb + 1, (unsigned long long)vl);
+                if (ka >= 0) {
+                    unsigned long long* ob = (unsigned long long*)(r.acc + (int64_t)ka * kAcc + kAccW);
+                    atomicAdd(ob, (unsigned long long)(-vh));
+                    if (WEIGHTED) atomicAdd(ob + 1, (unsigned long long)(-vl));
                 }
             }
             pend &= ~mm;
         }
     }
 
-    // counters
-    const unsigned long long cev = (unsigned long long)n_eval * (unsigned long long)ncand;
-    if (n_eval) atomicAdd(&s_cnt[0], (unsigned long long)n_eval);
-    if (n_skip) atomicAdd(&s_cnt[1], (unsigned long long)n_skip);
-    if (n_rechk) atomicAdd(&s_cnt[2], (unsigned long long)n_rechk);
-    if (n_chg) atomicAdd(&s_cnt[3], (unsigned long long)n_chg);
-    if (cev) atomicAdd(&s_cnt[4], cev);
+    // counters: wave sums, then one slot per 64 tiles (never a single address)
+    unsigned long long cv[5] = {n_eval, n_skip, n_rechk, n_chg,
+                                (unsigned long long)n_eval * (unsigned long long)ncand};
+#pragma unroll
+    for (int j = 0; j < 5; ++j) cv[j] = (unsigned long long)wave_sum_ll((long long)cv[j]);
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+            if (cv[j]) atomicAdd(&s_cnt[j], cv[j]);
+    }
     __syncthreads();
-    if (tid == 0) {
-        if (s_cnt[0]) atomicAdd(&st->evaluated, s_cnt[0]);
-        if (s_cnt[1]) atomicAdd(&st->skipped, s_cnt[1]);
-        if (s_cnt[2]) atomicAdd(&st->rechecked, s_cnt[2]);
-        if (s_cnt[3]) atomicAdd(&st->changed, s_cnt[3]);
-        if (s_cnt[4]) atomicAdd(&st->cand_evals, s_cnt[4]);
-        if (overflow) atomicAdd(&st->overflow_tiles, 1ULL);
+    if (tid < 5 && s_cnt[tid]) {
+        unsigned long long* slot = r.cnt + (int64_t)(tile % kCntSlots) * kCntWords;
+        atomicAdd(slot + tid, s_cnt[tid]);
+    }
+    if (tid == 0 && hd.overflow) {
+        unsigned long long* slot = r.cnt + (int64_t)(tile % kCntSlots) * kCntWords;
+        atomicAdd(slot + kCntOverflow, 1ULL);
     }
 }
 
@@ -542,6 +621,20 @@ hipError_t launch_supercand(const RunDev& r, hipStream_t s)
         k_supercand<2><<<r.nsuper, kBlock, 0, s>>>(r);
     else
         k_supercand<3><<<r.nsuper, kBlock, 0, s>>>(r);
+    return hipGetLastError();
+}
+
+hipError_t launch_tilecand(const RunDev& r, hipStream_t s)
+{
+    const unsigned g = (unsigned)((r.ntiles + kBlock / kWave - 1) / (kBlock / kWave));
+    const bool f32 = r.precision == BKM_PREC_F32_RECHECK;
+    if (r.d == 2) {
+        if (f32) k_tilecand<2, BKM_PREC_F32_RECHECK><<<g, kBlock, 0, s>>>(r);
+        else k_tilecand<2, BKM_PREC_F64><<<g, kBlock, 0, s>>>(r);
+    } else {
+        if (f32) k_tilecand<3, BKM_PREC_F32_RECHECK><<<g, kBlock, 0, s>>>(r);
+        else k_tilecand<3, BKM_PREC_F64><<<g, kBlock, 0, s>>>(r);
+    }
     return hipGetLastError();
 }
 

@@ -75,6 +75,7 @@ __global__ __launch_bounds__(1024) void k_balance(RunDev r)
             const double in = io * f;
             r.I[c] = in;
             r.clus[c].y = 1.0 / in;
+            r.clus32[c].y = f32_up(1.0 / in);
             m = fmin(m, io / in);
         }
         mu = block_reduce_1024(m, sh, OpMin());
@@ -96,58 +97,164 @@ __global__ __launch_bounds__(1024) void k_balance(RunDev r)
     }
 }
 
-// Exact bounding box of every block under the round's final assignment.  A
-// 64-point group whose points all sit in one block contributes its stored
-// group box; a mixed group reads its coordinates.
+// Coordinate sums and exact bounding boxes of every block under the round's
+// final assignment (the weighted means of Alg. 2 and the beta of the erosion,
+// Sec. 4.2).  Each block covers kPassGroups 64-point groups.  A group whose
+// points all sit in one block contributes its precomputed fixed-point sums
+// and box; a mixed group reads its coordinates and reduces every run of equal
+// blocks with a segmented wave scan.  Contributions meet in an LDS hash table
+// keyed by block, and each distinct block costs one set of global atomics
+// per pass block.  Integer sums and min/max are order-independent, so the
+// result does not depend on scheduling.
+constexpr int kPassGroups = 64;
+constexpr int kHashSlots = 256;
+constexpr int kPassBatch = 8;
+
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_block_boxes(RunDev r)
+struct PassTable {
+    int key[kHashSlots];
+    unsigned long long val[kHashSlots][4 * D];   // 2D sums (two's complement), D min, D max (encoded)
+};
+
+// Slot of `key` in the table (inserted if new), or -1 when the table is full.
+template <int D>
+__device__ inline int pass_slot(PassTable<D>& t, int key)
+{
+    int slot = (int)(((unsigned)key * 2654435761u) >> 24) & (kHashSlots - 1);
+    for (int probe = 0; probe < kHashSlots; ++probe) {
+        const int old = atomicCAS(&t.key[slot], -1, key);
+        if (old == -1 || old == key) return slot;
+        slot = (slot + 1) & (kHashSlots - 1);
+    }
+    return -1;
+}
+
+// Value v (index j of the 4D entry values) into slot, or straight into the
+// global arrays when the table is full.
+template <int D>
+__device__ inline void pass_add(PassTable<D>& t, const RunDev& r, int slot, int key, int j,
+                                unsigned long long v)
+{
+    if (slot >= 0) {
+        if (j < 2 * D) atomicAdd(&t.val[slot][j], v);
+        else if (j < 3 * D) atomicMin(&t.val[slot][j], v);
+        else atomicMax(&t.val[slot][j], v);
+    } else {
+        if (j < 2 * D) atomicAdd((unsigned long long*)(r.acc + (int64_t)key * kAcc + j), v);
+        else if (j < 3 * D) atomicMin(r.bb + (int64_t)key * 2 * D + (j - 2 * D), v);
+        else atomicMax(r.bb + (int64_t)key * 2 * D + (j - 2 * D), v);
+    }
+}
+
+template <int D, bool WEIGHTED>
+__global__ __launch_bounds__(kBlock) void k_round_pass(RunDev r)
 {
     const DevState* st = r.st;
     if (st->done || !st->round_done) return;
-    const int lane = threadIdx.x % kWave;
-    const int64_t gstride = (int64_t)gridDim.x * (kBlock / kWave);
-    for (int64_t g = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-         g * kWave < r.n; g += gstride) {
-        const int64_t p = g * kWave + lane;
-        const bool valid = p < r.n;
-        const int a = valid ? r.A[p] : -1;
-        const int a0 = __shfl(a, 0, kWave);
-        const bool uniform = __ballot(valid && a != a0) == 0ULL;
-        if (uniform) {
-            if (lane < 2 * D && a0 >= 0) {
-                const double v = r.gbox[g * 2 * D + lane];
-                unsigned long long* dst = r.bb + (int64_t)a0 * 2 * D + lane;
-                if (lane < D)
-                    atomicMin(dst, enc_ord(v));
-                else
-                    atomicMax(dst, enc_ord(v));
-            }
-            continue;
-        }
-        double xv[D];
+    __shared__ PassTable<D> tab;
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    for (int i = tid; i < kHashSlots; i += kBlock) {
+        tab.key[i] = -1;
 #pragma unroll
-        for (int j = 0; j < D; ++j)
-            xv[j] = valid ? (r.in_f32 ? (double)r.xs32[j][p] : r.xs64[j][p]) : 0.0;
-        unsigned long long pend = __ballot(valid);
-        while (pend) {
-            const int leader = __builtin_ctzll(pend);
-            const int key = __shfl(a, leader, kWave);
-            const bool mine = valid && a == key;
+        for (int j = 0; j < 4 * D; ++j) tab.val[i][j] = j < 3 * D && j >= 2 * D ? ~0ULL : 0ULL;
+    }
+    __syncthreads();
+    double lov[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) lov[j] = st->lo[j];
+    const double sxs = st->sx_scale;
+    const int64_t g0 = (int64_t)blockIdx.x * kPassGroups;
+    const int64_t g1 = min((int64_t)r.ngroups, g0 + kPassGroups);
+    constexpr int kWaves = kBlock / kWave;
+    for (int64_t gb = g0 + wv; gb < g1; gb += kWaves * kPassBatch) {
+        // block ids of a batch of groups first, so their loads overlap
+        int av[kPassBatch];
+#pragma unroll
+        for (int u = 0; u < kPassBatch; ++u) {
+            const int64_t g = gb + (int64_t)u * kWaves;
+            av[u] = g < g1 ? r.A[g * kWave + lane] : kPad;
+        }
+#pragma unroll
+        for (int u = 0; u < kPassBatch; ++u) {
+            const int64_t g = gb + (int64_t)u * kWaves;
+            if (g >= g1) break;
+            const int a = av[u];
+            const int a0 = __shfl(a, 0, kWave);
+            if (__ballot(a != a0) == 0ULL) {
+                if (a0 < 0) continue;
+                int slot = 0;
+                if (lane == 0) slot = pass_slot<D>(tab, a0);
+                slot = __shfl(slot, 0, kWave);
+                if (lane < 4 * D) {
+                    unsigned long long v;
+                    if (lane < 2 * D)
+                        v = (unsigned long long)r.gsum[g * 2 * D + lane];
+                    else
+                        v = enc_ord(r.gbox[g * 2 * D + (lane - 2 * D)]);
+                    pass_add<D>(tab, r, slot, a0, lane, v);
+                }
+                continue;
+            }
+            // mixed group: exact per-point terms, reduced per run of equal blocks
+            const int64_t p = g * kWave + lane;
+            const bool real = a >= 0;
+            double xv[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) xv[j] = r.in_f32 ? (double)r.xs32[j][p] : r.xs64[j][p];
+            long long t[2 * D];
+            coord_terms<D>(xv, lov, WEIGHTED ? (real ? r.ws[p] : 0.0) : 1.0, WEIGHTED, sxs, t);
             double mn[D], mx[D];
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                mn[j] = wave_min_d(mine ? xv[j] : INFINITY);
-                mx[j] = wave_max_d(mine ? xv[j] : -INFINITY);
+                mn[j] = real ? xv[j] : INFINITY;
+                mx[j] = real ? xv[j] : -INFINITY;
+                t[2 * j] = real ? t[2 * j] : 0;
+                t[2 * j + 1] = real ? t[2 * j + 1] : 0;
             }
-            if (lane == leader && key >= 0) {
-                unsigned long long* dst = r.bb + (int64_t)key * 2 * D;
+            const int up = __shfl_up(a, 1, kWave);
+            const bool head = lane == 0 || a != up;
+            const unsigned long long hm = __ballot(head);
+            const int start = 63 - __clzll(hm & ((2ULL << lane) - 1ULL));
+            for (int off = 1; off < kWave; off <<= 1) {
+                const bool take = lane - off >= start;
+#pragma unroll
+                for (int j = 0; j < 2 * D; ++j) {
+                    const long long o = __shfl_up(t[j], off, kWave);
+                    t[j] = take ? t[j] + o : t[j];
+                }
 #pragma unroll
                 for (int j = 0; j < D; ++j) {
-                    atomicMin(dst + j, enc_ord(mn[j]));
-                    atomicMax(dst + D + j, enc_ord(mx[j]));
+                    const double omn = __shfl_up(mn[j], off, kWave);
+                    const double omx = __shfl_up(mx[j], off, kWave);
+                    mn[j] = take ? fmin(mn[j], omn) : mn[j];
+                    mx[j] = take ? fmax(mx[j], omx) : mx[j];
                 }
             }
-            pend &= ~__ballot(mine);
+            const bool tail = lane == kWave - 1 || ((hm >> (lane + 1)) & 1ULL);
+            if (tail && real) {
+                const int slot = pass_slot<D>(tab, a);
+#pragma unroll
+                for (int j = 0; j < 2 * D; ++j) pass_add<D>(tab, r, slot, a, j, (unsigned long long)t[j]);
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    pass_add<D>(tab, r, slot, a, 2 * D + j, enc_ord(mn[j]));
+                    pass_add<D>(tab, r, slot, a, 3 * D + j, enc_ord(mx[j]));
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < kHashSlots; i += kBlock) {
+        const int key = tab.key[i];
+        if (key < 0) continue;
+        unsigned long long* sums = (unsigned long long*)(r.acc + (int64_t)key * kAcc);
+        unsigned long long* box = r.bb + (int64_t)key * 2 * D;
+#pragma unroll
+        for (int j = 0; j < 2 * D; ++j) atomicAdd(sums + j, tab.val[i][j]);
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            atomicMin(box + j, tab.val[i][2 * D + j]);
+            atomicMax(box + D + j, tab.val[i][3 * D + j]);
         }
     }
 }
@@ -211,6 +318,7 @@ __global__ __launch_bounds__(1024) void k_move(RunDev r, double* delta)
             r.I[c] = in;
             const double dacc = (r.clus[c].x + dl) * kUp;
             r.clus[c] = make_double2(dacc, 1.0 / in);
+            r.clus32[c] = make_float2(f32_up(dacc), f32_up(1.0 / in));
             m = fmin(m, io / in);
             e = fmax(e, dl / in);
         }
@@ -234,8 +342,10 @@ __global__ __launch_bounds__(1024) void k_move(RunDev r, double* delta)
         st->round_done = 0;
         st->sweep_in_round = 0;
     }
-    for (int i = threadIdx.x; i < k * 2 * D; i += 1024)
+    for (int i = threadIdx.x; i < k * 2 * D; i += 1024) {
         r.bb[i] = (i % (2 * D)) < D ? ~0ULL : 0ULL;
+        r.acc[(int64_t)(i / (2 * D)) * kAcc + i % (2 * D)] = 0;
+    }
 }
 
 // Fresh run state: influence 1, no assignment, empty sums, open bounds.
@@ -243,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_init_points(RunDev r)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= r.npad) return;
-    r.A[i] = -1;
+    r.A[i] = r.perm[i] >= 0 ? -1 : kPad;
     r.ubt[i] = INFINITY;
     r.lbt[i] = 0.0f;
 }
@@ -254,11 +364,13 @@ __global__ __launch_bounds__(kBlock) void k_init_clusters(RunDev r, const double
 {
     const int c = blockIdx.x * kBlock + threadIdx.x;
     const int D = r.d;
+    if (c < kCntSlots * kCntWords) r.cnt[c] = 0;
     if (c < r.k) {
         if (cinit)
             for (int j = 0; j < D; ++j) r.C[(int64_t)j * r.k + c] = cinit[(int64_t)c * D + j];
         r.I[c] = 1.0;
         r.clus[c] = make_double2(0.0, 1.0);
+        r.clus32[c] = make_float2(0.0f, 1.0f);
         for (int a = 0; a < kAcc; ++a) r.acc[(int64_t)c * kAcc + a] = 0;
         for (int j = 0; j < 2 * D; ++j) r.bb[(int64_t)c * 2 * D + j] = j < D ? ~0ULL : 0ULL;
     }
@@ -284,8 +396,6 @@ __global__ __launch_bounds__(kBlock) void k_init_clusters(RunDev r, const double
         }
         st->target = W / (double)r.k;
         st->delta_threshold = dthr < 0.0 ? 1e-5 * st->ext : dthr;
-        st->evaluated = st->skipped = st->rechecked = st->changed = 0;
-        st->cand_evals = st->overflow_tiles = 0;
     }
 }
 
@@ -315,6 +425,7 @@ __global__ __launch_bounds__(1024) void k_set_step(RunDev r, const double* crm,
         r.I[c] = in;
         const double dacc = first ? 0.0 : (r.clus[c].x + dl) * kUp;
         r.clus[c] = make_double2(dacc, 1.0 / in);
+        r.clus32[c] = make_float2(f32_up(dacc), f32_up(1.0 / in));
         m = fmin(m, io / in);
         e = fmax(e, dl / in);
     }
@@ -337,7 +448,10 @@ __global__ __launch_bounds__(1024) void k_set_step(RunDev r, const double* crm,
 __global__ __launch_bounds__(kBlock) void k_scatter_back(RunDev r, int32_t* out)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < r.n) out[r.perm[i]] = r.A[i];
+    if (i < r.npad) {
+        const int32_t src = r.perm[i];
+        if (src >= 0) out[src] = r.A[i];
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_cluster_out(RunDev r, double* cout, double* iout,
@@ -508,7 +622,7 @@ hipError_t launch_init_run(const RunDev& r, const double* cinit, int max_iter,
                            int max_balance_iter, double eps, double dthr, hipStream_t s)
 {
     k_init_points<<<nblocks(r.npad, kBlock), kBlock, 0, s>>>(r);
-    k_init_clusters<<<nblocks(r.k, kBlock), kBlock, 0, s>>>(r, cinit, max_iter,
+    k_init_clusters<<<nblocks(std::max(r.k, kCntSlots * kCntWords), kBlock), kBlock, 0, s>>>(r, cinit, max_iter,
                                                             max_balance_iter, eps, dthr);
     return hipGetLastError();
 }
@@ -524,12 +638,14 @@ hipError_t launch_balance(const RunDev& r, hipStream_t s)
 
 hipError_t launch_block_boxes(const RunDev& r, hipStream_t s)
 {
-    const int64_t groups = (r.n + kWave - 1) / kWave;
-    const unsigned g = (unsigned)std::min<int64_t>((groups + 3) / 4, 8192);
-    if (r.d == 2)
-        k_block_boxes<2><<<g, kBlock, 0, s>>>(r);
-    else
-        k_block_boxes<3><<<g, kBlock, 0, s>>>(r);
+    const unsigned g = (unsigned)((r.ngroups + kPassGroups - 1) / kPassGroups);
+    if (r.d == 2) {
+        if (r.weighted) k_round_pass<2, true><<<g, kBlock, 0, s>>>(r);
+        else k_round_pass<2, false><<<g, kBlock, 0, s>>>(r);
+    } else {
+        if (r.weighted) k_round_pass<3, true><<<g, kBlock, 0, s>>>(r);
+        else k_round_pass<3, false><<<g, kBlock, 0, s>>>(r);
+    }
     return hipGetLastError();
 }
 
@@ -555,7 +671,7 @@ hipError_t launch_set_step(const RunDev& r, const double* crm, const double* inf
 hipError_t launch_finish(const RunDev& r, int32_t* asg, double* cout, double* iout,
                          double* bwout, hipStream_t s)
 {
-    if (asg) k_scatter_back<<<nblocks(r.n, kBlock), kBlock, 0, s>>>(r, asg);
+    if (asg) k_scatter_back<<<nblocks(r.npad, kBlock), kBlock, 0, s>>>(r, asg);
     k_cluster_out<<<nblocks(r.k, kBlock), kBlock, 0, s>>>(r, cout, iout, bwout);
     return hipGetLastError();
 }

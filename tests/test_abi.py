@@ -42,7 +42,7 @@ def test_every_declared_symbol_is_exported(bkm):
 def test_struct_layouts_match_header(bkm):
     assert C.sizeof(bkm.Points) == 48
     assert C.sizeof(bkm.Params) == 64
-    assert C.sizeof(bkm.Info) == 136
+    assert C.sizeof(bkm.Info) == 144
     assert C.sizeof(bkm.Stats) == 32
 
 

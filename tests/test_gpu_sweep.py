@@ -107,3 +107,18 @@ def test_sweep_duplicate_points_and_centers():
         Ao, _, _ = oracle.assign(X, C, Is[0])
         assert np.array_equal(A[0].cpu().numpy(), Ao)
         assert not np.any(A[0].cpu().numpy() == 7)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_sweep_far_apart_clusters(d):
+    """Clusters separated by empty space: the Hilbert order jumps between
+    them; tiles are realigned at the jumps, so no tile gets a huge box and
+    the candidate lists stay short."""
+    rng = np.random.default_rng(40 + d)
+    n = 90001
+    offs = np.array([[0.0] * d, [9.0] + [0.0] * (d - 1), [0.0, 7.0] + [0.0] * (d - 2)])
+    lab = rng.integers(0, 3, n)
+    X = [rng.random(n) + offs[lab, j] for j in range(d)]
+    for prec in ("f64", "f32_recheck"):
+        info = run_and_compare(X, 60, prec, True, 1024, steps=4, seed=d)
+        assert info["overflow_tiles"] == 0
