@@ -112,6 +112,9 @@ struct RunDev {
     double2* clus;            // [k] (accumulated movement, 1/influence)
     float2* clus32;           // [k] the same rounded up to FP32, for the Hamerly test
     long long* gsum;          // [ngroups][2d] fixed-point coordinate sums of each 64-point group
+    int32_t* gblk;            // [ngroups] block of every point of the group after the last
+                              // sweep; -1 if they may differ (always when a point of the
+                              // group changed block in it); kPad if all padding
     long long* acc;           // [k][kAcc] fixed-point block sums
     unsigned long long* bb;   // [k][2d] encoded block boxes (min..., max...)
     DevState* st;

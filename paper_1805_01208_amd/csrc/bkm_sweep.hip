@@ -303,6 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(RunDev r)
     constexpr int T = kBlock * PPT;
     __shared__ int s_off[T];      // tile offsets of the points to evaluate
     __shared__ int s_aold[T];     // and their current block
+    __shared__ int s_gflag[T / kWave];  // per 64-point group: common block, or -1
     __shared__ float4 s_q[kTileCap];
     __shared__ int s_cid[kTileCap];
     __shared__ double s_c64[F32 ? 1 : 4][F32 ? 1 : kTileCap];
@@ -381,6 +382,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep(RunDev r)
             s_aold[pos] = aold[q];
             ++n_eval;
         }
+        // the wave holds one whole 64-point group here: its common block
+        const int a0 = __shfl(aold[q], 0, kWave);
+        const bool same = __ballot(aold[q] != a0) == 0ULL;
+        if (lane == 0) s_gflag[q * (kBlock / kWave) + tid / kWave] = same ? a0 : -1;
     }
     __syncthreads();
     const int nl = s_nl;
@@ -536,6 +541,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(RunDev r)
                 chg = true;
                 ++n_chg;
                 r.A[p] = cbest;
+                s_gflag[off / kWave] = -1;   // conservatively mixed from now on
                 if (WEIGHTED) fix_split(r.ws[p] * wsc, wh, wl);
             }
         }
@@ -579,6 +585,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep(RunDev r)
             if (cv[j]) atomicAdd(&s_cnt[j], cv[j]);
     }
     __syncthreads();
+    // per 64-point group: the common block of its points (or -1, also when a
+    // point of it changed block in this sweep), for the round-end pass
+    if (tid < T / kWave) r.gblk[base / kWave + tid] = s_gflag[tid];
     if (tid < 5 && s_cnt[tid]) {
         unsigned long long* slot = r.cnt + (int64_t)(tile % kCntSlots) * kCntWords;
         atomicAdd(slot + tid, s_cnt[tid]);

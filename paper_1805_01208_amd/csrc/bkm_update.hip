@@ -99,16 +99,18 @@ __global__ __launch_bounds__(1024) void k_balance(RunDev r)
 
 // Coordinate sums and exact bounding boxes of every block under the round's
 // final assignment (the weighted means of Alg. 2 and the beta of the erosion,
-// Sec. 4.2).  Each block covers kPassGroups 64-point groups.  A group whose
-// points all sit in one block contributes its precomputed fixed-point sums
-// and box; a mixed group reads its coordinates and reduces every run of equal
-// blocks with a segmented wave scan.  Contributions meet in an LDS hash table
-// keyed by block, and each distinct block costs one set of global atomics
-// per pass block.  Integer sums and min/max are order-independent, so the
-// result does not depend on scheduling.
-constexpr int kPassGroups = 64;
+// Sec. 4.2).  A pass block covers kPassGroups consecutive 64-point groups.
+// The last sweep recorded, per group, the block shared by all its points (or
+// -1): those groups contribute their precomputed fixed-point sums and boxes,
+// one lane per group, reduced over runs of consecutive groups with the same
+// block.  Mixed groups read their coordinates, a wave per group, and reduce
+// every run of equal blocks with a segmented wave scan.  Contributions meet in
+// an LDS hash table keyed by block, and each distinct block costs one set of
+// global atomics per pass block.  Integer sums and min/max are
+// order-independent, so the result does not depend on scheduling.
+constexpr int kPassGroups = kBlock;      // one group per thread in the uniform step
 constexpr int kHashSlots = 256;
-constexpr int kPassBatch = 8;
+constexpr int kMixBatch = 4;             // mixed groups a wave has in flight
 
 template <int D>
 struct PassTable {
@@ -129,8 +131,8 @@ __device__ inline int pass_slot(PassTable<D>& t, int key)
     return -1;
 }
 
-// Value v (index j of the 4D entry values) into slot, or straight into the
-// global arrays when the table is full.
+// Entry value j (0..2D-1 sums, then D minima, D maxima) into the table, or
+// straight into the global arrays when the table is full.
 template <int D>
 __device__ inline void pass_add(PassTable<D>& t, const RunDev& r, int slot, int key, int j,
                                 unsigned long long v)
@@ -146,101 +148,165 @@ __device__ inline void pass_add(PassTable<D>& t, const RunDev& r, int slot, int 
     }
 }
 
+// Lane-shift of a 64-bit value by the data-parallel-primitive network of the
+// wave (row shifts within rows of 16 lanes, then the row-15 and row-31
+// broadcasts); lanes the pattern does not feed get 0 and must not use it.
+template <int CTRL, int ROWS>
+__device__ inline unsigned long long dpp_u64(unsigned long long v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, ROWS, 0xf, false);
+    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+template <int D, int CTRL, int ROWS>
+__device__ inline void run_step(bool take, long long* t, double* mn, double* mx)
+{
+#pragma unroll
+    for (int j = 0; j < 2 * D; ++j) {
+        const long long o = (long long)dpp_u64<CTRL, ROWS>((unsigned long long)t[j]);
+        t[j] = take ? t[j] + o : t[j];
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        const double omn = __longlong_as_double((long long)dpp_u64<CTRL, ROWS>(
+            (unsigned long long)__double_as_longlong(mn[j])));
+        const double omx = __longlong_as_double((long long)dpp_u64<CTRL, ROWS>(
+            (unsigned long long)__double_as_longlong(mx[j])));
+        mn[j] = take ? fmin(mn[j], omn) : mn[j];
+        mx[j] = take ? fmax(mx[j], omx) : mx[j];
+    }
+}
+
+// Segmented inclusive reduction over runs of equal `key` across the wave's
+// lanes; afterwards the last lane of every run holds the run's totals.
+// Returns true on those lanes.  A lane folds in the value of a source lane
+// only when that source lies in its own run (source index >= run start).
+template <int D>
+__device__ inline bool run_reduce(int key, long long* t, double* mn, double* mx)
+{
+    const int lane = threadIdx.x % kWave;
+    const int up = __shfl_up(key, 1, kWave);
+    const bool head = lane == 0 || key != up;
+    const unsigned long long hm = __ballot(head);
+    const int start = 63 - __clzll(hm & ((2ULL << lane) - 1ULL));
+    const int rl = lane & 15, row = lane >> 4;
+    run_step<D, 0x111, 0xf>(rl >= 1 && lane - 1 >= start, t, mn, mx);     // row_shr:1
+    run_step<D, 0x112, 0xf>(rl >= 2 && lane - 2 >= start, t, mn, mx);     // row_shr:2
+    run_step<D, 0x114, 0xf>(rl >= 4 && lane - 4 >= start, t, mn, mx);     // row_shr:4
+    run_step<D, 0x118, 0xf>(rl >= 8 && lane - 8 >= start, t, mn, mx);     // row_shr:8
+    run_step<D, 0x142, 0xa>((row & 1) && row * 16 - 1 >= start, t, mn, mx);  // row_bcast:15
+    run_step<D, 0x143, 0xc>(row >= 2 && 31 >= start, t, mn, mx);          // row_bcast:31
+    return lane == kWave - 1 || ((hm >> (lane + 1)) & 1ULL);
+}
+
+template <int D>
+__device__ inline void run_insert(PassTable<D>& tab, const RunDev& r, int key, const long long* t,
+                                  const double* mn, const double* mx)
+{
+    const int slot = pass_slot<D>(tab, key);
+#pragma unroll
+    for (int j = 0; j < 2 * D; ++j) pass_add<D>(tab, r, slot, key, j, (unsigned long long)t[j]);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        pass_add<D>(tab, r, slot, key, 2 * D + j, enc_ord(mn[j]));
+        pass_add<D>(tab, r, slot, key, 3 * D + j, enc_ord(mx[j]));
+    }
+}
+
 template <int D, bool WEIGHTED>
 __global__ __launch_bounds__(kBlock) void k_round_pass(RunDev r)
 {
     const DevState* st = r.st;
     if (st->done || !st->round_done) return;
     __shared__ PassTable<D> tab;
+    __shared__ int s_mix[kPassGroups];
+    __shared__ int s_nmix;
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     for (int i = tid; i < kHashSlots; i += kBlock) {
         tab.key[i] = -1;
 #pragma unroll
         for (int j = 0; j < 4 * D; ++j) tab.val[i][j] = j < 3 * D && j >= 2 * D ? ~0ULL : 0ULL;
     }
+    if (tid == 0) s_nmix = 0;
     __syncthreads();
+
+    // uniform groups: one lane per group
+    const int64_t g = (int64_t)blockIdx.x * kPassGroups + tid;
+    const int f = g < r.ngroups ? r.gblk[g] : kPad;
+    {
+        long long t[2 * D];
+        double mn[D], mx[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            t[2 * j] = t[2 * j + 1] = 0;
+            mn[j] = INFINITY;
+            mx[j] = -INFINITY;
+        }
+        if (f >= 0) {
+#pragma unroll
+            for (int j = 0; j < 2 * D; ++j) t[j] = r.gsum[g * 2 * D + j];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                mn[j] = r.gbox[g * 2 * D + j];
+                mx[j] = r.gbox[g * 2 * D + D + j];
+            }
+        }
+        const bool tail = run_reduce<D>(f, t, mn, mx);
+        if (tail && f >= 0) run_insert<D>(tab, r, f, t, mn, mx);
+    }
+    // mixed groups of this pass block, in order
+    {
+        const bool mixed = f == -1;
+        const unsigned long long b = __ballot(mixed);
+        int pos = 0;
+        if (lane == 0 && b) pos = atomicAdd(&s_nmix, (int)__popcll(b));
+        pos = __shfl(pos, 0, kWave) + (int)__popcll(b & ((1ULL << lane) - 1ULL));
+        if (mixed) s_mix[pos] = (int)(g - (int64_t)blockIdx.x * kPassGroups);
+    }
+    __syncthreads();
+    const int nmix = s_nmix;
     double lov[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) lov[j] = st->lo[j];
     const double sxs = st->sx_scale;
-    const int64_t g0 = (int64_t)blockIdx.x * kPassGroups;
-    const int64_t g1 = min((int64_t)r.ngroups, g0 + kPassGroups);
     constexpr int kWaves = kBlock / kWave;
-    for (int64_t gb = g0 + wv; gb < g1; gb += kWaves * kPassBatch) {
-        // block ids of a batch of groups first, so their loads overlap
-        int av[kPassBatch];
+    for (int m0 = wv * kMixBatch; m0 < nmix; m0 += kWaves * kMixBatch) {
+        // loads of a batch of mixed groups first, so their latencies overlap
+        int av[kMixBatch];
+        double xv[kMixBatch][D];
+        double wv8[kMixBatch];
 #pragma unroll
-        for (int u = 0; u < kPassBatch; ++u) {
-            const int64_t g = gb + (int64_t)u * kWaves;
-            av[u] = g < g1 ? r.A[g * kWave + lane] : kPad;
+        for (int u = 0; u < kMixBatch; ++u) {
+            av[u] = kPad;
+            wv8[u] = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) xv[u][j] = 0.0;
+            if (m0 + u < nmix) {
+                const int64_t p = ((int64_t)blockIdx.x * kPassGroups + s_mix[m0 + u]) * kWave + lane;
+                av[u] = r.A[p];
+#pragma unroll
+                for (int j = 0; j < D; ++j) xv[u][j] = r.in_f32 ? (double)r.xs32[j][p] : r.xs64[j][p];
+                if (WEIGHTED) wv8[u] = r.ws[p];
+            }
         }
 #pragma unroll
-        for (int u = 0; u < kPassBatch; ++u) {
-            const int64_t g = gb + (int64_t)u * kWaves;
-            if (g >= g1) break;
+        for (int u = 0; u < kMixBatch; ++u) {
+            if (m0 + u >= nmix) break;
             const int a = av[u];
-            const int a0 = __shfl(a, 0, kWave);
-            if (__ballot(a != a0) == 0ULL) {
-                if (a0 < 0) continue;
-                int slot = 0;
-                if (lane == 0) slot = pass_slot<D>(tab, a0);
-                slot = __shfl(slot, 0, kWave);
-                if (lane < 4 * D) {
-                    unsigned long long v;
-                    if (lane < 2 * D)
-                        v = (unsigned long long)r.gsum[g * 2 * D + lane];
-                    else
-                        v = enc_ord(r.gbox[g * 2 * D + (lane - 2 * D)]);
-                    pass_add<D>(tab, r, slot, a0, lane, v);
-                }
-                continue;
-            }
-            // mixed group: exact per-point terms, reduced per run of equal blocks
-            const int64_t p = g * kWave + lane;
             const bool real = a >= 0;
-            double xv[D];
-#pragma unroll
-            for (int j = 0; j < D; ++j) xv[j] = r.in_f32 ? (double)r.xs32[j][p] : r.xs64[j][p];
             long long t[2 * D];
-            coord_terms<D>(xv, lov, WEIGHTED ? (real ? r.ws[p] : 0.0) : 1.0, WEIGHTED, sxs, t);
+            coord_terms<D>(xv[u], lov, real ? wv8[u] : 0.0, WEIGHTED, sxs, t);
             double mn[D], mx[D];
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                mn[j] = real ? xv[j] : INFINITY;
-                mx[j] = real ? xv[j] : -INFINITY;
+                mn[j] = real ? xv[u][j] : INFINITY;
+                mx[j] = real ? xv[u][j] : -INFINITY;
                 t[2 * j] = real ? t[2 * j] : 0;
                 t[2 * j + 1] = real ? t[2 * j + 1] : 0;
             }
-            const int up = __shfl_up(a, 1, kWave);
-            const bool head = lane == 0 || a != up;
-            const unsigned long long hm = __ballot(head);
-            const int start = 63 - __clzll(hm & ((2ULL << lane) - 1ULL));
-            for (int off = 1; off < kWave; off <<= 1) {
-                const bool take = lane - off >= start;
-#pragma unroll
-                for (int j = 0; j < 2 * D; ++j) {
-                    const long long o = __shfl_up(t[j], off, kWave);
-                    t[j] = take ? t[j] + o : t[j];
-                }
-#pragma unroll
-                for (int j = 0; j < D; ++j) {
-                    const double omn = __shfl_up(mn[j], off, kWave);
-                    const double omx = __shfl_up(mx[j], off, kWave);
-                    mn[j] = take ? fmin(mn[j], omn) : mn[j];
-                    mx[j] = take ? fmax(mx[j], omx) : mx[j];
-                }
-            }
-            const bool tail = lane == kWave - 1 || ((hm >> (lane + 1)) & 1ULL);
-            if (tail && real) {
-                const int slot = pass_slot<D>(tab, a);
-#pragma unroll
-                for (int j = 0; j < 2 * D; ++j) pass_add<D>(tab, r, slot, a, j, (unsigned long long)t[j]);
-#pragma unroll
-                for (int j = 0; j < D; ++j) {
-                    pass_add<D>(tab, r, slot, a, 2 * D + j, enc_ord(mn[j]));
-                    pass_add<D>(tab, r, slot, a, 3 * D + j, enc_ord(mx[j]));
-                }
-            }
+            const bool tail = run_reduce<D>(a, t, mn, mx);
+            if (tail && real) run_insert<D>(tab, r, a, t, mn, mx);
         }
     }
     __syncthreads();
