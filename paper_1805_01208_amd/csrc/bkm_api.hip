@@ -210,8 +210,9 @@ size_t layout(RunDev& r, Arena* a, bool full)
         both((double*)nullptr, (size_t)k, r.I);
         both((double2*)nullptr, (size_t)k, r.clus);
         both((float2*)nullptr, (size_t)k, r.clus32);
-        both((long long*)nullptr, (size_t)(np / kWave) * 2 * d, r.gsum);
         both((int32_t*)nullptr, (size_t)(np / kWave), r.gblk);
+        both((int32_t*)nullptr, (size_t)(np / kWave), r.gdirty);
+        both((int32_t*)nullptr, np, r.Aprev);
         both((long long*)nullptr, (size_t)k * kAcc, r.acc);
         both((unsigned long long*)nullptr, (size_t)k * 2 * d, r.bb);
     }

@@ -111,7 +111,8 @@ struct RunDev {
     double* I;                // [k] influence
     double2* clus;            // [k] (accumulated movement, 1/influence)
     float2* clus32;           // [k] the same rounded up to FP32, for the Hamerly test
-    long long* gsum;          // [ngroups][2d] fixed-point coordinate sums of each 64-point group
+    int32_t* Aprev;           // [npad] block of each point at the previous round end
+    int32_t* gdirty;          // [ngroups] 1 if a point of the group changed block in this round
     int32_t* gblk;            // [ngroups] block of every point of the group after the last
                               // sweep; -1 if they may differ (always when a point of the
                               // group changed block in it); kPad if all padding
@@ -219,6 +220,36 @@ __device__ inline long long wave_sum_ll(long long v)
 {
     for (int m = kWave / 2; m > 0; m >>= 1) v += shfl_xor_ll(v, m);
     return v;
+}
+
+// Lane-shift of a 64-bit value through the data-parallel-primitive network
+// (row shifts within rows of 16 lanes, then the row-15 and row-31
+// broadcasts); lanes the pattern does not feed get 0 and must not use it.
+template <int CTRL, int ROWS>
+__device__ inline unsigned long long dpp_u64(unsigned long long v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, ROWS, 0xf, false);
+    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+// Sum of a 64-bit integer over the wave, returned on every lane: an
+// inclusive scan through the shift network (VALU only, no LDS), whose last
+// lane holds the total.
+__device__ inline long long wave_sum_dpp(long long v)
+{
+    const int lane = threadIdx.x % kWave;
+    const int rl = lane & 15, row = lane >> 4;
+    unsigned long long u = (unsigned long long)v, o;
+    o = dpp_u64<0x111, 0xf>(u); u += rl >= 1 ? o : 0ULL;
+    o = dpp_u64<0x112, 0xf>(u); u += rl >= 2 ? o : 0ULL;
+    o = dpp_u64<0x114, 0xf>(u); u += rl >= 4 ? o : 0ULL;
+    o = dpp_u64<0x118, 0xf>(u); u += rl >= 8 ? o : 0ULL;
+    o = dpp_u64<0x142, 0xa>(u); u += (row & 1) ? o : 0ULL;
+    o = dpp_u64<0x143, 0xc>(u); u += row >= 2 ? o : 0ULL;
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, kWave - 1);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), kWave - 1);
+    return (long long)(((unsigned long long)hi << 32) | lo);
 }
 
 // Fixed-point pair (hi, lo) of a non-negative FP64 value already scaled so

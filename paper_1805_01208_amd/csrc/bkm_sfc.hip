@@ -522,31 +522,13 @@ __global__ __launch_bounds__(kBlock) void k_tile_prep(RunDev r)
             tmn[j] = fmin(tmn[j], gmn[j]);
             tmx[j] = fmax(tmx[j], gmx[j]);
         }
-        // fixed-point coordinate sums of the group's real points
-        long long t[2 * D];
-        {
-            double xv[D], lov[D];
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                xv[j] = xs_at(r, j, i);
-                lov[j] = r.st->lo[j];
-            }
-            const bool real = r.perm[i] >= 0;
-            const double w = (r.ws && real) ? r.ws[i] : 1.0;
-            coord_terms<D>(xv, lov, w, r.ws != nullptr, r.st->sx_scale, t);
-#pragma unroll
-            for (int j = 0; j < 2 * D; ++j) t[j] = wave_sum_ll(real ? t[j] : 0);
-        }
         if (lane == 0) {
             double* gb = r.gbox + (g0 / kWave) * 2 * D;
-            long long* gs = r.gsum + (g0 / kWave) * 2 * D;
 #pragma unroll
             for (int j = 0; j < D; ++j) {
                 gb[j] = gmn[j];
                 gb[D + j] = gmx[j];
             }
-#pragma unroll
-            for (int j = 0; j < 2 * D; ++j) gs[j] = t[j];
         }
     }
     if (lane == 0) {

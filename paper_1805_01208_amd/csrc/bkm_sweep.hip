@@ -304,6 +304,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(RunDev r)
     __shared__ int s_off[T];      // tile offsets of the points to evaluate
     __shared__ int s_aold[T];     // and their current block
     __shared__ int s_gflag[T / kWave];  // per 64-point group: common block, or -1
+    __shared__ int s_gdirty[T / kWave]; // per 64-point group: a point of it changed block
     __shared__ float4 s_q[kTileCap];
     __shared__ int s_cid[kTileCap];
     __shared__ double s_c64[F32 ? 1 : 4][F32 ? 1 : kTileCap];
@@ -318,6 +319,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(RunDev r)
     const double* __restrict__ I = r.I;
     if (tid < 5) s_cnt[tid] = 0;
     if (tid == 0) s_nl = 0;
+    if (tid < T / kWave) s_gdirty[tid] = 0;
 
     // ---- phase 1: block ids and stored bounds (arrays are padded to whole tiles)
     int aold[PPT];
@@ -542,6 +544,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(RunDev r)
                 ++n_chg;
                 r.A[p] = cbest;
                 s_gflag[off / kWave] = -1;   // conservatively mixed from now on
+                s_gdirty[off / kWave] = 1;
                 if (WEIGHTED) fix_split(r.ws[p] * wsc, wh, wl);
             }
         }
@@ -587,7 +590,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep(RunDev r)
     __syncthreads();
     // per 64-point group: the common block of its points (or -1, also when a
     // point of it changed block in this sweep), for the round-end pass
-    if (tid < T / kWave) r.gblk[base / kWave + tid] = s_gflag[tid];
+    if (tid < T / kWave) {
+        r.gblk[base / kWave + tid] = s_gflag[tid];
+        // the round-end pass moves the coordinate sums of these groups' points
+        if (s_gdirty[tid]) r.gdirty[base / kWave + tid] = 1;
+    }
     if (tid < 5 && s_cnt[tid]) {
         unsigned long long* slot = r.cnt + (int64_t)(tile % kCntSlots) * kCntWords;
         atomicAdd(slot + tid, s_cnt[tid]);

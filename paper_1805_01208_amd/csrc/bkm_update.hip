@@ -97,30 +97,37 @@ __global__ __launch_bounds__(1024) void k_balance(RunDev r)
     }
 }
 
-// Coordinate sums and exact bounding boxes of every block under the round's
-// final assignment (the weighted means of Alg. 2 and the beta of the erosion,
-// Sec. 4.2).  A pass block covers kPassGroups consecutive 64-point groups.
-// The last sweep recorded, per group, the block shared by all its points (or
-// -1): those groups contribute their precomputed fixed-point sums and boxes,
-// one lane per group, reduced over runs of consecutive groups with the same
-// block.  Mixed groups read their coordinates, a wave per group, and reduce
-// every run of equal blocks with a segmented wave scan.  Contributions meet in
-// an LDS hash table keyed by block, and each distinct block costs one set of
-// global atomics per pass block.  Integer sums and min/max are
-// order-independent, so the result does not depend on scheduling.
+// Round end (Alg. 2): the block coordinate sums for the new centers and the
+// exact block boxes for beta, the average block diameter of the erosion
+// (Sec. 4.2), under the round's final assignment.  One pass block covers
+// kPassGroups consecutive 64-point groups and meets all its contributions in
+// an LDS table keyed by block, flushed with one set of global atomics per
+// distinct block.
+//   * sums are kept exactly and incrementally: every point remembers its
+//     block at the previous round end, and each group in which a sweep of
+//     this round changed a block (marked by the sweep) moves the
+//     fixed-point coordinate terms of its changed points from the old
+//     block's entry to the new one's;
+//   * boxes are rebuilt: a group whose points share one block (recorded by
+//     the last sweep) contributes its static box, one lane per group,
+//     reduced over runs of equal blocks; the points of mixed groups read
+//     their coordinates and touch the table only when they widen it.
+// Integer sums and min/max of the order-preserving encoding are exact and
+// order-independent, so nothing depends on scheduling.
 constexpr int kPassGroups = kBlock;      // one group per thread in the uniform step
 constexpr int kHashSlots = 256;
-constexpr int kMixBatch = 4;             // mixed groups a wave has in flight
+constexpr int kMixBatch = 4;             // listed groups a wave has in flight
 
 template <int D>
-struct PassTable {
+struct RoundTable {
     int key[kHashSlots];
-    unsigned long long val[kHashSlots][4 * D];   // 2D sums (two's complement), D min, D max (encoded)
+    unsigned long long sum[kHashSlots][2 * D];   // two's complement fixed-point sums
+    unsigned long long box[kHashSlots][2 * D];   // D minima, D maxima (encoded)
 };
 
 // Slot of `key` in the table (inserted if new), or -1 when the table is full.
 template <int D>
-__device__ inline int pass_slot(PassTable<D>& t, int key)
+__device__ inline int table_slot(RoundTable<D>& t, int key)
 {
     int slot = (int)(((unsigned)key * 2654435761u) >> 24) & (kHashSlots - 1);
     for (int probe = 0; probe < kHashSlots; ++probe) {
@@ -131,59 +138,45 @@ __device__ inline int pass_slot(PassTable<D>& t, int key)
     return -1;
 }
 
-// Entry value j (0..2D-1 sums, then D minima, D maxima) into the table, or
-// straight into the global arrays when the table is full.
+// Table slot of every lane's key (lanes with want): one lookup per distinct
+// key of the wave, made by a leader lane and broadcast.
 template <int D>
-__device__ inline void pass_add(PassTable<D>& t, const RunDev& r, int slot, int key, int j,
-                                unsigned long long v)
+__device__ inline int wave_slots(RoundTable<D>& t, int key, bool want)
 {
-    if (slot >= 0) {
-        if (j < 2 * D) atomicAdd(&t.val[slot][j], v);
-        else if (j < 3 * D) atomicMin(&t.val[slot][j], v);
-        else atomicMax(&t.val[slot][j], v);
-    } else {
-        if (j < 2 * D) atomicAdd((unsigned long long*)(r.acc + (int64_t)key * kAcc + j), v);
-        else if (j < 3 * D) atomicMin(r.bb + (int64_t)key * 2 * D + (j - 2 * D), v);
-        else atomicMax(r.bb + (int64_t)key * 2 * D + (j - 2 * D), v);
+    const int lane = threadIdx.x % kWave;
+    unsigned long long pend = __ballot(want);
+    int slot = -1;
+    while (pend) {
+        const int leader = __builtin_ctzll(pend);
+        const int lk = __shfl(key, leader, kWave);
+        int ls = 0;
+        if (lane == leader) ls = table_slot<D>(t, lk);
+        ls = __shfl(ls, leader, kWave);
+        const bool mine = want && key == lk;
+        if (mine) slot = ls;
+        pend &= ~__ballot(mine);
     }
+    return slot;
 }
 
-// Lane-shift of a 64-bit value by the data-parallel-primitive network of the
-// wave (row shifts within rows of 16 lanes, then the row-15 and row-31
-// broadcasts); lanes the pattern does not feed get 0 and must not use it.
-template <int CTRL, int ROWS>
-__device__ inline unsigned long long dpp_u64(unsigned long long v)
+template <int CTRL, int ROWS, int D>
+__device__ inline void box_step(bool take, unsigned long long* mn, unsigned long long* mx)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, ROWS, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, ROWS, 0xf, false);
-    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
-}
-
-template <int D, int CTRL, int ROWS>
-__device__ inline void run_step(bool take, long long* t, double* mn, double* mx)
-{
-#pragma unroll
-    for (int j = 0; j < 2 * D; ++j) {
-        const long long o = (long long)dpp_u64<CTRL, ROWS>((unsigned long long)t[j]);
-        t[j] = take ? t[j] + o : t[j];
-    }
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        const double omn = __longlong_as_double((long long)dpp_u64<CTRL, ROWS>(
-            (unsigned long long)__double_as_longlong(mn[j])));
-        const double omx = __longlong_as_double((long long)dpp_u64<CTRL, ROWS>(
-            (unsigned long long)__double_as_longlong(mx[j])));
-        mn[j] = take ? fmin(mn[j], omn) : mn[j];
-        mx[j] = take ? fmax(mx[j], omx) : mx[j];
+        const unsigned long long omn = dpp_u64<CTRL, ROWS>(mn[j]);
+        const unsigned long long omx = dpp_u64<CTRL, ROWS>(mx[j]);
+        mn[j] = take && omn < mn[j] ? omn : mn[j];
+        mx[j] = take && omx > mx[j] ? omx : mx[j];
     }
 }
 
-// Segmented inclusive reduction over runs of equal `key` across the wave's
-// lanes; afterwards the last lane of every run holds the run's totals.
-// Returns true on those lanes.  A lane folds in the value of a source lane
-// only when that source lies in its own run (source index >= run start).
+// Segmented inclusive min/max over runs of equal `key` across the wave's
+// lanes; afterwards the last lane of every run holds the run's box.  Returns
+// true on those lanes.  A lane folds in a source lane's value only when the
+// source lies in its own run (source index >= run start).
 template <int D>
-__device__ inline bool run_reduce(int key, long long* t, double* mn, double* mx)
+__device__ inline bool run_box(int key, unsigned long long* mn, unsigned long long* mx)
 {
     const int lane = threadIdx.x % kWave;
     const int up = __shfl_up(key, 1, kWave);
@@ -191,122 +184,182 @@ __device__ inline bool run_reduce(int key, long long* t, double* mn, double* mx)
     const unsigned long long hm = __ballot(head);
     const int start = 63 - __clzll(hm & ((2ULL << lane) - 1ULL));
     const int rl = lane & 15, row = lane >> 4;
-    run_step<D, 0x111, 0xf>(rl >= 1 && lane - 1 >= start, t, mn, mx);     // row_shr:1
-    run_step<D, 0x112, 0xf>(rl >= 2 && lane - 2 >= start, t, mn, mx);     // row_shr:2
-    run_step<D, 0x114, 0xf>(rl >= 4 && lane - 4 >= start, t, mn, mx);     // row_shr:4
-    run_step<D, 0x118, 0xf>(rl >= 8 && lane - 8 >= start, t, mn, mx);     // row_shr:8
-    run_step<D, 0x142, 0xa>((row & 1) && row * 16 - 1 >= start, t, mn, mx);  // row_bcast:15
-    run_step<D, 0x143, 0xc>(row >= 2 && 31 >= start, t, mn, mx);          // row_bcast:31
+    box_step<0x111, 0xf, D>(rl >= 1 && lane - 1 >= start, mn, mx);          // row_shr:1
+    box_step<0x112, 0xf, D>(rl >= 2 && lane - 2 >= start, mn, mx);          // row_shr:2
+    box_step<0x114, 0xf, D>(rl >= 4 && lane - 4 >= start, mn, mx);          // row_shr:4
+    box_step<0x118, 0xf, D>(rl >= 8 && lane - 8 >= start, mn, mx);          // row_shr:8
+    box_step<0x142, 0xa, D>((row & 1) && row * 16 - 1 >= start, mn, mx);    // row_bcast:15
+    box_step<0x143, 0xc, D>(row >= 2 && 31 >= start, mn, mx);               // row_bcast:31
     return lane == kWave - 1 || ((hm >> (lane + 1)) & 1ULL);
 }
 
+// Adds sign * v to a slot's sums (or to block c's global sums without a slot).
 template <int D>
-__device__ inline void run_insert(PassTable<D>& tab, const RunDev& r, int key, const long long* t,
-                                  const double* mn, const double* mx)
+__device__ inline void add_sums(RoundTable<D>& t, const RunDev& r, int slot, int c,
+                                const long long* v, long long sign)
 {
-    const int slot = pass_slot<D>(tab, key);
+    unsigned long long* dst =
+        slot >= 0 ? t.sum[slot] : (unsigned long long*)(r.acc + (int64_t)c * kAcc);
 #pragma unroll
-    for (int j = 0; j < 2 * D; ++j) pass_add<D>(tab, r, slot, key, j, (unsigned long long)t[j]);
+    for (int j = 0; j < 2 * D; ++j) atomicAdd(dst + j, (unsigned long long)(sign * v[j]));
+}
+
+// Widens a slot's box (or block c's global box) by an encoded box, touching
+// an entry only when the value improves it.
+template <int D>
+__device__ inline void widen_box(RoundTable<D>& t, const RunDev& r, int slot, int c,
+                                 const unsigned long long* mn, const unsigned long long* mx)
+{
+    unsigned long long* dst = slot >= 0 ? t.box[slot] : r.bb + (int64_t)c * 2 * D;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        pass_add<D>(tab, r, slot, key, 2 * D + j, enc_ord(mn[j]));
-        pass_add<D>(tab, r, slot, key, 3 * D + j, enc_ord(mx[j]));
+        if (mn[j] < dst[j]) atomicMin(dst + j, mn[j]);
+        if (mx[j] > dst[D + j]) atomicMax(dst + D + j, mx[j]);
     }
 }
 
 template <int D, bool WEIGHTED>
-__global__ __launch_bounds__(kBlock) void k_round_pass(RunDev r)
+__global__ __launch_bounds__(kBlock) void k_round_end(RunDev r)
 {
     const DevState* st = r.st;
     if (st->done || !st->round_done) return;
-    __shared__ PassTable<D> tab;
-    __shared__ int s_mix[kPassGroups];
-    __shared__ int s_nmix;
+    __shared__ RoundTable<D> tab;
+    __shared__ int s_list[kPassGroups];
+    __shared__ int s_n;
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     for (int i = tid; i < kHashSlots; i += kBlock) {
         tab.key[i] = -1;
 #pragma unroll
-        for (int j = 0; j < 4 * D; ++j) tab.val[i][j] = j < 3 * D && j >= 2 * D ? ~0ULL : 0ULL;
+        for (int j = 0; j < D; ++j) {
+            tab.sum[i][2 * j] = tab.sum[i][2 * j + 1] = 0ULL;
+            tab.box[i][j] = ~0ULL;
+            tab.box[i][D + j] = 0ULL;
+        }
     }
-    if (tid == 0) s_nmix = 0;
+    if (tid == 0) s_n = 0;
     __syncthreads();
 
-    // uniform groups: one lane per group
-    const int64_t g = (int64_t)blockIdx.x * kPassGroups + tid;
+    // groups of one block: their static boxes, one lane per group
+    const int64_t g0 = (int64_t)blockIdx.x * kPassGroups;
+    const int64_t g = g0 + tid;
     const int f = g < r.ngroups ? r.gblk[g] : kPad;
+    const bool dirty = g < r.ngroups && r.gdirty[g] != 0;
     {
-        long long t[2 * D];
-        double mn[D], mx[D];
+        unsigned long long mn[D], mx[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            t[2 * j] = t[2 * j + 1] = 0;
-            mn[j] = INFINITY;
-            mx[j] = -INFINITY;
+            mn[j] = ~0ULL;
+            mx[j] = 0ULL;
         }
         if (f >= 0) {
 #pragma unroll
-            for (int j = 0; j < 2 * D; ++j) t[j] = r.gsum[g * 2 * D + j];
-#pragma unroll
             for (int j = 0; j < D; ++j) {
-                mn[j] = r.gbox[g * 2 * D + j];
-                mx[j] = r.gbox[g * 2 * D + D + j];
+                mn[j] = enc_ord(r.gbox[g * 2 * D + j]);
+                mx[j] = enc_ord(r.gbox[g * 2 * D + D + j]);
             }
         }
-        const bool tail = run_reduce<D>(f, t, mn, mx);
-        if (tail && f >= 0) run_insert<D>(tab, r, f, t, mn, mx);
+        const bool tail = run_box<D>(f, mn, mx);
+        const bool put = tail && f >= 0;
+        const int slot = wave_slots<D>(tab, f, put);
+        if (put) widen_box<D>(tab, r, slot, f, mn, mx);
     }
-    // mixed groups of this pass block, in order
+    // mixed groups (boxes) and groups with changed points (sums), listed
     {
-        const bool mixed = f == -1;
-        const unsigned long long b = __ballot(mixed);
+        const bool listed = f == -1 || dirty;
+        const unsigned long long b = __ballot(listed);
         int pos = 0;
-        if (lane == 0 && b) pos = atomicAdd(&s_nmix, (int)__popcll(b));
+        if (lane == 0 && b) pos = atomicAdd(&s_n, (int)__popcll(b));
         pos = __shfl(pos, 0, kWave) + (int)__popcll(b & ((1ULL << lane) - 1ULL));
-        if (mixed) s_mix[pos] = (int)(g - (int64_t)blockIdx.x * kPassGroups);
+        if (listed) s_list[pos] = tid | (f == -1 ? 0x100 : 0) | (dirty ? 0x200 : 0);
     }
     __syncthreads();
-    const int nmix = s_nmix;
+    const int nl = s_n;
     double lov[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) lov[j] = st->lo[j];
     const double sxs = st->sx_scale;
     constexpr int kWaves = kBlock / kWave;
-    for (int m0 = wv * kMixBatch; m0 < nmix; m0 += kWaves * kMixBatch) {
-        // loads of a batch of mixed groups first, so their latencies overlap
-        int av[kMixBatch];
+    for (int m0 = wv * kMixBatch; m0 < nl; m0 += kWaves * kMixBatch) {
+        int av[kMixBatch], pv[kMixBatch], ent[kMixBatch];
         double xv[kMixBatch][D];
-        double wv8[kMixBatch];
+        // block ids first, then the coordinates the lanes need, so that the
+        // loads of the whole batch overlap
 #pragma unroll
         for (int u = 0; u < kMixBatch; ++u) {
-            av[u] = kPad;
-            wv8[u] = 0.0;
-#pragma unroll
-            for (int j = 0; j < D; ++j) xv[u][j] = 0.0;
-            if (m0 + u < nmix) {
-                const int64_t p = ((int64_t)blockIdx.x * kPassGroups + s_mix[m0 + u]) * kWave + lane;
+            ent[u] = m0 + u < nl ? s_list[m0 + u] : 0;
+            av[u] = pv[u] = kPad;
+            if (m0 + u < nl) {
+                const int64_t p = (g0 + (ent[u] & 0xff)) * kWave + lane;
                 av[u] = r.A[p];
-#pragma unroll
-                for (int j = 0; j < D; ++j) xv[u][j] = r.in_f32 ? (double)r.xs32[j][p] : r.xs64[j][p];
-                if (WEIGHTED) wv8[u] = r.ws[p];
+                pv[u] = (ent[u] & 0x200) ? r.Aprev[p] : av[u];
             }
         }
 #pragma unroll
         for (int u = 0; u < kMixBatch; ++u) {
-            if (m0 + u >= nmix) break;
-            const int a = av[u];
-            const bool real = a >= 0;
-            long long t[2 * D];
-            coord_terms<D>(xv[u], lov, real ? wv8[u] : 0.0, WEIGHTED, sxs, t);
-            double mn[D], mx[D];
+            const bool need = m0 + u < nl && (((ent[u] & 0x100) && av[u] >= 0) || av[u] != pv[u]);
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                mn[j] = real ? xv[u][j] : INFINITY;
-                mx[j] = real ? xv[u][j] : -INFINITY;
-                t[2 * j] = real ? t[2 * j] : 0;
-                t[2 * j + 1] = real ? t[2 * j + 1] : 0;
+                xv[u][j] = 0.0;
+                if (need) {
+                    const int64_t p = (g0 + (ent[u] & 0xff)) * kWave + lane;
+                    xv[u][j] = r.in_f32 ? (double)r.xs32[j][p] : r.xs64[j][p];
+                }
             }
-            const bool tail = run_reduce<D>(a, t, mn, mx);
-            if (tail && real) run_insert<D>(tab, r, a, t, mn, mx);
+        }
+#pragma unroll
+        for (int u = 0; u < kMixBatch; ++u) {
+            if (m0 + u >= nl) break;
+            const int64_t gg = g0 + (ent[u] & 0xff);
+            const int64_t p = gg * kWave + lane;
+            const int a = av[u], ap = pv[u];
+            if (ent[u] & 0x100) {
+                // mixed group: every point may widen its block's box
+                const bool want = a >= 0;
+                const int slot = wave_slots<D>(tab, a, want);
+                if (want) {
+                    unsigned long long e[D];
+#pragma unroll
+                    for (int j = 0; j < D; ++j) e[j] = enc_ord(xv[u][j]);
+                    widen_box<D>(tab, r, slot, a, e, e);
+                }
+            }
+            if (ent[u] & 0x200) {
+                // changed points move their terms from the old block to the new
+                const bool chg = a != ap;
+                if (lane == 0) r.gdirty[gg] = 0;
+                const unsigned long long cm = __ballot(chg);
+                if (cm == 0ULL) continue;
+                long long t[2 * D];
+                coord_terms<D>(xv[u], lov, WEIGHTED && chg ? r.ws[p] : 1.0, WEIGHTED, sxs, t);
+                if (chg) r.Aprev[p] = a;
+                if (__popcll(cm) >= 16) {
+                    // many changed points (the first round): sum each
+                    // (old, new) pair over the wave first
+                    unsigned long long pend = cm;
+                    while (pend) {
+                        const int leader = __builtin_ctzll(pend);
+                        const int la = __shfl(ap, leader, kWave);
+                        const int lb = __shfl(a, leader, kWave);
+                        const bool mine = chg && ap == la && a == lb;
+                        const unsigned long long mm = __ballot(mine);
+                        long long v[2 * D];
+#pragma unroll
+                        for (int j = 0; j < 2 * D; ++j) v[j] = wave_sum_dpp(mine ? t[j] : 0);
+                        if (lane == leader) {
+                            add_sums<D>(tab, r, table_slot<D>(tab, lb), lb, v, 1);
+                            if (la >= 0) add_sums<D>(tab, r, table_slot<D>(tab, la), la, v, -1);
+                        }
+                        pend &= ~mm;
+                    }
+                } else {
+                    const int sb = wave_slots<D>(tab, a, chg);
+                    const int sa = wave_slots<D>(tab, ap, chg && ap >= 0);
+                    if (chg) {
+                        add_sums<D>(tab, r, sb, a, t, 1);
+                        if (ap >= 0) add_sums<D>(tab, r, sa, ap, t, -1);
+                    }
+                }
+            }
         }
     }
     __syncthreads();
@@ -316,11 +369,12 @@ __global__ __launch_bounds__(kBlock) void k_round_pass(RunDev r)
         unsigned long long* sums = (unsigned long long*)(r.acc + (int64_t)key * kAcc);
         unsigned long long* box = r.bb + (int64_t)key * 2 * D;
 #pragma unroll
-        for (int j = 0; j < 2 * D; ++j) atomicAdd(sums + j, tab.val[i][j]);
+        for (int j = 0; j < 2 * D; ++j)
+            if (tab.sum[i][j]) atomicAdd(sums + j, tab.sum[i][j]);
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            atomicMin(box + j, tab.val[i][2 * D + j]);
-            atomicMax(box + D + j, tab.val[i][3 * D + j]);
+            if (tab.box[i][j] != ~0ULL) atomicMin(box + j, tab.box[i][j]);
+            if (tab.box[i][D + j] != 0ULL) atomicMax(box + D + j, tab.box[i][D + j]);
         }
     }
 }
@@ -408,10 +462,7 @@ __global__ __launch_bounds__(1024) void k_move(RunDev r, double* delta)
         st->round_done = 0;
         st->sweep_in_round = 0;
     }
-    for (int i = threadIdx.x; i < k * 2 * D; i += 1024) {
-        r.bb[i] = (i % (2 * D)) < D ? ~0ULL : 0ULL;
-        r.acc[(int64_t)(i / (2 * D)) * kAcc + i % (2 * D)] = 0;
-    }
+    for (int i = threadIdx.x; i < k * 2 * D; i += 1024) r.bb[i] = (i % (2 * D)) < D ? ~0ULL : 0ULL;
 }
 
 // Fresh run state: influence 1, no assignment, empty sums, open bounds.
@@ -420,8 +471,10 @@ __global__ __launch_bounds__(kBlock) void k_init_points(RunDev r)
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= r.npad) return;
     r.A[i] = r.perm[i] >= 0 ? -1 : kPad;
+    r.Aprev[i] = r.A[i];
     r.ubt[i] = INFINITY;
     r.lbt[i] = 0.0f;
+    if (i < r.ngroups) r.gdirty[i] = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_init_clusters(RunDev r, const double* cinit,
@@ -706,11 +759,11 @@ hipError_t launch_block_boxes(const RunDev& r, hipStream_t s)
 {
     const unsigned g = (unsigned)((r.ngroups + kPassGroups - 1) / kPassGroups);
     if (r.d == 2) {
-        if (r.weighted) k_round_pass<2, true><<<g, kBlock, 0, s>>>(r);
-        else k_round_pass<2, false><<<g, kBlock, 0, s>>>(r);
+        if (r.weighted) k_round_end<2, true><<<g, kBlock, 0, s>>>(r);
+        else k_round_end<2, false><<<g, kBlock, 0, s>>>(r);
     } else {
-        if (r.weighted) k_round_pass<3, true><<<g, kBlock, 0, s>>>(r);
-        else k_round_pass<3, false><<<g, kBlock, 0, s>>>(r);
+        if (r.weighted) k_round_end<3, true><<<g, kBlock, 0, s>>>(r);
+        else k_round_end<3, false><<<g, kBlock, 0, s>>>(r);
     }
     return hipGetLastError();
 }
