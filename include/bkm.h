@@ -67,7 +67,8 @@ typedef struct {
     int32_t hilbert_order;    /* bits per axis of the Hilbert index: 1..31 (2D), 1..21 (3D); default 16 */
     int32_t precision;        /* bkm_precision; default BKM_PREC_F32_RECHECK */
     int32_t use_bounds;       /* 1: Hamerly upper/lower bounds skip points (Sec. 4.3); default 1 */
-    int32_t tile_points;      /* points per tile of the sweep: 256, 512 or 1024; 0 = default */
+    int32_t tile_points;      /* points per tile of the sweep: 256, 512 or 1024; 0 = chosen
+                                 from the mean number of points per block */
     int32_t super_tiles;      /* tiles per candidate super-tile, >= 1; 0 = default */
     int32_t timing;           /* 1: time every kernel of the round loop with HIP events on
                                  `stream` and report the sums in bkm_info; default 0 */
@@ -159,6 +160,30 @@ int bkm_balanced_kmeans(const bkm_points* pts, const bkm_params* prm,
                         const double* centers_init, int32_t* assignment_out,
                         double* centers_out, double* influence_out,
                         double* block_weights_out, bkm_info* info, void* stream);
+
+/* Many independent balanced k-means runs (Alg. 2 around Alg. 1, each exactly
+ * as bkm_balanced_kmeans with SFC-bootstrap centers) in one call.  Instances
+ * may differ in n, k, d, dtype, weights and parameters.  Their bootstraps run
+ * side by side on worker streams; then every per-sweep kernel is one launch
+ * over all instances that share d, precision, tile size and weighting, each
+ * block finding its instance in a block map, and the round loop is captured
+ * once in a HIP graph and replayed until every instance is done (a finished
+ * instance turns its kernels into no-ops).  Results are identical to
+ * count separate bkm_balanced_kmeans calls with the same parameters.
+ *   pts   [host] count point sets (device coordinate/weight pointers inside).
+ *   prm   [host] count parameter sets; tile_points 0 picks the tile size from
+ *         the mean number of points per block; timing is ignored.
+ *   assignment_out [host] count device pointers, n_i int32 each (input order).
+ *   centers_out    [host] count device pointers, k_i*d_i doubles each [k][d].
+ *   info  [host] count records, or NULL; bootstrap_ms and total_ms are those
+ *         of the whole call.
+ * Returns BKM_OK when every instance balanced, BKM_WUNBALANCED when some did
+ * not (outputs valid), or an error code; bkm_last_error names the instance
+ * of an argument or data error.  Workspace for all instances is one
+ * stream-ordered allocation on `stream`, released before return. */
+int bkm_balanced_kmeans_batched(const bkm_points* pts, const bkm_params* prm, int32_t count,
+                                int32_t* const* assignment_out, double* const* centers_out,
+                                bkm_info* info, void* stream);
 
 /* A sequence of `steps` assignment sweeps with caller-given centers and
  * influence (the Alg. 1 inner loop with the bound relaxation of Alg. 2

@@ -58,7 +58,8 @@ class BkmError(RuntimeError):
 
 _LIB = None
 FUNCTIONS = ("bkm_default_params", "bkm_init_centers_sfc", "bkm_balanced_kmeans",
-             "bkm_assign_sweeps", "bkm_partition_stats", "bkm_last_error")
+             "bkm_balanced_kmeans_batched", "bkm_assign_sweeps", "bkm_partition_stats",
+             "bkm_last_error")
 
 
 def lib():
@@ -79,10 +80,12 @@ def lib():
                                         C.c_int32, C.c_int32, P, P, C.POINTER(Info), P]
         L.bkm_partition_stats.argtypes = [C.POINTER(Points), P, C.c_int32, C.c_double, P, P,
                                           C.POINTER(Stats), P]
+        L.bkm_balanced_kmeans_batched.argtypes = [C.POINTER(Points), C.POINTER(Params), C.c_int32,
+                                                  C.POINTER(P), C.POINTER(P), C.POINTER(Info), P]
         L.bkm_last_error.argtypes = []
         L.bkm_last_error.restype = C.c_char_p
         for f in ("bkm_init_centers_sfc", "bkm_balanced_kmeans", "bkm_assign_sweeps",
-                  "bkm_partition_stats"):
+                  "bkm_partition_stats", "bkm_balanced_kmeans_batched"):
             getattr(L, f).restype = C.c_int
         _LIB = L
     return _LIB
@@ -183,6 +186,50 @@ def balanced_kmeans(X, k, W=None, eps=0.03, max_iter=50, max_balance_iter=20,
     res["info"] = info_dict(info)
     res["code"] = rc
     return res
+
+
+def balanced_kmeans_batched(instances, eps=0.03, max_iter=50, max_balance_iter=20,
+                            delta_threshold=-1.0, hilbert_order=16, precision="f32_recheck",
+                            use_bounds=True, tile_points=0, super_tiles=0, recheck_rel_gap=1e-5):
+    """Many balanced k-means runs in one call.  instances: list of (X, k) or
+    (X, k, W) with X a list of d device tensors.  Scalar parameters apply to
+    every instance; a list gives one value per instance.  Returns a list of
+    dict(A, centers, info) and the call's return code."""
+    m = len(instances)
+
+    def per(v, i):
+        return v[i] if isinstance(v, (list, tuple)) else v
+
+    pts = (Points * m)()
+    prm = (Params * m)()
+    outs = []
+    for i, inst in enumerate(instances):
+        X, k = inst[0], int(inst[1])
+        W = inst[2] if len(inst) > 2 else None
+        pts[i] = make_points(X, W)
+        p = default_params(k)
+        p.epsilon = float(per(eps, i))
+        p.max_iter = int(per(max_iter, i))
+        p.max_balance_iter = int(per(max_balance_iter, i))
+        p.delta_threshold = float(per(delta_threshold, i))
+        p.hilbert_order = int(per(hilbert_order, i))
+        pr = per(precision, i)
+        p.precision = PRECISIONS[pr] if isinstance(pr, str) else int(pr)
+        p.use_bounds = 1 if per(use_bounds, i) else 0
+        p.tile_points = int(per(tile_points, i))
+        p.super_tiles = int(per(super_tiles, i))
+        p.recheck_rel_gap = float(per(recheck_rel_gap, i))
+        prm[i] = p
+        dev = X[0].device
+        outs.append(dict(A=torch.empty(pts[i].n, dtype=torch.int32, device=dev),
+                         centers=torch.empty((k, pts[i].d), dtype=torch.float64, device=dev)))
+    asg = (C.c_void_p * m)(*[o["A"].data_ptr() for o in outs])
+    cen = (C.c_void_p * m)(*[o["centers"].data_ptr() for o in outs])
+    info = (Info * m)()
+    rc = _check(lib().bkm_balanced_kmeans_batched(pts, prm, m, asg, cen, info, _stream()))
+    for i, o in enumerate(outs):
+        o["info"] = info_dict(info[i])
+    return outs, rc
 
 
 def assign_sweeps(X, centers_seq, influence_seq, precision="f32_recheck", use_bounds=True,

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "bkm_internal.h"
 
@@ -286,6 +287,76 @@ int bootstrap(RunDev& r, int order, hipStream_t s, bool tiles)
 
 int check_tile(int T) { return T == 0 || T == 256 || T == 512 || T == 1024; }
 
+// Arguments of one balanced k-means run.
+int check_run(const bkm_points* pts, const bkm_params* prm)
+{
+    int rc = check_points(pts);
+    if (rc) return rc;
+    if (!prm) return fail(BKM_EINVAL, "params is NULL");
+    const bkm_params& p = *prm;
+    if (p.k < 1 || p.k > pts->n) return fail(BKM_EINVAL, "k = %d outside [1, n]", p.k);
+    if (!(p.epsilon >= 0.0)) return fail(BKM_EINVAL, "epsilon must be >= 0");
+    if (p.max_iter < 1 || p.max_balance_iter < 1)
+        return fail(BKM_EINVAL, "max_iter and max_balance_iter must be >= 1");
+    if ((rc = check_order(pts->d, p.hilbert_order))) return rc;
+    if (p.precision != BKM_PREC_F64 && p.precision != BKM_PREC_F32_RECHECK)
+        return fail(BKM_EINVAL, "precision %d unknown", p.precision);
+    if (!check_tile(p.tile_points)) return fail(BKM_EINVAL, "tile_points %d not 0/256/512/1024", p.tile_points);
+    if (p.super_tiles < 0) return fail(BKM_EINVAL, "super_tiles must be >= 0");
+    if (!(p.recheck_rel_gap >= 0.0) || !std::isfinite(p.recheck_rel_gap))
+        return fail(BKM_EINVAL, "recheck_rel_gap must be finite and >= 0");
+    if (std::isnan(p.delta_threshold)) return fail(BKM_EINVAL, "delta_threshold is NaN");
+    return BKM_OK;
+}
+
+// Tile size for tile_points = 0, from the mean number of points per block:
+// smaller blocks want smaller tiles, whose boxes keep fewer candidates.
+int auto_tile(int64_t n, int k)
+{
+    const double ppb = (double)n / (double)k;
+    return ppb >= 2048.0 ? 1024 : ppb >= 512.0 ? 512 : 256;
+}
+
+void fill_info(bkm_info* info, const DevState& h, const unsigned long long* cnt)
+{
+    std::memset(info, 0, sizeof(*info));
+    info->rounds = h.rounds;
+    info->sweeps = h.sweeps;
+    info->balanced = h.balanced;
+    info->converged = h.converged;
+    info->l_max = h.lmax;
+    info->max_block_weight = h.max_weight;
+    info->imbalance = h.max_weight / h.target - 1.0;
+    info->evaluated = (int64_t)cnt[kCntEvaluated];
+    info->skipped = (int64_t)cnt[kCntSkipped];
+    info->rechecked = (int64_t)cnt[kCntRechecked];
+    info->changed = (int64_t)cnt[kCntChanged];
+    info->candidate_evals = (int64_t)cnt[kCntCandEvals];
+    info->overflow_tiles = (int64_t)cnt[kCntOverflow];
+}
+
+// Owned HIP objects of a batched call, released on every return path.
+struct BatchRes {
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+    DevState* hstates = nullptr;
+    unsigned long long* hcnt = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~BatchRes()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (auto e : events) (void)hipEventDestroy(e);
+        for (auto q : streams) {
+            (void)hipStreamSynchronize(q);
+            (void)hipStreamDestroy(q);
+        }
+        if (hstates) (void)hipHostFree(hstates);
+        if (hcnt) (void)hipHostFree(hcnt);
+    }
+};
+
 }  // namespace
 
 extern "C" {
@@ -347,27 +418,14 @@ int bkm_balanced_kmeans(const bkm_points* pts, const bkm_params* prm, const doub
                         double* block_weights_out, bkm_info* info, void* stream)
 {
     g_err.clear();
-    int rc = check_points(pts);
+    int rc = check_run(pts, prm);
     if (rc) return rc;
-    if (!prm) return fail(BKM_EINVAL, "params is NULL");
     const bkm_params p = *prm;
-    if (p.k < 1 || p.k > pts->n) return fail(BKM_EINVAL, "k = %d outside [1, n]", p.k);
-    if (!(p.epsilon >= 0.0)) return fail(BKM_EINVAL, "epsilon must be >= 0");
-    if (p.max_iter < 1 || p.max_balance_iter < 1)
-        return fail(BKM_EINVAL, "max_iter and max_balance_iter must be >= 1");
-    if ((rc = check_order(pts->d, p.hilbert_order))) return rc;
-    if (p.precision != BKM_PREC_F64 && p.precision != BKM_PREC_F32_RECHECK)
-        return fail(BKM_EINVAL, "precision %d unknown", p.precision);
-    if (!check_tile(p.tile_points)) return fail(BKM_EINVAL, "tile_points %d not 0/256/512/1024", p.tile_points);
-    if (p.super_tiles < 0) return fail(BKM_EINVAL, "super_tiles must be >= 0");
-    if (!(p.recheck_rel_gap >= 0.0) || !std::isfinite(p.recheck_rel_gap))
-        return fail(BKM_EINVAL, "recheck_rel_gap must be finite and >= 0");
-    if (std::isnan(p.delta_threshold)) return fail(BKM_EINVAL, "delta_threshold is NaN");
     if (!assignment_out || !centers_out) return fail(BKM_EINVAL, "assignment_out/centers_out is NULL");
 
     hipStream_t s = (hipStream_t)stream;
     keep_pool_memory();
-    const int T = p.tile_points ? p.tile_points : 1024;
+    const int T = p.tile_points ? p.tile_points : auto_tile(pts->n, p.k);
     const int ST = p.super_tiles ? p.super_tiles : 16;
     RunDev r;
     plan(r, pts, p.k, T, ST, p.precision, p.use_bounds ? 1 : 0, p.recheck_rel_gap);
@@ -437,20 +495,7 @@ int bkm_balanced_kmeans(const bkm_points* pts, const bkm_params* prm, const doub
     if ((rc = read_counters(r, s, cnt))) return rc;
 
     if (info) {
-        std::memset(info, 0, sizeof(*info));
-        info->rounds = h.rounds;
-        info->sweeps = h.sweeps;
-        info->balanced = h.balanced;
-        info->converged = h.converged;
-        info->l_max = h.lmax;
-        info->max_block_weight = h.max_weight;
-        info->imbalance = h.max_weight / h.target - 1.0;
-        info->evaluated = (int64_t)cnt[kCntEvaluated];
-        info->skipped = (int64_t)cnt[kCntSkipped];
-        info->rechecked = (int64_t)cnt[kCntRechecked];
-        info->changed = (int64_t)cnt[kCntChanged];
-        info->candidate_evals = (int64_t)cnt[kCntCandEvals];
-        info->overflow_tiles = (int64_t)cnt[kCntOverflow];
+        fill_info(info, h, cnt);
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) info->bootstrap_ms = ms;
         if (hipEventElapsedTime(&ms, ev[0], ev[2]) == hipSuccess) info->total_ms = ms;
@@ -556,6 +601,315 @@ int bkm_partition_stats(const bkm_points* pts, const int32_t* assignment, int32_
     out->empty_blocks = (int32_t)h6[3];
     out->overloaded_blocks = (int32_t)h6[4];
     return BKM_OK;
+}
+
+int bkm_balanced_kmeans_batched(const bkm_points* pts, const bkm_params* prm, int32_t count,
+                                int32_t* const* assignment_out, double* const* centers_out,
+                                bkm_info* info, void* stream)
+{
+    g_err.clear();
+    if (count < 1) return fail(BKM_EINVAL, "count = %d must be >= 1", count);
+    if (!pts || !prm || !assignment_out || !centers_out)
+        return fail(BKM_EINVAL, "points/params/assignment_out/centers_out array is NULL");
+    for (int i = 0; i < count; ++i) {
+        int rc = check_run(&pts[i], &prm[i]);
+        if (!rc && (!assignment_out[i] || !centers_out[i]))
+            rc = fail(BKM_EINVAL, "assignment_out/centers_out is NULL");
+        if (rc) {
+            g_err = "instance " + std::to_string(i) + ": " + g_err;
+            return rc;
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    keep_pool_memory();
+    BatchRes res;
+    hipEvent_t t0, t1, t2;
+    for (hipEvent_t* e : {&t0, &t1, &t2}) {
+        HIPCHK(hipEventCreate(e));
+        res.events.push_back(*e);
+    }
+    HIPCHK(hipEventRecord(t0, s));
+
+    // one workspace for all instances; their run states side by side, so a
+    // single copy reads them all
+    std::vector<RunDev> rs(count);
+    Sizes z;
+    z.add<DevState>(count);
+    for (int i = 0; i < count; ++i) {
+        const bkm_params& p = prm[i];
+        const int T = p.tile_points ? p.tile_points : auto_tile(pts[i].n, p.k);
+        plan(rs[i], &pts[i], p.k, T, p.super_tiles ? p.super_tiles : 16, p.precision,
+             p.use_bounds ? 1 : 0, p.recheck_rel_gap);
+        z.total += layout(rs[i], nullptr, true);
+    }
+    Arena a;
+    a.s = s;
+    // on an early return, the worker streams finish before the workspace goes
+    struct SyncWorkers {
+        std::vector<hipStream_t>& v;
+        ~SyncWorkers() { for (auto q : v) (void)hipStreamSynchronize(q); }
+    } sync_workers{res.streams};
+    {
+        hipError_t e = hipMallocAsync((void**)&a.base, z.total, s);
+        if (e != hipSuccess) {
+            a.base = nullptr;
+            return fail(e == hipErrorOutOfMemory ? BKM_ENOMEM : BKM_EHIP,
+                        "hipMallocAsync(%zu bytes): %s", z.total, hipGetErrorString(e));
+        }
+        a.cap = z.total;
+    }
+    DevState* states = a.take<DevState>(count);
+    for (int i = 0; i < count; ++i) {
+        layout(rs[i], &a, true);
+        rs[i].st = states + i;
+    }
+    HIPCHK(hipMemsetAsync(states, 0, (size_t)count * sizeof(DevState), s));
+    HIPCHK(hipHostMalloc((void**)&res.hstates, (size_t)count * sizeof(DevState), hipHostMallocDefault));
+    auto read_all = [&]() -> int {
+        HIPCHK(hipMemcpyAsync(res.hstates, states, (size_t)count * sizeof(DevState),
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return BKM_OK;
+    };
+
+    // bootstrap: instances spread over worker streams, in three phases split
+    // by the two host reads (data checks, padded layout sizes)
+    const int W = std::min(count, 8);
+    for (int w = 0; w < W; ++w) {
+        hipStream_t q;
+        HIPCHK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+        res.streams.push_back(q);
+        hipEvent_t e;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        res.events.push_back(e);
+    }
+    hipEvent_t efork;
+    HIPCHK(hipEventCreateWithFlags(&efork, hipEventDisableTiming));
+    res.events.push_back(efork);
+    auto fork = [&]() -> int {
+        HIPCHK(hipEventRecord(efork, s));
+        for (auto q : res.streams) HIPCHK(hipStreamWaitEvent(q, efork, 0));
+        return BKM_OK;
+    };
+    auto join = [&]() -> int {
+        for (int w = 0; w < W; ++w) {
+            hipEvent_t e = res.events[3 + w];
+            HIPCHK(hipEventRecord(e, res.streams[w]));
+            HIPCHK(hipStreamWaitEvent(s, e, 0));
+        }
+        return BKM_OK;
+    };
+    int rc;
+    if ((rc = fork())) return rc;
+    for (int i = 0; i < count; ++i) HIPCHK(launch_bbox(rs[i], prm[i].hilbert_order, res.streams[i % W]));
+    if ((rc = join()) || (rc = read_all())) return rc;
+    for (int i = 0; i < count; ++i)
+        if (res.hstates[i].bad_data)
+            return fail(BKM_EDATA, "instance %d: %s", i,
+                        rs[i].weighted ? "non-finite coordinate or weight <= 0 / non-finite"
+                                       : "non-finite coordinate");
+    if ((rc = fork())) return rc;
+    for (int i = 0; i < count; ++i) {
+        RunDev& r = rs[i];
+        hipStream_t q = res.streams[i % W];
+        HIPCHK(launch_keys(r, prm[i].hilbert_order, r.sperm, q));
+        HIPCHK(radix_sort_pairs(r, r.keys, r.sperm, r.d * prm[i].hilbert_order, q));
+        HIPCHK(launch_permute(r, q));
+        HIPCHK(launch_jump_plan(r, q));
+    }
+    if ((rc = join()) || (rc = read_all())) return rc;
+    for (int i = 0; i < count; ++i) {
+        const int64_t np = res.hstates[i].npad;
+        if (np < rs[i].n || np > rs[i].npad_cap)
+            return fail(BKM_EHIP, "instance %d: padded layout of %lld points outside [n, %lld]", i,
+                        (long long)np, (long long)rs[i].npad_cap);
+        set_layout_size(rs[i], np);
+    }
+    if ((rc = fork())) return rc;
+    for (int i = 0; i < count; ++i) {
+        const RunDev& r = rs[i];
+        const bkm_params& p = prm[i];
+        hipStream_t q = res.streams[i % W];
+        HIPCHK(launch_place(r, q));
+        HIPCHK(launch_tile_prep(r, q));
+        HIPCHK(launch_centers_from_sorted(r, r.C, 0, q));
+        HIPCHK(launch_init_run(r, nullptr, p.max_iter, p.max_balance_iter, p.epsilon,
+                               p.delta_threshold, q));
+    }
+    if ((rc = join())) return rc;
+    HIPCHK(hipEventRecord(t1, s));
+
+    // Classes of the still active instances that share kernels, with the
+    // block maps of their per-sweep launches, and the round loop captured in
+    // a graph over them: kGraphBatches batches (every class: candidates,
+    // sweep, balance, round end, move), replayed until every instance is
+    // done.  An instance that is done turns its kernels into no-ops; when the
+    // active set has shrunk by a fifth, the maps and the graph are rebuilt
+    // without the finished instances, so their blocks stop being launched.
+    // The loop runs on a worker stream (capture needs a stream of its own),
+    // joined to the caller's stream before and after.
+    hipStream_t ls = res.streams[0];
+    HIPCHK(hipEventRecord(efork, s));
+    HIPCHK(hipStreamWaitEvent(ls, efork, 0));
+    constexpr int kGraphBatches = 4;
+    std::vector<MultiSet> ms;
+    Arena a2;
+    a2.s = ls;
+    {
+        // room for the maps of all instances; rebuilds reuse it from the start
+        Sizes z2;
+        z2.add<RunDev>(count);
+        for (int i = 0; i < count; ++i) {
+            const RunDev& r = rs[i];
+            z2.add<int2>(r.nsuper);
+            z2.add<int2>((r.ntiles + kBlock / kWave - 1) / (kBlock / kWave));
+            z2.add<int2>(r.ntiles);
+            z2.add<int2>((r.ngroups + kPassGroupsHost - 1) / kPassGroupsHost);
+        }
+        z2.add<int2>(count);
+        z2.total += 64 * 6 * 256;  // per-class rounding (at most 24 classes of 6 arrays)
+        HIPCHK(hipMallocAsync((void**)&a2.base, z2.total, ls));
+        a2.cap = z2.total;
+    }
+    std::vector<std::vector<RunDev>> hrs;
+    std::vector<std::vector<int2>> hmap;
+    auto build = [&](const std::vector<int>& act) -> int {
+        ms.clear();
+        std::vector<std::vector<int>> cls;
+        for (int i : act) {
+            const RunDev& r = rs[i];
+            size_t c = 0;
+            for (; c < ms.size(); ++c)
+                if (ms[c].d == r.d && ms[c].precision == r.precision && ms[c].ppt == r.ppt &&
+                    ms[c].weighted == r.weighted)
+                    break;
+            if (c == ms.size()) {
+                MultiSet m{};
+                m.d = r.d;
+                m.precision = r.precision;
+                m.ppt = r.ppt;
+                m.weighted = r.weighted;
+                ms.push_back(m);
+                cls.emplace_back();
+            }
+            cls[c].push_back(i);
+        }
+        hrs.assign(ms.size(), {});
+        hmap.assign(ms.size() * 5, {});
+        a2.off = 0;
+        for (size_t c = 0; c < ms.size(); ++c) {
+            MultiSet& m = ms[c];
+            m.ninst = (int)cls[c].size();
+            for (int j = 0; j < m.ninst; ++j) {
+                const RunDev& r = rs[cls[c][j]];
+                hrs[c].push_back(r);
+                const int nq = (r.ntiles + kBlock / kWave - 1) / (kBlock / kWave);
+                const int npass = (r.ngroups + kPassGroupsHost - 1) / kPassGroupsHost;
+                for (int b = 0; b < r.nsuper; ++b) hmap[c * 5 + 0].push_back(make_int2(j, b));
+                for (int b = 0; b < nq; ++b) hmap[c * 5 + 1].push_back(make_int2(j, b));
+                for (int b = 0; b < r.ntiles; ++b) hmap[c * 5 + 2].push_back(make_int2(j, b));
+                for (int b = 0; b < npass; ++b) hmap[c * 5 + 3].push_back(make_int2(j, b));
+                hmap[c * 5 + 4].push_back(make_int2(j, 0));
+            }
+            m.nb_super = (int)hmap[c * 5 + 0].size();
+            m.nb_quad = (int)hmap[c * 5 + 1].size();
+            m.nb_tile = (int)hmap[c * 5 + 2].size();
+            m.nb_pass = (int)hmap[c * 5 + 3].size();
+            RunDev* drs = a2.take<RunDev>(m.ninst);
+            if (a2.off > a2.cap) return fail(BKM_EHIP, "block maps exceed their workspace");
+            HIPCHK(hipMemcpyAsync(drs, hrs[c].data(), m.ninst * sizeof(RunDev), hipMemcpyHostToDevice, ls));
+            m.rs = drs;
+            const int2** dst[5] = {&m.map_super, &m.map_quad, &m.map_tile, &m.map_pass, &m.map_inst};
+            for (int t = 0; t < 5; ++t) {
+                const std::vector<int2>& v = hmap[c * 5 + t];
+                int2* d = a2.take<int2>(v.size());
+                if (a2.off > a2.cap) return fail(BKM_EHIP, "block maps exceed their workspace");
+                if (!v.empty())
+                    HIPCHK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(int2), hipMemcpyHostToDevice, ls));
+                *dst[t] = d;
+            }
+        }
+        HIPCHK(hipStreamSynchronize(ls));
+        return BKM_OK;
+    };
+    auto enqueue = [&]() -> int {
+        for (int g = 0; g < kGraphBatches; ++g)
+            for (const MultiSet& m : ms) {
+                HIPCHK(launch_sweep_multi(m, ls));
+                HIPCHK(launch_update_multi(m, ls));
+            }
+        return BKM_OK;
+    };
+    bool use_graph = true;
+    auto capture = [&]() -> int {
+        if (res.exec) (void)hipGraphExecDestroy(res.exec);
+        if (res.graph) (void)hipGraphDestroy(res.graph);
+        res.exec = nullptr;
+        res.graph = nullptr;
+        use_graph = hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (!use_graph) return BKM_OK;
+        const int erc = enqueue();
+        const hipError_t e = hipStreamEndCapture(ls, &res.graph);
+        if (erc) return erc;
+        HIPCHK(e);
+        HIPCHK(hipGraphInstantiate(&res.exec, res.graph, nullptr, nullptr, 0));
+        return BKM_OK;
+    };
+    std::vector<int> act(count);
+    for (int i = 0; i < count; ++i) act[i] = i;
+    if ((rc = build(act)) || (rc = capture())) return rc;
+    size_t built_for = act.size();
+    int64_t max_batches = 0;
+    for (int i = 0; i < count; ++i)
+        max_batches = std::max<int64_t>(max_batches,
+                                        (int64_t)prm[i].max_iter * (prm[i].max_balance_iter + 1) + 8);
+    for (int64_t nb = 0;; nb += kGraphBatches) {
+        if (nb >= max_batches + kGraphBatches) return fail(BKM_EHIP, "round loop made no progress");
+        if (use_graph)
+            HIPCHK(hipGraphLaunch(res.exec, ls));
+        else if ((rc = enqueue()))
+            return rc;
+        HIPCHK(hipMemcpyAsync(res.hstates, states, (size_t)count * sizeof(DevState),
+                              hipMemcpyDeviceToHost, ls));
+        HIPCHK(hipStreamSynchronize(ls));
+        act.clear();
+        for (int i = 0; i < count; ++i)
+            if (!res.hstates[i].done) act.push_back(i);
+        if (act.empty()) break;
+        if (act.size() * 5 <= built_for * 4) {
+            if ((rc = build(act)) || (rc = capture())) return rc;
+            built_for = act.size();
+        }
+    }
+    HIPCHK(hipEventRecord(res.events[3], ls));
+    HIPCHK(hipStreamWaitEvent(s, res.events[3], 0));
+
+    for (int i = 0; i < count; ++i)
+        HIPCHK(launch_finish(rs[i], assignment_out[i], centers_out[i], nullptr, nullptr, s));
+    HIPCHK(hipEventRecord(t2, s));
+    HIPCHK(hipHostMalloc((void**)&res.hcnt, (size_t)count * kCntSlots * kCntWords * sizeof(unsigned long long),
+                         hipHostMallocDefault));
+    for (int i = 0; i < count; ++i)
+        HIPCHK(hipMemcpyAsync(res.hcnt + (size_t)i * kCntSlots * kCntWords, rs[i].cnt,
+                              kCntSlots * kCntWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    if ((rc = read_all())) return rc;
+    bool balanced = true;
+    float boot_ms = 0.0f, tot_ms = 0.0f;
+    (void)hipEventElapsedTime(&boot_ms, t0, t1);
+    (void)hipEventElapsedTime(&tot_ms, t0, t2);
+    for (int i = 0; i < count; ++i) {
+        balanced = balanced && res.hstates[i].balanced;
+        if (!info) continue;
+        unsigned long long cnt[kCntWords];
+        for (int j = 0; j < kCntWords; ++j) {
+            cnt[j] = 0;
+            for (int q = 0; q < kCntSlots; ++q) cnt[j] += res.hcnt[(size_t)i * kCntSlots * kCntWords + q * kCntWords + j];
+        }
+        fill_info(&info[i], res.hstates[i], cnt);
+        info[i].bootstrap_ms = boot_ms;
+        info[i].total_ms = tot_ms;
+    }
+    return balanced ? BKM_OK : BKM_WUNBALANCED;
 }
 
 }  // extern "C"

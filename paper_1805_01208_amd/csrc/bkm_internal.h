@@ -290,6 +290,24 @@ hipError_t launch_tilecand(const RunDev& r, hipStream_t s);
 hipError_t launch_sweep(const RunDev& r, hipStream_t s);
 hipError_t launch_balance(const RunDev& r, hipStream_t s);
 hipError_t launch_block_boxes(const RunDev& r, hipStream_t s);
+
+// Instances of one class (same d, precision, tile size and weighting) whose
+// per-sweep kernels run as one launch each.  The maps give, for every block
+// of a launch, its instance and its block within that instance.
+struct MultiSet {
+    int d, precision, ppt, weighted;
+    int ninst;
+    const RunDev* rs;          // device [ninst]
+    const int2* map_super;     // one block per super-tile
+    const int2* map_quad;      // one block per 4 tiles (a wave per tile)
+    const int2* map_tile;      // one block per tile
+    const int2* map_pass;      // one block per kPassGroups groups
+    const int2* map_inst;      // one block per instance
+    int nb_super, nb_quad, nb_tile, nb_pass;
+};
+constexpr int kPassGroupsHost = 256;   // groups per block of the round-end pass
+hipError_t launch_sweep_multi(const MultiSet& m, hipStream_t s);    // candidates + sweep
+hipError_t launch_update_multi(const MultiSet& m, hipStream_t s);   // balance + round end + move
 hipError_t launch_move(const RunDev& r, hipStream_t s);
 hipError_t launch_set_step(const RunDev& r, const double* centers_rm, const double* infl,
                            int first, hipStream_t s);

@@ -82,14 +82,14 @@ __device__ inline double sorted_coord(const RunDev& r, int j, int64_t p)
 }
 
 // ------------------------------------------------------------ super-tiles
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_supercand(RunDev r)
+template <int D, typename RT>
+__device__ __forceinline__ void supercand_body(RT r, const int bid)
 {
     const DevState* st = r.st;
     if (st->done || st->round_done) return;
     __shared__ double sa[kBlock / kWave], sb[kBlock / kWave];
     __shared__ int cnt;
-    const int s = blockIdx.x, tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    const int s = bid, tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     const int k = r.k;
     double lo[D], hi[D];
 #pragma unroll
@@ -133,6 +133,21 @@ __global__ __launch_bounds__(kBlock) void k_supercand(RunDev r)
     if (tid == 0) r.scount[s] = cnt;
 }
 
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_supercand(RunDev r)
+{
+    supercand_body<D, const RunDev>(r, blockIdx.x);
+}
+
+// Many instances in one launch: block b works on instance map[b].x as its
+// block map[b].y.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_supercand_multi(const RunDev* rs, const int2* map)
+{
+    const int2 m = map[blockIdx.x];
+    supercand_body<D, const RunDev&>(rs[m.x], m.y);
+}
+
 // ------------------------------------------------------------------ tiles
 // One wave per tile: filter the super-tile list against the tile box and
 // write the survivors' records plus the FP32 error bounds of the tile.
@@ -144,15 +159,15 @@ __global__ __launch_bounds__(kBlock) void k_supercand(RunDev r)
 // square root) within 3.6*u*(Rn + r_c) of the exact distance; dmax uses
 // 8*u*(Rn + r_c), and tau that times 1/influence(c), maximised over the
 // candidates.
-template <int D, int PREC>
-__global__ __launch_bounds__(kBlock) void k_tilecand(RunDev r)
+template <int D, int PREC, typename RT>
+__device__ __forceinline__ void tilecand_body(RT r, const int bid)
 {
     const DevState* st = r.st;
     if (st->done || st->round_done) return;
     constexpr bool F32 = PREC == BKM_PREC_F32_RECHECK;
     constexpr int kCpl = 4;   // candidates a lane keeps in registers between passes
     const int lane = threadIdx.x % kWave;
-    const int tile = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const int tile = bid * (kBlock / kWave) + threadIdx.x / kWave;
     if (tile >= r.ntiles) return;
     const int k = r.k;
     const double* __restrict__ C = r.C;
@@ -284,6 +299,21 @@ __global__ __launch_bounds__(kBlock) void k_tilecand(RunDev r)
     }
 }
 
+template <int D, int PREC>
+__global__ __launch_bounds__(kBlock) void k_tilecand(RunDev r)
+{
+    tilecand_body<D, PREC, const RunDev>(r, blockIdx.x);
+}
+
+// Many instances in one launch: block b works on instance map[b].x as its
+// block map[b].y.
+template <int D, int PREC>
+__global__ __launch_bounds__(kBlock) void k_tilecand_multi(const RunDev* rs, const int2* map)
+{
+    const int2 m = map[blockIdx.x];
+    tilecand_body<D, PREC, const RunDev&>(rs[m.x], m.y);
+}
+
 // ------------------------------------------------------------------ sweep
 // Block = one tile of T = 256 * PPT consecutive Hilbert-ordered points.
 // Phase 1 streams every point of the tile (thread t, points base + t + 256 q,
@@ -294,8 +324,8 @@ __global__ __launch_bounds__(kBlock) void k_tilecand(RunDev r)
 // and the block-weight bookkeeping, so skipped points cost no candidate
 // arithmetic.  The coordinate sums of the center update are not touched
 // here: the round-end pass rebuilds them from the final assignment.
-template <int D, int PREC, int PPT, bool WEIGHTED>
-__global__ __launch_bounds__(kBlock) void k_sweep(RunDev r)
+template <int D, int PREC, int PPT, bool WEIGHTED, typename RT>
+__device__ __forceinline__ void sweep_body(RT r, const int bid)
 {
     DevState* st = r.st;
     if (st->done || st->round_done) return;
@@ -312,7 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(RunDev r)
     __shared__ unsigned long long s_cnt[5];
 
     const int tid = threadIdx.x, lane = tid % kWave;
-    const int tile = blockIdx.x;
+    const int tile = bid;
     const int64_t base = (int64_t)tile * T;
     const int k = r.k;
     const double* __restrict__ C = r.C;
@@ -605,6 +635,21 @@ __global__ __launch_bounds__(kBlock) void k_sweep(RunDev r)
     }
 }
 
+template <int D, int PREC, int PPT, bool WEIGHTED>
+__global__ __launch_bounds__(kBlock) void k_sweep(RunDev r)
+{
+    sweep_body<D, PREC, PPT, WEIGHTED, const RunDev>(r, blockIdx.x);
+}
+
+// Many instances in one launch: block b works on instance map[b].x as its
+// block map[b].y.
+template <int D, int PREC, int PPT, bool WEIGHTED>
+__global__ __launch_bounds__(kBlock) void k_sweep_multi(const RunDev* rs, const int2* map)
+{
+    const int2 m = map[blockIdx.x];
+    sweep_body<D, PREC, PPT, WEIGHTED, const RunDev&>(rs[m.x], m.y);
+}
+
 template <int D, int PREC, bool WEIGHTED>
 hipError_t sweep_ppt(const RunDev& r, hipStream_t s)
 {
@@ -657,6 +702,34 @@ hipError_t launch_tilecand(const RunDev& r, hipStream_t s)
 hipError_t launch_sweep(const RunDev& r, hipStream_t s)
 {
     return r.d == 2 ? sweep_p<2>(r, s) : sweep_p<3>(r, s);
+}
+
+template <int D, int PREC, bool WEIGHTED>
+hipError_t sweep_multi_ppt(const MultiSet& m, hipStream_t s)
+{
+    switch (m.ppt) {
+    case 1: k_sweep_multi<D, PREC, 1, WEIGHTED><<<m.nb_tile, kBlock, 0, s>>>(m.rs, m.map_tile); break;
+    case 2: k_sweep_multi<D, PREC, 2, WEIGHTED><<<m.nb_tile, kBlock, 0, s>>>(m.rs, m.map_tile); break;
+    default: k_sweep_multi<D, PREC, 4, WEIGHTED><<<m.nb_tile, kBlock, 0, s>>>(m.rs, m.map_tile); break;
+    }
+    return hipGetLastError();
+}
+
+template <int D, int PREC>
+hipError_t sweep_multi_p(const MultiSet& m, hipStream_t s)
+{
+    if (m.nb_super) k_supercand_multi<D><<<m.nb_super, kBlock, 0, s>>>(m.rs, m.map_super);
+    if (m.nb_quad) k_tilecand_multi<D, PREC><<<m.nb_quad, kBlock, 0, s>>>(m.rs, m.map_quad);
+    if (!m.nb_tile) return hipGetLastError();
+    return m.weighted ? sweep_multi_ppt<D, PREC, true>(m, s) : sweep_multi_ppt<D, PREC, false>(m, s);
+}
+
+hipError_t launch_sweep_multi(const MultiSet& m, hipStream_t s)
+{
+    const bool f32 = m.precision == BKM_PREC_F32_RECHECK;
+    if (m.d == 2)
+        return f32 ? sweep_multi_p<2, BKM_PREC_F32_RECHECK>(m, s) : sweep_multi_p<2, BKM_PREC_F64>(m, s);
+    return f32 ? sweep_multi_p<3, BKM_PREC_F32_RECHECK>(m, s) : sweep_multi_p<3, BKM_PREC_F64>(m, s);
 }
 
 }  // namespace bkm

@@ -44,8 +44,8 @@ struct OpMax { __device__ double operator()(double a, double b) const { return f
 struct OpMin { __device__ double operator()(double a, double b) const { return fmin(a, b); } };
 struct OpAdd { __device__ double operator()(double a, double b) const { return a + b; } };
 
-template <int D>
-__global__ __launch_bounds__(1024) void k_balance(RunDev r)
+template <int D, typename RT>
+__device__ __forceinline__ void balance_body(RT r, const int bid)
 {
     DevState* st = r.st;
     if (st->done || st->round_done) return;
@@ -97,6 +97,21 @@ __global__ __launch_bounds__(1024) void k_balance(RunDev r)
     }
 }
 
+template <int D>
+__global__ __launch_bounds__(1024) void k_balance(RunDev r)
+{
+    balance_body<D, const RunDev>(r, blockIdx.x);
+}
+
+// Many instances in one launch: block b works on instance map[b].x as its
+// block map[b].y.
+template <int D>
+__global__ __launch_bounds__(1024) void k_balance_multi(const RunDev* rs, const int2* map)
+{
+    const int2 m = map[blockIdx.x];
+    balance_body<D, const RunDev&>(rs[m.x], m.y);
+}
+
 // Round end (Alg. 2): the block coordinate sums for the new centers and the
 // exact block boxes for beta, the average block diameter of the erosion
 // (Sec. 4.2), under the round's final assignment.  One pass block covers
@@ -117,6 +132,7 @@ __global__ __launch_bounds__(1024) void k_balance(RunDev r)
 constexpr int kPassGroups = kBlock;      // one group per thread in the uniform step
 constexpr int kHashSlots = 256;
 constexpr int kMixBatch = 4;             // listed groups a wave has in flight
+constexpr int kRoundThreadsMulti = 1024; // threads per block of the many-instance round end
 
 template <int D>
 struct RoundTable {
@@ -218,8 +234,10 @@ __device__ inline void widen_box(RoundTable<D>& t, const RunDev& r, int slot, in
     }
 }
 
-template <int D, bool WEIGHTED>
-__global__ __launch_bounds__(kBlock) void k_round_end(RunDev r)
+// NT threads per block: kPassGroups of them take one group each in the
+// uniform step; all of them walk the listed groups.
+template <int D, bool WEIGHTED, int NT, typename RT>
+__device__ __forceinline__ void round_end_body(RT r, const int bid)
 {
     const DevState* st = r.st;
     if (st->done || !st->round_done) return;
@@ -227,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_round_end(RunDev r)
     __shared__ int s_list[kPassGroups];
     __shared__ int s_n;
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
-    for (int i = tid; i < kHashSlots; i += kBlock) {
+    for (int i = tid; i < kHashSlots; i += NT) {
         tab.key[i] = -1;
 #pragma unroll
         for (int j = 0; j < D; ++j) {
@@ -239,12 +257,14 @@ __global__ __launch_bounds__(kBlock) void k_round_end(RunDev r)
     if (tid == 0) s_n = 0;
     __syncthreads();
 
-    // groups of one block: their static boxes, one lane per group
-    const int64_t g0 = (int64_t)blockIdx.x * kPassGroups;
+    // groups of one block: their static boxes, one lane per group (the
+    // first kPassGroups threads)
+    const int64_t g0 = (int64_t)bid * kPassGroups;
     const int64_t g = g0 + tid;
-    const int f = g < r.ngroups ? r.gblk[g] : kPad;
-    const bool dirty = g < r.ngroups && r.gdirty[g] != 0;
-    {
+    const bool own = tid < kPassGroups;
+    const int f = own && g < r.ngroups ? r.gblk[g] : kPad;
+    const bool dirty = own && g < r.ngroups && r.gdirty[g] != 0;
+    if (own) {
         unsigned long long mn[D], mx[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) {
@@ -264,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_round_end(RunDev r)
         if (put) widen_box<D>(tab, r, slot, f, mn, mx);
     }
     // mixed groups (boxes) and groups with changed points (sums), listed
-    {
+    if (own) {
         const bool listed = f == -1 || dirty;
         const unsigned long long b = __ballot(listed);
         int pos = 0;
@@ -278,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_round_end(RunDev r)
 #pragma unroll
     for (int j = 0; j < D; ++j) lov[j] = st->lo[j];
     const double sxs = st->sx_scale;
-    constexpr int kWaves = kBlock / kWave;
+    constexpr int kWaves = NT / kWave;   // every wave of the block walks the list
     for (int m0 = wv * kMixBatch; m0 < nl; m0 += kWaves * kMixBatch) {
         int av[kMixBatch], pv[kMixBatch], ent[kMixBatch];
         double xv[kMixBatch][D];
@@ -363,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void k_round_end(RunDev r)
         }
     }
     __syncthreads();
-    for (int i = tid; i < kHashSlots; i += kBlock) {
+    for (int i = tid; i < kHashSlots; i += NT) {
         const int key = tab.key[i];
         if (key < 0) continue;
         unsigned long long* sums = (unsigned long long*)(r.acc + (int64_t)key * kAcc);
@@ -379,10 +399,29 @@ __global__ __launch_bounds__(kBlock) void k_round_end(RunDev r)
     }
 }
 
-// Center movement, convergence, erosion and bound-frame update of one round.
-template <int D>
-__global__ __launch_bounds__(1024) void k_move(RunDev r, double* delta)
+template <int D, bool WEIGHTED>
+__global__ __launch_bounds__(kBlock, 6) void k_round_end(RunDev r)
 {
+    round_end_body<D, WEIGHTED, kBlock, const RunDev>(r, blockIdx.x);
+}
+
+// Many instances in one launch: block b works on instance map[b].x as its
+// block map[b].y.
+// (16 waves per block here: an instance may have only a few blocks, whose
+// walk over their listed groups must not be long)
+template <int D, bool WEIGHTED>
+__global__ __launch_bounds__(kRoundThreadsMulti) void k_round_end_multi(const RunDev* rs, const int2* map)
+{
+    const int2 m = map[blockIdx.x];
+    round_end_body<D, WEIGHTED, kRoundThreadsMulti, const RunDev>(rs[m.x], m.y);
+}
+
+// Center movement, convergence, erosion and bound-frame update of one round.
+template <int D, typename RT>
+__device__ __forceinline__ void move_body(RT r, const int bid)
+{
+    double* delta = r.red;
+    (void)bid;
     DevState* st = r.st;
     if (st->done || !st->round_done) return;
     __shared__ double sh[1024 / kWave];
@@ -463,6 +502,21 @@ __global__ __launch_bounds__(1024) void k_move(RunDev r, double* delta)
         st->sweep_in_round = 0;
     }
     for (int i = threadIdx.x; i < k * 2 * D; i += 1024) r.bb[i] = (i % (2 * D)) < D ? ~0ULL : 0ULL;
+}
+
+template <int D>
+__global__ __launch_bounds__(1024) void k_move(RunDev r)
+{
+    move_body<D, const RunDev>(r, blockIdx.x);
+}
+
+// Many instances in one launch: block b works on instance map[b].x as its
+// block map[b].y.
+template <int D>
+__global__ __launch_bounds__(1024) void k_move_multi(const RunDev* rs, const int2* map)
+{
+    const int2 m = map[blockIdx.x];
+    move_body<D, const RunDev&>(rs[m.x], m.y);
 }
 
 // Fresh run state: influence 1, no assignment, empty sums, open bounds.
@@ -771,9 +825,9 @@ hipError_t launch_block_boxes(const RunDev& r, hipStream_t s)
 hipError_t launch_move(const RunDev& r, hipStream_t s)
 {
     if (r.d == 2)
-        k_move<2><<<1, 1024, 0, s>>>(r, r.red);
+        k_move<2><<<1, 1024, 0, s>>>(r);
     else
-        k_move<3><<<1, 1024, 0, s>>>(r, r.red);
+        k_move<3><<<1, 1024, 0, s>>>(r);
     return hipGetLastError();
 }
 
@@ -815,6 +869,24 @@ hipError_t launch_stats(const RunDev& r, const int32_t* asg, double eps, double*
     }
     k_stats_final<<<1, kBlock, 0, s>>>(r, nparts, eps, out6);
     return hipGetLastError();
+}
+
+template <int D>
+hipError_t update_multi_d(const MultiSet& m, hipStream_t s)
+{
+    k_balance_multi<D><<<m.ninst, 1024, 0, s>>>(m.rs, m.map_inst);
+    if (m.nb_pass) {
+        if (m.weighted) k_round_end_multi<D, true><<<m.nb_pass, kRoundThreadsMulti, 0, s>>>(m.rs, m.map_pass);
+        else k_round_end_multi<D, false><<<m.nb_pass, kRoundThreadsMulti, 0, s>>>(m.rs, m.map_pass);
+    }
+    k_move_multi<D><<<m.ninst, 1024, 0, s>>>(m.rs, m.map_inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_multi(const MultiSet& m, hipStream_t s)
+{
+    static_assert(kPassGroups == kPassGroupsHost, "round-end pass geometry");
+    return m.d == 2 ? update_multi_d<2>(m, s) : update_multi_d<3>(m, s);
 }
 
 }  // namespace bkm

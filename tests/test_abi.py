@@ -27,8 +27,8 @@ def bkm():
 
 def test_header_declares_the_boundary():
     names = declared()
-    for f in ("bkm_init_centers_sfc", "bkm_balanced_kmeans", "bkm_partition_stats",
-              "bkm_last_error"):
+    for f in ("bkm_init_centers_sfc", "bkm_balanced_kmeans", "bkm_balanced_kmeans_batched",
+              "bkm_partition_stats", "bkm_last_error"):
         assert f in names
 
 
@@ -101,6 +101,25 @@ def test_3d_order_limit_and_null_outputs(bkm):
     assert rc == bkm.BKM_EINVAL
     rc = L.bkm_assign_sweeps(C.byref(p), 4, 0, None, None, 0, 1, 0, None, None, None, None)
     assert rc == bkm.BKM_EINVAL
+
+
+def test_batched_argument_errors(bkm):
+    """Checked per instance before any device work; the message names the instance."""
+    L = bkm.lib()
+    pts = (bkm.Points * 3)(_pts(bkm), _pts(bkm, d=3), _pts(bkm))
+    prm = (bkm.Params * 3)(bkm.default_params(10), bkm.default_params(10), bkm.default_params(10))
+    outs = (C.c_void_p * 3)(0x2000, 0x2000, 0x2000)
+    cen = (C.c_void_p * 3)(0x3000, 0x3000, 0x3000)
+    assert L.bkm_balanced_kmeans_batched(pts, prm, 0, outs, cen, None, None) == bkm.BKM_EINVAL
+    assert "count" in L.bkm_last_error().decode()
+    assert L.bkm_balanced_kmeans_batched(None, prm, 3, outs, cen, None, None) == bkm.BKM_EINVAL
+    prm[1].k = 0
+    assert L.bkm_balanced_kmeans_batched(pts, prm, 3, outs, cen, None, None) == bkm.BKM_EINVAL
+    assert L.bkm_last_error().decode().startswith("instance 1: k = 0")
+    prm[1].k = 10
+    cen[2] = None
+    assert L.bkm_balanced_kmeans_batched(pts, prm, 3, outs, cen, None, None) == bkm.BKM_EINVAL
+    assert L.bkm_last_error().decode().startswith("instance 2:")
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
