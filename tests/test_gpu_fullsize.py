@@ -1,0 +1,143 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch
+configuration the benchmark times (default tile size; FP32 screen + FP64
+recheck, and plain FP64 on the 2D refined cloud).
+
+The oracle cannot run these sizes end to end (a brute-force sweep of the 3D
+shell cloud is 2.6e11 distance evaluations), so the checks are:
+  * Hilbert keys of every point against the oracle's keys (bit-exact), the
+    sort order and the initial centers against their definitions (Alg. 2);
+  * sweeps with injected states (Alg. 1, bounds carried across steps):
+    assignments of a random sample of points against the oracle's
+    brute-force argmin computed for those points alone (Sec. 4.2), block
+    weights of every step against an exact count;
+  * full runs: block weights against an exact recount, centers against the
+    weighted means of their blocks (Alg. 2), the balance bound when balanced.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import assert_assignment_parity, cuda, torch, widened
+from paper_1805_01208_amd import workloads
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow, pytest.mark.timeout(900)]
+
+SAMPLE = 20000
+
+
+@pytest.fixture(scope="module")
+def c2():
+    cfg = workloads.c2()
+    return cfg, cuda(cfg["X"])
+
+
+@pytest.fixture(scope="module")
+def c3():
+    cfg = workloads.c3()
+    return cfg, cuda(cfg["X"])
+
+
+@pytest.fixture(scope="module")
+def c5():
+    cfg = workloads.c5()
+    return cfg, cuda(cfg["X"]), torch.from_numpy(cfg["W"]).cuda()
+
+
+def check_bootstrap(cfg, X):
+    from paper_1805_01208_amd import bkm
+    k = cfg["k"]
+    print(f"case full-size bootstrap {cfg['name']} k={k}", flush=True)
+    Xw = widened(cfg["X"])
+    n = len(Xw[0])
+    cen, perm, keys = bkm.init_centers_sfc(X, k, 16)
+    keys = keys.cpu().numpy().view(np.uint64)
+    perm = perm.cpu().numpy().astype(np.int64)
+    assert np.array_equal(keys, oracle.sfc_keys(Xw, 16))
+    # a permutation, sorted by (key, input index)
+    assert np.all(np.bincount(perm, minlength=n) == 1)
+    ks = keys[perm]
+    assert np.all(ks[1:] >= ks[:-1])
+    tie = ks[1:] == ks[:-1]
+    assert np.all(perm[1:][tie] > perm[:-1][tie])
+    pos = (np.arange(k, dtype=np.int64) * n) // k + n // (2 * k)
+    ref = np.stack([x[perm[pos]] for x in Xw], axis=1)
+    assert np.array_equal(cen.cpu().numpy(), ref)
+    return ref
+
+
+def check_sweeps(cfg, X, C0, precision, seed):
+    from paper_1805_01208_amd import bkm
+    k = cfg["k"]
+    Xw = widened(cfg["X"])
+    n = len(Xw[0])
+    ext = max(float(x.max() - x.min()) for x in Xw)
+    rng = np.random.default_rng(seed)
+    Cs = [C0, C0 + rng.normal(0.0, 0.002 * ext, C0.shape),
+          C0 + rng.normal(0.0, 0.01 * ext, C0.shape)]
+    Is = [np.ones(k), rng.uniform(0.95, 1.05, k), rng.uniform(0.8, 1.25, k)]
+    print(f"case full-size sweeps {cfg['name']} n={n} k={k} {precision}", flush=True)
+    A, bw, info = bkm.assign_sweeps(X, torch.from_numpy(np.stack(Cs)), torch.from_numpy(np.stack(Is)),
+                                    precision=precision)
+    A = A.cpu().numpy()
+    bw = bw.cpu().numpy()
+    idx = np.sort(rng.choice(n, size=SAMPLE, replace=False))
+    Xs = [x[idx] for x in Xw]
+    for s in range(len(Cs)):
+        Ao, best, second = oracle.assign(Xs, Cs[s], Is[s])
+        assert_assignment_parity(A[s][idx], Ao, best, second, f"step {s}")
+        assert np.array_equal(bw[s], np.bincount(A[s], minlength=k).astype(np.float64))
+    assert info["skipped"] > 0
+    return info
+
+
+def check_run(cfg, X, W=None, precision="f32_recheck"):
+    from paper_1805_01208_amd import bkm
+    k = cfg["k"]
+    Xw = widened(cfg["X"])
+    Wh = cfg["W"]
+    print(f"case full-size run {cfg['name']} k={k} {precision}", flush=True)
+    g = bkm.balanced_kmeans(X, k, W=W, eps=cfg["eps"], max_iter=50, precision=precision)
+    A = g["A"].cpu().numpy()
+    assert A.min() >= 0 and A.max() < k
+    if Wh is None:
+        cnt = np.bincount(A, minlength=k).astype(np.float64)
+        assert np.array_equal(g["block_weights"].cpu().numpy(), cnt)
+        wsum = cnt
+    else:
+        wsum = np.bincount(A, weights=Wh, minlength=k)
+        assert np.allclose(g["block_weights"].cpu().numpy(), wsum, rtol=1e-12, atol=0)
+    C = g["centers"].cpu().numpy()
+    ext = max(float(x.max() - x.min()) for x in Xw)
+    for j, x in enumerate(Xw):
+        s = np.bincount(A, weights=x if Wh is None else Wh * x, minlength=k)
+        ref = s / np.where(wsum > 0, wsum, 1.0)
+        ne = wsum > 0
+        err = np.max(np.abs(C[ne, j] - ref[ne]))
+        assert err <= 1e-10 * max(ext, float(np.max(np.abs(ref[ne])))), f"axis {j}: {err}"
+    if g["info"]["balanced"]:
+        assert wsum.max() <= g["info"]["l_max"]
+    return g
+
+
+def test_c2_refined2d_16M(c2):
+    cfg, X = c2
+    C0 = check_bootstrap(cfg, X)
+    for prec, seed in (("f64", 21), ("f32_recheck", 22)):
+        check_sweeps(cfg, X, C0, prec, seed)
+    g = check_run(cfg, X, precision="f64")
+    assert g["info"]["balanced"] == 1
+
+
+def test_c3_shells3d_64M(c3):
+    cfg, X = c3
+    C0 = check_bootstrap(cfg, X)
+    check_sweeps(cfg, X, C0, "f32_recheck", 31)
+    g = check_run(cfg, X)
+    assert g["info"]["balanced"] == 1
+
+
+def test_c5_radial2d_250M_weighted(c5):
+    cfg, X, W = c5
+    C0 = check_bootstrap(cfg, X)
+    check_sweeps(cfg, X, C0, "f32_recheck", 51)
+    check_run(cfg, X, W=W)
