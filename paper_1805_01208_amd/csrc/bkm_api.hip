@@ -446,23 +446,33 @@ int bkm_balanced_kmeans(const bkm_points* pts, const bkm_params* prm, const doub
     // One sweep per batch: most AssignAndBalance calls balance after their
     // first sweep, and a batch of one never launches a sweep that has nothing
     // to do.  Every batch ends a call or adds a sweep to it, so the loop is
-    // bounded.
-    DevState h;
-    int prev_rounds = 0;
+    // bounded.  One batch runs ahead: batch b+1 is enqueued before the host
+    // waits for the state copied at the end of batch b, so the device never
+    // idles on the host's decision; a batch enqueued after the end is a no-op.
     const bool timing = p.timing != 0;
-    hipEvent_t tev[6];
-    int ntev = 0;
-    struct TevFree {
-        hipEvent_t* e; int* n;
-        ~TevFree() { for (int i = 0; i < *n; ++i) (void)hipEventDestroy(e[i]); }
-    } tevf{tev, &ntev};
-    if (timing)
-        for (; ntev < 6; ++ntev) HIPCHK(hipEventCreate(&tev[ntev]));
+    struct LoopRes {
+        hipStream_t s;
+        hipEvent_t ev[2][7] = {};
+        DevState* ring = nullptr;
+        ~LoopRes()
+        {
+            (void)hipStreamSynchronize(s);   // no copy into the ring may be left in flight
+            for (auto& row : ev)
+                for (auto e : row)
+                    if (e) (void)hipEventDestroy(e);
+            if (ring) (void)hipHostFree(ring);
+        }
+    } lr{s};
+    HIPCHK(hipHostMalloc((void**)&lr.ring, 2 * sizeof(DevState), hipHostMallocDefault));
+    for (auto& row : lr.ev) {
+        for (int i = 0; i < 6; ++i)
+            if (timing) HIPCHK(hipEventCreate(&row[i]));
+        HIPCHK(hipEventCreateWithFlags(&row[6], hipEventDisableTiming));
+    }
     double tk[5] = {0, 0, 0, 0, 0};
-    auto mark = [&](int i) -> hipError_t { return timing ? hipEventRecord(tev[i], s) : hipSuccess; };
-    const int64_t max_batches = (int64_t)p.max_iter * (p.max_balance_iter + 1) + 8;
-    for (int64_t nb = 0;; ++nb) {
-        if (nb >= max_batches) return fail(BKM_EHIP, "round loop made no progress");
+    auto enqueue = [&](int64_t nb) -> int {
+        hipEvent_t* ev = lr.ev[nb & 1];
+        auto mark = [&](int i) -> hipError_t { return timing ? hipEventRecord(ev[i], s) : hipSuccess; };
         HIPCHK(mark(0));
         HIPCHK(launch_supercand(r, s));
         HIPCHK(launch_tilecand(r, s));
@@ -475,13 +485,25 @@ int bkm_balanced_kmeans(const bkm_points* pts, const bkm_params* prm, const doub
         HIPCHK(mark(4));
         HIPCHK(launch_move(r, s));
         HIPCHK(mark(5));
-        if ((rc = read_state(r, s, &h))) return rc;
+        HIPCHK(hipMemcpyAsync(&lr.ring[nb & 1], r.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(ev[6], s));
+        return BKM_OK;
+    };
+    DevState h;
+    int prev_rounds = 0;
+    const int64_t max_batches = (int64_t)p.max_iter * (p.max_balance_iter + 1) + 8;
+    if ((rc = enqueue(0))) return rc;
+    for (int64_t nb = 0;; ++nb) {
+        if (nb >= max_batches) return fail(BKM_EHIP, "round loop made no progress");
+        if ((rc = enqueue(nb + 1))) return rc;
+        HIPCHK(hipEventSynchronize(lr.ev[nb & 1][6]));
+        h = lr.ring[nb & 1];
         const bool round_ended = h.rounds > prev_rounds;
         if (timing) {
             for (int i = 0; i < 5; ++i) {
                 if (i >= 3 && !round_ended) continue;
                 float ms = 0.0f;
-                HIPCHK(hipEventElapsedTime(&ms, tev[i], tev[i + 1]));
+                HIPCHK(hipEventElapsedTime(&ms, lr.ev[nb & 1][i], lr.ev[nb & 1][i + 1]));
                 tk[i] += ms;
             }
         }
