@@ -34,8 +34,9 @@ def algorithmic_bytes(info, d, precision, weighted):
     """Bytes a sweep must move, from the run's visit counters.
 
     every visit: block id (4) + stored upper and lower bound (4 + 4), read;
-    evaluated:   working coordinates (FP32 tile offsets: 4d, FP64: 8d) read,
-                 both bounds written (8);
+    evaluated:   working coordinates read (FP32 screen: one packed fixed-point
+                 word, 4 bytes in 2D and 8 in 3D; plain FP64: 8d), both bounds
+                 written (8);
     changed:     block id written (4), the weight (8, weighted) read for the
                  block-weight transfer;
     rechecked:   FP64 coordinates read (8d);
@@ -43,7 +44,7 @@ def algorithmic_bytes(info, d, precision, weighted):
     visits = info["evaluated"] + info["skipped"]
     f32 = precision == "f32_recheck"
     b = 12 * visits + 4 * visits / 64
-    b += info["evaluated"] * ((4 * d if f32 else 8 * d) + 8)
+    b += info["evaluated"] * ((4 if d == 2 else 8) if f32 else 8 * d) + info["evaluated"] * 8
     b += info["changed"] * (4 + (8 if weighted else 0))
     if f32:
         b += info["rechecked"] * 8 * d

@@ -124,6 +124,7 @@ void set_layout_size(RunDev& r, int64_t npad)
     r.npad = npad;
     r.ntiles = (int)(npad / r.T);
     r.nsuper = (r.ntiles + r.super_tiles - 1) / r.super_tiles;
+    r.nhyper = (r.nsuper + kHyper - 1) / kHyper;
     r.ngroups = (int)(npad / kWave);
 }
 
@@ -196,13 +197,17 @@ size_t layout(RunDev& r, Arena* a, bool full)
                 both((double*)nullptr, np, r.xs64[j]);
         }
         if (r.precision == BKM_PREC_F32_RECHECK)
-            for (int j = 0; j < d; ++j) both((float*)nullptr, np, r.ofs[j]);
+            both((uint32_t*)nullptr, (size_t)np * (d == 3 ? 2 : 1), *reinterpret_cast<uint32_t**>(&r.ofs));
         if (r.weighted) both((double*)nullptr, np, r.ws);
         both((int32_t*)nullptr, np, r.A);
         both((float*)nullptr, np, r.ubt);
         both((float*)nullptr, np, r.lbt);
         both((double*)nullptr, (size_t)ntiles * 2 * d, r.tbox);
         both((double*)nullptr, (size_t)(np / kWave) * 2 * d, r.gbox);
+        const int64_t nhyper = (nsuper + kHyper - 1) / kHyper;
+        both((double*)nullptr, (size_t)nhyper * 2 * d, r.hbox);
+        both((int32_t*)nullptr, (size_t)nhyper * k, r.hlist);
+        both((int32_t*)nullptr, (size_t)nhyper, r.hcount);
         both((double*)nullptr, (size_t)nsuper * 2 * d, r.sbox);
         both((int32_t*)nullptr, (size_t)nsuper * k, r.slist);
         both((int32_t*)nullptr, (size_t)nsuper, r.scount);
@@ -783,13 +788,14 @@ int bkm_balanced_kmeans_batched(const bkm_points* pts, const bkm_params* prm, in
         z2.add<RunDev>(count);
         for (int i = 0; i < count; ++i) {
             const RunDev& r = rs[i];
+            z2.add<int2>(r.nhyper);
             z2.add<int2>(r.nsuper);
             z2.add<int2>((r.ntiles + kBlock / kWave - 1) / (kBlock / kWave));
             z2.add<int2>(r.ntiles);
             z2.add<int2>((r.ngroups + kPassGroupsHost - 1) / kPassGroupsHost);
         }
         z2.add<int2>(count);
-        z2.total += 64 * 6 * 256;  // per-class rounding (at most 24 classes of 6 arrays)
+        z2.total += 64 * 7 * 256;  // per-class rounding (at most 24 classes of 7 arrays)
         HIPCHK(hipMallocAsync((void**)&a2.base, z2.total, ls));
         a2.cap = z2.total;
     }
@@ -817,7 +823,7 @@ int bkm_balanced_kmeans_batched(const bkm_points* pts, const bkm_params* prm, in
             cls[c].push_back(i);
         }
         hrs.assign(ms.size(), {});
-        hmap.assign(ms.size() * 5, {});
+        hmap.assign(ms.size() * 6, {});
         a2.off = 0;
         for (size_t c = 0; c < ms.size(); ++c) {
             MultiSet& m = ms[c];
@@ -827,23 +833,26 @@ int bkm_balanced_kmeans_batched(const bkm_points* pts, const bkm_params* prm, in
                 hrs[c].push_back(r);
                 const int nq = (r.ntiles + kBlock / kWave - 1) / (kBlock / kWave);
                 const int npass = (r.ngroups + kPassGroupsHost - 1) / kPassGroupsHost;
-                for (int b = 0; b < r.nsuper; ++b) hmap[c * 5 + 0].push_back(make_int2(j, b));
-                for (int b = 0; b < nq; ++b) hmap[c * 5 + 1].push_back(make_int2(j, b));
-                for (int b = 0; b < r.ntiles; ++b) hmap[c * 5 + 2].push_back(make_int2(j, b));
-                for (int b = 0; b < npass; ++b) hmap[c * 5 + 3].push_back(make_int2(j, b));
-                hmap[c * 5 + 4].push_back(make_int2(j, 0));
+                for (int b = 0; b < r.nsuper; ++b) hmap[c * 6 + 0].push_back(make_int2(j, b));
+                for (int b = 0; b < nq; ++b) hmap[c * 6 + 1].push_back(make_int2(j, b));
+                for (int b = 0; b < r.ntiles; ++b) hmap[c * 6 + 2].push_back(make_int2(j, b));
+                for (int b = 0; b < npass; ++b) hmap[c * 6 + 3].push_back(make_int2(j, b));
+                hmap[c * 6 + 4].push_back(make_int2(j, 0));
+                for (int b = 0; b < r.nhyper; ++b) hmap[c * 6 + 5].push_back(make_int2(j, b));
             }
-            m.nb_super = (int)hmap[c * 5 + 0].size();
-            m.nb_quad = (int)hmap[c * 5 + 1].size();
-            m.nb_tile = (int)hmap[c * 5 + 2].size();
-            m.nb_pass = (int)hmap[c * 5 + 3].size();
+            m.nb_super = (int)hmap[c * 6 + 0].size();
+            m.nb_quad = (int)hmap[c * 6 + 1].size();
+            m.nb_tile = (int)hmap[c * 6 + 2].size();
+            m.nb_pass = (int)hmap[c * 6 + 3].size();
+            m.nb_hyper = (int)hmap[c * 6 + 5].size();
             RunDev* drs = a2.take<RunDev>(m.ninst);
             if (a2.off > a2.cap) return fail(BKM_EHIP, "block maps exceed their workspace");
             HIPCHK(hipMemcpyAsync(drs, hrs[c].data(), m.ninst * sizeof(RunDev), hipMemcpyHostToDevice, ls));
             m.rs = drs;
-            const int2** dst[5] = {&m.map_super, &m.map_quad, &m.map_tile, &m.map_pass, &m.map_inst};
-            for (int t = 0; t < 5; ++t) {
-                const std::vector<int2>& v = hmap[c * 5 + t];
+            const int2** dst[6] = {&m.map_super, &m.map_quad, &m.map_tile, &m.map_pass, &m.map_inst,
+                                   &m.map_hyper};
+            for (int t = 0; t < 6; ++t) {
+                const std::vector<int2>& v = hmap[c * 6 + t];
                 int2* d = a2.take<int2>(v.size());
                 if (a2.off > a2.cap) return fail(BKM_EHIP, "block maps exceed their workspace");
                 if (!v.empty())

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <stdint.h>
 
 #include "bkm.h"
@@ -11,7 +12,8 @@ namespace bkm {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;          // threads per block of the point kernels
-constexpr int kTileCap = 128;        // candidate records kept per tile
+constexpr int kTileCap = 128;
+constexpr int kHyper = 16;         // super-tiles per hyper-tile of the candidate hierarchy        // candidate records kept per tile
 constexpr int kFixShift = 30;        // fixed-point sums: term = hi * 2^30 + lo
 constexpr long long kFixLoMask = (1LL << kFixShift) - 1;
 constexpr int kPad = -2;             // block id of a padding point (never evaluated)
@@ -58,11 +60,11 @@ enum { kCntEvaluated = 0, kCntSkipped, kCntRechecked, kCntChanged, kCntCandEvals
 struct TileHead {
     int32_t n;                // records in use
     int32_t overflow;         // 1: more than kTileCap candidates; sweep the super-tile list
-    int32_t pad0, pad1;
+    float step[3];            // FP32 value of one unit of the tile's fixed-point offsets, per axis
+    float pad;
     double tau;               // bound on |FP32 effective distance - exact| over the candidates
     double dmax;              // bound on |FP32 distance - exact| over the candidates
     double lb_out;            // lower bound on the effective distance of every center left out
-    double pad2;
 };
 
 // One candidate center of a tile: FP32 offset of the center from the tile
@@ -79,7 +81,7 @@ struct RunDev {
     int64_t n, npad, npad_cap;  // points, padded layout size, its capacity
     int d, k, in_f32, weighted;
     int maxjumps;
-    int T, ppt, ntiles, super_tiles, nsuper, ngroups;
+    int T, ppt, ntiles, super_tiles, nsuper, nhyper, ngroups;
     int precision, use_bounds;
     double recheck_gap;
 
@@ -88,7 +90,8 @@ struct RunDev {
 
     double* xs64[3];          // sorted master coordinates (FP64 input)
     float* xs32[3];           // sorted master coordinates (FP32 input)
-    float* ofs[3];            // FP32 offsets from the tile anchor (FP32 sweep)
+    void* ofs;                // packed fixed-point offsets from the tile anchor, one word
+                              // per point (FP32 sweep): 2D 32 bits, 3D 64 bits
     double* ws;               // sorted weights or null
     int32_t* sperm;           // Hilbert order -> input index (n entries, no padding)
     int32_t* perm;            // padded layout position -> input index, -1 for padding
@@ -102,6 +105,9 @@ struct RunDev {
     float* lbt;               // stored lower bounds (lazy frame)
     double* tbox;             // [ntiles][2d] lo..., hi...
     double* gbox;             // [ngroups][2d] boxes of 64-point groups
+    double* hbox;             // [nhyper][2d] boxes of hyper-tiles (kHyper super-tiles)
+    int32_t* hlist;           // [nhyper][k] candidate centers of each hyper-tile
+    int32_t* hcount;          // [nhyper]
     double* sbox;             // [nsuper][2d]
     int32_t* slist;           // [nsuper][k] candidate centers of each super-tile
     int32_t* scount;          // [nsuper]
@@ -153,6 +159,56 @@ __device__ inline void coord_terms(const double* x, const double* lo, double w, 
         t[2 * j] = h;
         t[2 * j + 1] = l;
     }
+}
+
+// Fixed-point point offsets of the FP32 screen: per tile and axis, the
+// offset from the tile anchor X (box center) in units of h/FixMax, h the box
+// half-extent on that axis, rounded to nearest; one packed word per point:
+// 2D two 16-bit fields in 32 bits, 3D three 21-bit fields in 64 bits.
+template <int D> struct FixPack;
+template <> struct FixPack<2> {
+    using word = uint32_t;
+    static constexpr int kBits = 16;
+    static constexpr double kMax = 32767.0;
+};
+template <> struct FixPack<3> {
+    using word = unsigned long long;
+    static constexpr int kBits = 21;
+    static constexpr double kMax = 1048575.0;
+};
+
+// Field value of offset v on an axis of half-extent h.
+template <int D>
+__device__ inline long long fix_offset(double v, double h)
+{
+    constexpr double m = FixPack<D>::kMax;
+    if (!(h > 0.0)) return 0;
+    double q = rint(v / h * m);
+    q = fmin(fmax(q, -m), m);
+    return (long long)q;
+}
+
+template <int D>
+__device__ inline typename FixPack<D>::word fix_pack(const long long* q)
+{
+    using W = typename FixPack<D>::word;
+    constexpr int b = FixPack<D>::kBits;
+    constexpr W mask = (W(1) << b) - 1;
+    W w = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) w |= ((W)q[j] & mask) << (b * j);
+    return w;
+}
+
+// Field j of a packed word, sign-extended, as FP32 (exact: |field| < 2^21).
+template <int D>
+__device__ inline float fix_field(typename FixPack<D>::word w, int j)
+{
+    constexpr int b = FixPack<D>::kBits;
+    constexpr int nb = 8 * (int)sizeof(w);
+    using S = std::conditional_t<D == 3, long long, int>;
+    const S v = (S)(w << (nb - b * (j + 1))) >> (nb - b);
+    return (float)v;
 }
 
 // ------------------------------------------------------------------ helpers
@@ -303,7 +359,8 @@ struct MultiSet {
     const int2* map_tile;      // one block per tile
     const int2* map_pass;      // one block per kPassGroups groups
     const int2* map_inst;      // one block per instance
-    int nb_super, nb_quad, nb_tile, nb_pass;
+    const int2* map_hyper;     // one block per hyper-tile
+    int nb_super, nb_quad, nb_tile, nb_pass, nb_hyper;
 };
 constexpr int kPassGroupsHost = 256;   // groups per block of the round-end pass
 hipError_t launch_sweep_multi(const MultiSet& m, hipStream_t s);    // candidates + sweep

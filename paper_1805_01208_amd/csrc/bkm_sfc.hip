@@ -495,7 +495,8 @@ __device__ inline double xs_at(const RunDev& r, int j, int64_t i)
 }
 
 // Per tile (one block of T sorted points): exact FP64 box, boxes of its
-// 64-point groups, and the FP32 offsets of its points from the box center.
+// 64-point groups, and the fixed-point offsets of its points from the box
+// center.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_tile_prep(RunDev r)
 {
@@ -548,13 +549,18 @@ __global__ __launch_bounds__(kBlock) void k_tile_prep(RunDev r)
     }
     __syncthreads();
     if (r.precision == BKM_PREC_F32_RECHECK) {
-        double X[D];
+        double X[D], h[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) X[j] = 0.5 * (box[j] + box[D + j]);
+        for (int j = 0; j < D; ++j) {
+            X[j] = 0.5 * (box[j] + box[D + j]);
+            h[j] = fmax(box[D + j] - X[j], X[j] - box[j]);
+        }
         for (int q = 0; q < r.ppt; ++q) {
             const int64_t i = base + (int64_t)q * kBlock + threadIdx.x;
+            long long f[D];
 #pragma unroll
-            for (int j = 0; j < D; ++j) r.ofs[j][i] = (float)(xs_at(r, j, i) - X[j]);
+            for (int j = 0; j < D; ++j) f[j] = fix_offset<D>(xs_at(r, j, i) - X[j], h[j]);
+            static_cast<typename FixPack<D>::word*>(r.ofs)[i] = fix_pack<D>(f);
         }
     }
 }
@@ -582,6 +588,31 @@ __global__ __launch_bounds__(kBlock) void k_super_boxes(RunDev r)
     }
 #pragma unroll
     for (int j = 0; j < 2 * D; ++j) r.sbox[(int64_t)s * 2 * D + j] = b[j];
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_hyper_boxes(RunDev r)
+{
+    const int h = blockIdx.x * kBlock + threadIdx.x;
+    if (h >= r.nhyper) return;
+    const int s0 = h * kHyper;
+    const int s1 = min(r.nsuper, s0 + kHyper);
+    double b[2 * D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        b[j] = INFINITY;
+        b[D + j] = -INFINITY;
+    }
+    for (int s = s0; s < s1; ++s) {
+        const double* sb = r.sbox + (int64_t)s * 2 * D;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            b[j] = fmin(b[j], sb[j]);
+            b[D + j] = fmax(b[D + j], sb[D + j]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 2 * D; ++j) r.hbox[(int64_t)h * 2 * D + j] = b[j];
 }
 
 // Initial centers: center c is the sorted point floor(c*n/k) + floor(n/(2k)).
@@ -691,9 +722,11 @@ hipError_t launch_tile_prep(const RunDev& r, hipStream_t s)
     if (r.d == 2) {
         k_tile_prep<2><<<r.ntiles, kBlock, 0, s>>>(r);
         k_super_boxes<2><<<nblocks(r.nsuper, kBlock), kBlock, 0, s>>>(r);
+        k_hyper_boxes<2><<<nblocks(r.nhyper, kBlock), kBlock, 0, s>>>(r);
     } else {
         k_tile_prep<3><<<r.ntiles, kBlock, 0, s>>>(r);
         k_super_boxes<3><<<nblocks(r.nsuper, kBlock), kBlock, 0, s>>>(r);
+        k_hyper_boxes<3><<<nblocks(r.nhyper, kBlock), kBlock, 0, s>>>(r);
     }
     return hipGetLastError();
 }

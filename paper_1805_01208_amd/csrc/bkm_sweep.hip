@@ -34,6 +34,8 @@ namespace bkm {
 namespace {
 
 constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24, unit roundoff of FP32
+constexpr double kFixPt2 = 1.53e-05;               // >= 1.0001 * 2^-16: 16-bit point offsets, times Rn
+constexpr double kFixPt3 = 4.77e-07;               // >= 1.0001 * 2^-21: 21-bit point offsets, times Rn
 constexpr double kCandSlack = 1e-9;               // relative slack of the center filter
 constexpr double kTiny = 1e-12;                   // relative slack of FP64 bound arithmetic
 constexpr double kInf = INFINITY;
@@ -81,24 +83,27 @@ __device__ inline double sorted_coord(const RunDev& r, int j, int64_t p)
     return r.in_f32 ? (double)r.xs32[j][p] : r.xs64[j][p];
 }
 
-// ------------------------------------------------------------ super-tiles
+// ------------------------------------------------- hyper- and super-tiles
+// Candidate filter of one box [lo, hi] against the centers of `list` (all k
+// centers when list is NULL): c stays iff its smallest effective distance to
+// the box is at most the second-smallest largest one (Sec. 4.4: no point of
+// the box can have c as best or second-best otherwise).  A box inside a
+// parent box may filter the parent's list instead of all centers: its
+// smallest distances are no smaller and its second-smallest largest distance
+// is no larger, so every center the parent drops it drops too, and the two
+// centers of its smallest largest distances are on the parent's list.
 template <int D, typename RT>
-__device__ __forceinline__ void supercand_body(RT r, const int bid)
+__device__ __forceinline__ void box_filter(RT r, const double* lo, const double* hi,
+                                           const int* __restrict__ list, int L, int* out,
+                                           int* count_out)
 {
-    const DevState* st = r.st;
-    if (st->done || st->round_done) return;
     __shared__ double sa[kBlock / kWave], sb[kBlock / kWave];
     __shared__ int cnt;
-    const int s = bid, tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     const int k = r.k;
-    double lo[D], hi[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-        lo[j] = r.sbox[(int64_t)s * 2 * D + j];
-        hi[j] = r.sbox[(int64_t)s * 2 * D + D + j];
-    }
     Two t{kInf, kInf};
-    for (int c = tid; c < k; c += kBlock) {
+    for (int i = tid; i < L; i += kBlock) {
+        const int c = list ? list[i] : i;
         double lo2, hi2;
         box_eff2<D>(lo, hi, r.C, k, c, r.clus[c].y, lo2, hi2);
         t = merge_two(t, Two{hi2, kInf});
@@ -113,12 +118,13 @@ __device__ __forceinline__ void supercand_body(RT r, const int bid)
     Two all{sa[0], sb[0]};
     for (int w = 1; w < kBlock / kWave; ++w) all = merge_two(all, Two{sa[w], sb[w]});
     const double thr2 = all.b * (1.0 + 2.0 * kCandSlack);
-    int* out = r.slist + (int64_t)s * k;
     const unsigned long long below = (1ULL << lane) - 1ULL;
-    for (int c0 = 0; c0 < k; c0 += kBlock) {
-        const int c = c0 + tid;
+    for (int i0 = 0; i0 < L; i0 += kBlock) {
+        const int i = i0 + tid;
+        int c = 0;
         bool keep = false;
-        if (c < k) {
+        if (i < L) {
+            c = list ? list[i] : i;
             double lo2, hi2;
             box_eff2<D>(lo, hi, r.C, k, c, r.clus[c].y, lo2, hi2);
             keep = lo2 <= thr2;
@@ -130,7 +136,52 @@ __device__ __forceinline__ void supercand_body(RT r, const int bid)
         if (keep) out[off + __popcll(b & below)] = c;
     }
     __syncthreads();
-    if (tid == 0) r.scount[s] = cnt;
+    if (tid == 0) *count_out = cnt;
+}
+
+// Hyper-tiles (kHyper super-tiles) against all k centers.
+template <int D, typename RT>
+__device__ __forceinline__ void hypercand_body(RT r, const int bid)
+{
+    const DevState* st = r.st;
+    if (st->done || st->round_done) return;
+    double lo[D], hi[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        lo[j] = r.hbox[(int64_t)bid * 2 * D + j];
+        hi[j] = r.hbox[(int64_t)bid * 2 * D + D + j];
+    }
+    box_filter<D, RT>(r, lo, hi, nullptr, r.k, r.hlist + (int64_t)bid * r.k, r.hcount + bid);
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_hypercand(RunDev r)
+{
+    hypercand_body<D, const RunDev>(r, blockIdx.x);
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_hypercand_multi(const RunDev* rs, const int2* map)
+{
+    const int2 m = map[blockIdx.x];
+    hypercand_body<D, const RunDev&>(rs[m.x], m.y);
+}
+
+// Super-tiles against their hyper-tile's list.
+template <int D, typename RT>
+__device__ __forceinline__ void supercand_body(RT r, const int bid)
+{
+    const DevState* st = r.st;
+    if (st->done || st->round_done) return;
+    double lo[D], hi[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        lo[j] = r.sbox[(int64_t)bid * 2 * D + j];
+        hi[j] = r.sbox[(int64_t)bid * 2 * D + D + j];
+    }
+    const int h = bid / kHyper;
+    box_filter<D, RT>(r, lo, hi, r.hlist + (int64_t)h * r.k, r.hcount[h],
+                      r.slist + (int64_t)bid * r.k, r.scount + bid);
 }
 
 template <int D>
@@ -152,13 +203,18 @@ __global__ __launch_bounds__(kBlock) void k_supercand_multi(const RunDev* rs, co
 // One wave per tile: filter the super-tile list against the tile box and
 // write the survivors' records plus the FP32 error bounds of the tile.
 //
-// FP32 error bound.  With anchor X (tile box center), half-extent norm Rn and
-// a candidate c at distance r_c from X, the FP32 offsets of point and center
-// are each within 1.0001*u*(Rn + r_c) of exact (u = 2^-24), their difference
-// within 2.001*u*(Rn + r_c), and the FP32 norm (two fused multiply-adds and a
-// square root) within 3.6*u*(Rn + r_c) of the exact distance; dmax uses
-// 8*u*(Rn + r_c), and tau that times 1/influence(c), maximised over the
-// candidates.
+// FP32 error bound.  Points enter the FP32 screen as fixed-point offsets
+// from the tile anchor X (tile box center): on axis j in units of h_j/M, h_j
+// the box half-extent, rounded to nearest, with M = 2^15 - 1 (2D, 16-bit
+// fields) or 2^20 - 1 (3D, 21-bit fields), so each stored coordinate is
+// within h_j/(2M) of exact and the point within 1.0001*Rn/(2M), Rn the norm of
+// the half-extents (2^-16 resp. 2^-21 relative).  The FP32 value of a point
+// coordinate (unit times integer, the unit itself rounded) adds 2*u*Rn
+// (u = 2^-24); the FP32 center offset is within 1.0001*u*r_c, r_c the
+// distance of center c from X; the FP32 difference and norm (two fused
+// multiply-adds and a square root) add at most 3.6*u*(Rn + r_c).  dmax uses
+// Rn/(2M)*1.0001 + 8*u*(Rn + r_c), and tau that times 1/influence(c),
+// maximised over the candidates.
 template <int D, int PREC, typename RT>
 __device__ __forceinline__ void tilecand_body(RT r, const int bid)
 {
@@ -174,6 +230,7 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
 
     double blo[D], bhi[D], X[D];
     double rn2 = 0.0;
+    float step[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         blo[j] = r.tbox[(int64_t)tile * 2 * D + j];
@@ -181,8 +238,10 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
         X[j] = 0.5 * (blo[j] + bhi[j]);
         const double h = fmax(bhi[j] - X[j], X[j] - blo[j]);
         rn2 += h * h;
+        step[j] = (float)(h / FixPack<D>::kMax);
     }
     const double Rn = sqrt(rn2) * (1.0 + kTiny);
+    const double pnt = (D == 3 ? kFixPt3 : kFixPt2) * Rn;   // fixed-point term of the bound
     const int sidx = tile / r.super_tiles;
     const int L = r.scount[sidx];
     const int* __restrict__ sl = r.slist + (int64_t)sidx * k;
@@ -203,7 +262,7 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
                 q[j] = C[(int64_t)j * k + c] - X[j];
                 dd += q[j] * q[j];
             }
-            const double delta = 8.0 * kU32 * (Rn + sqrt(dd) * (1.0 + kTiny));
+            const double delta = pnt + 8.0 * kU32 * (Rn + sqrt(dd) * (1.0 + kTiny));
             dmax = fmax(dmax, delta);
             tau = fmax(tau, delta * iv);
             if (pos < kTileCap) {
@@ -279,7 +338,7 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
                 const double v = C[(int64_t)j * k + c] - X[j];
                 dd += v * v;
             }
-            const double delta = 8.0 * kU32 * (Rn + sqrt(dd) * (1.0 + kTiny));
+            const double delta = pnt + 8.0 * kU32 * (Rn + sqrt(dd) * (1.0 + kTiny));
             dmax = fmax(dmax, delta);
             tau = fmax(tau, delta * r.clus[c].y);
         }
@@ -290,11 +349,13 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
         TileHead h;
         h.n = overflow ? 0 : cnt;
         h.overflow = overflow ? 1 : 0;
-        h.pad0 = h.pad1 = 0;
         h.tau = tau * (1.0 + kTiny);
         h.dmax = dmax * (1.0 + kTiny);
         h.lb_out = sqrt(t.b) * (1.0 - kTiny);
-        h.pad2 = 0.0;
+        h.step[0] = step[0];
+        h.step[1] = step[1];
+        h.step[2] = step[2];
+        h.pad = 0.0f;
         r.thead[tile] = h;
     }
 }
@@ -339,7 +400,7 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
     __shared__ int s_cid[kTileCap];
     __shared__ double s_c64[F32 ? 1 : 4][F32 ? 1 : kTileCap];
     __shared__ int s_nl;
-    __shared__ unsigned long long s_cnt[5];
+    __shared__ unsigned long long s_cnt[kBlock / kWave][5];   // counters of each wave
 
     const int tid = threadIdx.x, lane = tid % kWave;
     const int tile = bid;
@@ -347,7 +408,6 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
     const int k = r.k;
     const double* __restrict__ C = r.C;
     const double* __restrict__ I = r.I;
-    if (tid < 5) s_cnt[tid] = 0;
     if (tid == 0) s_nl = 0;
     if (tid < T / kWave) s_gdirty[tid] = 0;
 
@@ -391,6 +451,7 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
         bool ev = aold[q] != kPad && ncand > 0;
+        bool sk = false;
         if (ev && r.use_bounds && aold[q] >= 0) {
             // Hamerly test (Sec. 4.3): upper bound on the own effective
             // distance below the lower bound on the second-best one.  FP32
@@ -402,17 +463,19 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
             const float lb = (m - Ef) - 0x1p-20f * (m + Ef);
             if (ub < lb) {
                 ev = false;
-                ++n_skip;
+                sk = true;
             }
         }
         const unsigned long long b = __ballot(ev);
+        // counters are wave-uniform: popcounts of ballots
+        n_skip += (unsigned)__popcll(__ballot(sk));
+        n_eval += (unsigned)__popcll(b);
         int pos = 0;
         if (lane == 0 && b) pos = atomicAdd(&s_nl, (int)__popcll(b));
         pos = __shfl(pos, 0, kWave) + (int)__popcll(b & below);
         if (ev) {
             s_off[pos] = q * kBlock + tid;
             s_aold[pos] = aold[q];
-            ++n_eval;
         }
         // the wave holds one whole 64-point group here: its common block
         const int a0 = __shfl(aold[q], 0, kWave);
@@ -446,31 +509,62 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
         for (int j = 0; j < D; ++j) {
             o[j] = 0.0f;
             x[j] = 0.0;
-            if (act) {
-                if (F32)
-                    o[j] = r.ofs[j][p];
-                else
-                    x[j] = sorted_coord(r, j, p);
+        }
+        if (act) {
+            if (F32) {
+                // one load per point: its packed fixed-point offsets
+                const auto w = static_cast<const typename FixPack<D>::word*>(r.ofs)[p];
+#pragma unroll
+                for (int j = 0; j < D; ++j) o[j] = fix_field<D>(w, j) * hd.step[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < D; ++j) x[j] = sorted_coord(r, j, p);
             }
         }
         // best and second-best over the tile's candidates
-        float b2 = INFINITY, s2 = INFINITY, bd2 = INFINITY;
+        float b2 = INFINITY, s2 = INFINITY;
+        int bi = 0;
         double be = kInf, se = kInf, bs2 = kInf;
         int bc = 0x7fffffff;
-        auto consider32 = [&](int c, float qx, float qy, float qz, float w2) {
+        // FP32 squared distance (scaled units) and effective squared distance
+        auto eff32 = [&](float qx, float qy, float qz, float w2, float& d2) {
             const float dx = o[0] - qx;
             const float dy = o[1] - qy;
-            float d2 = dx * dx;
+            d2 = dx * dx;
             d2 = __builtin_fmaf(dy, dy, d2);
             if (D == 3) {
                 const float dz = o[D - 1] - qz;
                 d2 = __builtin_fmaf(dz, dz, d2);
             }
-            const float e2 = d2 * w2;
+            return d2 * w2;
+        };
+        // the FP32 record of candidate c0 of the tile (the overflow path
+        // forms it from the centers)
+        auto rec32 = [&](int c0, int& c, float& qx, float& qy, float& qz, float& w2) {
+            if (!hd.overflow) {
+                c = s_cid[c0];
+                const float4 qv = s_q[c0];
+                qx = qv.x;
+                qy = qv.y;
+                qz = qv.z;
+                w2 = qv.w;
+            } else {
+                c = sl[c0];
+                const float fi = (float)r.clus[c].y;
+                qx = (float)(C[c] - X[0]);
+                qy = (float)(C[(int64_t)k + c] - X[1]);
+                qz = D == 3 ? (float)(C[(int64_t)(D - 1) * k + c] - X[D - 1]) : 0.0f;
+                w2 = fi * fi;
+            }
+        };
+        // best and second-best FP32 values with b2 <= s2: the new second is
+        // the median of (b2, s2, e2); only the best's record index is kept
+        auto consider32 = [&](int c0, float qx, float qy, float qz, float w2) {
+            float d2;
+            const float e2 = eff32(qx, qy, qz, w2, d2);
             const bool better = e2 < b2;
-            s2 = better ? b2 : fminf(s2, e2);
-            bd2 = better ? d2 : bd2;
-            bc = better ? c : bc;
+            s2 = __builtin_amdgcn_fmed3f(b2, s2, e2);
+            bi = better ? c0 : bi;
             b2 = better ? e2 : b2;
         };
         auto consider64 = [&](int c, double cx, double cy, double cz, double ic) {
@@ -488,7 +582,7 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
                     const int c = s_cid[c0];
                     if (F32) {
                         const float4 qv = s_q[c0];
-                        consider32(c, qv.x, qv.y, qv.z, qv.w);
+                        consider32(c0, qv.x, qv.y, qv.z, qv.w);
                     } else {
                         consider64(c, s_c64[0][F32 ? 0 : c0], s_c64[F32 ? 0 : 1][F32 ? 0 : c0],
                                    s_c64[F32 ? 0 : 2][F32 ? 0 : c0], s_c64[F32 ? 0 : 3][F32 ? 0 : c0]);
@@ -498,10 +592,10 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
                 for (int c0 = 0; c0 < ncand; ++c0) {
                     const int c = sl[c0];
                     if (F32) {
-                        const float fi = (float)r.clus[c].y;
-                        consider32(c, (float)(C[c] - X[0]), (float)(C[(int64_t)k + c] - X[1]),
-                                   D == 3 ? (float)(C[(int64_t)(D - 1) * k + c] - X[D - 1]) : 0.0f,
-                                   fi * fi);
+                        int cc;
+                        float qx, qy, qz, w2;
+                        rec32(c0, cc, qx, qy, qz, w2);
+                        consider32(c0, qx, qy, qz, w2);
                     } else {
                         consider64(c, C[c], C[(int64_t)k + c],
                                    D == 3 ? C[(int64_t)(D - 1) * k + c] : 0.0, I[c]);
@@ -510,11 +604,19 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
             }
         }
         int cbest = ao;
-        bool chg = false;
+        bool chg = false, rck = false;
         long long wh = 1, wl = 0;
         if (act) {
             double ubd, lb;
             if (F32) {
+                // the best candidate's id and FP32 squared distance, recomputed
+                // from its record exactly as in the loop
+                float bd2;
+                {
+                    float qx, qy, qz, w2;
+                    rec32(bi, bc, qx, qy, qz, w2);
+                    (void)eff32(qx, qy, qz, w2, bd2);
+                }
                 const float eb = __builtin_sqrtf(b2);
                 const float es = __builtin_sqrtf(s2);
                 // one candidate: certain; an overflowed FP32 value: decide in FP64
@@ -529,14 +631,23 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
                     ubd = (double)__builtin_sqrtf(bd2) * (1.0 + 4.0 * kU32) + hd.dmax;
                     lb = (double)es * (1.0 - 8.0 * kU32) - hd.tau;
                 } else {
-                    // FP64 recheck over every candidate of the tile
-                    ++n_rechk;
+                    // FP64 recheck of the candidates that can still be the best:
+                    // every FP32 value is within [e(1-8u) - tau, e(1+8u) + tau] of
+                    // exact, so the exact best has e(1-8u) <= eb(1+8u) + 2 tau
+                    // (the window), and every candidate outside it is farther
+                    // than window - tau.
+                    rck = true;
 #pragma unroll
                     for (int j = 0; j < D; ++j) x[j] = sorted_coord(r, j, p);
+                    const double win = (double)eb * (1.0 + 8.0 * kU32) + 2.0 * hd.tau;
                     double b = kInf, s = kInf, bsq = kInf;
                     int bcc = 0x7fffffff;
                     for (int c0 = 0; c0 < ncand; ++c0) {
-                        const int c = hd.overflow ? sl[c0] : s_cid[c0];
+                        int c;
+                        float qx, qy, qz, w2, d2;
+                        rec32(c0, c, qx, qy, qz, w2);
+                        const float e32 = __builtin_sqrtf(eff32(qx, qy, qz, w2, d2));
+                        if (!((double)e32 * (1.0 - 8.0 * kU32) <= win)) continue;
                         double sq;
                         const double e = eff64<D>(x, C[c], C[(int64_t)k + c],
                                                   D == 3 ? C[(int64_t)(D - 1) * k + c] : 0.0, I[c], sq);
@@ -551,7 +662,7 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
                     }
                     cbest = bcc;
                     ubd = sqrt(bsq) * (1.0 + kTiny);
-                    lb = s * (1.0 - kTiny);
+                    lb = fmin(s, win - hd.tau) * (1.0 - kTiny);
                 }
             } else {
                 cbest = bc;
@@ -571,15 +682,16 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
             }
             if (cbest != ao) {
                 chg = true;
-                ++n_chg;
                 r.A[p] = cbest;
                 s_gflag[off / kWave] = -1;   // conservatively mixed from now on
                 s_gdirty[off / kWave] = 1;
                 if (WEIGHTED) fix_split(r.ws[p] * wsc, wh, wl);
             }
         }
+        n_rechk += (unsigned)__popcll(__ballot(rck));
         // wave-aggregated transfer of the point's weight from the old to the new block
         unsigned long long pend = __ballot(chg);
+        n_chg += (unsigned)__popcll(pend);
         while (pend) {
             const int leader = __builtin_ctzll(pend);
             const int ka = __shfl(ao, leader, kWave);
@@ -607,15 +719,14 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
         }
     }
 
-    // counters: wave sums, then one slot per 64 tiles (never a single address)
-    unsigned long long cv[5] = {n_eval, n_skip, n_rechk, n_chg,
-                                (unsigned long long)n_eval * (unsigned long long)ncand};
-#pragma unroll
-    for (int j = 0; j < 5; ++j) cv[j] = (unsigned long long)wave_sum_ll((long long)cv[j]);
+    // counters: per wave in LDS, then per block one slot of 64 (never a single address)
     if (lane == 0) {
-#pragma unroll
-        for (int j = 0; j < 5; ++j)
-            if (cv[j]) atomicAdd(&s_cnt[j], cv[j]);
+        const int wv = tid / kWave;
+        s_cnt[wv][0] = n_eval;
+        s_cnt[wv][1] = n_skip;
+        s_cnt[wv][2] = n_rechk;
+        s_cnt[wv][3] = n_chg;
+        s_cnt[wv][4] = (unsigned long long)n_eval * (unsigned long long)ncand;
     }
     __syncthreads();
     // per 64-point group: the common block of its points (or -1, also when a
@@ -625,9 +736,12 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
         // the round-end pass moves the coordinate sums of these groups' points
         if (s_gdirty[tid]) r.gdirty[base / kWave + tid] = 1;
     }
-    if (tid < 5 && s_cnt[tid]) {
+    if (tid < 5) {
+        unsigned long long v = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / kWave; ++w) v += s_cnt[w][tid];
         unsigned long long* slot = r.cnt + (int64_t)(tile % kCntSlots) * kCntWords;
-        atomicAdd(slot + tid, s_cnt[tid]);
+        if (v) atomicAdd(slot + tid, v);
     }
     if (tid == 0 && hd.overflow) {
         unsigned long long* slot = r.cnt + (int64_t)(tile % kCntSlots) * kCntWords;
@@ -636,7 +750,7 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
 }
 
 template <int D, int PREC, int PPT, bool WEIGHTED>
-__global__ __launch_bounds__(kBlock) void k_sweep(RunDev r)
+__global__ __launch_bounds__(kBlock, 7) void k_sweep(RunDev r)
 {
     sweep_body<D, PREC, PPT, WEIGHTED, const RunDev>(r, blockIdx.x);
 }
@@ -678,10 +792,13 @@ hipError_t sweep_p(const RunDev& r, hipStream_t s)
 
 hipError_t launch_supercand(const RunDev& r, hipStream_t s)
 {
-    if (r.d == 2)
+    if (r.d == 2) {
+        k_hypercand<2><<<r.nhyper, kBlock, 0, s>>>(r);
         k_supercand<2><<<r.nsuper, kBlock, 0, s>>>(r);
-    else
+    } else {
+        k_hypercand<3><<<r.nhyper, kBlock, 0, s>>>(r);
         k_supercand<3><<<r.nsuper, kBlock, 0, s>>>(r);
+    }
     return hipGetLastError();
 }
 
@@ -718,6 +835,7 @@ hipError_t sweep_multi_ppt(const MultiSet& m, hipStream_t s)
 template <int D, int PREC>
 hipError_t sweep_multi_p(const MultiSet& m, hipStream_t s)
 {
+    if (m.nb_hyper) k_hypercand_multi<D><<<m.nb_hyper, kBlock, 0, s>>>(m.rs, m.map_hyper);
     if (m.nb_super) k_supercand_multi<D><<<m.nb_super, kBlock, 0, s>>>(m.rs, m.map_super);
     if (m.nb_quad) k_tilecand_multi<D, PREC><<<m.nb_quad, kBlock, 0, s>>>(m.rs, m.map_quad);
     if (!m.nb_tile) return hipGetLastError();
