@@ -410,7 +410,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_round_end(RunDev r)
 // (16 waves per block here: an instance may have only a few blocks, whose
 // walk over their listed groups must not be long)
 template <int D, bool WEIGHTED>
-__global__ __launch_bounds__(kRoundThreadsMulti) void k_round_end_multi(const RunDev* rs, const int2* map)
+__global__ __launch_bounds__(kRoundThreadsMulti, 2) void k_round_end_multi(const RunDev* rs, const int2* map)
 {
     const int2 m = map[blockIdx.x];
     round_end_body<D, WEIGHTED, kRoundThreadsMulti, const RunDev>(rs[m.x], m.y);
