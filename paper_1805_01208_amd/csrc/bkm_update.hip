@@ -138,7 +138,7 @@ template <int D>
 struct RoundTable {
     int key[kHashSlots];
     unsigned long long sum[kHashSlots][2 * D];   // two's complement fixed-point sums
-    unsigned long long box[kHashSlots][2 * D];   // D minima, D maxima (encoded)
+    double box[kHashSlots][2 * D];               // D minima, D maxima
 };
 
 // Slot of `key` in the table (inserted if new), or -1 when the table is full.
@@ -209,28 +209,39 @@ __device__ inline bool run_box(int key, unsigned long long* mn, unsigned long lo
     return lane == kWave - 1 || ((hm >> (lane + 1)) & 1ULL);
 }
 
-// Adds sign * v to a slot's sums (or to block c's global sums without a slot).
+// Adds v (or -v) to a slot's sums (or to block c's global sums without a slot).
 template <int D>
 __device__ inline void add_sums(RoundTable<D>& t, const RunDev& r, int slot, int c,
-                                const long long* v, long long sign)
+                                const long long* v, bool negate)
 {
     unsigned long long* dst =
         slot >= 0 ? t.sum[slot] : (unsigned long long*)(r.acc + (int64_t)c * kAcc);
 #pragma unroll
-    for (int j = 0; j < 2 * D; ++j) atomicAdd(dst + j, (unsigned long long)(sign * v[j]));
+    for (int j = 0; j < 2 * D; ++j)
+        atomicAdd(dst + j, negate ? 0ULL - (unsigned long long)v[j] : (unsigned long long)v[j]);
 }
 
-// Widens a slot's box (or block c's global box) by an encoded box, touching
-// an entry only when the value improves it.
+// Widens a slot's box (or block c's global box) by a box, touching an entry
+// only when the value improves it (the entries only ever widen, so a stale
+// read only lets an update through).
 template <int D>
 __device__ inline void widen_box(RoundTable<D>& t, const RunDev& r, int slot, int c,
-                                 const unsigned long long* mn, const unsigned long long* mx)
+                                 const double* mn, const double* mx)
 {
-    unsigned long long* dst = slot >= 0 ? t.box[slot] : r.bb + (int64_t)c * 2 * D;
+    if (slot >= 0) {
+        double* dst = t.box[slot];
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-        if (mn[j] < dst[j]) atomicMin(dst + j, mn[j]);
-        if (mx[j] > dst[D + j]) atomicMax(dst + D + j, mx[j]);
+        for (int j = 0; j < D; ++j) {
+            if (mn[j] < dst[j]) atomicMin(dst + j, mn[j]);
+            if (mx[j] > dst[D + j]) atomicMax(dst + D + j, mx[j]);
+        }
+    } else {
+        unsigned long long* dst = r.bb + (int64_t)c * 2 * D;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            atomicMin(dst + j, enc_ord(mn[j]));
+            atomicMax(dst + D + j, enc_ord(mx[j]));
+        }
     }
 }
 
@@ -250,8 +261,8 @@ __device__ __forceinline__ void round_end_body(RT r, const int bid)
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             tab.sum[i][2 * j] = tab.sum[i][2 * j + 1] = 0ULL;
-            tab.box[i][j] = ~0ULL;
-            tab.box[i][D + j] = 0ULL;
+            tab.box[i][j] = INFINITY;
+            tab.box[i][D + j] = -INFINITY;
         }
     }
     if (tid == 0) s_n = 0;
@@ -281,7 +292,15 @@ __device__ __forceinline__ void round_end_body(RT r, const int bid)
         const bool tail = run_box<D>(f, mn, mx);
         const bool put = tail && f >= 0;
         const int slot = wave_slots<D>(tab, f, put);
-        if (put) widen_box<D>(tab, r, slot, f, mn, mx);
+        if (put) {
+            double dmn[D], dmx[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                dmn[j] = dec_ord(mn[j]);
+                dmx[j] = dec_ord(mx[j]);
+            }
+            widen_box<D>(tab, r, slot, f, dmn, dmx);
+        }
     }
     // mixed groups (boxes) and groups with changed points (sums), listed
     if (own) {
@@ -306,7 +325,8 @@ __device__ __forceinline__ void round_end_body(RT r, const int bid)
         // loads of the whole batch overlap
 #pragma unroll
         for (int u = 0; u < kMixBatch; ++u) {
-            ent[u] = m0 + u < nl ? s_list[m0 + u] : 0;
+            // wave-uniform: decisions and addresses on it stay scalar
+            ent[u] = __builtin_amdgcn_readfirstlane(m0 + u < nl ? s_list[m0 + u] : 0);
             av[u] = pv[u] = kPad;
             if (m0 + u < nl) {
                 const int64_t p = (g0 + (ent[u] & 0xff)) * kWave + lane;
@@ -332,20 +352,15 @@ __device__ __forceinline__ void round_end_body(RT r, const int bid)
             const int64_t gg = g0 + (ent[u] & 0xff);
             const int64_t p = gg * kWave + lane;
             const int a = av[u], ap = pv[u];
+            const bool chg = (ent[u] & 0x200) && a != ap;
+            // the slot of each lane's block, shared by both steps below
+            const int sb = wave_slots<D>(tab, a, a >= 0 && ((ent[u] & 0x100) || chg));
             if (ent[u] & 0x100) {
                 // mixed group: every point may widen its block's box
-                const bool want = a >= 0;
-                const int slot = wave_slots<D>(tab, a, want);
-                if (want) {
-                    unsigned long long e[D];
-#pragma unroll
-                    for (int j = 0; j < D; ++j) e[j] = enc_ord(xv[u][j]);
-                    widen_box<D>(tab, r, slot, a, e, e);
-                }
+                if (a >= 0) widen_box<D>(tab, r, sb, a, xv[u], xv[u]);
             }
             if (ent[u] & 0x200) {
                 // changed points move their terms from the old block to the new
-                const bool chg = a != ap;
                 if (lane == 0) r.gdirty[gg] = 0;
                 const unsigned long long cm = __ballot(chg);
                 if (cm == 0ULL) continue;
@@ -366,17 +381,16 @@ __device__ __forceinline__ void round_end_body(RT r, const int bid)
 #pragma unroll
                         for (int j = 0; j < 2 * D; ++j) v[j] = wave_sum_dpp(mine ? t[j] : 0);
                         if (lane == leader) {
-                            add_sums<D>(tab, r, table_slot<D>(tab, lb), lb, v, 1);
-                            if (la >= 0) add_sums<D>(tab, r, table_slot<D>(tab, la), la, v, -1);
+                            add_sums<D>(tab, r, table_slot<D>(tab, lb), lb, v, false);
+                            if (la >= 0) add_sums<D>(tab, r, table_slot<D>(tab, la), la, v, true);
                         }
                         pend &= ~mm;
                     }
                 } else {
-                    const int sb = wave_slots<D>(tab, a, chg);
                     const int sa = wave_slots<D>(tab, ap, chg && ap >= 0);
                     if (chg) {
-                        add_sums<D>(tab, r, sb, a, t, 1);
-                        if (ap >= 0) add_sums<D>(tab, r, sa, ap, t, -1);
+                        add_sums<D>(tab, r, sb, a, t, false);
+                        if (ap >= 0) add_sums<D>(tab, r, sa, ap, t, true);
                     }
                 }
             }
@@ -393,8 +407,8 @@ __device__ __forceinline__ void round_end_body(RT r, const int bid)
             if (tab.sum[i][j]) atomicAdd(sums + j, tab.sum[i][j]);
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            if (tab.box[i][j] != ~0ULL) atomicMin(box + j, tab.box[i][j]);
-            if (tab.box[i][D + j] != 0ULL) atomicMax(box + D + j, tab.box[i][D + j]);
+            if (tab.box[i][j] != INFINITY) atomicMin(box + j, enc_ord(tab.box[i][j]));
+            if (tab.box[i][D + j] != -INFINITY) atomicMax(box + D + j, enc_ord(tab.box[i][D + j]));
         }
     }
 }
