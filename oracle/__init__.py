@@ -59,7 +59,10 @@ def lib():
         L.oracle_erode.restype = None
         L.oracle_balanced_kmeans.argtypes = [
             I64, C.c_int, P, P, C.c_int, D, C.c_int, C.c_int, D, C.c_int,
-            P, P, P, P, P, P, C.POINTER(OracleInfo)]
+            P, P, P, P, P, P, P, C.POINTER(OracleInfo)]
+        L.oracle_balanced_kmeans_sampled.argtypes = [
+            I64, C.c_int, P, P, C.c_int, D, C.c_int, C.c_int, D, C.c_int,
+            I64, P, P, P, P, P, P, C.POINTER(OracleInfo), P, P]
         L.oracle_partition_stats.argtypes = [
             I64, C.c_int, P, P, P, C.c_int, D, P, P, C.POINTER(OracleStats)]
         L.oracle_num_threads.argtypes = []
@@ -207,8 +210,11 @@ def erode(delta, beta_value, influence):
 
 
 def balanced_kmeans(X, k, eps, W=None, max_iter=50, max_balance_iter=20,
-                    delta_threshold=None, hilbert_order=16, centers_init=None):
+                    delta_threshold=None, hilbert_order=16, centers_init=None,
+                    influence_init=None, sample_keys=None, sample_start=100):
     """Full balanced k-means.  delta_threshold None -> 1e-5 * largest bbox extent.
+    With sample_keys (one uint64 per point) the run starts with the
+    random-sample initialization over the order of (key, index).
 
     Returns dict(A, centers, influence, block_weights, sweeps_per_round, info)."""
     p = _Points(X)
@@ -221,15 +227,30 @@ def balanced_kmeans(X, k, eps, W=None, max_iter=50, max_balance_iter=20,
     infl = np.empty(k)
     bw = np.empty(k)
     spr = np.zeros(max_iter, dtype=np.int32)
-    ci = None if centers_init is None else np.ascontiguousarray(centers_init, dtype=np.float64)
     info = OracleInfo()
-    _check(lib().oracle_balanced_kmeans(
-        p.n, p.d, p.arr, _ptr(W), int(k), float(eps), int(max_iter), int(max_balance_iter),
-        float(delta_threshold), int(hilbert_order), _ptr(ci), _ptr(A), _ptr(centers),
-        _ptr(infl), _ptr(bw), _ptr(spr), C.byref(info)), "balanced_kmeans")
-    return dict(A=A, centers=centers, influence=infl, block_weights=bw,
-                sweeps_per_round=spr[:info.rounds].copy(),
-                info={f: getattr(info, f) for f, _ in OracleInfo._fields_})
+    extra = {}
+    if sample_keys is None:
+        ci = None if centers_init is None else np.ascontiguousarray(centers_init, dtype=np.float64)
+        ii = None if influence_init is None else np.ascontiguousarray(influence_init, dtype=np.float64)
+        _check(lib().oracle_balanced_kmeans(
+            p.n, p.d, p.arr, _ptr(W), int(k), float(eps), int(max_iter), int(max_balance_iter),
+            float(delta_threshold), int(hilbert_order), _ptr(ci), _ptr(ii), _ptr(A),
+            _ptr(centers), _ptr(infl), _ptr(bw), _ptr(spr), C.byref(info)), "balanced_kmeans")
+    else:
+        keys = np.ascontiguousarray(sample_keys, dtype=np.uint64)
+        sr = np.zeros(1, dtype=np.int32)
+        ss = np.zeros(1, dtype=np.int32)
+        _check(lib().oracle_balanced_kmeans_sampled(
+            p.n, p.d, p.arr, _ptr(W), int(k), float(eps), int(max_iter), int(max_balance_iter),
+            float(delta_threshold), int(hilbert_order), int(sample_start), _ptr(keys), _ptr(A),
+            _ptr(centers), _ptr(infl), _ptr(bw), _ptr(spr), C.byref(info), _ptr(sr), _ptr(ss)),
+            "balanced_kmeans_sampled")
+        extra = dict(sample_rounds=int(sr[0]), sample_sweeps=int(ss[0]))
+    out = dict(A=A, centers=centers, influence=infl, block_weights=bw,
+               sweeps_per_round=spr[:info.rounds].copy(),
+               info={f: getattr(info, f) for f, _ in OracleInfo._fields_})
+    out["info"].update(extra)
+    return out
 
 
 def partition_stats(X, A, k, eps, W=None):

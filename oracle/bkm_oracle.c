@@ -431,15 +431,19 @@ typedef struct {
  * centers_init ([k][d]) may be NULL: then the SFC bootstrap picks them.
  * sweeps_per_round, if not NULL, receives the sweep count of every round
  * (max_iter entries). */
+/* Balanced k-means (Alg. 2 around Alg. 1).  centers_init ([k][d]) and
+ * influence_init ([k]) may be NULL: SFC-bootstrap centers, influence 1.
+ * k may exceed n only when the centers are given (a sample round of the
+ * random-sample initialization). */
 int oracle_balanced_kmeans(int64_t n, int d, const double* const* X, const double* W,
                            int k, double eps, int max_iter, int max_balance_iter,
                            double delta_threshold, int hilbert_order,
-                           const double* centers_init, int32_t* A, double* centers_out,
-                           double* influence_out, double* block_weights_out,
+                           const double* centers_init, const double* influence_init, int32_t* A,
+                           double* centers_out, double* influence_out, double* block_weights_out,
                            int32_t* sweeps_per_round, oracle_info* info)
 {
-    if (n < 1 || d < 2 || d > 3 || k < 1 || k > n || !(eps >= 0.0) || max_iter < 1 ||
-        max_balance_iter < 1)
+    if (n < 1 || d < 2 || d > 3 || k < 1 || (k > n && !centers_init) || !(eps >= 0.0) ||
+        max_iter < 1 || max_balance_iter < 1)
         return ORC_EINVAL;
     int rc = ORC_OK;
     double* C = (double*)malloc((size_t)k * d * sizeof(double));
@@ -453,7 +457,7 @@ int oracle_balanced_kmeans(int64_t n, int d, const double* const* X, const doubl
         memcpy(C, centers_init, (size_t)k * d * sizeof(double));
     else if ((rc = oracle_init_centers_sfc(n, d, X, k, hilbert_order, C, NULL, NULL)) != ORC_OK)
         goto done;
-    for (int c = 0; c < k; ++c) I[c] = 1.0;
+    for (int c = 0; c < k; ++c) I[c] = influence_init ? influence_init[c] : 1.0;
 
     double wtot = oracle_total_weight(n, W);
     double lmax = oracle_lmax(n, k, eps, wtot, W == NULL);
@@ -500,6 +504,66 @@ int oracle_balanced_kmeans(int64_t n, int d, const double* const* X, const doubl
     if (info) *info = inf;
 done:
     free(C); free(Cn); free(I); free(sz); free(delta);
+    return rc;
+}
+
+/* Random-sample initialization (described with Alg. 2 in Sec. 4: random
+ * initialization).  The points are put in a random order, given as one key
+ * per point (order by (key, index)).  Starting from the SFC centers and
+ * influence 1, rounds run on the first s points of that order, s =
+ * sample_start and doubling after every round, each carrying centers and
+ * influence on; once s >= n, the run on all points continues from them.
+ * Each sample round is one AssignAndBalance with the sample's own balance
+ * target and L_max, then one center movement with erosion (a round whose
+ * movement is below delta_threshold returns its centers without erosion).
+ * The sample rounds do not count towards max_iter. */
+int oracle_balanced_kmeans_sampled(int64_t n, int d, const double* const* X, const double* W,
+                                   int k, double eps, int max_iter, int max_balance_iter,
+                                   double delta_threshold, int hilbert_order,
+                                   int64_t sample_start, const uint64_t* sample_keys,
+                                   int32_t* A, double* centers_out, double* influence_out,
+                                   double* block_weights_out, int32_t* sweeps_per_round,
+                                   oracle_info* info, int32_t* sample_rounds,
+                                   int32_t* sample_sweeps)
+{
+    if (n < 1 || d < 2 || d > 3 || k < 1 || k > n || sample_start < 1 || !sample_keys)
+        return ORC_EINVAL;
+    int rc = ORC_OK;
+    double* C = (double*)malloc((size_t)k * d * sizeof(double));
+    double* I = (double*)malloc((size_t)k * sizeof(double));
+    int64_t* order = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    double* xs = (double*)malloc((size_t)n * d * sizeof(double));
+    double* ws = W ? (double*)malloc((size_t)n * sizeof(double)) : NULL;
+    int32_t* As = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+    if (!C || !I || !order || !xs || (W && !ws) || !As) { rc = ORC_ENOMEM; goto done; }
+    if ((rc = oracle_init_centers_sfc(n, d, X, k, hilbert_order, C, NULL, NULL)) != ORC_OK)
+        goto done;
+    for (int c = 0; c < k; ++c) I[c] = 1.0;
+    if ((rc = oracle_sfc_order(n, sample_keys, order)) != ORC_OK) goto done;
+    int32_t rounds = 0, sweeps = 0;
+    for (int64_t s = sample_start; s < n; s *= 2) {
+        const double* Xs[3];
+        for (int j = 0; j < d; ++j) {
+            double* col = xs + (int64_t)j * n;
+            for (int64_t i = 0; i < s; ++i) col[i] = X[j][order[i]];
+            Xs[j] = col;
+        }
+        if (W)
+            for (int64_t i = 0; i < s; ++i) ws[i] = W[order[i]];
+        oracle_info si;
+        rc = oracle_balanced_kmeans(s, d, Xs, ws, k, eps, 1, max_balance_iter, delta_threshold,
+                                    hilbert_order, C, I, As, C, I, NULL, NULL, &si);
+        if (rc != ORC_OK) goto done;
+        rounds += 1;
+        sweeps += si.sweeps;
+    }
+    if (sample_rounds) *sample_rounds = rounds;
+    if (sample_sweeps) *sample_sweeps = sweeps;
+    rc = oracle_balanced_kmeans(n, d, X, W, k, eps, max_iter, max_balance_iter, delta_threshold,
+                                hilbert_order, C, I, A, centers_out, influence_out,
+                                block_weights_out, sweeps_per_round, info);
+done:
+    free(C); free(I); free(order); free(xs); free(ws); free(As);
     return rc;
 }
 

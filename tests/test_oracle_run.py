@@ -86,3 +86,71 @@ def test_influence_balances_a_skewed_cloud():
     lmax = oracle.lmax(30000, k, 0.03)
     assert r0["block_weights"].max() > lmax
     assert r["info"]["balanced"] == 1 and r["block_weights"].max() <= lmax
+
+
+# ---------------------------------------------------------------- random-sample initialization
+def test_sample_init_with_eps_infinite_is_lloyd_on_nested_samples():
+    """With eps = infinity every AssignAndBalance call balances at its first
+    sweep and the influence stays 1, so the random-sample initialization is
+    one Lloyd step on each nested sample (the first s points of the random
+    order, s = 100, 200, ...) followed by the run on all points; checked
+    against scikit-learn's Lloyd steps from the same SFC centers."""
+    from sklearn.cluster import KMeans
+    rng = np.random.default_rng(31)
+    n, k = 2000, 4
+    X = [rng.random(n), rng.random(n)]
+    keys = rng.integers(0, 2**63, n, dtype=np.uint64)
+    r = oracle.balanced_kmeans(X, k, math.inf, max_iter=1, delta_threshold=0.0,
+                               sample_keys=keys, sample_start=100)
+    assert r["info"]["sample_rounds"] == math.ceil(math.log2(n / 100))
+    assert np.all(r["influence"] == 1.0)
+    order = np.lexsort((np.arange(n), keys))        # by key, then index
+    P = np.stack(X, axis=1)
+    C, _, _ = oracle.init_centers_sfc(X, k, 16)
+    s = 100
+    while s < n:
+        C = KMeans(n_clusters=k, init=C, n_init=1, max_iter=1, tol=0.0,
+                   algorithm="lloyd").fit(P[order[:s]]).cluster_centers_
+        s *= 2
+    C = KMeans(n_clusters=k, init=C, n_init=1, max_iter=1, tol=0.0,
+               algorithm="lloyd").fit(P).cluster_centers_
+    assert np.allclose(r["centers"], C, rtol=0, atol=1e-12)
+
+
+def test_sample_init_with_one_sample_covering_everything_is_the_plain_run():
+    cfg = workloads.c1(n=90)
+    keys = np.arange(90, dtype=np.uint64)[::-1].copy()
+    a = oracle.balanced_kmeans(cfg["X"], 6, 0.03, max_iter=8, sample_keys=keys, sample_start=100)
+    b = oracle.balanced_kmeans(cfg["X"], 6, 0.03, max_iter=8)
+    assert a["info"]["sample_rounds"] == 0
+    assert np.array_equal(a["A"], b["A"])
+    assert np.array_equal(a["centers"], b["centers"])
+    assert np.array_equal(a["influence"], b["influence"])
+
+
+def test_sample_init_finishes_balanced_with_block_means():
+    """A weighted 3D run with the random-sample start still ends balanced,
+    with centers the weighted means."""
+    rng = np.random.default_rng(33)
+    n, k = 8000, 40
+    X = [rng.random(n) for _ in range(3)]
+    W = rng.lognormal(0.0, 0.5, n)
+    keys = rng.integers(0, 2**63, n, dtype=np.uint64)
+    r = oracle.balanced_kmeans(X, k, 0.05, W=W, max_iter=30, sample_keys=keys)
+    assert r["info"]["sample_rounds"] == math.ceil(math.log2(n / 100))
+    assert r["info"]["balanced"] == 1
+    assert r["block_weights"].max() <= r["info"]["lmax"]
+    _check_means(X, W, r["A"], r["centers"])
+
+
+def test_sample_rounds_with_more_blocks_than_sample_points():
+    """k = 300 > the first sample of 100 points: the sample rounds run with
+    empty blocks (they keep their centers and gain influence) and the run
+    on all points still ends with centers the means of their blocks."""
+    rng = np.random.default_rng(34)
+    n, k = 6000, 300
+    X = [rng.random(n), rng.random(n)]
+    keys = rng.integers(0, 2**63, n, dtype=np.uint64)
+    r = oracle.balanced_kmeans(X, k, 0.05, max_iter=10, sample_keys=keys)
+    assert r["info"]["sample_rounds"] == math.ceil(math.log2(n / 100))
+    _check_means(X, None, r["A"], r["centers"])
