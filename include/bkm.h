@@ -72,9 +72,25 @@ typedef struct {
     int32_t super_tiles;      /* tiles per candidate super-tile, >= 1; 0 = default */
     int32_t timing;           /* 1: time every kernel of the round loop with HIP events on
                                  `stream` and report the sums in bkm_info; default 0 */
+    int32_t sample_init;      /* 1: random-sample initialization before the main loop (the
+                                 random initialization of Sec. 4.5): rounds on
+                                 the first s points of a random order, s = sample_start
+                                 doubling after each round while s < n, carrying centers
+                                 and influence on; each such round is one AssignAndBalance
+                                 with the sample's own balance target, then one center
+                                 movement with erosion; they do not count towards
+                                 max_iter.  Default 0 */
     double epsilon;           /* imbalance eps >= 0 (may be +inf); default 0.03 */
-    double delta_threshold;   /* absolute; < 0 selects 1e-5 * largest bounding-box extent */
+    double delta_threshold;   /* absolute; < 0 selects 1e-5 * largest bounding-box extent
+                                 (of all points, also in the sample rounds) */
     double recheck_rel_gap;   /* FP64 recheck window, relative, >= 0; default 1e-5 */
+    int64_t sample_start;     /* first sample size, >= 1; default 100 */
+    uint64_t seed;            /* random order: point i gets key splitmix64 output i of the
+                                 stream seeded with `seed` (Steele, Lea, Flood 2014:
+                                 z = seed + (i+1)*0x9E3779B97F4A7C15, then the mixer);
+                                 ties by index.  Default 0 */
+    const uint64_t* sample_keys;  /* [device] n keys in input order replacing the generated
+                                     ones, or NULL */
 } bkm_params;
 
 /* Counters of one bkm_balanced_kmeans call (host struct). */
@@ -101,6 +117,8 @@ typedef struct {
     double balance_ms;        /* balance test + influence update, one per sweep */
     double boxes_ms;          /* block bounding boxes, one per round */
     double move_ms;           /* center move + erosion, one per round */
+    int32_t sample_rounds;    /* rounds of the random-sample initialization */
+    int32_t sample_sweeps;    /* sweeps made in them */
 } bkm_info;
 
 typedef struct {
@@ -172,7 +190,8 @@ int bkm_balanced_kmeans(const bkm_points* pts, const bkm_params* prm,
  * count separate bkm_balanced_kmeans calls with the same parameters.
  *   pts   [host] count point sets (device coordinate/weight pointers inside).
  *   prm   [host] count parameter sets; tile_points 0 picks the tile size from
- *         the mean number of points per block; timing is ignored.
+ *         the mean number of points per block; timing is ignored;
+ *         sample_init must be 0 (BKM_EINVAL otherwise).
  *   assignment_out [host] count device pointers, n_i int32 each (input order).
  *   centers_out    [host] count device pointers, k_i*d_i doubles each [k][d].
  *   info  [host] count records, or NULL; bootstrap_ms and total_ms are those

@@ -29,8 +29,10 @@ class Params(C.Structure):
     _fields_ = [("k", C.c_int32), ("max_iter", C.c_int32), ("max_balance_iter", C.c_int32),
                 ("hilbert_order", C.c_int32), ("precision", C.c_int32),
                 ("use_bounds", C.c_int32), ("tile_points", C.c_int32),
-                ("super_tiles", C.c_int32), ("timing", C.c_int32), ("epsilon", C.c_double),
-                ("delta_threshold", C.c_double), ("recheck_rel_gap", C.c_double)]
+                ("super_tiles", C.c_int32), ("timing", C.c_int32), ("sample_init", C.c_int32),
+                ("epsilon", C.c_double), ("delta_threshold", C.c_double),
+                ("recheck_rel_gap", C.c_double), ("sample_start", C.c_int64),
+                ("seed", C.c_uint64), ("sample_keys", C.c_void_p)]
 
 
 class Info(C.Structure):
@@ -42,7 +44,8 @@ class Info(C.Structure):
                 ("overflow_tiles", C.c_int64),
                 ("bootstrap_ms", C.c_double), ("total_ms", C.c_double),
                 ("cand_ms", C.c_double), ("sweep_ms", C.c_double), ("balance_ms", C.c_double),
-                ("boxes_ms", C.c_double), ("move_ms", C.c_double)]
+                ("boxes_ms", C.c_double), ("move_ms", C.c_double),
+                ("sample_rounds", C.c_int32), ("sample_sweeps", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -154,8 +157,12 @@ def init_centers_sfc(X, k, hilbert_order=16):
 def balanced_kmeans(X, k, W=None, eps=0.03, max_iter=50, max_balance_iter=20,
                     delta_threshold=-1.0, hilbert_order=16, precision="f32_recheck",
                     use_bounds=True, tile_points=0, super_tiles=0, recheck_rel_gap=1e-5,
-                    centers_init=None, timing=False, out=None):
-    """Balanced k-means; returns dict(A, centers, influence, block_weights, info, code)."""
+                    centers_init=None, timing=False, out=None, sample_init=False,
+                    sample_start=100, seed=0, sample_keys=None):
+    """Balanced k-means; returns dict(A, centers, influence, block_weights, info, code).
+    sample_init: start with rounds on random samples doubling from sample_start
+    points (order by splitmix64(seed, index), or by sample_keys, n uint64
+    keys on the device)."""
     dev = X[0].device
     pts = make_points(X, W)
     prm = default_params(k)
@@ -170,6 +177,15 @@ def balanced_kmeans(X, k, W=None, eps=0.03, max_iter=50, max_balance_iter=20,
     prm.super_tiles = int(super_tiles)
     prm.recheck_rel_gap = float(recheck_rel_gap)
     prm.timing = 1 if timing else 0
+    prm.sample_init = 1 if sample_init else 0
+    prm.sample_start = int(sample_start)
+    prm.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    sk = None
+    if sample_keys is not None:
+        if sample_keys.numel() != pts.n or sample_keys.element_size() != 8:
+            raise ValueError("sample_keys must hold n 64-bit keys")
+        sk = sample_keys.to(device=dev).contiguous()
+        prm.sample_keys = sk.data_ptr()
     if out is None:
         out = dict(A=torch.empty(pts.n, dtype=torch.int32, device=dev),
                    centers=torch.empty((k, pts.d), dtype=torch.float64, device=dev),

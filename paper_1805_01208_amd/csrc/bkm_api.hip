@@ -311,6 +311,7 @@ int check_run(const bkm_points* pts, const bkm_params* prm)
     if (!(p.recheck_rel_gap >= 0.0) || !std::isfinite(p.recheck_rel_gap))
         return fail(BKM_EINVAL, "recheck_rel_gap must be finite and >= 0");
     if (std::isnan(p.delta_threshold)) return fail(BKM_EINVAL, "delta_threshold is NaN");
+    if (p.sample_init && p.sample_start < 1) return fail(BKM_EINVAL, "sample_start must be >= 1");
     return BKM_OK;
 }
 
@@ -362,74 +363,14 @@ struct BatchRes {
     }
 };
 
-}  // namespace
-
-extern "C" {
-
-void bkm_default_params(bkm_params* p, int32_t k)
+// One balanced k-means run (Alg. 2 around Alg. 1) on checked arguments.
+// centers_init ([k][d]) and influence_init ([k]) may be NULL (SFC centers,
+// influence 1); with centers given, k may exceed n (a sample round).
+int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_init,
+             const double* influence_init, int32_t* assignment_out, double* centers_out,
+             double* influence_out, double* block_weights_out, bkm_info* info, hipStream_t s)
 {
-    if (!p) return;
-    std::memset(p, 0, sizeof(*p));
-    p->k = k;
-    p->max_iter = 50;
-    p->max_balance_iter = 20;
-    p->hilbert_order = 16;
-    p->precision = BKM_PREC_F32_RECHECK;
-    p->use_bounds = 1;
-    p->tile_points = 0;
-    p->super_tiles = 0;
-    p->timing = 0;
-    p->epsilon = 0.03;
-    p->delta_threshold = -1.0;
-    p->recheck_rel_gap = 1e-5;
-}
-
-const char* bkm_last_error(void) { return g_err.c_str(); }
-
-int bkm_init_centers_sfc(const bkm_points* pts, int32_t k, int32_t hilbert_order,
-                         double* centers_out, int32_t* perm_out, uint64_t* keys_out,
-                         void* stream)
-{
-    g_err.clear();
-    int rc = check_points(pts);
-    if (rc) return rc;
-    if (k < 1 || k > pts->n) return fail(BKM_EINVAL, "k = %d outside [1, n]", k);
-    if ((rc = check_order(pts->d, hilbert_order))) return rc;
-    if (!centers_out) return fail(BKM_EINVAL, "centers_out is NULL");
-    hipStream_t s = (hipStream_t)stream;
-    keep_pool_memory();
-    RunDev r;
-    plan(r, pts, k, 1024, 16, BKM_PREC_F64, 0, 0.0);
-    Arena a;
-    if ((rc = alloc_run(r, a, s, false))) return rc;
-    HIPCHK(launch_bbox(r, hilbert_order, s));
-    DevState h;
-    if ((rc = read_state(r, s, &h))) return rc;
-    if (h.bad_data) return fail(BKM_EDATA, "non-finite coordinate");
-    HIPCHK(launch_keys(r, hilbert_order, r.sperm, s));
-    if (keys_out)
-        HIPCHK(hipMemcpyAsync(keys_out, r.keys, r.n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
-    HIPCHK(radix_sort_pairs(r, r.keys, r.sperm, r.d * hilbert_order, s));
-    HIPCHK(launch_permute(r, s));
-    HIPCHK(launch_centers_from_sorted(r, centers_out, 1, s));
-    if (perm_out)
-        HIPCHK(hipMemcpyAsync(perm_out, r.sperm, r.n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
-    return BKM_OK;
-}
-
-int bkm_balanced_kmeans(const bkm_points* pts, const bkm_params* prm, const double* centers_init,
-                        int32_t* assignment_out, double* centers_out, double* influence_out,
-                        double* block_weights_out, bkm_info* info, void* stream)
-{
-    g_err.clear();
-    int rc = check_run(pts, prm);
-    if (rc) return rc;
-    const bkm_params p = *prm;
-    if (!assignment_out || !centers_out) return fail(BKM_EINVAL, "assignment_out/centers_out is NULL");
-
-    hipStream_t s = (hipStream_t)stream;
-    keep_pool_memory();
+    int rc;
     const int T = p.tile_points ? p.tile_points : auto_tile(pts->n, p.k);
     const int ST = p.super_tiles ? p.super_tiles : 16;
     RunDev r;
@@ -443,9 +384,70 @@ int bkm_balanced_kmeans(const bkm_points* pts, const bkm_params* prm, const doub
     HIPCHK(hipEventRecord(ev[0], s));
 
     if ((rc = bootstrap(r, p.hilbert_order, s, true))) return rc;
-    if (!centers_init) HIPCHK(launch_centers_from_sorted(r, r.C, 0, s));
-    HIPCHK(launch_init_run(r, centers_init, p.max_iter, p.max_balance_iter, p.epsilon,
-                           p.delta_threshold, s));
+
+    // random-sample initialization: rounds on the first sz points of a random
+    // order, sz doubling, each one AssignAndBalance and one center movement
+    // with erosion on the sample alone (its own balance target), carrying
+    // centers and influence on; the delta threshold is that of all points
+    int32_t sample_rounds = 0, sample_sweeps = 0;
+    const double* cinit = centers_init;
+    const double* iinit = influence_init;
+    double dthr = p.delta_threshold;
+    Arena sa;
+    if (p.sample_init && p.sample_start < pts->n) {
+        DevState h0;
+        if ((rc = read_state(r, s, &h0))) return rc;
+        if (dthr < 0.0) dthr = 1e-5 * h0.ext;
+        const int64_t n = pts->n;
+        const size_t esz = r.in_f32 ? sizeof(float) : sizeof(double);
+        Sizes z;
+        z.add<double>((size_t)p.k * r.d);
+        z.add<double>((size_t)p.k);
+        z.add<int32_t>((size_t)n);
+        for (int j = 0; j < r.d; ++j) z.add<double>((size_t)n);   // room for either dtype
+        if (r.weighted) z.add<double>((size_t)n);
+        sa.s = s;
+        HIPCHK(hipMallocAsync((void**)&sa.base, z.total, s));
+        sa.cap = z.total;
+        double* cbuf = sa.take<double>((size_t)p.k * r.d);
+        double* ibuf = sa.take<double>((size_t)p.k);
+        int32_t* abuf = sa.take<int32_t>((size_t)n);
+        void* xb[3] = {nullptr, nullptr, nullptr};
+        for (int j = 0; j < r.d; ++j) xb[j] = sa.take<double>((size_t)n);
+        double* wb = r.weighted ? sa.take<double>((size_t)n) : nullptr;
+        (void)esz;
+        if (centers_init)
+            HIPCHK(hipMemcpyAsync(cbuf, centers_init, (size_t)p.k * r.d * sizeof(double),
+                                  hipMemcpyDeviceToDevice, s));
+        else
+            HIPCHK(launch_centers_from_sorted(r, cbuf, 1, s));
+        if (influence_init)
+            HIPCHK(hipMemcpyAsync(ibuf, influence_init, (size_t)p.k * sizeof(double),
+                                  hipMemcpyDeviceToDevice, s));
+        HIPCHK(launch_sample_order(r, p.seed, p.sample_keys, s));
+        bkm_params q = p;
+        q.sample_init = 0;
+        q.max_iter = 1;
+        q.delta_threshold = dthr;
+        q.timing = 0;
+        for (int64_t sz = p.sample_start; sz < n; sz *= 2) {
+            HIPCHK(launch_gather_sample(r, sz, xb, wb, s));
+            bkm_points ps = *pts;
+            ps.n = sz;
+            for (int j = 0; j < r.d; ++j) ps.coords[j] = xb[j];
+            ps.weights = wb;
+            bkm_info si;
+            rc = run_core(&ps, q, cbuf, (sample_rounds || influence_init) ? ibuf : nullptr, abuf,
+                          cbuf, ibuf, nullptr, &si, s);
+            if (rc < 0) return rc;
+            sample_rounds += 1;
+            sample_sweeps += si.sweeps;
+        }
+        cinit = cbuf;
+        iinit = ibuf;
+    }
+    if (!cinit) HIPCHK(launch_centers_from_sorted(r, r.C, 0, s));
+    HIPCHK(launch_init_run(r, cinit, iinit, p.max_iter, p.max_balance_iter, p.epsilon, dthr, s));
     HIPCHK(hipEventRecord(ev[1], s));
 
     // One sweep per batch: most AssignAndBalance calls balance after their
@@ -523,6 +525,8 @@ int bkm_balanced_kmeans(const bkm_points* pts, const bkm_params* prm, const doub
 
     if (info) {
         fill_info(info, h, cnt);
+        info->sample_rounds = sample_rounds;
+        info->sample_sweeps = sample_sweeps;
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) info->bootstrap_ms = ms;
         if (hipEventElapsedTime(&ms, ev[0], ev[2]) == hipSuccess) info->total_ms = ms;
@@ -533,6 +537,79 @@ int bkm_balanced_kmeans(const bkm_points* pts, const bkm_params* prm, const doub
         info->move_ms = tk[4];
     }
     return h.balanced ? BKM_OK : BKM_WUNBALANCED;
+}
+
+}  // namespace
+
+extern "C" {
+
+void bkm_default_params(bkm_params* p, int32_t k)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->k = k;
+    p->max_iter = 50;
+    p->max_balance_iter = 20;
+    p->hilbert_order = 16;
+    p->precision = BKM_PREC_F32_RECHECK;
+    p->use_bounds = 1;
+    p->tile_points = 0;
+    p->super_tiles = 0;
+    p->timing = 0;
+    p->sample_init = 0;
+    p->sample_start = 100;
+    p->seed = 0;
+    p->sample_keys = nullptr;
+    p->epsilon = 0.03;
+    p->delta_threshold = -1.0;
+    p->recheck_rel_gap = 1e-5;
+}
+
+const char* bkm_last_error(void) { return g_err.c_str(); }
+
+int bkm_init_centers_sfc(const bkm_points* pts, int32_t k, int32_t hilbert_order,
+                         double* centers_out, int32_t* perm_out, uint64_t* keys_out,
+                         void* stream)
+{
+    g_err.clear();
+    int rc = check_points(pts);
+    if (rc) return rc;
+    if (k < 1 || k > pts->n) return fail(BKM_EINVAL, "k = %d outside [1, n]", k);
+    if ((rc = check_order(pts->d, hilbert_order))) return rc;
+    if (!centers_out) return fail(BKM_EINVAL, "centers_out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    keep_pool_memory();
+    RunDev r;
+    plan(r, pts, k, 1024, 16, BKM_PREC_F64, 0, 0.0);
+    Arena a;
+    if ((rc = alloc_run(r, a, s, false))) return rc;
+    HIPCHK(launch_bbox(r, hilbert_order, s));
+    DevState h;
+    if ((rc = read_state(r, s, &h))) return rc;
+    if (h.bad_data) return fail(BKM_EDATA, "non-finite coordinate");
+    HIPCHK(launch_keys(r, hilbert_order, r.sperm, s));
+    if (keys_out)
+        HIPCHK(hipMemcpyAsync(keys_out, r.keys, r.n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    HIPCHK(radix_sort_pairs(r, r.keys, r.sperm, r.d * hilbert_order, s));
+    HIPCHK(launch_permute(r, s));
+    HIPCHK(launch_centers_from_sorted(r, centers_out, 1, s));
+    if (perm_out)
+        HIPCHK(hipMemcpyAsync(perm_out, r.sperm, r.n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return BKM_OK;
+}
+
+int bkm_balanced_kmeans(const bkm_points* pts, const bkm_params* prm, const double* centers_init,
+                        int32_t* assignment_out, double* centers_out, double* influence_out,
+                        double* block_weights_out, bkm_info* info, void* stream)
+{
+    g_err.clear();
+    int rc = check_run(pts, prm);
+    if (rc) return rc;
+    if (!assignment_out || !centers_out) return fail(BKM_EINVAL, "assignment_out/centers_out is NULL");
+    keep_pool_memory();
+    return run_core(pts, *prm, centers_init, nullptr, assignment_out, centers_out, influence_out,
+                    block_weights_out, info, (hipStream_t)stream);
 }
 
 int bkm_assign_sweeps(const bkm_points* pts, int32_t k, int32_t steps, const double* centers,
@@ -557,7 +634,7 @@ int bkm_assign_sweeps(const bkm_points* pts, int32_t k, int32_t steps, const dou
     Arena a;
     if ((rc = alloc_run(r, a, s, true))) return rc;
     if ((rc = bootstrap(r, 16, s, true))) return rc;
-    HIPCHK(launch_init_run(r, nullptr, 1, 1, 0.0, -1.0, s));
+    HIPCHK(launch_init_run(r, nullptr, nullptr, 1, 1, 0.0, -1.0, s));
     for (int t = 0; t < steps; ++t) {
         HIPCHK(launch_set_step(r, centers + (int64_t)t * k * r.d, influence + (int64_t)t * k,
                                t == 0, s));
@@ -642,6 +719,8 @@ int bkm_balanced_kmeans_batched(const bkm_points* pts, const bkm_params* prm, in
         int rc = check_run(&pts[i], &prm[i]);
         if (!rc && (!assignment_out[i] || !centers_out[i]))
             rc = fail(BKM_EINVAL, "assignment_out/centers_out is NULL");
+        if (!rc && prm[i].sample_init)
+            rc = fail(BKM_EINVAL, "sample_init is not supported by the batched call");
         if (rc) {
             g_err = "instance " + std::to_string(i) + ": " + g_err;
             return rc;
@@ -760,7 +839,7 @@ int bkm_balanced_kmeans_batched(const bkm_points* pts, const bkm_params* prm, in
         HIPCHK(launch_place(r, q));
         HIPCHK(launch_tile_prep(r, q));
         HIPCHK(launch_centers_from_sorted(r, r.C, 0, q));
-        HIPCHK(launch_init_run(r, nullptr, p.max_iter, p.max_balance_iter, p.epsilon,
+        HIPCHK(launch_init_run(r, nullptr, nullptr, p.max_iter, p.max_balance_iter, p.epsilon,
                                p.delta_threshold, q));
     }
     if ((rc = join())) return rc;

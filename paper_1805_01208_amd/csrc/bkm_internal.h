@@ -339,8 +339,14 @@ hipError_t launch_tile_prep(const RunDev& r, hipStream_t s);
 hipError_t launch_centers_from_sorted(const RunDev& r, double* out, int row_major,
                                       hipStream_t s);
 hipError_t launch_init_run(const RunDev& r, const double* centers_init_rowmajor,
-                           int max_iter, int max_balance_iter, double eps,
-                           double delta_threshold, hipStream_t s);
+                           const double* influence_init, int max_iter, int max_balance_iter,
+                           double eps, double delta_threshold, hipStream_t s);
+// random-sample initialization: order of the points by (key, index), keys from
+// splitmix64 or given; the first `count` points of it gathered
+hipError_t launch_sample_order(const RunDev& r, uint64_t seed, const uint64_t* given,
+                               hipStream_t s);
+hipError_t launch_gather_sample(const RunDev& r, int64_t count, void* const* x, double* w,
+                                hipStream_t s);
 hipError_t launch_supercand(const RunDev& r, hipStream_t s);
 hipError_t launch_tilecand(const RunDev& r, hipStream_t s);
 hipError_t launch_sweep(const RunDev& r, hipStream_t s);

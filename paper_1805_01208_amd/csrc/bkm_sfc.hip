@@ -738,4 +738,61 @@ hipError_t launch_centers_from_sorted(const RunDev& r, double* out, int row_majo
     return hipGetLastError();
 }
 
+// ------------------------------------------------- random-sample order
+// Key of point i for the random order: output i of splitmix64 seeded with
+// `seed` (Steele, Lea, Flood, "Fast splittable pseudorandom number
+// generators", 2014): state seed + (i+1)*golden gamma, then the 64-bit mixer.
+__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sample_keys(RunDev r, uint64_t seed,
+                                                         const uint64_t* given)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= r.n) return;
+    r.keys[i] = given ? given[i] : splitmix64_at(seed, (uint64_t)i);
+    r.sperm[i] = (int32_t)i;
+}
+
+// The first s points of the random order, gathered in that order.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather_sample(RunDev r, int64_t s, T* x0, T* x1,
+                                                          T* x2, double* w)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= s) return;
+    const int64_t o = r.sperm[i];
+    const T* const* in = reinterpret_cast<const T* const*>(r.in_x);
+    x0[i] = in[0][o];
+    x1[i] = in[1][o];
+    if (r.d == 3) x2[i] = in[2][o];
+    if (w) w[i] = r.in_w[o];
+}
+
+hipError_t launch_sample_order(const RunDev& r, uint64_t seed, const uint64_t* given,
+                               hipStream_t s)
+{
+    k_sample_keys<<<nblocks(r.n, kBlock), kBlock, 0, s>>>(r, seed, given);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return radix_sort_pairs(r, r.keys, r.sperm, 64, s);
+}
+
+hipError_t launch_gather_sample(const RunDev& r, int64_t count, void* const* x, double* w,
+                                hipStream_t s)
+{
+    if (r.in_f32)
+        k_gather_sample<float><<<nblocks(count, kBlock), kBlock, 0, s>>>(
+            r, count, (float*)x[0], (float*)x[1], (float*)x[2], w);
+    else
+        k_gather_sample<double><<<nblocks(count, kBlock), kBlock, 0, s>>>(
+            r, count, (double*)x[0], (double*)x[1], (double*)x[2], w);
+    return hipGetLastError();
+}
+
 }  // namespace bkm

@@ -546,8 +546,8 @@ __global__ __launch_bounds__(kBlock) void k_init_points(RunDev r)
 }
 
 __global__ __launch_bounds__(kBlock) void k_init_clusters(RunDev r, const double* cinit,
-                                                          int max_iter, int max_bal,
-                                                          double eps, double dthr)
+                                                          const double* iinit, int max_iter,
+                                                          int max_bal, double eps, double dthr)
 {
     const int c = blockIdx.x * kBlock + threadIdx.x;
     const int D = r.d;
@@ -555,9 +555,10 @@ __global__ __launch_bounds__(kBlock) void k_init_clusters(RunDev r, const double
     if (c < r.k) {
         if (cinit)
             for (int j = 0; j < D; ++j) r.C[(int64_t)j * r.k + c] = cinit[(int64_t)c * D + j];
-        r.I[c] = 1.0;
-        r.clus[c] = make_double2(0.0, 1.0);
-        r.clus32[c] = make_float2(0.0f, 1.0f);
+        const double in = iinit ? iinit[c] : 1.0;
+        r.I[c] = in;
+        r.clus[c] = make_double2(0.0, 1.0 / in);
+        r.clus32[c] = make_float2(0.0f, f32_up(1.0 / in));
         for (int a = 0; a < kAcc; ++a) r.acc[(int64_t)c * kAcc + a] = 0;
         for (int j = 0; j < 2 * D; ++j) r.bb[(int64_t)c * 2 * D + j] = j < D ? ~0ULL : 0ULL;
     }
@@ -805,12 +806,12 @@ inline unsigned nblocks(int64_t n, int per) { return (unsigned)((n + per - 1) / 
 
 }  // namespace
 
-hipError_t launch_init_run(const RunDev& r, const double* cinit, int max_iter,
+hipError_t launch_init_run(const RunDev& r, const double* cinit, const double* iinit, int max_iter,
                            int max_balance_iter, double eps, double dthr, hipStream_t s)
 {
     k_init_points<<<nblocks(r.npad, kBlock), kBlock, 0, s>>>(r);
-    k_init_clusters<<<nblocks(std::max(r.k, kCntSlots * kCntWords), kBlock), kBlock, 0, s>>>(r, cinit, max_iter,
-                                                            max_balance_iter, eps, dthr);
+    k_init_clusters<<<nblocks(std::max(r.k, kCntSlots * kCntWords), kBlock), kBlock, 0, s>>>(
+        r, cinit, iinit, max_iter, max_balance_iter, eps, dthr);
     return hipGetLastError();
 }
 

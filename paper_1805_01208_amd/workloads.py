@@ -161,3 +161,18 @@ def c4(seed=4, count=256, n_lo=10_000, n_hi=2_000_000, k_lo=8, k_hi=512):
 
 
 CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
+
+
+def splitmix64(seed, n):
+    """Random order keys for the random-sample initialization: outputs 0..n-1
+    of splitmix64 seeded with `seed` (Steele, Lea, Flood, "Fast splittable
+    pseudorandom number generators", OOPSLA 2014): output i mixes the state
+    seed + (i+1) * 0x9E3779B97F4A7C15 (mod 2^64) with the 64-bit finaliser of
+    shift-xors by 30, 27, 31 and multiplies by 0xBF58476D1CE4E5B9 and
+    0x94D049BB133111EB.  Returns uint64[n]."""
+    with np.errstate(over="ignore"):
+        z = (np.arange(1, n + 1, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15)
+             + np.uint64(seed & 0xFFFFFFFFFFFFFFFF))
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))

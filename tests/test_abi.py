@@ -2,6 +2,7 @@
 declares; argument errors are reported without touching a GPU."""
 import ctypes as C
 import os
+import subprocess
 import re
 
 import pytest
@@ -39,11 +40,31 @@ def test_every_declared_symbol_is_exported(bkm):
     assert set(bkm.FUNCTIONS) == set(declared())
 
 
-def test_struct_layouts_match_header(bkm):
-    assert C.sizeof(bkm.Points) == 48
-    assert C.sizeof(bkm.Params) == 64
-    assert C.sizeof(bkm.Info) == 144
-    assert C.sizeof(bkm.Stats) == 32
+def test_struct_layouts_match_header(bkm, tmp_path):
+    """Size and every field offset of the binding's structs against the
+    header, compiled by the host C compiler."""
+    structs = {"bkm_points": bkm.Points, "bkm_params": bkm.Params, "bkm_info": bkm.Info,
+               "bkm_stats": bkm.Stats}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "bkm.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                               text=True).stdout.splitlines():
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
 
 
 def test_default_params(bkm):
@@ -51,6 +72,7 @@ def test_default_params(bkm):
     assert (p.k, p.max_iter, p.max_balance_iter, p.hilbert_order) == (16, 50, 20, 16)
     assert p.precision == bkm.PREC_F32_RECHECK and p.use_bounds == 1
     assert p.epsilon == 0.03 and p.delta_threshold < 0 and p.recheck_rel_gap == 1e-5
+    assert (p.sample_init, p.sample_start, p.seed, p.sample_keys) == (0, 100, 0, None)
 
 
 def _pts(bkm, n=100, d=2, dtype=1):
@@ -75,6 +97,7 @@ def _pts(bkm, n=100, d=2, dtype=1):
     (lambda p, q: setattr(q, "precision", 5), "precision"),
     (lambda p, q: setattr(q, "tile_points", 300), "tile_points"),
     (lambda p, q: setattr(q, "recheck_rel_gap", -1.0), "recheck_rel_gap"),
+    (lambda p, q: (setattr(q, "sample_init", 1), setattr(q, "sample_start", 0)), "sample_start"),
 ])
 def test_invalid_arguments(bkm, mutate, needle):
     L = bkm.lib()
@@ -120,6 +143,10 @@ def test_batched_argument_errors(bkm):
     cen[2] = None
     assert L.bkm_balanced_kmeans_batched(pts, prm, 3, outs, cen, None, None) == bkm.BKM_EINVAL
     assert L.bkm_last_error().decode().startswith("instance 2:")
+    cen[2] = 0x3000
+    prm[0].sample_init = 1
+    assert L.bkm_balanced_kmeans_batched(pts, prm, 3, outs, cen, None, None) == bkm.BKM_EINVAL
+    assert L.bkm_last_error().decode().startswith("instance 0: sample_init")
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
