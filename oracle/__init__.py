@@ -44,7 +44,7 @@ def lib():
         L.oracle_hilbert_index.restype = C.c_uint64
         L.oracle_sfc_keys.argtypes = [I64, C.c_int, P, C.c_int, P]
         L.oracle_sfc_order.argtypes = [I64, P, P]
-        L.oracle_init_centers_sfc.argtypes = [I64, C.c_int, P, C.c_int, C.c_int, P, P, P]
+        L.oracle_init_centers_sfc.argtypes = [I64, C.c_int, P, C.c_int, C.c_int, P, P, P, P]
         L.oracle_assign.argtypes = [I64, C.c_int, P, C.c_int, P, P, P, P, P]
         L.oracle_block_weights.argtypes = [I64, P, P, C.c_int, P]
         L.oracle_total_weight.argtypes = [I64, P]
@@ -52,6 +52,8 @@ def lib():
         L.oracle_lmax.argtypes = [I64, C.c_int, D, D, C.c_int]
         L.oracle_lmax.restype = D
         L.oracle_balance_step.argtypes = [C.c_int, C.c_int, P, D, D, P]
+        L.oracle_balance_step_targets.argtypes = [C.c_int, C.c_int, P, P, P, P]
+        L.oracle_targets.argtypes = [I64, C.c_int, D, D, C.c_int, P, P, P]
         L.oracle_new_centers.argtypes = [I64, C.c_int, P, P, P, C.c_int, P, P, P]
         L.oracle_beta.argtypes = [I64, C.c_int, P, P, C.c_int]
         L.oracle_beta.restype = D
@@ -59,12 +61,12 @@ def lib():
         L.oracle_erode.restype = None
         L.oracle_balanced_kmeans.argtypes = [
             I64, C.c_int, P, P, C.c_int, D, C.c_int, C.c_int, D, C.c_int,
-            P, P, P, P, P, P, P, C.POINTER(OracleInfo)]
+            P, P, P, P, P, P, P, P, C.POINTER(OracleInfo)]
         L.oracle_balanced_kmeans_sampled.argtypes = [
             I64, C.c_int, P, P, C.c_int, D, C.c_int, C.c_int, D, C.c_int,
-            I64, P, P, P, P, P, P, C.POINTER(OracleInfo), P, P]
+            I64, P, P, P, P, P, P, P, C.POINTER(OracleInfo), P, P]
         L.oracle_partition_stats.argtypes = [
-            I64, C.c_int, P, P, P, C.c_int, D, P, P, C.POINTER(OracleStats)]
+            I64, C.c_int, P, P, P, C.c_int, D, P, P, P, C.POINTER(OracleStats)]
         L.oracle_num_threads.argtypes = []
         _ = I32
         _LIB = L
@@ -131,14 +133,25 @@ def sfc_order(keys):
     return perm
 
 
-def init_centers_sfc(X, k, m):
+def _targets(t, k):
+    if t is None:
+        return None
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    if t.shape != (k,):
+        raise ValueError("target_sizes must hold k values")
+    return t
+
+
+def init_centers_sfc(X, k, m, target_sizes=None):
     """Returns (centers [k][d], perm sorted->original, keys original order)."""
     p = _Points(X)
     centers = np.empty((k, p.d), dtype=np.float64)
     perm = np.empty(p.n, dtype=np.int64)
     keys = np.empty(p.n, dtype=np.uint64)
-    _check(lib().oracle_init_centers_sfc(p.n, p.d, p.arr, int(k), int(m), _ptr(centers),
-                                         _ptr(perm), _ptr(keys)), "init_centers_sfc")
+    t = _targets(target_sizes, k)
+    _check(lib().oracle_init_centers_sfc(p.n, p.d, p.arr, int(k), int(m), _ptr(t),
+                                         _ptr(centers), _ptr(perm), _ptr(keys)),
+           "init_centers_sfc")
     return centers, perm, keys
 
 
@@ -172,6 +185,27 @@ def total_weight(n, W):
 
 def lmax(n, k, eps, W=None):
     return float(lib().oracle_lmax(int(n), int(k), float(eps), total_weight(n, W), W is None))
+
+
+def targets(n, k, eps, W=None, target_sizes=None):
+    """Per-block targets T_c and limits L_max,c: (T, L)."""
+    T = np.empty(k)
+    L = np.empty(k)
+    t = _targets(target_sizes, k)
+    _check(lib().oracle_targets(int(n), int(k), float(eps), total_weight(n, W), W is None,
+                                _ptr(t), _ptr(T), _ptr(L)), "targets")
+    return T, L
+
+
+def balance_step_targets(sizes, d, L, T, influence):
+    """Balance test + influence update with a limit and target per block."""
+    sizes = np.ascontiguousarray(sizes, dtype=np.float64)
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    infl = np.array(influence, dtype=np.float64, copy=True)
+    b = lib().oracle_balance_step_targets(sizes.shape[0], int(d), _ptr(sizes), _ptr(L), _ptr(T),
+                                          _ptr(infl))
+    return bool(b), infl
 
 
 def balance_step(sizes, d, lmax_value, target, influence):
@@ -211,10 +245,12 @@ def erode(delta, beta_value, influence):
 
 def balanced_kmeans(X, k, eps, W=None, max_iter=50, max_balance_iter=20,
                     delta_threshold=None, hilbert_order=16, centers_init=None,
-                    influence_init=None, sample_keys=None, sample_start=100):
+                    influence_init=None, sample_keys=None, sample_start=100,
+                    target_sizes=None):
     """Full balanced k-means.  delta_threshold None -> 1e-5 * largest bbox extent.
     With sample_keys (one uint64 per point) the run starts with the
     random-sample initialization over the order of (key, index).
+    target_sizes: k relative block sizes, or None for equal blocks.
 
     Returns dict(A, centers, influence, block_weights, sweeps_per_round, info)."""
     p = _Points(X)
@@ -229,12 +265,13 @@ def balanced_kmeans(X, k, eps, W=None, max_iter=50, max_balance_iter=20,
     spr = np.zeros(max_iter, dtype=np.int32)
     info = OracleInfo()
     extra = {}
+    t = _targets(target_sizes, k)
     if sample_keys is None:
         ci = None if centers_init is None else np.ascontiguousarray(centers_init, dtype=np.float64)
         ii = None if influence_init is None else np.ascontiguousarray(influence_init, dtype=np.float64)
         _check(lib().oracle_balanced_kmeans(
             p.n, p.d, p.arr, _ptr(W), int(k), float(eps), int(max_iter), int(max_balance_iter),
-            float(delta_threshold), int(hilbert_order), _ptr(ci), _ptr(ii), _ptr(A),
+            float(delta_threshold), int(hilbert_order), _ptr(ci), _ptr(ii), _ptr(t), _ptr(A),
             _ptr(centers), _ptr(infl), _ptr(bw), _ptr(spr), C.byref(info)), "balanced_kmeans")
     else:
         keys = np.ascontiguousarray(sample_keys, dtype=np.uint64)
@@ -242,7 +279,8 @@ def balanced_kmeans(X, k, eps, W=None, max_iter=50, max_balance_iter=20,
         ss = np.zeros(1, dtype=np.int32)
         _check(lib().oracle_balanced_kmeans_sampled(
             p.n, p.d, p.arr, _ptr(W), int(k), float(eps), int(max_iter), int(max_balance_iter),
-            float(delta_threshold), int(hilbert_order), int(sample_start), _ptr(keys), _ptr(A),
+            float(delta_threshold), int(hilbert_order), int(sample_start), _ptr(keys), _ptr(t),
+            _ptr(A),
             _ptr(centers), _ptr(infl), _ptr(bw), _ptr(spr), C.byref(info), _ptr(sr), _ptr(ss)),
             "balanced_kmeans_sampled")
         extra = dict(sample_rounds=int(sr[0]), sample_sweeps=int(ss[0]))
@@ -253,14 +291,15 @@ def balanced_kmeans(X, k, eps, W=None, max_iter=50, max_balance_iter=20,
     return out
 
 
-def partition_stats(X, A, k, eps, W=None):
+def partition_stats(X, A, k, eps, W=None, target_sizes=None):
     p = _Points(X)
+    t = _targets(target_sizes, k)
     W = _weights(W)
     A = np.ascontiguousarray(A, dtype=np.int32)
     bw = np.empty(k)
     centers = np.empty((k, p.d))
     st = OracleStats()
     _check(lib().oracle_partition_stats(p.n, p.d, p.arr, _ptr(W), _ptr(A), int(k), float(eps),
-                                        _ptr(bw), _ptr(centers), C.byref(st)), "partition_stats")
+                                        _ptr(t), _ptr(bw), _ptr(centers), C.byref(st)), "partition_stats")
     return dict(block_weights=bw, centers=centers,
                 **{f: getattr(st, f) for f, _ in OracleStats._fields_})

@@ -54,6 +54,25 @@
  *       largest bounding-box extent (isotropic scaling); ext = 0 gives key 0.
  *   R12 Initial center i is the sorted point floor(i*n/k) + floor(n/(2k)).
  *
+ * Non-uniform target block sizes (the footnote to the objective at the start
+ * of Sec. 4: other block sizes than the average, e.g. for heterogeneous
+ * machines):
+ *   N1  The caller gives k relative sizes t_c > 0.  tsum = t_0 + t_1 + ...
+ *       summed in index order; block c has target T_c = (W * t_c) / tsum.
+ *   N2  L_max,c = (1+eps) * ceil((n * t_c) / tsum) for unit weights and
+ *       (1+eps) * T_c for node weights; balanced <=> weight(c) <= L_max,c
+ *       for every c; the influence factor is (T_c / weight(c))^(1/d) with
+ *       the clamp of R2.
+ *   N3  Initial center c is the sorted point
+ *       floor((n * S_c) / tsum) + floor((n * t_c) / (2 tsum)), at most n-1,
+ *       with S_c = t_0 + ... + t_{c-1} summed in index order: the middle of
+ *       the c-th stretch of the curve when the curve is cut in proportion
+ *       to the targets.
+ *   N4  Imbalance is max_c weight(c) / T_c - 1.
+ *   With all t_c equal and their sums exact in FP64 (small integers, dyadic
+ *   fractions) these are R4, R12 and the uniform imbalance exactly (for
+ *   n*k < 2^53).
+ *
  * Parity pins: see tests/test_oracle_*.py.  The full multi-round trajectory
  * on large inputs has no independent pin (the paper prints no trace): parity
  * unpinned there beyond the per-step pins and invariants.
@@ -70,6 +89,8 @@
 #define ORC_OK 0
 #define ORC_EINVAL (-1)
 #define ORC_ENOMEM (-3)
+
+double oracle_lmax(int64_t n, int k, double eps, double total_weight, int unit);
 
 /* ------------------------------------------------------------------------ */
 /* Compensated (Neumaier) summation: the running sum plus a correction term. */
@@ -198,11 +219,54 @@ int oracle_sfc_order(int64_t n, const uint64_t* keys, int64_t* perm)
     return ORC_OK;
 }
 
+/* Sum of the k target sizes in index order (reading N1). */
+static double target_sum(int k, const double* t)
+{
+    double sum = 0.0;
+    for (int c = 0; c < k; ++c) sum += t[c];
+    return sum;
+}
+
+/* Sorted position of initial center c: R12, or N3 with target sizes. */
+static int64_t center_position(int64_t n, int k, int64_t c, const double* t, double tsum,
+                               double prefix)
+{
+    if (!t) return (c * n) / k + n / (2 * (int64_t)k);
+    int64_t pos = (int64_t)floor(((double)n * prefix) / tsum) +
+                  (int64_t)floor(((double)n * t[c]) / (2.0 * tsum));
+    return pos < n - 1 ? pos : n - 1;
+}
+
+/* Per-block targets T_c and limits L_max,c (readings R4 / N1, N2).  t may be
+ * NULL (uniform).  Returns 0, or ORC_EINVAL for a non-positive or
+ * non-finite target size. */
+int oracle_targets(int64_t n, int k, double eps, double total_weight, int unit,
+                   const double* t, double* T, double* L)
+{
+    if (!t) {
+        for (int c = 0; c < k; ++c) {
+            T[c] = total_weight / (double)k;
+            L[c] = oracle_lmax(n, k, eps, total_weight, unit);
+        }
+        return ORC_OK;
+    }
+    for (int c = 0; c < k; ++c)
+        if (!(t[c] > 0.0) || !isfinite(t[c])) return ORC_EINVAL;
+    double tsum = target_sum(k, t);
+    for (int c = 0; c < k; ++c) {
+        T[c] = (total_weight * t[c]) / tsum;
+        L[c] = unit ? (1.0 + eps) * ceil(((double)n * t[c]) / tsum) : (1.0 + eps) * T[c];
+    }
+    return ORC_OK;
+}
+
 /* SFC bootstrap (Alg. 2): keys, stable order, centers at evenly spaced sorted
- * positions (reading R12).  centers is [k][d] row-major.  perm (sorted ->
- * original index) and keys (original order) may be NULL. */
+ * positions (reading R12), or at positions in proportion to target sizes
+ * (reading N3; target_sizes may be NULL).  centers is [k][d] row-major.  perm
+ * (sorted -> original index) and keys (original order) may be NULL. */
 int oracle_init_centers_sfc(int64_t n, int d, const double* const* X, int k, int m,
-                            double* centers, int64_t* perm_out, uint64_t* keys_out)
+                            const double* target_sizes, double* centers, int64_t* perm_out,
+                            uint64_t* keys_out)
 {
     if (n < 1 || d < 2 || d > 3 || k < 1 || k > n) return ORC_EINVAL;
     uint64_t* keys = keys_out ? keys_out : (uint64_t*)malloc((size_t)n * sizeof(uint64_t));
@@ -211,9 +275,12 @@ int oracle_init_centers_sfc(int64_t n, int d, const double* const* X, int k, int
     int rc = oracle_sfc_keys(n, d, X, m, keys);
     if (rc == ORC_OK) rc = oracle_sfc_order(n, keys, perm);
     if (rc == ORC_OK) {
+        double tsum = target_sizes ? target_sum(k, target_sizes) : 0.0;
+        double prefix = 0.0;
         for (int64_t i = 0; i < k; ++i) {
-            int64_t pos = (i * n) / k + n / (2 * (int64_t)k);
+            int64_t pos = center_position(n, k, i, target_sizes, tsum, prefix);
             for (int j = 0; j < d; ++j) centers[i * d + j] = X[j][perm[pos]];
+            if (target_sizes) prefix += target_sizes[i];
         }
     }
     if (!keys_out) free(keys);
@@ -330,6 +397,29 @@ int oracle_balance_step(int k, int d, const double* sizes, double lmax, double t
     return 0;
 }
 
+/* The same step with a target and a limit per block (readings N1, N2). */
+int oracle_balance_step_targets(int k, int d, const double* sizes, const double* L,
+                                const double* T, double* influence)
+{
+    int over = 0;
+    for (int c = 0; c < k; ++c)
+        if (sizes[c] > L[c]) over = 1;
+    if (!over) return 1;
+    for (int c = 0; c < k; ++c) {
+        double f;
+        if (sizes[c] > 0.0) {
+            double g = T[c] / sizes[c];
+            f = (d == 2) ? sqrt(g) : cbrt(g);
+            if (f > 1.05) f = 1.05;
+            if (f < 0.95) f = 0.95;
+        } else {
+            f = 1.05;
+        }
+        influence[c] = influence[c] * f;
+    }
+    return 0;
+}
+
 /* New centers (Alg. 2 center update; weighted mean, R9) and the distance
  * delta[c] each center moved.  centers_old/new are [k][d]. */
 int oracle_new_centers(int64_t n, int d, const double* const* X, const double* W,
@@ -422,23 +512,23 @@ typedef struct {
     int32_t sweeps;           /* assignment sweeps made, all calls */
     int32_t balanced;         /* the last call ended balanced */
     int32_t converged;        /* max delta fell below the threshold */
-    double imbalance;         /* max_c weight / (W/k) - 1 of the returned A */
+    double imbalance;         /* max_c weight / T_c - 1 of the returned A */
     double max_block_weight;
-    double lmax;
+    double lmax;              /* L_max (the largest L_max,c with target sizes) */
 } oracle_info;
 
 /* Balanced k-means (Alg. 2 around Alg. 1) with readings R1-R12.
- * centers_init ([k][d]) may be NULL: then the SFC bootstrap picks them.
+ * centers_init ([k][d]) and influence_init ([k]) may be NULL: SFC-bootstrap
+ * centers, influence 1.  k may exceed n only when the centers are given (a
+ * sample round of the random-sample initialization).  target_sizes ([k]
+ * relative sizes, readings N1-N4) may be NULL for equal blocks.
  * sweeps_per_round, if not NULL, receives the sweep count of every round
  * (max_iter entries). */
-/* Balanced k-means (Alg. 2 around Alg. 1).  centers_init ([k][d]) and
- * influence_init ([k]) may be NULL: SFC-bootstrap centers, influence 1.
- * k may exceed n only when the centers are given (a sample round of the
- * random-sample initialization). */
 int oracle_balanced_kmeans(int64_t n, int d, const double* const* X, const double* W,
                            int k, double eps, int max_iter, int max_balance_iter,
                            double delta_threshold, int hilbert_order,
-                           const double* centers_init, const double* influence_init, int32_t* A,
+                           const double* centers_init, const double* influence_init,
+                           const double* target_sizes, int32_t* A,
                            double* centers_out, double* influence_out, double* block_weights_out,
                            int32_t* sweeps_per_round, oracle_info* info)
 {
@@ -451,28 +541,37 @@ int oracle_balanced_kmeans(int64_t n, int d, const double* const* X, const doubl
     double* I = (double*)malloc((size_t)k * sizeof(double));
     double* sz = (double*)malloc((size_t)k * sizeof(double));
     double* delta = (double*)malloc((size_t)k * sizeof(double));
-    if (!C || !Cn || !I || !sz || !delta) { rc = ORC_ENOMEM; goto done; }
+    double* T = (double*)malloc((size_t)k * sizeof(double));
+    double* L = (double*)malloc((size_t)k * sizeof(double));
+    if (!C || !Cn || !I || !sz || !delta || !T || !L) { rc = ORC_ENOMEM; goto done; }
 
+    double wtot = oracle_total_weight(n, W);
+    if ((rc = oracle_targets(n, k, eps, wtot, W == NULL, target_sizes, T, L)) != ORC_OK)
+        goto done;
     if (centers_init)
         memcpy(C, centers_init, (size_t)k * d * sizeof(double));
-    else if ((rc = oracle_init_centers_sfc(n, d, X, k, hilbert_order, C, NULL, NULL)) != ORC_OK)
+    else if ((rc = oracle_init_centers_sfc(n, d, X, k, hilbert_order, target_sizes, C, NULL,
+                                           NULL)) != ORC_OK)
         goto done;
     for (int c = 0; c < k; ++c) I[c] = influence_init ? influence_init[c] : 1.0;
 
-    double wtot = oracle_total_weight(n, W);
     double lmax = oracle_lmax(n, k, eps, wtot, W == NULL);
     double target = wtot / (double)k;
 
     oracle_info inf;
     memset(&inf, 0, sizeof(inf));
-    inf.lmax = lmax;
+    inf.lmax = L[0];
+    for (int c = 1; c < k; ++c)
+        if (L[c] > inf.lmax) inf.lmax = L[c];
     for (int it = 0; it < max_iter; ++it) {
         int balanced = 0, sw = 0;
         for (int b = 0; b < max_balance_iter; ++b) {
             oracle_assign(n, d, X, k, C, I, A, NULL, NULL);
             oracle_block_weights(n, A, W, k, sz);
             sw += 1;
-            if (oracle_balance_step(k, d, sz, lmax, target, I)) { balanced = 1; break; }
+            int bal = target_sizes ? oracle_balance_step_targets(k, d, sz, L, T, I)
+                                   : oracle_balance_step(k, d, sz, lmax, target, I);
+            if (bal) { balanced = 1; break; }
         }
         if (sweeps_per_round) sweeps_per_round[it] = sw;
         inf.rounds += 1;
@@ -497,13 +596,20 @@ int oracle_balanced_kmeans(int64_t n, int d, const double* const* X, const doubl
     inf.max_block_weight = sz[0];
     for (int c = 1; c < k; ++c)
         if (sz[c] > inf.max_block_weight) inf.max_block_weight = sz[c];
-    inf.imbalance = inf.max_block_weight / target - 1.0;
+    if (target_sizes) {
+        double r = sz[0] / T[0];
+        for (int c = 1; c < k; ++c)
+            if (sz[c] / T[c] > r) r = sz[c] / T[c];
+        inf.imbalance = r - 1.0;
+    } else {
+        inf.imbalance = inf.max_block_weight / target - 1.0;
+    }
     if (centers_out) memcpy(centers_out, C, (size_t)k * d * sizeof(double));
     if (influence_out) memcpy(influence_out, I, (size_t)k * sizeof(double));
     if (block_weights_out) memcpy(block_weights_out, sz, (size_t)k * sizeof(double));
     if (info) *info = inf;
 done:
-    free(C); free(Cn); free(I); free(sz); free(delta);
+    free(C); free(Cn); free(I); free(sz); free(delta); free(T); free(L);
     return rc;
 }
 
@@ -521,7 +627,7 @@ int oracle_balanced_kmeans_sampled(int64_t n, int d, const double* const* X, con
                                    int k, double eps, int max_iter, int max_balance_iter,
                                    double delta_threshold, int hilbert_order,
                                    int64_t sample_start, const uint64_t* sample_keys,
-                                   int32_t* A, double* centers_out, double* influence_out,
+                                   const double* target_sizes, int32_t* A, double* centers_out, double* influence_out,
                                    double* block_weights_out, int32_t* sweeps_per_round,
                                    oracle_info* info, int32_t* sample_rounds,
                                    int32_t* sample_sweeps)
@@ -536,7 +642,8 @@ int oracle_balanced_kmeans_sampled(int64_t n, int d, const double* const* X, con
     double* ws = W ? (double*)malloc((size_t)n * sizeof(double)) : NULL;
     int32_t* As = (int32_t*)malloc((size_t)n * sizeof(int32_t));
     if (!C || !I || !order || !xs || (W && !ws) || !As) { rc = ORC_ENOMEM; goto done; }
-    if ((rc = oracle_init_centers_sfc(n, d, X, k, hilbert_order, C, NULL, NULL)) != ORC_OK)
+    if ((rc = oracle_init_centers_sfc(n, d, X, k, hilbert_order, target_sizes, C, NULL,
+                                      NULL)) != ORC_OK)
         goto done;
     for (int c = 0; c < k; ++c) I[c] = 1.0;
     if ((rc = oracle_sfc_order(n, sample_keys, order)) != ORC_OK) goto done;
@@ -552,7 +659,8 @@ int oracle_balanced_kmeans_sampled(int64_t n, int d, const double* const* X, con
             for (int64_t i = 0; i < s; ++i) ws[i] = W[order[i]];
         oracle_info si;
         rc = oracle_balanced_kmeans(s, d, Xs, ws, k, eps, 1, max_balance_iter, delta_threshold,
-                                    hilbert_order, C, I, As, C, I, NULL, NULL, &si);
+                                    hilbert_order, C, I, target_sizes, As, C, I, NULL, NULL,
+                                    &si);
         if (rc != ORC_OK) goto done;
         rounds += 1;
         sweeps += si.sweeps;
@@ -560,7 +668,7 @@ int oracle_balanced_kmeans_sampled(int64_t n, int d, const double* const* X, con
     if (sample_rounds) *sample_rounds = rounds;
     if (sample_sweeps) *sample_sweeps = sweeps;
     rc = oracle_balanced_kmeans(n, d, X, W, k, eps, max_iter, max_balance_iter, delta_threshold,
-                                hilbert_order, C, I, A, centers_out, influence_out,
+                                hilbert_order, C, I, target_sizes, A, centers_out, influence_out,
                                 block_weights_out, sweeps_per_round, info);
 done:
     free(C); free(I); free(order); free(xs); free(ws); free(As);
@@ -569,18 +677,19 @@ done:
 
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    double imbalance;        /* max_c weight / (W/k) - 1 */
+    double imbalance;        /* max_c weight / T_c - 1 */
     double objective;        /* sum_p w(p) * dist(p, mean of its block)^2 */
-    double lmax;
+    double lmax;             /* L_max (the largest L_max,c with target sizes) */
     int32_t empty_blocks;
-    int32_t overloaded_blocks;  /* weight > L_max (Sec. 2 "overloaded") */
+    int32_t overloaded_blocks;  /* weight > L_max,c (Sec. 2 "overloaded") */
 } oracle_stats;
 
 /* Partition statistics of a given assignment: block weights, block means
- * (NaN for an empty block), imbalance, k-means objective. */
+ * (NaN for an empty block), imbalance, k-means objective; target_sizes may
+ * be NULL (equal blocks; readings N1, N2, N4 otherwise). */
 int oracle_partition_stats(int64_t n, int d, const double* const* X, const double* W,
-                           const int32_t* A, int k, double eps, double* block_weights,
-                           double* centers, oracle_stats* st)
+                           const int32_t* A, int k, double eps, const double* target_sizes,
+                           double* block_weights, double* centers, oracle_stats* st)
 {
     if (n < 1 || d < 2 || d > 3 || k < 1) return ORC_EINVAL;
     for (int64_t i = 0; i < n; ++i)
@@ -589,20 +698,29 @@ int oracle_partition_stats(int64_t n, int d, const double* const* X, const doubl
     double* C = (double*)malloc((size_t)k * d * sizeof(double));
     double* C0 = (double*)calloc((size_t)k * d, sizeof(double));
     double* dl = (double*)malloc((size_t)k * sizeof(double));
-    if (!bw || !C || !C0 || !dl) { free(bw); free(C); free(C0); free(dl); return ORC_ENOMEM; }
+    double* T = (double*)malloc((size_t)k * sizeof(double));
+    double* L = (double*)malloc((size_t)k * sizeof(double));
+    if (!bw || !C || !C0 || !dl || !T || !L) {
+        free(bw); free(C); free(C0); free(dl); free(T); free(L);
+        return ORC_ENOMEM;
+    }
+    double wtot = oracle_total_weight(n, W);
+    if (oracle_targets(n, k, eps, wtot, W == NULL, target_sizes, T, L) != ORC_OK) {
+        free(bw); free(C); free(C0); free(dl); free(T); free(L);
+        return ORC_EINVAL;
+    }
     oracle_block_weights(n, A, W, k, bw);
     oracle_new_centers(n, d, X, W, A, k, C0, C, dl);
-    double wtot = oracle_total_weight(n, W);
-    double lmax = oracle_lmax(n, k, eps, wtot, W == NULL);
-    double mx = bw[0];
+    double ratio = bw[0] / T[0], lmax = L[0];
     int32_t empty = 0, over = 0;
     for (int c = 0; c < k; ++c) {
-        if (bw[c] > mx) mx = bw[c];
+        if (bw[c] / T[c] > ratio) ratio = bw[c] / T[c];
+        if (L[c] > lmax) lmax = L[c];
         if (bw[c] == 0.0) {
             empty += 1;
             for (int j = 0; j < d; ++j) C[(int64_t)c * d + j] = NAN;
         }
-        if (bw[c] > lmax) over += 1;
+        if (bw[c] > L[c]) over += 1;
     }
     ksum obj = {0.0, 0.0};
     for (int64_t i = 0; i < n; ++i) {
@@ -616,14 +734,14 @@ int oracle_partition_stats(int64_t n, int d, const double* const* X, const doubl
         }
         ksum_add(&obj, (W ? W[i] : 1.0) * s);
     }
-    st->imbalance = mx / (wtot / (double)k) - 1.0;
+    st->imbalance = ratio - 1.0;
     st->objective = ksum_get(&obj);
     st->lmax = lmax;
     st->empty_blocks = empty;
     st->overloaded_blocks = over;
     if (block_weights) memcpy(block_weights, bw, (size_t)k * sizeof(double));
     if (centers) memcpy(centers, C, (size_t)k * d * sizeof(double));
-    free(bw); free(C); free(C0); free(dl);
+    free(bw); free(C); free(C0); free(dl); free(T); free(L);
     return ORC_OK;
 }
 
