@@ -91,17 +91,28 @@ typedef struct {
                                  ties by index.  Default 0 */
     const uint64_t* sample_keys;  /* [device] n keys in input order replacing the generated
                                      ones, or NULL */
+    const double* target_sizes;   /* [device] k relative block sizes t_c (finite, > 0), or
+                                     NULL for equal blocks (the footnote to the objective at
+                                     the start of Sec. 4).  Block c gets target weight
+                                     T_c = W*t_c/tsum (tsum summed in index order) and limit
+                                     (1+eps)*ceil(n*t_c/tsum), or (1+eps)*T_c with node
+                                     weights; initial center c is the sorted point
+                                     floor(n*S_c/tsum) + floor(n*t_c/(2*tsum)) (S_c the sum
+                                     of the sizes before c), at most n-1.  Invalid sizes
+                                     give BKM_EINVAL after the bounding box is taken */
 } bkm_params;
 
 /* Counters of one bkm_balanced_kmeans call (host struct). */
 typedef struct {
     int32_t rounds;           /* AssignAndBalance calls made */
     int32_t sweeps;           /* assignment sweeps made over all calls */
-    int32_t balanced;         /* last call ended with every block <= L_max */
+    int32_t balanced;         /* last call ended with every block <= its L_max */
     int32_t converged;        /* max center movement fell below delta_threshold */
-    double imbalance;         /* max block weight / (W/k) - 1 of the returned assignment */
+    double imbalance;         /* max over blocks of weight / target - 1 of the returned
+                                 assignment (target W/k, or T_c with target sizes) */
     double max_block_weight;
-    double l_max;             /* (1+eps)*ceil(n/k), or (1+eps)*W/k with node weights */
+    double l_max;             /* (1+eps)*ceil(n/k), or (1+eps)*W/k with node weights; the
+                                 largest block limit with target sizes */
     int64_t evaluated;        /* point visits that evaluated candidate centers */
     int64_t skipped;          /* point visits skipped by the bounds (Sec. 4.3) */
     int64_t rechecked;        /* evaluated visits decided again in FP64 */
@@ -122,18 +133,18 @@ typedef struct {
 } bkm_info;
 
 typedef struct {
-    double imbalance;         /* max block weight / (W/k) - 1 */
+    double imbalance;         /* max over blocks of weight / target - 1 */
     double objective;         /* sum_p w(p) * dist(p, weighted mean of its block)^2 */
-    double l_max;
+    double l_max;             /* L_max; the largest block limit with target sizes */
     int32_t empty_blocks;
-    int32_t overloaded_blocks; /* blocks with weight > L_max (Sec. 2) */
+    int32_t overloaded_blocks; /* blocks with weight > their L_max (Sec. 2) */
 } bkm_stats;
 
 /* Fill *p with the defaults listed above for k blocks. */
 void bkm_default_params(bkm_params* p, int32_t k);
 
-/* Hilbert space-filling-curve bootstrap (Alg. 2, lines computing sfcIndex,
- * sorting by it and picking the initial centers; Sec. 4.1).
+/* Hilbert space-filling-curve bootstrap (Alg. 2: the curve index of every
+ * point, the sort by it and the initial centers; Sec. 4.1).
  *   Key of point i: with lo/hi the global bounding box and ext its largest
  *   extent, cell q_j = min(2^m-1, floor((x_j - lo_j) * (2^m / ext))), then the
  *   order-m Hilbert index of (q_0..q_{d-1}) (Skilling's transpose algorithm,
@@ -225,13 +236,14 @@ int bkm_assign_sweeps(const bkm_points* pts, int32_t k, int32_t steps,
  * means (NaN for an empty block), imbalance, k-means objective, empty and
  * overloaded block counts.
  *   assignment [device] n int32 in [0, k).
+ *   target_sizes [device] k relative block sizes as in bkm_params, or NULL.
  *   block_weights_out, centers_out [device] k and k*d doubles, or NULL.
  *   out [host] required.
  * Errors: BKM_EINVAL (also for an assignment outside [0,k)), BKM_EDATA,
  * BKM_ENOMEM, BKM_EHIP. */
 int bkm_partition_stats(const bkm_points* pts, const int32_t* assignment, int32_t k,
-                        double epsilon, double* block_weights_out, double* centers_out,
-                        bkm_stats* out, void* stream);
+                        double epsilon, const double* target_sizes, double* block_weights_out,
+                        double* centers_out, bkm_stats* out, void* stream);
 
 /* Message of the last nonzero return on the calling thread ("" if none). */
 const char* bkm_last_error(void);

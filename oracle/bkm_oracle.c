@@ -239,7 +239,7 @@ static int64_t center_position(int64_t n, int k, int64_t c, const double* t, dou
 
 /* Per-block targets T_c and limits L_max,c (readings R4 / N1, N2).  t may be
  * NULL (uniform).  Returns 0, or ORC_EINVAL for a non-positive or
- * non-finite target size. */
+ * non-finite target size or a sum that overflows. */
 int oracle_targets(int64_t n, int k, double eps, double total_weight, int unit,
                    const double* t, double* T, double* L)
 {
@@ -253,6 +253,7 @@ int oracle_targets(int64_t n, int k, double eps, double total_weight, int unit,
     for (int c = 0; c < k; ++c)
         if (!(t[c] > 0.0) || !isfinite(t[c])) return ORC_EINVAL;
     double tsum = target_sum(k, t);
+    if (!isfinite(tsum)) return ORC_EINVAL;
     for (int c = 0; c < k; ++c) {
         T[c] = (total_weight * t[c]) / tsum;
         L[c] = unit ? (1.0 + eps) * ceil(((double)n * t[c]) / tsum) : (1.0 + eps) * T[c];

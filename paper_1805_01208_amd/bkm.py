@@ -32,7 +32,8 @@ class Params(C.Structure):
                 ("super_tiles", C.c_int32), ("timing", C.c_int32), ("sample_init", C.c_int32),
                 ("epsilon", C.c_double), ("delta_threshold", C.c_double),
                 ("recheck_rel_gap", C.c_double), ("sample_start", C.c_int64),
-                ("seed", C.c_uint64), ("sample_keys", C.c_void_p)]
+                ("seed", C.c_uint64), ("sample_keys", C.c_void_p),
+                ("target_sizes", C.c_void_p)]
 
 
 class Info(C.Structure):
@@ -81,7 +82,7 @@ def lib():
                                           C.POINTER(Info), P]
         L.bkm_assign_sweeps.argtypes = [C.POINTER(Points), C.c_int32, C.c_int32, P, P, C.c_int32,
                                         C.c_int32, C.c_int32, P, P, C.POINTER(Info), P]
-        L.bkm_partition_stats.argtypes = [C.POINTER(Points), P, C.c_int32, C.c_double, P, P,
+        L.bkm_partition_stats.argtypes = [C.POINTER(Points), P, C.c_int32, C.c_double, P, P, P,
                                           C.POINTER(Stats), P]
         L.bkm_balanced_kmeans_batched.argtypes = [C.POINTER(Points), C.POINTER(Params), C.c_int32,
                                                   C.POINTER(P), C.POINTER(P), C.POINTER(Info), P]
@@ -154,15 +155,26 @@ def init_centers_sfc(X, k, hilbert_order=16):
     return cen, perm, keys
 
 
+def _targets(t, k, dev):
+    """Target sizes as a contiguous float64 device tensor of k values, or None."""
+    if t is None:
+        return None
+    t = torch.as_tensor(t, dtype=torch.float64).to(device=dev).contiguous()
+    if t.numel() != k:
+        raise ValueError("target_sizes must hold k values")
+    return t
+
+
 def balanced_kmeans(X, k, W=None, eps=0.03, max_iter=50, max_balance_iter=20,
                     delta_threshold=-1.0, hilbert_order=16, precision="f32_recheck",
                     use_bounds=True, tile_points=0, super_tiles=0, recheck_rel_gap=1e-5,
                     centers_init=None, timing=False, out=None, sample_init=False,
-                    sample_start=100, seed=0, sample_keys=None):
+                    sample_start=100, seed=0, sample_keys=None, target_sizes=None):
     """Balanced k-means; returns dict(A, centers, influence, block_weights, info, code).
     sample_init: start with rounds on random samples doubling from sample_start
     points (order by splitmix64(seed, index), or by sample_keys, n uint64
-    keys on the device)."""
+    keys on the device).  target_sizes: k relative block sizes (device
+    tensor), or None for equal blocks."""
     dev = X[0].device
     pts = make_points(X, W)
     prm = default_params(k)
@@ -186,6 +198,8 @@ def balanced_kmeans(X, k, W=None, eps=0.03, max_iter=50, max_balance_iter=20,
             raise ValueError("sample_keys must hold n 64-bit keys")
         sk = sample_keys.to(device=dev).contiguous()
         prm.sample_keys = sk.data_ptr()
+    ts = _targets(target_sizes, k, dev)
+    prm.target_sizes = None if ts is None else ts.data_ptr()
     if out is None:
         out = dict(A=torch.empty(pts.n, dtype=torch.int32, device=dev),
                    centers=torch.empty((k, pts.d), dtype=torch.float64, device=dev),
@@ -206,11 +220,13 @@ def balanced_kmeans(X, k, W=None, eps=0.03, max_iter=50, max_balance_iter=20,
 
 def balanced_kmeans_batched(instances, eps=0.03, max_iter=50, max_balance_iter=20,
                             delta_threshold=-1.0, hilbert_order=16, precision="f32_recheck",
-                            use_bounds=True, tile_points=0, super_tiles=0, recheck_rel_gap=1e-5):
+                            use_bounds=True, tile_points=0, super_tiles=0, recheck_rel_gap=1e-5,
+                            target_sizes=None):
     """Many balanced k-means runs in one call.  instances: list of (X, k) or
     (X, k, W) with X a list of d device tensors.  Scalar parameters apply to
-    every instance; a list gives one value per instance.  Returns a list of
-    dict(A, centers, info) and the call's return code."""
+    every instance; a list gives one value per instance (target_sizes: a
+    list of per-instance tensors or None).  Returns a list of dict(A,
+    centers, info) and the call's return code."""
     m = len(instances)
 
     def per(v, i):
@@ -219,6 +235,7 @@ def balanced_kmeans_batched(instances, eps=0.03, max_iter=50, max_balance_iter=2
     pts = (Points * m)()
     prm = (Params * m)()
     outs = []
+    keep = []
     for i, inst in enumerate(instances):
         X, k = inst[0], int(inst[1])
         W = inst[2] if len(inst) > 2 else None
@@ -235,8 +252,11 @@ def balanced_kmeans_batched(instances, eps=0.03, max_iter=50, max_balance_iter=2
         p.tile_points = int(per(tile_points, i))
         p.super_tiles = int(per(super_tiles, i))
         p.recheck_rel_gap = float(per(recheck_rel_gap, i))
-        prm[i] = p
         dev = X[0].device
+        ts = _targets(None if target_sizes is None else target_sizes[i], k, dev)
+        keep.append(ts)
+        p.target_sizes = None if ts is None else ts.data_ptr()
+        prm[i] = p
         outs.append(dict(A=torch.empty(pts[i].n, dtype=torch.int32, device=dev),
                          centers=torch.empty((k, pts[i].d), dtype=torch.float64, device=dev)))
     asg = (C.c_void_p * m)(*[o["A"].data_ptr() for o in outs])
@@ -267,14 +287,15 @@ def assign_sweeps(X, centers_seq, influence_seq, precision="f32_recheck", use_bo
     return A, bw, info_dict(info)
 
 
-def partition_stats(X, A, k, eps=0.03, W=None):
+def partition_stats(X, A, k, eps=0.03, W=None, target_sizes=None):
     dev = X[0].device
     pts = make_points(X, W)
+    ts = _targets(target_sizes, k, dev)
     bw = torch.empty(k, dtype=torch.float64, device=dev)
     cen = torch.empty((k, pts.d), dtype=torch.float64, device=dev)
     st = Stats()
     _check(lib().bkm_partition_stats(C.byref(pts), _ptr(A.contiguous()), int(k), float(eps),
-                                     _ptr(bw), _ptr(cen), C.byref(st), _stream()))
+                                     _ptr(ts), _ptr(bw), _ptr(cen), C.byref(st), _stream()))
     res = {f: getattr(st, f) for f, _ in Stats._fields_}
     res.update(block_weights=bw, centers=cen)
     return res

@@ -214,6 +214,11 @@ size_t layout(RunDev& r, Arena* a, bool full)
         both((TileHead*)nullptr, (size_t)ntiles, r.thead);
         both((CandRec*)nullptr, (size_t)ntiles * kTileCap, r.tcand);
         both((double*)nullptr, (size_t)k, r.I);
+        if (r.tsz) {
+            both((double*)nullptr, (size_t)k, r.tT);
+            both((double*)nullptr, (size_t)k, r.tL);
+            both((double*)nullptr, (size_t)k + 1, r.tpre);
+        }
         both((double2*)nullptr, (size_t)k, r.clus);
         both((float2*)nullptr, (size_t)k, r.clus32);
         both((int32_t*)nullptr, (size_t)(np / kWave), r.gblk);
@@ -266,12 +271,15 @@ int read_counters(const RunDev& r, hipStream_t s, unsigned long long out[kCntWor
 // SFC bootstrap: bounding box (+ data checks), keys, sort, coordinates in
 // Hilbert order; with `tiles`, also the jump-aligned padded layout and the
 // tile, group and super-tile boxes.
-int bootstrap(RunDev& r, int order, hipStream_t s, bool tiles)
+int bootstrap(RunDev& r, int order, hipStream_t s, bool tiles, double eps = 0.0)
 {
     HIPCHK(launch_bbox(r, order, s));
+    if (r.tsz) HIPCHK(launch_target_prep(r, eps, s));
     DevState h;
     int rc = read_state(r, s, &h);
     if (rc) return rc;
+    if (h.bad_data & 4)
+        return fail(BKM_EINVAL, "target_sizes must be finite and > 0, with a finite sum");
     if (h.bad_data)
         return fail(BKM_EDATA, r.weighted ? "non-finite coordinate or weight <= 0 / non-finite"
                                           : "non-finite coordinate");
@@ -332,7 +340,7 @@ void fill_info(bkm_info* info, const DevState& h, const unsigned long long* cnt)
     info->converged = h.converged;
     info->l_max = h.lmax;
     info->max_block_weight = h.max_weight;
-    info->imbalance = h.max_weight / h.target - 1.0;
+    info->imbalance = h.max_ratio - 1.0;
     info->evaluated = (int64_t)cnt[kCntEvaluated];
     info->skipped = (int64_t)cnt[kCntSkipped];
     info->rechecked = (int64_t)cnt[kCntRechecked];
@@ -375,6 +383,7 @@ int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_i
     const int ST = p.super_tiles ? p.super_tiles : 16;
     RunDev r;
     plan(r, pts, p.k, T, ST, p.precision, p.use_bounds ? 1 : 0, p.recheck_rel_gap);
+    r.tsz = p.target_sizes;
     Arena a;
     if ((rc = alloc_run(r, a, s, true))) return rc;
 
@@ -383,7 +392,7 @@ int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_i
     struct EvFree { hipEvent_t* e; ~EvFree() { for (int i = 0; i < 3; ++i) (void)hipEventDestroy(e[i]); } } evf{ev};
     HIPCHK(hipEventRecord(ev[0], s));
 
-    if ((rc = bootstrap(r, p.hilbert_order, s, true))) return rc;
+    if ((rc = bootstrap(r, p.hilbert_order, s, true, p.epsilon))) return rc;
 
     // random-sample initialization: rounds on the first sz points of a random
     // order, sz doubling, each one AssignAndBalance and one center movement
@@ -560,6 +569,7 @@ void bkm_default_params(bkm_params* p, int32_t k)
     p->sample_start = 100;
     p->seed = 0;
     p->sample_keys = nullptr;
+    p->target_sizes = nullptr;
     p->epsilon = 0.03;
     p->delta_threshold = -1.0;
     p->recheck_rel_gap = 1e-5;
@@ -660,8 +670,8 @@ int bkm_assign_sweeps(const bkm_points* pts, int32_t k, int32_t steps, const dou
 }
 
 int bkm_partition_stats(const bkm_points* pts, const int32_t* assignment, int32_t k,
-                        double epsilon, double* block_weights_out, double* centers_out,
-                        bkm_stats* out, void* stream)
+                        double epsilon, const double* target_sizes, double* block_weights_out,
+                        double* centers_out, bkm_stats* out, void* stream)
 {
     g_err.clear();
     int rc = check_points(pts);
@@ -680,6 +690,11 @@ int bkm_partition_stats(const bkm_points* pts, const int32_t* assignment, int32_
     z.add<double>((size_t)k * r.d);
     z.add<long long>((size_t)k * kAcc);
     z.add<double>(8);
+    if (target_sizes) {
+        z.add<double>((size_t)k);
+        z.add<double>((size_t)k);
+        z.add<double>((size_t)k + 1);
+    }
     Arena a;
     a.s = s;
     HIPCHK(hipMallocAsync((void**)&a.base, z.total, s));
@@ -688,15 +703,24 @@ int bkm_partition_stats(const bkm_points* pts, const int32_t* assignment, int32_
     r.C = a.take<double>((size_t)k * r.d);
     r.acc = a.take<long long>((size_t)k * kAcc);
     double* out6 = a.take<double>(8);
+    if (target_sizes) {
+        r.tsz = target_sizes;
+        r.tT = a.take<double>((size_t)k);
+        r.tL = a.take<double>((size_t)k);
+        r.tpre = a.take<double>((size_t)k + 1);
+    }
     HIPCHK(hipMemsetAsync(r.st, 0, sizeof(DevState), s));
     HIPCHK(hipMemsetAsync(r.acc, 0, (size_t)k * kAcc * sizeof(long long), s));
     HIPCHK(launch_bbox(r, 16, s));
+    if (r.tsz) HIPCHK(launch_target_prep(r, epsilon, s));
     HIPCHK(launch_stats(r, assignment, epsilon, block_weights_out, centers_out, out6, s));
     double h6[8];
     HIPCHK(hipMemcpyAsync(h6, out6, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     DevState h;
     if ((rc = read_state(r, s, &h))) return rc;
+    if (h.bad_data & 4)
+        return fail(BKM_EINVAL, "target_sizes must be finite and > 0, with a finite sum");
     if (h.bad_data & 2) return fail(BKM_EINVAL, "assignment outside [0, k)");
     if (h.bad_data & 1) return fail(BKM_EDATA, "non-finite coordinate or bad weight");
     out->imbalance = h6[0];
@@ -746,6 +770,7 @@ int bkm_balanced_kmeans_batched(const bkm_points* pts, const bkm_params* prm, in
         const int T = p.tile_points ? p.tile_points : auto_tile(pts[i].n, p.k);
         plan(rs[i], &pts[i], p.k, T, p.super_tiles ? p.super_tiles : 16, p.precision,
              p.use_bounds ? 1 : 0, p.recheck_rel_gap);
+        rs[i].tsz = p.target_sizes;
         z.total += layout(rs[i], nullptr, true);
     }
     Arena a;
@@ -807,8 +832,14 @@ int bkm_balanced_kmeans_batched(const bkm_points* pts, const bkm_params* prm, in
     };
     int rc;
     if ((rc = fork())) return rc;
-    for (int i = 0; i < count; ++i) HIPCHK(launch_bbox(rs[i], prm[i].hilbert_order, res.streams[i % W]));
+    for (int i = 0; i < count; ++i) {
+        HIPCHK(launch_bbox(rs[i], prm[i].hilbert_order, res.streams[i % W]));
+        if (rs[i].tsz) HIPCHK(launch_target_prep(rs[i], prm[i].epsilon, res.streams[i % W]));
+    }
     if ((rc = join()) || (rc = read_all())) return rc;
+    for (int i = 0; i < count; ++i)
+        if (res.hstates[i].bad_data & 4)
+            return fail(BKM_EINVAL, "instance %d: target_sizes must be finite and > 0, with a finite sum", i);
     for (int i = 0; i < count; ++i)
         if (res.hstates[i].bad_data)
             return fail(BKM_EDATA, "instance %d: %s", i,

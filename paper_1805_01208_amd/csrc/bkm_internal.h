@@ -51,6 +51,7 @@ struct DevState {
     double w_scale;           // power of two: weight term = rint(w*w_scale) (1 for unit weights)
     double wmax;
     double beta, max_delta, max_weight, total_weight;
+    double max_ratio;         // largest weight / target over the blocks at the last balance test
 };
 
 // Sweep counters, summed over the kCntSlots slots by the host.
@@ -87,6 +88,7 @@ struct RunDev {
 
     const void* in_x[3];      // caller's coordinates (input order)
     const double* in_w;       // caller's weights or null
+    const double* tsz;        // caller's relative target sizes [k], or null (equal blocks)
 
     double* xs64[3];          // sorted master coordinates (FP64 input)
     float* xs32[3];           // sorted master coordinates (FP32 input)
@@ -115,6 +117,9 @@ struct RunDev {
     CandRec* tcand;           // [ntiles][kTileCap]
     double* C;                // [d][k] centers (SoA)
     double* I;                // [k] influence
+    double* tT;               // [k] target weight of each block (with target sizes)
+    double* tL;               // [k] weight limit of each block (with target sizes)
+    double* tpre;             // [k+1] prefix sums of the target sizes in index order; [k] = total
     double2* clus;            // [k] (accumulated movement, 1/influence)
     float2* clus32;           // [k] the same rounded up to FP32, for the Hamerly test
     int32_t* Aprev;           // [npad] block of each point at the previous round end
@@ -338,6 +343,7 @@ hipError_t launch_place(const RunDev& r, hipStream_t s);
 hipError_t launch_tile_prep(const RunDev& r, hipStream_t s);
 hipError_t launch_centers_from_sorted(const RunDev& r, double* out, int row_major,
                                       hipStream_t s);
+hipError_t launch_target_prep(const RunDev& r, double eps, hipStream_t s);
 hipError_t launch_init_run(const RunDev& r, const double* centers_init_rowmajor,
                            const double* influence_init, int max_iter, int max_balance_iter,
                            double eps, double delta_threshold, hipStream_t s);

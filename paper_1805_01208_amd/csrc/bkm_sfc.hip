@@ -615,13 +615,25 @@ __global__ __launch_bounds__(kBlock) void k_hyper_boxes(RunDev r)
     for (int j = 0; j < 2 * D; ++j) r.hbox[(int64_t)h * 2 * D + j] = b[j];
 }
 
-// Initial centers: center c is the sorted point floor(c*n/k) + floor(n/(2k)).
+// Initial centers (Alg. 2): center c is the sorted point
+// floor(c*n/k) + floor(n/(2k)); with target sizes t it is
+// floor(n*S_c/tsum) + floor(n*t_c/(2 tsum)), at most n-1, S_c the prefix sum.
 __global__ __launch_bounds__(kBlock) void k_centers_from_sorted(RunDev r, double* out,
                                                                int row_major)
 {
     const int c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= r.k) return;
-    const int64_t pos = ((int64_t)c * r.n) / r.k + r.n / (2 * (int64_t)r.k);
+    int64_t pos;
+    if (r.tsz) {
+        // the middle of the c-th stretch when the curve is cut in
+        // proportion to the target sizes
+        const double tsum = r.tpre[r.k];
+        pos = (int64_t)floor(((double)r.n * r.tpre[c]) / tsum) +
+              (int64_t)floor(((double)r.n * r.tsz[c]) / (2.0 * tsum));
+        if (pos > r.n - 1) pos = r.n - 1;
+    } else {
+        pos = ((int64_t)c * r.n) / r.k + r.n / (2 * (int64_t)r.k);
+    }
     for (int j = 0; j < r.d; ++j) {
         double v = tx_at(r, j, pos);
         if (row_major)

@@ -51,20 +51,32 @@ __device__ __forceinline__ void balance_body(RT r, const int bid)
     if (st->done || st->round_done) return;
     __shared__ double sh[1024 / kWave];
     const int k = r.k;
-    double mx = -INFINITY;
-    for (int c = threadIdx.x; c < k; c += 1024) mx = fmax(mx, block_weight(r, c));
+    const bool per_block = r.tsz != nullptr;
+    double mx = -INFINITY, over = 0.0, ratio = -INFINITY;
+    for (int c = threadIdx.x; c < k; c += 1024) {
+        const double b = block_weight(r, c);
+        mx = fmax(mx, b);
+        if (per_block) {
+            if (b > r.tL[c]) over = 1.0;
+            ratio = fmax(ratio, b / r.tT[c]);
+        }
+    }
     mx = block_reduce_1024(mx, sh, OpMax());
-    const bool bal = mx <= st->lmax;
+    if (per_block) {
+        over = block_reduce_1024(over, sh, OpMax());
+        ratio = block_reduce_1024(ratio, sh, OpMax());
+    }
+    // balanced: every block within its limit (one common limit, or its own)
+    const bool bal = per_block ? over == 0.0 : mx <= st->lmax;
     const int sweep_no = st->sweep_in_round + 1;
     double mu = 1.0;
     if (!bal) {
-        const double target = st->target;
         double m = INFINITY;
         for (int c = threadIdx.x; c < k; c += 1024) {
             const double s = block_weight(r, c);
             double f;
             if (s > 0.0) {
-                const double g = target / s;
+                const double g = (per_block ? r.tT[c] : st->target) / s;
                 f = D == 2 ? sqrt(g) : cbrt(g);
                 if (f > 1.05) f = 1.05;
                 if (f < 0.95) f = 0.95;
@@ -86,6 +98,7 @@ __device__ __forceinline__ void balance_body(RT r, const int bid)
         st->sweeps += 1;
         st->balanced = bal ? 1 : 0;
         st->max_weight = mx;
+        st->max_ratio = per_block ? ratio : mx / st->target;
         if (bal) {
             st->round_done = 1;
         } else {
@@ -545,6 +558,65 @@ __global__ __launch_bounds__(kBlock) void k_init_points(RunDev r)
     if (i < r.ngroups) r.gdirty[i] = 0;
 }
 
+// Non-uniform target sizes (the footnote to the objective at the start of
+// Sec. 4).  Prefix sums of the caller's relative sizes are taken in index
+// order by one thread over chunks staged in LDS (the order fixes the
+// rounding); then every block gets its target weight W*t/tsum and its limit,
+// (1+eps)*ceil(n*t/tsum) for unit weights or (1+eps)*target for node
+// weights, and the largest limit goes to the state.  A size that is not
+// finite and positive, or a total that overflows, sets bad_data bit 4.
+constexpr int kPrepChunk = 4096;
+
+__global__ __launch_bounds__(1024) void k_target_prep(RunDev r, double eps)
+{
+    __shared__ double buf[kPrepChunk];
+    __shared__ double sh[1024 / kWave];
+    __shared__ double total;
+    __shared__ int bad;
+    const int k = r.k;
+    double run = 0.0;
+    int b = 0;
+    for (int base = 0; base < k; base += kPrepChunk) {
+        const int m = min(kPrepChunk, k - base);
+        for (int i = threadIdx.x; i < m; i += 1024) buf[i] = r.tsz[base + i];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int i = 0; i < m; ++i) {
+                const double t = buf[i];
+                r.tpre[base + i] = run;
+                if (!(t > 0.0) || !isfinite(t)) b = 1;
+                run += t;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        r.tpre[k] = run;
+        if (!isfinite(run)) b = 1;
+        total = run;
+        bad = b;
+    }
+    __syncthreads();
+    if (bad) {
+        if (threadIdx.x == 0) atomicOr(&r.st->bad_data, 4);
+        return;
+    }
+    const double W = r.st->total_weight;
+    const double tsum = total;
+    double lm = 0.0;
+    for (int c = threadIdx.x; c < k; c += 1024) {
+        const double t = r.tsz[c];
+        const double T = (W * t) / tsum;
+        const double L = r.weighted ? (1.0 + eps) * T
+                                    : (1.0 + eps) * ceil(((double)r.n * t) / tsum);
+        r.tT[c] = T;
+        r.tL[c] = L;
+        lm = fmax(lm, L);
+    }
+    lm = block_reduce_1024(lm, sh, OpMax());
+    if (threadIdx.x == 0) r.st->lmax = lm;
+}
+
 __global__ __launch_bounds__(kBlock) void k_init_clusters(RunDev r, const double* cinit,
                                                           const double* iinit, int max_iter,
                                                           int max_bal, double eps, double dthr)
@@ -576,11 +648,13 @@ __global__ __launch_bounds__(kBlock) void k_init_clusters(RunDev r, const double
         st->M = 1.0;
         st->E = 0.0;
         const double W = st->total_weight;
-        if (r.weighted) {
-            st->lmax = (1.0 + eps) * (W / (double)r.k);
-        } else {
-            const int64_t ck = (r.n + r.k - 1) / r.k;
-            st->lmax = (1.0 + eps) * (double)ck;
+        if (!r.tsz) {   // with target sizes, the prep left the largest limit here
+            if (r.weighted) {
+                st->lmax = (1.0 + eps) * (W / (double)r.k);
+            } else {
+                const int64_t ck = (r.n + r.k - 1) / r.k;
+                st->lmax = (1.0 + eps) * (double)ck;
+            }
         }
         st->target = W / (double)r.k;
         st->delta_threshold = dthr < 0.0 ? 1e-5 * st->ext : dthr;
@@ -763,11 +837,18 @@ __global__ __launch_bounds__(kBlock) void k_stats_final(RunDev r, int nparts, do
         const int64_t ck = (r.n + r.k - 1) / r.k;
         lmax = (1.0 + eps) * (double)ck;
     }
+    // with target sizes mx is the largest weight / target, and every block
+    // has its own limit
     for (int c = threadIdx.x; c < r.k; c += kBlock) {
         const double b = block_weight(r, c);
-        mx = fmax(mx, b);
+        if (r.tsz) {
+            mx = fmax(mx, b / r.tT[c]);
+            if (b > r.tL[c]) over += 1.0;
+        } else {
+            mx = fmax(mx, b);
+            if (b > lmax) over += 1.0;
+        }
         if (b == 0.0) empty += 1.0;
-        if (b > lmax) over += 1.0;
     }
     mx = wave_max_d(mx);
     empty = wave_sum_d(empty);
@@ -777,11 +858,11 @@ __global__ __launch_bounds__(kBlock) void k_stats_final(RunDev r, int nparts, do
     if (threadIdx.x == 0) {
         double m = sh[0];
         for (int w = 1; w < kBlock / kWave; ++w) m = fmax(m, sh[w]);
-        out6[0] = m / (W / (double)r.k) - 1.0;
+        out6[0] = r.tsz ? m - 1.0 : m / (W / (double)r.k) - 1.0;
         double obj = 0.0;
         for (int b = 0; b < nparts; ++b) obj += r.red[b];
         out6[1] = obj;
-        out6[2] = lmax;
+        out6[2] = r.tsz ? st->lmax : lmax;
     }
     __syncthreads();
     if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = empty;
@@ -805,6 +886,12 @@ __global__ __launch_bounds__(kBlock) void k_stats_final(RunDev r, int nparts, do
 inline unsigned nblocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
+
+hipError_t launch_target_prep(const RunDev& r, double eps, hipStream_t s)
+{
+    k_target_prep<<<1, 1024, 0, s>>>(r, eps);
+    return hipGetLastError();
+}
 
 hipError_t launch_init_run(const RunDev& r, const double* cinit, const double* iinit, int max_iter,
                            int max_balance_iter, double eps, double dthr, hipStream_t s)

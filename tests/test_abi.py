@@ -73,6 +73,7 @@ def test_default_params(bkm):
     assert p.precision == bkm.PREC_F32_RECHECK and p.use_bounds == 1
     assert p.epsilon == 0.03 and p.delta_threshold < 0 and p.recheck_rel_gap == 1e-5
     assert (p.sample_init, p.sample_start, p.seed, p.sample_keys) == (0, 100, 0, None)
+    assert p.target_sizes is None
 
 
 def _pts(bkm, n=100, d=2, dtype=1):
@@ -120,7 +121,7 @@ def test_3d_order_limit_and_null_outputs(bkm):
     q = bkm.default_params(4)
     rc = L.bkm_balanced_kmeans(C.byref(p), C.byref(q), None, None, None, None, None, None, None)
     assert rc == bkm.BKM_EINVAL
-    rc = L.bkm_partition_stats(None, None, 4, 0.03, None, None, None, None)
+    rc = L.bkm_partition_stats(None, None, 4, 0.03, None, None, None, None, None)
     assert rc == bkm.BKM_EINVAL
     rc = L.bkm_assign_sweeps(C.byref(p), 4, 0, None, None, 0, 1, 0, None, None, None, None)
     assert rc == bkm.BKM_EINVAL
