@@ -32,6 +32,14 @@ class OracleStats(C.Structure):
     ]
 
 
+class OracleGraphStats(C.Structure):
+    _fields_ = [
+        ("edge_cut", C.c_int64), ("max_comm", C.c_int64), ("total_comm", C.c_int64),
+        ("max_diameter", C.c_int32), ("disconnected_blocks", C.c_int32),
+        ("harmonic_diameter", C.c_double),
+    ]
+
+
 def lib():
     global _LIB
     if _LIB is None:
@@ -67,6 +75,10 @@ def lib():
             I64, P, P, P, P, P, P, P, C.POINTER(OracleInfo), P, P]
         L.oracle_partition_stats.argtypes = [
             I64, C.c_int, P, P, P, C.c_int, D, P, P, P, C.POINTER(OracleStats)]
+        L.oracle_knn.argtypes = [I64, C.c_int, P, C.c_int, P]
+        L.oracle_knn_symmetrize.argtypes = [I64, C.c_int, P, P, P, P]
+        L.oracle_graph_metrics.argtypes = [I64, P, P, P, C.c_int, P, P,
+                                           C.POINTER(OracleGraphStats)]
         L.oracle_num_threads.argtypes = []
         _ = I32
         _LIB = L
@@ -303,3 +315,40 @@ def partition_stats(X, A, k, eps, W=None, target_sizes=None):
                                         _ptr(t), _ptr(bw), _ptr(centers), C.byref(st)), "partition_stats")
     return dict(block_weights=bw, centers=centers,
                 **{f: getattr(st, f) for f, _ in OracleStats._fields_})
+
+
+# ---------------------------------------------------------------- graph quality
+def knn(X, K):
+    """K nearest neighbours of every point, [n][K] input indices, nearest first."""
+    p = _Points(X)
+    nbr = np.empty((p.n, int(K)), dtype=np.int32)
+    _check(lib().oracle_knn(p.n, p.d, p.arr, int(K), _ptr(nbr)), "knn")
+    return nbr
+
+
+def knn_symmetrize(nbr):
+    """Undirected graph of neighbour lists as CSR: (row_ptr int64[n+1], col int32[nnz])."""
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    n, K = nbr.shape
+    row_ptr = np.empty(n + 1, dtype=np.int64)
+    col = np.empty(2 * n * K, dtype=np.int32)
+    nnz = np.zeros(1, dtype=np.int64)
+    _check(lib().oracle_knn_symmetrize(n, K, _ptr(nbr), _ptr(row_ptr), _ptr(col), _ptr(nnz)),
+           "knn_symmetrize")
+    return row_ptr, col[:int(nnz[0])].copy()
+
+
+def graph_metrics(row_ptr, col, A, k):
+    """Edge cut, communication volumes and block diameter bounds of A."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    A = np.ascontiguousarray(A, dtype=np.int32)
+    n = A.shape[0]
+    comm = np.empty(k, dtype=np.int64)
+    diam = np.empty(k, dtype=np.int32)
+    st = OracleGraphStats()
+    _check(lib().oracle_graph_metrics(n, _ptr(row_ptr), _ptr(col), _ptr(A), int(k), _ptr(comm),
+                                      _ptr(diam), C.byref(st)), "graph_metrics")
+    out = {f: getattr(st, f) for f, _ in OracleGraphStats._fields_}
+    out.update(comm=comm, diameter=diam)
+    return out

@@ -8,14 +8,14 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "bkm_oracle.c")
+SRCS = [os.path.join(HERE, "bkm_oracle.c"), os.path.join(HERE, "graph_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
     cmd = [
         "gcc", "-std=c11", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-        "-fPIC", "-shared", "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm",
+        "-fPIC", "-shared", "-Wall", "-Wextra", "-o", LIB + ".tmp", *SRCS, "-lm",
     ]
     if verbose:
         print(" ".join(cmd), flush=True)
