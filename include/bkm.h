@@ -245,6 +245,71 @@ int bkm_partition_stats(const bkm_points* pts, const int32_t* assignment, int32_
                         double epsilon, const double* target_sizes, double* block_weights_out,
                         double* centers_out, bkm_stats* out, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Graph-quality evaluation (Sec. 2, the block measures; Sec. 5.2, Metrics).
+ * The paper measures partitions on the meshes' graphs; these calls build
+ * k-nearest-neighbour graphs of point clouds and evaluate any graph given as
+ * CSR.
+ * ------------------------------------------------------------------------- */
+
+/* The knn nearest neighbours of every point: the knn points q != p with the
+ * smallest (squared Euclidean distance in FP64, ((dx*dx + dy*dy) + dz*dz),
+ * input index of q), nearest first.  Exact, not approximate.
+ *   knn          1..16, at most n-1.
+ *   nbr_out      [device] n*knn int32, [n][knn], input indices.
+ *   group_visits [host] number of (64-point group, 64-point group) pairs
+ *                compared, or NULL.
+ * Errors: BKM_EINVAL, BKM_EDATA (non-finite coordinate), BKM_ENOMEM,
+ * BKM_EHIP. */
+int bkm_knn(const bkm_points* pts, int32_t knn, int32_t* nbr_out, int64_t* group_visits,
+            void* stream);
+
+/* The undirected graph of neighbour lists: edge {p, q} when q is in p's list
+ * or p in q's; CSR with both directions, each row sorted ascending.
+ *   nbr      [device] n*knn int32 from bkm_knn (or any lists without self
+ *            entries).
+ *   row_ptr_out [device] n+1 int64.
+ *   col_out  [device] room for 2*n*knn int32; the first *nnz_out are used.
+ *   nnz_out  [host] or NULL.
+ * Errors: BKM_EINVAL (also for an entry outside [0, n) or equal to its own
+ * row), BKM_ENOMEM, BKM_EHIP. */
+int bkm_knn_graph(int64_t n, int32_t knn, const int32_t* nbr, int64_t* row_ptr_out,
+                  int32_t* col_out, int64_t* nnz_out, void* stream);
+
+typedef struct {
+    int64_t edge_cut;           /* undirected edges between different blocks */
+    int64_t max_comm;           /* max over blocks of comm(V_i) */
+    int64_t total_comm;         /* sum over blocks of comm(V_i) */
+    int32_t max_diameter;       /* largest finite block diameter bound */
+    int32_t disconnected_blocks;
+    double harmonic_diameter;   /* harmonic mean of the bounds over blocks of >= 2
+                                   vertices (1/inf = 0); inf if all are disconnected,
+                                   0 if there are none */
+    int32_t bfs_levels;         /* breadth-first levels run (both sweeps) */
+    int32_t pad;
+} bkm_graph_stats;
+
+/* Edge cut, communication volume and block diameters of a partition of an
+ * undirected graph (Sec. 2 definitions):
+ *   comm(V_i) = sum over v in V_i of the number of blocks other than V_i
+ *   holding a neighbour of v;
+ *   the diameter of a block is bounded from below by a double sweep of
+ *   breadth-first searches inside the block (Sec. 5.2 uses such a bound,
+ *   within a factor 2 of the exact value): from the block's lowest vertex to
+ *   the farthest vertex found (largest distance, lowest index on ties),
+ *   whose eccentricity is the bound; -1 if the block is disconnected, 0 if
+ *   it is empty.
+ *   row_ptr [device] n+1 int64, col [device] nnz int32: CSR holding both
+ *           directions of every edge.
+ *   assignment [device] n int32 in [0, k).
+ *   comm_out [device] k int64, diameter_out [device] k int32, or NULL.
+ *   out [host] required.
+ * Errors: BKM_EINVAL (also for an assignment, row pointer or column out of
+ * range), BKM_ENOMEM, BKM_EHIP. */
+int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
+                      const int32_t* assignment, int32_t k, int64_t* comm_out,
+                      int32_t* diameter_out, bkm_graph_stats* out, void* stream);
+
 /* Message of the last nonzero return on the calling thread ("" if none). */
 const char* bkm_last_error(void);
 

@@ -76,6 +76,7 @@ def lib():
         L.oracle_partition_stats.argtypes = [
             I64, C.c_int, P, P, P, C.c_int, D, P, P, P, C.POINTER(OracleStats)]
         L.oracle_knn.argtypes = [I64, C.c_int, P, C.c_int, P]
+        L.oracle_knn_of.argtypes = [I64, C.c_int, P, C.c_int, I64, P, P]
         L.oracle_knn_symmetrize.argtypes = [I64, C.c_int, P, P, P, P]
         L.oracle_graph_metrics.argtypes = [I64, P, P, P, C.c_int, P, P,
                                            C.POINTER(OracleGraphStats)]
@@ -323,6 +324,15 @@ def knn(X, K):
     p = _Points(X)
     nbr = np.empty((p.n, int(K)), dtype=np.int32)
     _check(lib().oracle_knn(p.n, p.d, p.arr, int(K), _ptr(nbr)), "knn")
+    return nbr
+
+
+def knn_of(X, K, queries):
+    """K nearest neighbours (over all points) of the given query points."""
+    p = _Points(X)
+    q = np.ascontiguousarray(queries, dtype=np.int64)
+    nbr = np.empty((q.shape[0], int(K)), dtype=np.int32)
+    _check(lib().oracle_knn_of(p.n, p.d, p.arr, int(K), q.shape[0], _ptr(q), _ptr(nbr)), "knn_of")
     return nbr
 
 

@@ -60,14 +60,18 @@ static int nb_before(double da, int32_t ia, double db, int32_t ib)
     return da < db || (da == db && ia < ib);
 }
 
-/* K nearest neighbours of every point by brute force (reading K1).
- * nbr is [n][K], input indices, nearest first. */
-int oracle_knn(int64_t n, int d, const double* const* X, int K, int32_t* nbr)
+/* K nearest neighbours of the points queries[0..nq) by brute force over all
+ * n points (reading K1).  nbr is [nq][K], input indices, nearest first. */
+int oracle_knn_of(int64_t n, int d, const double* const* X, int K, int64_t nq,
+                  const int64_t* queries, int32_t* nbr)
 {
     if (n < 2 || n > INT32_MAX || d < 2 || d > 3 || K < 1 || K > KNN_MAX || K > n - 1)
         return ORC_EINVAL;
+    for (int64_t t = 0; t < nq; ++t)
+        if (queries[t] < 0 || queries[t] >= n) return ORC_EINVAL;
 #pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t t = 0; t < nq; ++t) {
+        const int64_t i = queries[t];
         double bd[KNN_MAX];
         int32_t bi[KNN_MAX];
         for (int m = 0; m < K; ++m) {
@@ -87,9 +91,21 @@ int oracle_knn(int64_t n, int d, const double* const* X, int K, int32_t* nbr)
             bd[m] = s;
             bi[m] = (int32_t)j;
         }
-        memcpy(nbr + i * K, bi, (size_t)K * sizeof(int32_t));
+        memcpy(nbr + t * K, bi, (size_t)K * sizeof(int32_t));
     }
     return ORC_OK;
+}
+
+/* K nearest neighbours of every point (reading K1): nbr is [n][K]. */
+int oracle_knn(int64_t n, int d, const double* const* X, int K, int32_t* nbr)
+{
+    if (n < 2 || n > INT32_MAX) return ORC_EINVAL;
+    int64_t* all = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    if (!all) return ORC_ENOMEM;
+    for (int64_t i = 0; i < n; ++i) all[i] = i;
+    int rc = oracle_knn_of(n, d, X, K, n, all, nbr);
+    free(all);
+    return rc;
 }
 
 static int cmp_pair(const void* a, const void* b)

@@ -54,6 +54,13 @@ class Stats(C.Structure):
                 ("empty_blocks", C.c_int32), ("overloaded_blocks", C.c_int32)]
 
 
+class GraphStats(C.Structure):
+    _fields_ = [("edge_cut", C.c_int64), ("max_comm", C.c_int64), ("total_comm", C.c_int64),
+                ("max_diameter", C.c_int32), ("disconnected_blocks", C.c_int32),
+                ("harmonic_diameter", C.c_double), ("bfs_levels", C.c_int32),
+                ("pad", C.c_int32)]
+
+
 class BkmError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libbkm error {code}: {msg}")
@@ -63,7 +70,7 @@ class BkmError(RuntimeError):
 _LIB = None
 FUNCTIONS = ("bkm_default_params", "bkm_init_centers_sfc", "bkm_balanced_kmeans",
              "bkm_balanced_kmeans_batched", "bkm_assign_sweeps", "bkm_partition_stats",
-             "bkm_last_error")
+             "bkm_knn", "bkm_knn_graph", "bkm_graph_metrics", "bkm_last_error")
 
 
 def lib():
@@ -86,10 +93,15 @@ def lib():
                                           C.POINTER(Stats), P]
         L.bkm_balanced_kmeans_batched.argtypes = [C.POINTER(Points), C.POINTER(Params), C.c_int32,
                                                   C.POINTER(P), C.POINTER(P), C.POINTER(Info), P]
+        L.bkm_knn.argtypes = [C.POINTER(Points), C.c_int32, P, C.POINTER(C.c_int64), P]
+        L.bkm_knn_graph.argtypes = [C.c_int64, C.c_int32, P, P, P, C.POINTER(C.c_int64), P]
+        L.bkm_graph_metrics.argtypes = [C.c_int64, C.c_int64, P, P, P, C.c_int32, P, P,
+                                        C.POINTER(GraphStats), P]
         L.bkm_last_error.argtypes = []
         L.bkm_last_error.restype = C.c_char_p
         for f in ("bkm_init_centers_sfc", "bkm_balanced_kmeans", "bkm_assign_sweeps",
-                  "bkm_partition_stats", "bkm_balanced_kmeans_batched"):
+                  "bkm_partition_stats", "bkm_balanced_kmeans_batched", "bkm_knn",
+                  "bkm_knn_graph", "bkm_graph_metrics"):
             getattr(L, f).restype = C.c_int
         _LIB = L
     return _LIB
@@ -298,4 +310,42 @@ def partition_stats(X, A, k, eps=0.03, W=None, target_sizes=None):
                                      _ptr(ts), _ptr(bw), _ptr(cen), C.byref(st), _stream()))
     res = {f: getattr(st, f) for f, _ in Stats._fields_}
     res.update(block_weights=bw, centers=cen)
+    return res
+
+
+def knn(X, K):
+    """Exact K nearest neighbours of every point: (nbr [n][K] int32 device
+    tensor, input indices nearest first; number of group pairs compared)."""
+    dev = X[0].device
+    pts = make_points(X)
+    nbr = torch.empty((pts.n, int(K)), dtype=torch.int32, device=dev)
+    visits = C.c_int64(0)
+    _check(lib().bkm_knn(C.byref(pts), int(K), _ptr(nbr), C.byref(visits), _stream()))
+    return nbr, visits.value
+
+
+def knn_graph(nbr):
+    """Undirected graph of neighbour lists as CSR: (row_ptr int64, col int32)."""
+    n, K = nbr.shape
+    dev = nbr.device
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(2 * n * K, dtype=torch.int32, device=dev)
+    nnz = C.c_int64(0)
+    _check(lib().bkm_knn_graph(n, K, _ptr(nbr.contiguous()), _ptr(row_ptr), _ptr(col),
+                               C.byref(nnz), _stream()))
+    return row_ptr, col[:nnz.value]
+
+
+def graph_metrics(row_ptr, col, A, k):
+    """Edge cut, communication volumes and block diameter bounds of A."""
+    dev = A.device
+    n = A.numel()
+    comm = torch.empty(k, dtype=torch.int64, device=dev)
+    diam = torch.empty(k, dtype=torch.int32, device=dev)
+    st = GraphStats()
+    _check(lib().bkm_graph_metrics(n, col.numel(), _ptr(row_ptr.contiguous()),
+                                   _ptr(col.contiguous()), _ptr(A.contiguous()), int(k),
+                                   _ptr(comm), _ptr(diam), C.byref(st), _stream()))
+    res = {f: getattr(st, f) for f, _ in GraphStats._fields_ if f != "pad"}
+    res.update(comm=comm, diameter=diam)
     return res

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbkm.so")
-SOURCES = ["bkm_api.hip", "bkm_sfc.hip", "bkm_sweep.hip", "bkm_update.hip"]
+SOURCES = ["bkm_api.hip", "bkm_sfc.hip", "bkm_sweep.hip", "bkm_update.hip", "bkm_graph.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

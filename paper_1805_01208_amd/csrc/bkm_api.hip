@@ -575,6 +575,166 @@ void bkm_default_params(bkm_params* p, int32_t k)
     p->recheck_rel_gap = 1e-5;
 }
 
+int bkm_knn(const bkm_points* pts, int32_t knn, int32_t* nbr_out, int64_t* group_visits,
+            void* stream)
+{
+    g_err.clear();
+    int rc = check_points(pts);
+    if (rc) return rc;
+    if (knn < 1 || knn > 16) return fail(BKM_EINVAL, "knn = %d outside [1, 16]", knn);
+    if (knn > pts->n - 1) return fail(BKM_EINVAL, "knn = %d needs at least knn + 1 points", knn);
+    if (!nbr_out) return fail(BKM_EINVAL, "nbr_out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    keep_pool_memory();
+    // the search walks the box hierarchy of the tiled Hilbert layout
+    RunDev r;
+    plan(r, pts, 1, 256, 16, BKM_PREC_F64, 0, 0.0);
+    Arena a;
+    if ((rc = alloc_run(r, a, s, true))) return rc;
+    if ((rc = bootstrap(r, 16, s, true))) return rc;
+    unsigned long long* visits = reinterpret_cast<unsigned long long*>(r.red);
+    HIPCHK(hipMemsetAsync(visits, 0, sizeof(unsigned long long), s));
+    HIPCHK(launch_knn(r, knn, nbr_out, visits, s));
+    unsigned long long hv = 0;
+    HIPCHK(hipMemcpyAsync(&hv, visits, sizeof(hv), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (group_visits) *group_visits = (int64_t)hv;
+    return BKM_OK;
+}
+
+int bkm_knn_graph(int64_t n, int32_t knn, const int32_t* nbr, int64_t* row_ptr_out,
+                  int32_t* col_out, int64_t* nnz_out, void* stream)
+{
+    g_err.clear();
+    if (n < 2 || n > INT32_MAX) return fail(BKM_EINVAL, "n = %lld outside [2, 2^31-1]", (long long)n);
+    if (knn < 1 || knn > n - 1) return fail(BKM_EINVAL, "knn = %d outside [1, n-1]", knn);
+    if (!nbr || !row_ptr_out || !col_out) return fail(BKM_EINVAL, "nbr/row_ptr_out/col_out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    keep_pool_memory();
+    Sizes z;
+    z.add<int32_t>((size_t)n);
+    z.add<int32_t>((size_t)n);
+    z.add<int64_t>((size_t)scan_parts(n));
+    z.add<int>(1);
+    Arena a;
+    a.s = s;
+    HIPCHK(hipMallocAsync((void**)&a.base, z.total, s));
+    a.cap = z.total;
+    int32_t* extra = a.take<int32_t>((size_t)n);
+    int32_t* cursor = a.take<int32_t>((size_t)n);
+    int64_t* part = a.take<int64_t>((size_t)scan_parts(n));
+    int* bad = a.take<int>(1);
+    HIPCHK(hipMemsetAsync(extra, 0, (size_t)n * sizeof(int32_t), s));
+    HIPCHK(hipMemsetAsync(cursor, 0, (size_t)n * sizeof(int32_t), s));
+    HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), s));
+    HIPCHK(launch_sym_count(n, knn, nbr, extra, bad, s));
+    int hb = 0;
+    HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hb) return fail(BKM_EINVAL, "neighbour entry outside [0, n) or pointing to its own row");
+    HIPCHK(launch_sym_rows(n, knn, extra, part, row_ptr_out, s));
+    HIPCHK(launch_sym_fill(n, knn, nbr, row_ptr_out, cursor, col_out, s));
+    int64_t nnz = 0;
+    HIPCHK(hipMemcpyAsync(&nnz, row_ptr_out + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (nnz_out) *nnz_out = nnz;
+    return BKM_OK;
+}
+
+int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
+                      const int32_t* assignment, int32_t k, int64_t* comm_out,
+                      int32_t* diameter_out, bkm_graph_stats* out, void* stream)
+{
+    g_err.clear();
+    if (n < 1 || n > INT32_MAX) return fail(BKM_EINVAL, "n = %lld outside [1, 2^31-1]", (long long)n);
+    if (nnz < 0) return fail(BKM_EINVAL, "nnz < 0");
+    if (k < 1) return fail(BKM_EINVAL, "k = %d < 1", k);
+    if (!row_ptr || (!col && nnz > 0) || !assignment || !out)
+        return fail(BKM_EINVAL, "row_ptr/col/assignment/out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    keep_pool_memory();
+    Sizes z;
+    z.add<int64_t>((size_t)k);
+    for (int i = 0; i < 4; ++i) z.add<int32_t>((size_t)k);
+    z.add<unsigned long long>((size_t)k);
+    z.add<long long>(4);
+    z.add<int>(4);
+    z.add<double>(8);
+    for (int i = 0; i < 3; ++i) z.add<int32_t>((size_t)n);
+    Arena a;
+    a.s = s;
+    HIPCHK(hipMallocAsync((void**)&a.base, z.total, s));
+    a.cap = z.total;
+    GraphDev g;
+    g.comm = a.take<int64_t>((size_t)k);
+    g.size = a.take<int32_t>((size_t)k);
+    g.seed = a.take<int32_t>((size_t)k);
+    g.reached = a.take<int32_t>((size_t)k);
+    g.conn = a.take<int32_t>((size_t)k);
+    g.far = a.take<unsigned long long>((size_t)k);
+    long long* sc = a.take<long long>(4);
+    g.cut2 = sc;
+    g.sums = sc + 1;
+    int* ints = a.take<int>(4);
+    g.bad = ints;
+    int32_t* cnt = ints + 1;   // frontier counts
+    double* summary = a.take<double>(8);
+    int32_t* dist = a.take<int32_t>((size_t)n);
+    int32_t* qa = a.take<int32_t>((size_t)n);
+    int32_t* qb = a.take<int32_t>((size_t)n);
+    HIPCHK(hipMemsetAsync(g.comm, 0, (size_t)k * sizeof(int64_t), s));
+    HIPCHK(hipMemsetAsync(g.size, 0, (size_t)k * sizeof(int32_t), s));
+    HIPCHK(launch_fill_i32(g.seed, k, INT32_MAX, s));
+    HIPCHK(hipMemsetAsync(sc, 0, 4 * sizeof(long long), s));
+    HIPCHK(hipMemsetAsync(ints, 0, 4 * sizeof(int), s));
+    HIPCHK(launch_gm_vertex(n, nnz, row_ptr, col, assignment, k, g, s));
+    int hb = 0;
+    HIPCHK(hipMemcpyAsync(&hb, g.bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hb) return fail(BKM_EINVAL, "assignment outside [0, k), or row_ptr/col outside the graph");
+
+    // two breadth-first sweeps over all blocks at once; the host reads the
+    // frontier size after every level
+    int levels = 0;
+    for (int sweep = 0; sweep < 2; ++sweep) {
+        HIPCHK(launch_fill_i32(dist, n, -1, s));
+        HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t), s));
+        HIPCHK(launch_bfs_sources(k, g, sweep, dist, qa, cnt, s));
+        int32_t f = 0;
+        HIPCHK(hipMemcpyAsync(&f, cnt, sizeof(f), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        int32_t* cur = qa;
+        int32_t* nxt = qb;
+        for (int32_t level = 0; f > 0; ++level) {
+            if (level >= n) return fail(BKM_EHIP, "breadth-first search did not end");
+            HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t), s));
+            HIPCHK(launch_bfs_level(row_ptr, col, assignment, g, cur, f, level, dist, nxt, cnt, s));
+            HIPCHK(hipMemcpyAsync(&f, cnt, sizeof(f), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (f < 0 || f > n) return fail(BKM_EHIP, "frontier of %d vertices", f);
+            std::swap(cur, nxt);
+            ++levels;
+        }
+        if (sweep == 0) HIPCHK(launch_gm_connected(k, g, s));
+    }
+    HIPCHK(launch_gm_final(k, g, diameter_out, comm_out, summary, s));
+    double hs[8];
+    long long hl[4];
+    HIPCHK(hipMemcpyAsync(hs, summary, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hl, sc, sizeof(hl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::memset(out, 0, sizeof(*out));
+    out->edge_cut = hl[0] / 2;
+    out->max_comm = hl[1];
+    out->total_comm = hl[2];
+    out->disconnected_blocks = (int32_t)hl[3];
+    out->max_diameter = (int32_t)hs[3];
+    const double inv = hs[4], counted = hs[5];
+    out->harmonic_diameter = counted == 0.0 ? 0.0 : (inv == 0.0 ? INFINITY : counted / inv);
+    out->bfs_levels = levels;
+    return BKM_OK;
+}
+
 const char* bkm_last_error(void) { return g_err.c_str(); }
 
 int bkm_init_centers_sfc(const bkm_points* pts, int32_t k, int32_t hilbert_order,

@@ -12,8 +12,8 @@ namespace bkm {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;          // threads per block of the point kernels
-constexpr int kTileCap = 128;
-constexpr int kHyper = 16;         // super-tiles per hyper-tile of the candidate hierarchy        // candidate records kept per tile
+constexpr int kTileCap = 128;        // candidate records kept per tile
+constexpr int kHyper = 16;           // super-tiles per hyper-tile of the candidate hierarchy
 constexpr int kFixShift = 30;        // fixed-point sums: term = hi * 2^30 + lo
 constexpr long long kFixLoMask = (1LL << kFixShift) - 1;
 constexpr int kPad = -2;             // block id of a padding point (never evaluated)
@@ -333,6 +333,19 @@ __device__ inline float f32_down(double x) { return __double2float_rd(x); }
 
 // ------------------------------------------------------------- launchers
 // Each returns the hipError_t of its last launch.
+// Per-block working arrays of the graph metrics.
+struct GraphDev {
+    int64_t* comm;            // [k] communication volume
+    int32_t* size;            // [k] vertices
+    int32_t* seed;            // [k] lowest vertex (INT_MAX if empty)
+    int32_t* reached;         // [k] vertices reached by the current sweep
+    int32_t* conn;            // [k] 1 if the first sweep reached the whole block
+    unsigned long long* far;  // [k] (level << 32) | (2^32-1 - vertex) of the farthest vertex
+    long long* cut2;          // [1] cut entries (each undirected edge twice)
+    long long* sums;          // [3] max comm, total comm, disconnected blocks
+    int* bad;                 // [1] invalid input seen
+};
+
 hipError_t launch_bbox(const RunDev& r, int hilbert_order, hipStream_t s);
 hipError_t launch_keys(const RunDev& r, int hilbert_order, int32_t* vals, hipStream_t s);
 hipError_t radix_sort_pairs(const RunDev& r, uint64_t* keys, int32_t* vals, int nbits,
@@ -353,6 +366,27 @@ hipError_t launch_sample_order(const RunDev& r, uint64_t seed, const uint64_t* g
                                hipStream_t s);
 hipError_t launch_gather_sample(const RunDev& r, int64_t count, void* const* x, double* w,
                                 hipStream_t s);
+hipError_t launch_knn(const RunDev& r, int K, int32_t* nbr, unsigned long long* visits,
+                      hipStream_t s);
+hipError_t launch_sym_count(int64_t n, int K, const int32_t* nbr, int32_t* extra, int* bad,
+                            hipStream_t s);
+int64_t scan_parts(int64_t n);
+hipError_t launch_sym_rows(int64_t n, int K, const int32_t* extra, int64_t* part,
+                           int64_t* row_ptr, hipStream_t s);
+hipError_t launch_sym_fill(int64_t n, int K, const int32_t* nbr, const int64_t* row_ptr,
+                           int32_t* cursor, int32_t* col, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_gm_vertex(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
+                            const int32_t* A, int k, const GraphDev& g, hipStream_t s);
+hipError_t launch_bfs_sources(int k, const GraphDev& g, int second, int32_t* dist,
+                              int32_t* queue, int32_t* count, hipStream_t s);
+hipError_t launch_bfs_level(const int64_t* row_ptr, const int32_t* col, const int32_t* A,
+                            const GraphDev& g, const int32_t* frontier, int32_t fcount,
+                            int32_t level, int32_t* dist, int32_t* next, int32_t* ncount,
+                            hipStream_t s);
+hipError_t launch_gm_connected(int k, const GraphDev& g, hipStream_t s);
+hipError_t launch_gm_final(int k, const GraphDev& g, int32_t* diam_out, int64_t* comm_out,
+                           double* summary, hipStream_t s);
 hipError_t launch_supercand(const RunDev& r, hipStream_t s);
 hipError_t launch_tilecand(const RunDev& r, hipStream_t s);
 hipError_t launch_sweep(const RunDev& r, hipStream_t s);

@@ -44,7 +44,7 @@ def test_struct_layouts_match_header(bkm, tmp_path):
     """Size and every field offset of the binding's structs against the
     header, compiled by the host C compiler."""
     structs = {"bkm_points": bkm.Points, "bkm_params": bkm.Params, "bkm_info": bkm.Info,
-               "bkm_stats": bkm.Stats}
+               "bkm_stats": bkm.Stats, "bkm_graph_stats": bkm.GraphStats}
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "bkm.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -125,6 +125,28 @@ def test_3d_order_limit_and_null_outputs(bkm):
     assert rc == bkm.BKM_EINVAL
     rc = L.bkm_assign_sweeps(C.byref(p), 4, 0, None, None, 0, 1, 0, None, None, None, None)
     assert rc == bkm.BKM_EINVAL
+
+
+def test_graph_argument_errors(bkm):
+    """Rejected on the host before any device work."""
+    L = bkm.lib()
+    p = _pts(bkm, n=10)
+    assert L.bkm_knn(C.byref(p), 0, C.c_void_p(0x2000), None, None) == bkm.BKM_EINVAL
+    assert L.bkm_knn(C.byref(p), 17, C.c_void_p(0x2000), None, None) == bkm.BKM_EINVAL
+    assert L.bkm_knn(C.byref(p), 10, C.c_void_p(0x2000), None, None) == bkm.BKM_EINVAL
+    assert "knn + 1" in L.bkm_last_error().decode()
+    assert L.bkm_knn(C.byref(p), 4, None, None, None) == bkm.BKM_EINVAL
+    assert L.bkm_knn_graph(1, 1, C.c_void_p(0x2000), C.c_void_p(0x3000), C.c_void_p(0x4000),
+                           None, None) == bkm.BKM_EINVAL
+    assert L.bkm_knn_graph(10, 10, C.c_void_p(0x2000), C.c_void_p(0x3000), C.c_void_p(0x4000),
+                           None, None) == bkm.BKM_EINVAL
+    st = bkm.GraphStats()
+    assert L.bkm_graph_metrics(10, 5, None, None, None, 2, None, None, C.byref(st),
+                               None) == bkm.BKM_EINVAL
+    assert L.bkm_graph_metrics(10, -1, C.c_void_p(0x2000), C.c_void_p(0x3000),
+                               C.c_void_p(0x4000), 2, None, None, C.byref(st), None) == bkm.BKM_EINVAL
+    assert L.bkm_graph_metrics(10, 5, C.c_void_p(0x2000), C.c_void_p(0x3000),
+                               C.c_void_p(0x4000), 0, None, None, C.byref(st), None) == bkm.BKM_EINVAL
 
 
 def test_batched_argument_errors(bkm):

@@ -1,0 +1,130 @@
+"""Graph-quality evaluation on the GPU (Sec. 2 block measures; Sec. 5.2
+Metrics): exact k-nearest-neighbour lists, their undirected CSR graph, and
+edge cut / communication volume / block diameter bounds, each identical to
+the oracle's."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import cuda, torch, widened
+from paper_1805_01208_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _knn_both(X, K, what):
+    from paper_1805_01208_amd import bkm
+    print(f"case graph knn {what} n={len(X[0])} d={len(X)} K={K}", flush=True)
+    nbr, visits = bkm.knn(cuda(X), K)
+    ref = oracle.knn(widened(X), K)
+    assert np.array_equal(nbr.cpu().numpy(), ref), what
+    assert visits > 0
+    return nbr, ref
+
+
+@pytest.mark.parametrize("d,K,seed", [(2, 6, 1), (3, 12, 2), (2, 16, 3), (3, 1, 4)])
+def test_knn_uniform(d, K, seed):
+    _knn_both(workloads.uniform(20000, d, 60 + seed), K, "uniform")
+
+
+def test_knn_clustered_and_f32():
+    _knn_both(workloads.refined2d(30000, 65), 8, "refined2d")
+    _knn_both([x.astype(np.float32) for x in workloads.gauss3d(15000, 66)], 10, "gauss3d f32")
+
+
+def test_knn_lattice_ties_and_duplicates():
+    """Many equal distances (integer lattice, shuffled) and duplicate points:
+    ties go to the lower input index on both sides."""
+    rng = np.random.default_rng(67)
+    gx, gy = np.meshgrid(np.arange(150.0), np.arange(120.0))
+    P = np.stack([gx.ravel(), gy.ravel()], axis=1)
+    P = np.concatenate([P, P[rng.choice(len(P), 500, replace=False)]])
+    P = P[rng.permutation(len(P))]
+    _knn_both([P[:, 0].copy(), P[:, 1].copy()], 8, "lattice")
+    g3 = np.stack(np.meshgrid(np.arange(20.0), np.arange(20.0), np.arange(12.0)), -1).reshape(-1, 3)
+    g3 = g3[rng.permutation(len(g3))]
+    _knn_both([g3[:, j].copy() for j in range(3)], 14, "lattice3d")
+
+
+@pytest.mark.parametrize("n,K", [(2, 1), (5, 4), (65, 1), (300, 16), (1025, 7)])
+def test_knn_small_and_ragged(n, K):
+    _knn_both(workloads.uniform(n, 2, 68 + n), K, "small")
+
+
+def test_knn_graph_matches_oracle():
+    from paper_1805_01208_amd import bkm
+    X = workloads.gauss3d(12000, 69)
+    nbr, ref = _knn_both(X, 9, "for graph")
+    rp, col = bkm.knn_graph(nbr)
+    orp, ocol = oracle.knn_symmetrize(ref)
+    assert np.array_equal(rp.cpu().numpy(), orp)
+    assert np.array_equal(col.cpu().numpy(), ocol)
+
+
+def _metrics_both(rp, col, A, k, what):
+    from paper_1805_01208_amd import bkm
+    print(f"case graph metrics {what} k={k}", flush=True)
+    g = bkm.graph_metrics(rp, col, A, k)
+    o = oracle.graph_metrics(rp.cpu().numpy(), col.cpu().numpy(), A.cpu().numpy(), k)
+    for key in ("edge_cut", "max_comm", "total_comm", "max_diameter", "disconnected_blocks"):
+        assert g[key] == o[key], (what, key)
+    assert np.array_equal(g["comm"].cpu().numpy(), o["comm"])
+    assert np.array_equal(g["diameter"].cpu().numpy(), o["diameter"])
+    if np.isfinite(o["harmonic_diameter"]):
+        assert g["harmonic_diameter"] == pytest.approx(o["harmonic_diameter"], rel=1e-12)
+    else:
+        assert g["harmonic_diameter"] == o["harmonic_diameter"]
+    return g
+
+
+def test_metrics_of_partitions_match_oracle():
+    from paper_1805_01208_amd import bkm
+    X = workloads.uniform(25000, 2, 70)
+    Xd = cuda(X)
+    nbr, _ = bkm.knn(Xd, 6)
+    rp, col = bkm.knn_graph(nbr)
+    part = bkm.balanced_kmeans(Xd, 32, max_iter=20)
+    g = _metrics_both(rp, col, part["A"], 32, "balanced k-means")
+    assert g["bfs_levels"] > 0
+    rng = np.random.default_rng(71)
+    A = torch.from_numpy(rng.integers(0, 7, 25000).astype(np.int32)).cuda()
+    _metrics_both(rp, col, A, 7, "random blocks")
+    A = torch.from_numpy((X[0] * 5).astype(np.int32)).cuda()
+    _metrics_both(rp, col, A, 9, "bands, empty blocks 5-8")
+    _metrics_both(rp, col, torch.zeros(25000, dtype=torch.int32).cuda(), 1, "one block")
+
+
+def test_metrics_on_a_grid_graph():
+    """The 4-neighbour grid in strips: closed forms on both sides."""
+    w, s, b = 6, 5, 9
+    a = w * s
+    rows = []
+    for y in range(b):
+        for x in range(a):
+            rows.append([v for v, ok in ((x + a * (y - 1), y > 0), (x - 1 + a * y, x > 0),
+                                         (x + 1 + a * y, x < a - 1), (x + a * (y + 1), y < b - 1)) if ok])
+    rp = torch.tensor(np.concatenate([[0], np.cumsum([len(r) for r in rows])]), dtype=torch.int64).cuda()
+    col = torch.tensor([v for r in rows for v in r], dtype=torch.int32).cuda()
+    A = torch.tensor([(v % a) // w for v in range(a * b)], dtype=torch.int32).cuda()
+    g = _metrics_both(rp, col, A, s, "grid strips")
+    assert g["edge_cut"] == (s - 1) * b and g["max_diameter"] == (w - 1) + (b - 1)
+
+
+def test_invalid_graph_inputs_are_rejected():
+    from paper_1805_01208_amd import bkm
+    X = cuda(workloads.uniform(3000, 2, 72))
+    nbr, _ = bkm.knn(X, 4)
+    rp, col = bkm.knn_graph(nbr)
+    with pytest.raises(bkm.BkmError, match="assignment"):
+        bkm.graph_metrics(rp, col, torch.full((3000,), 3, dtype=torch.int32).cuda(), 3)
+    bad = col.clone()
+    bad[10] = 3000
+    with pytest.raises(bkm.BkmError, match="row_ptr/col"):
+        bkm.graph_metrics(rp, bad, torch.zeros(3000, dtype=torch.int32).cuda(), 1)
+    nb2 = nbr.clone()
+    nb2[7, 2] = 7
+    with pytest.raises(bkm.BkmError, match="neighbour"):
+        bkm.knn_graph(nb2)
+    nb2[7, 2] = -1
+    with pytest.raises(bkm.BkmError, match="neighbour"):
+        bkm.knn_graph(nb2)

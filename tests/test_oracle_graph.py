@@ -23,6 +23,12 @@ def test_knn_matches_scipy_kdtree(d, K):
     assert np.array_equal(nb, idx[:, 1:])
 
 
+def test_knn_of_selected_points_is_their_rows():
+    X = workloads.gauss3d(2000, 44)
+    q = np.array([0, 17, 1999, 17, 640])
+    assert np.array_equal(oracle.knn_of(X, 9, q), oracle.knn(X, 9)[q])
+
+
 def test_knn_ties_on_a_lattice_by_exact_brute_force():
     """Integer lattice points: squared distances are exact integers, so
     sorting (distance, index) pairs in Python is the definition."""
