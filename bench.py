@@ -16,6 +16,13 @@ visit counters (see algorithmic_bytes).  The CPU baseline is the plain FP64
 oracle timed on a bounded random sample of the same cloud.
 
 Prints one JSON line.
+
+With --graph it measures the graph-quality evaluation instead (Sec. 2 block
+measures on a k-nearest-neighbour graph of the cloud): one step = exact
+K-nearest-neighbour lists, their undirected CSR graph, and the edge cut,
+communication volume and block diameter bounds of the cloud's balanced
+k-means partition (computed once, untimed).  value = points per second
+through the step.
 """
 import argparse
 import json
@@ -166,6 +173,91 @@ def run_steps(bkm, torch, X, W, cfg, precision, steps, warmup, max_iter, tile=0,
     return wall, tot, infos[-1]
 
 
+FP64_PEAK_TFLOPS = 78.6
+
+
+def graph_cpu_baseline(cfg, K, budget_s):
+    """The oracle's brute-force K nearest neighbours of random query points
+    over the whole cloud (the dominant part of the evaluation)."""
+    import numpy as np
+    import oracle
+    X = [np.asarray(x, dtype=np.float64) for x in cfg["X"]]
+    n = len(X[0])
+    rng = np.random.default_rng(777)
+    q0 = 64
+    while True:   # grow the pilot until it is long enough to time
+        t0 = time.perf_counter()
+        oracle.knn_of(X, K, rng.choice(n, q0, replace=False))
+        t = time.perf_counter() - t0
+        if t >= 0.1 * budget_s or q0 >= n:
+            break
+        q0 = min(n, 4 * q0)
+    q = int(min(n, max(q0, q0 * budget_s / max(t, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.knn_of(X, K, rng.choice(n, q, replace=False))
+    t = time.perf_counter() - t0
+    return dict(value=q / t, unit="points/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"exact {K}-NN lists of {q} random query points by FP64 brute force over "
+                       f"all {n} points: {t:.2f} s (graph and metrics not included)")
+
+
+def graph_bench(args, torch, bkm, cfg, X):
+    """Steps of the graph-quality evaluation on the resident cloud."""
+    n, d, k, K = X[0].numel(), len(X), cfg["k"], args.knn
+    part = bkm.balanced_kmeans(X, k, eps=cfg["eps"], max_iter=args.max_iter)
+    A = part["A"]
+
+    def one():
+        nbr, kinfo = bkm.knn(X, K)
+        rp, col = bkm.knn_graph(nbr)
+        m = bkm.graph_metrics(rp, col, A, k)
+        return kinfo, m, col.numel()
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    res = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res.append(one())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    search_s = sum(r[0]["search_ms"] for r in res) / 1e3 / args.steps
+    layout_s = sum(r[0]["layout_ms"] for r in res) / 1e3 / args.steps
+    pairs = res[-1][0]["group_visits"] * 64 * 64
+    flops = pairs * (3 * d - 1)   # FP64 subtractions, squares and additions per pair
+    achieved = flops / search_s / 1e12
+    m, nnz = res[-1][1], res[-1][2]
+    line = {
+        "metric": f"points/s through exact {K}-NN graph + partition quality metrics",
+        "value": n * args.steps / wall,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"] + "_knn_graph", "n": n, "d": d, "knn": K, "k": k},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_knn", "avg_search_ms": search_s * 1e3,
+                     "pairs_per_launch": pairs, "flops_per_pair": 3 * d - 1},
+        "layout_ms": layout_s * 1e3,
+        "pairs_per_point": pairs / n,
+        "graph": {"nnz": nnz, "edge_cut": m["edge_cut"], "max_comm": m["max_comm"],
+                  "total_comm": m["total_comm"], "max_diameter": m["max_diameter"],
+                  "disconnected_blocks": m["disconnected_blocks"],
+                  "harmonic_diameter": m["harmonic_diameter"], "bfs_levels": m["bfs_levels"]},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = graph_cpu_baseline(cfg, K, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +271,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="measure the graph-quality evaluation instead of the partitioner")
+    ap.add_argument("--knn", type=int, default=6, help="neighbours per point (--graph)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for scaling the HBM byte counters)")
     args = ap.parse_args()
@@ -206,6 +301,9 @@ def main():
     W = None if cfg["W"] is None else torch.from_numpy(cfg["W"]).cuda()
     weighted = W is not None
     torch.cuda.synchronize()
+    if args.graph:
+        graph_bench(args, torch, bkm, cfg, X)
+        return
 
     wall, tot, last = run_steps(bkm, torch, X, W, cfg, "f32_recheck", args.steps, args.warmup,
                                 args.max_iter, args.tile, args.super)

@@ -252,16 +252,21 @@ int bkm_partition_stats(const bkm_points* pts, const int32_t* assignment, int32_
  * CSR.
  * ------------------------------------------------------------------------- */
 
+typedef struct {
+    int64_t group_visits;     /* (64-point group, 64-point group) pairs compared */
+    double layout_ms;         /* device time of the Hilbert tile layout it searches */
+    double search_ms;         /* device time of the neighbour search kernel */
+} bkm_knn_info;
+
 /* The knn nearest neighbours of every point: the knn points q != p with the
  * smallest (squared Euclidean distance in FP64, ((dx*dx + dy*dy) + dz*dz),
  * input index of q), nearest first.  Exact, not approximate.
- *   knn          1..16, at most n-1.
- *   nbr_out      [device] n*knn int32, [n][knn], input indices.
- *   group_visits [host] number of (64-point group, 64-point group) pairs
- *                compared, or NULL.
+ *   knn      1..16, at most n-1.
+ *   nbr_out  [device] n*knn int32, [n][knn], input indices.
+ *   info     [host] or NULL (then no events are recorded).
  * Errors: BKM_EINVAL, BKM_EDATA (non-finite coordinate), BKM_ENOMEM,
  * BKM_EHIP. */
-int bkm_knn(const bkm_points* pts, int32_t knn, int32_t* nbr_out, int64_t* group_visits,
+int bkm_knn(const bkm_points* pts, int32_t knn, int32_t* nbr_out, bkm_knn_info* info,
             void* stream);
 
 /* The undirected graph of neighbour lists: edge {p, q} when q is in p's list

@@ -61,6 +61,10 @@ class GraphStats(C.Structure):
                 ("pad", C.c_int32)]
 
 
+class KnnInfo(C.Structure):
+    _fields_ = [("group_visits", C.c_int64), ("layout_ms", C.c_double), ("search_ms", C.c_double)]
+
+
 class BkmError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libbkm error {code}: {msg}")
@@ -93,7 +97,7 @@ def lib():
                                           C.POINTER(Stats), P]
         L.bkm_balanced_kmeans_batched.argtypes = [C.POINTER(Points), C.POINTER(Params), C.c_int32,
                                                   C.POINTER(P), C.POINTER(P), C.POINTER(Info), P]
-        L.bkm_knn.argtypes = [C.POINTER(Points), C.c_int32, P, C.POINTER(C.c_int64), P]
+        L.bkm_knn.argtypes = [C.POINTER(Points), C.c_int32, P, C.POINTER(KnnInfo), P]
         L.bkm_knn_graph.argtypes = [C.c_int64, C.c_int32, P, P, P, C.POINTER(C.c_int64), P]
         L.bkm_graph_metrics.argtypes = [C.c_int64, C.c_int64, P, P, P, C.c_int32, P, P,
                                         C.POINTER(GraphStats), P]
@@ -315,13 +319,14 @@ def partition_stats(X, A, k, eps=0.03, W=None, target_sizes=None):
 
 def knn(X, K):
     """Exact K nearest neighbours of every point: (nbr [n][K] int32 device
-    tensor, input indices nearest first; number of group pairs compared)."""
+    tensor, input indices nearest first; dict(group_visits, layout_ms,
+    search_ms))."""
     dev = X[0].device
     pts = make_points(X)
     nbr = torch.empty((pts.n, int(K)), dtype=torch.int32, device=dev)
-    visits = C.c_int64(0)
-    _check(lib().bkm_knn(C.byref(pts), int(K), _ptr(nbr), C.byref(visits), _stream()))
-    return nbr, visits.value
+    info = KnnInfo()
+    _check(lib().bkm_knn(C.byref(pts), int(K), _ptr(nbr), C.byref(info), _stream()))
+    return nbr, {f: getattr(info, f) for f, _ in KnnInfo._fields_}
 
 
 def knn_graph(nbr):

@@ -575,7 +575,7 @@ void bkm_default_params(bkm_params* p, int32_t k)
     p->recheck_rel_gap = 1e-5;
 }
 
-int bkm_knn(const bkm_points* pts, int32_t knn, int32_t* nbr_out, int64_t* group_visits,
+int bkm_knn(const bkm_points* pts, int32_t knn, int32_t* nbr_out, bkm_knn_info* info,
             void* stream)
 {
     g_err.clear();
@@ -591,14 +591,28 @@ int bkm_knn(const bkm_points* pts, int32_t knn, int32_t* nbr_out, int64_t* group
     plan(r, pts, 1, 256, 16, BKM_PREC_F64, 0, 0.0);
     Arena a;
     if ((rc = alloc_run(r, a, s, true))) return rc;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    struct EvFree { hipEvent_t* e; ~EvFree() { for (int i = 0; i < 3; ++i) if (e[i]) (void)hipEventDestroy(e[i]); } } evf{ev};
+    if (info)
+        for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    if (info) HIPCHK(hipEventRecord(ev[0], s));
     if ((rc = bootstrap(r, 16, s, true))) return rc;
     unsigned long long* visits = reinterpret_cast<unsigned long long*>(r.red);
     HIPCHK(hipMemsetAsync(visits, 0, sizeof(unsigned long long), s));
+    if (info) HIPCHK(hipEventRecord(ev[1], s));
     HIPCHK(launch_knn(r, knn, nbr_out, visits, s));
+    if (info) HIPCHK(hipEventRecord(ev[2], s));
     unsigned long long hv = 0;
     HIPCHK(hipMemcpyAsync(&hv, visits, sizeof(hv), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (group_visits) *group_visits = (int64_t)hv;
+    if (info) {
+        float t01 = 0.f, t12 = 0.f;
+        HIPCHK(hipEventElapsedTime(&t01, ev[0], ev[1]));
+        HIPCHK(hipEventElapsedTime(&t12, ev[1], ev[2]));
+        info->group_visits = (int64_t)hv;
+        info->layout_ms = t01;
+        info->search_ms = t12;
+    }
     return BKM_OK;
 }
 

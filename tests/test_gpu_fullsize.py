@@ -141,3 +141,48 @@ def test_c5_radial2d_250M_weighted(c5):
     C0 = check_bootstrap(cfg, X)
     check_sweeps(cfg, X, C0, "f32_recheck", 51)
     check_run(cfg, X, W=W)
+
+
+def check_knn_graph(cfg, X, K, A=None, k=None):
+    """Exact K-NN lists of sampled points against the oracle's brute force
+    over the whole cloud; the CSR graph against its definition on the
+    sampled rows; the metrics of a partition against the oracle's metrics
+    of the same CSR graph."""
+    from paper_1805_01208_amd import bkm
+    Xw = widened(cfg["X"])
+    n = len(Xw[0])
+    print(f"case full-size knn graph {cfg['name']} K={K}", flush=True)
+    nbr, info = bkm.knn(X, K)
+    rng = np.random.default_rng(91)
+    q = np.sort(rng.choice(n, size=300, replace=False))
+    nb = nbr.cpu().numpy()
+    assert np.array_equal(nb[q], oracle.knn_of(Xw, K, q))
+    rp, col = bkm.knn_graph(nbr)
+    rph, colh = rp.cpu().numpy(), col.cpu().numpy()
+    assert rph[0] == 0 and rph[-1] == len(colh) and np.all(np.diff(rph) >= K)
+    for u in q[:50]:
+        row = colh[rph[u]:rph[u + 1]]
+        assert np.all(row[1:] > row[:-1])                     # sorted, no duplicates
+        assert set(nb[u]) <= set(row.tolist())
+        for v in row:                                          # every entry is a kNN relation
+            assert v in nb[u] or u in nb[v]
+    if A is not None:
+        print(f"case full-size graph metrics {cfg['name']} k={k}", flush=True)
+        g = bkm.graph_metrics(rp, col, A, k)
+        o = oracle.graph_metrics(rph, colh, A.cpu().numpy(), k)
+        for key in ("edge_cut", "max_comm", "total_comm", "max_diameter", "disconnected_blocks"):
+            assert g[key] == o[key], key
+        assert np.array_equal(g["diameter"].cpu().numpy(), o["diameter"])
+    return info
+
+
+def test_c2_knn_graph_and_metrics(c2):
+    from paper_1805_01208_amd import bkm
+    cfg, X = c2
+    part = bkm.balanced_kmeans(X, cfg["k"], eps=cfg["eps"], max_iter=20)
+    check_knn_graph(cfg, X, 6, part["A"], cfg["k"])
+
+
+def test_c3_knn(c3):
+    cfg, X = c3
+    check_knn_graph(cfg, X, 10)
