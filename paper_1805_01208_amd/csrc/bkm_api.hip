@@ -159,7 +159,7 @@ size_t layout(RunDev& r, Arena* a, bool full)
     const int64_t ntiles = np / r.T;
     const int64_t nsuper = (ntiles + r.super_tiles - 1) / r.super_tiles;
     const int d = r.d, k = r.k;
-    const int nblk = (int)((n + 4095) / 4096);
+    const int nblk = (int)((n + kSortChunk - 1) / kSortChunk);
     const int64_t hlen = (int64_t)256 * nblk;
     const int nseg = (int)((hlen + 1023) / 1024);
     auto both = [&](auto* tag, size_t count, auto*& ptr) {

@@ -21,6 +21,8 @@ constexpr int kMaxJumps = 8192;      // jumps between Hilbert-consecutive points
 constexpr int kGapBins = 128;        // log2 histogram of gaps between consecutive points
 constexpr int kCntSlots = 64;        // sweep counters spread over this many cache lines
 constexpr int kCntWords = 8;         // counters per slot (one 64-byte line)
+constexpr int kSortIpt = 8;          // radix sort: items per thread per pass
+constexpr int kSortChunk = kBlock * kSortIpt;   // items per block per pass
 
 // Control and scalar state of one run, resident in device memory.  Kernels
 // of a round read it to decide whether they still have work (a finished

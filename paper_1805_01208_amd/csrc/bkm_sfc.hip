@@ -179,8 +179,8 @@ __global__ __launch_bounds__(kBlock) void k_keys(RunDev r, int m, uint64_t* keys
 // Stable LSD radix sort of (64-bit key, int32 value), 8-bit digits.  Per pass:
 // block histograms (digit-major), one exclusive scan, then a stable scatter in
 // which every block ranks its items in input order with wave ballots.
-constexpr int kIpt = 16;                       // items per thread per pass
-constexpr int kChunk = kBlock * kIpt;          // items per block per pass
+constexpr int kIpt = kSortIpt;
+constexpr int kChunk = kSortChunk;
 constexpr int kScanSeg = 1024;
 
 __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t* keys, int64_t n,
@@ -271,65 +271,101 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t* data, int64_t le
     }
 }
 
+// Stable scatter of one block's chunk: the items are first placed in LDS in
+// (digit, input order) order, then written out so that each digit's items
+// leave as one contiguous run (coalesced stores).  offs is the scanned
+// histogram (digit-major): this block's items of digit d go to offs[d][blk]
+// onwards, and offs[d][blk+1] - offs[d][blk] of them exist.
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t* kin,
                                                          const int32_t* vin, uint64_t* kout,
                                                          int32_t* vout, int64_t n, int shift,
                                                          const uint32_t* offs, int nblk)
 {
-    __shared__ uint32_t run[256];
+    __shared__ uint64_t lk[kChunk];
+    __shared__ int32_t lv[kChunk];
+    __shared__ uint32_t lstart[256];   // chunk-local start of each digit
+    __shared__ uint32_t lrun[256];     // next chunk-local slot of each digit
+    __shared__ uint32_t goff[256];     // global position of the block's first item per digit
     __shared__ uint32_t wc[kBlock / kWave][256];
-    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
-    run[threadIdx.x] = offs[(int64_t)threadIdx.x * nblk + blockIdx.x];
-    for (int w = 0; w < kBlock / kWave; ++w) wc[w][threadIdx.x] = 0;
+    __shared__ uint32_t wsum[kBlock / kWave];
+    const int t = threadIdx.x, lane = t % kWave, wv = t / kWave;
+    const int64_t idx = (int64_t)t * nblk + blockIdx.x;
+    const int64_t len = (int64_t)256 * nblk;
+    const uint32_t g0 = offs[idx];
+    const uint32_t cnt = (idx + 1 < len ? offs[idx + 1] : (uint32_t)n) - g0;
+    goff[t] = g0;
+    // exclusive scan of the block's digit counts (256 = kBlock threads)
+    uint32_t x = cnt;
+    for (int m = 1; m < kWave; m <<= 1) {
+        const uint32_t y = __shfl_up(x, m, kWave);
+        if (lane >= m) x += y;
+    }
+    if (lane == kWave - 1) wsum[wv] = x;
+    for (int w = 0; w < kBlock / kWave; ++w) wc[w][t] = 0;
     __syncthreads();
+    uint32_t pre = 0;
+    for (int w = 0; w < wv; ++w) pre += wsum[w];
+    lstart[t] = pre + x - cnt;
+    lrun[t] = pre + x - cnt;
+    __syncthreads();
+
     const int64_t base = (int64_t)blockIdx.x * kChunk;
     const unsigned long long below = (1ULL << lane) - 1ULL;
     for (int it = 0; it < kIpt; ++it) {
-        const int64_t i = base + (int64_t)it * kBlock + threadIdx.x;
+        const int64_t i = base + (int64_t)it * kBlock + t;
         const bool valid = i < n;
-        uint64_t key = valid ? kin[i] : 0;
-        int32_t val = valid ? vin[i] : 0;
+        const uint64_t key = valid ? kin[i] : 0;
+        const int32_t val = valid ? vin[i] : 0;
         const uint32_t dig = (uint32_t)((key >> shift) & 255u);
         unsigned long long same = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            unsigned long long bal = __ballot((dig >> b) & 1u);
+            const unsigned long long bal = __ballot((dig >> b) & 1u);
             same &= ((dig >> b) & 1u) ? bal : ~bal;
         }
         const uint32_t rank = (uint32_t)__popcll(same & below);
         if (valid && rank == 0) wc[wv][dig] = (uint32_t)__popcll(same);
         __syncthreads();
         if (valid) {
-            uint32_t pos = run[dig] + rank;
-            for (int w = 0; w < wv; ++w) pos += wc[w][dig];
-            kout[pos] = key;
-            vout[pos] = val;
+            uint32_t lp = lrun[dig] + rank;
+            for (int w = 0; w < wv; ++w) lp += wc[w][dig];
+            lk[lp] = key;
+            lv[lp] = val;
         }
         __syncthreads();
         uint32_t tot = 0;
         for (int w = 0; w < kBlock / kWave; ++w) {
-            tot += wc[w][threadIdx.x];
-            wc[w][threadIdx.x] = 0;
+            tot += wc[w][t];
+            wc[w][t] = 0;
         }
-        run[threadIdx.x] += tot;
+        lrun[t] += tot;
         __syncthreads();
+    }
+    const int64_t m = n - base < kChunk ? n - base : kChunk;
+    for (int j = t; j < m; j += kBlock) {
+        const uint64_t key = lk[j];
+        const uint32_t d = (uint32_t)((key >> shift) & 255u);
+        const uint32_t gp = goff[d] + ((uint32_t)j - lstart[d]);
+        kout[gp] = key;
+        vout[gp] = lv[j];
     }
 }
 
 // ---------------------------------------------------------------- permute
 // Coordinates in Hilbert order (no padding yet).
 template <typename T>
+// One axis per grid row (blockIdx.y), so each gather works on one
+// coordinate array at a time.
 __global__ __launch_bounds__(kBlock) void k_permute(RunDev r)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= r.n) return;
     const int32_t s = r.sperm[i];
-    for (int j = 0; j < r.d; ++j) {
-        if (r.in_f32)
-            r.tx32[j][i] = ((const float*)r.in_x[j])[s];
-        else
-            r.tx64[j][i] = ((const double*)r.in_x[j])[s];
-    }
+    const int j = blockIdx.y;
+    if (r.in_f32)
+        r.tx32[j][i] = ((const float*)r.in_x[j])[s];
+    else
+        r.tx64[j][i] = ((const double*)r.in_x[j])[s];
 }
 
 __device__ inline double tx_at(const RunDev& r, int j, int64_t i)
@@ -705,7 +741,7 @@ hipError_t radix_sort_pairs(const RunDev& r, uint64_t* keys, int32_t* vals, int 
 
 hipError_t launch_permute(const RunDev& r, hipStream_t s)
 {
-    unsigned g = nblocks(r.n, kBlock);
+    const dim3 g(nblocks(r.n, kBlock), (unsigned)r.d);
     k_permute<double><<<g, kBlock, 0, s>>>(r);
     return hipGetLastError();
 }
