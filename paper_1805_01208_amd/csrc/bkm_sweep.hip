@@ -39,6 +39,23 @@ constexpr double kFixPt3 = 4.77e-07;               // >= 1.0001 * 2^-21: 21-bit 
 constexpr double kCandSlack = 1e-9;               // relative slack of the center filter
 constexpr double kTiny = 1e-12;                   // relative slack of FP64 bound arithmetic
 constexpr double kInf = INFINITY;
+// Absolute slack of the FP32 screen: squared distances or effective squared
+// distances below 2^-126 may lose relative accuracy (subnormal range), which
+// moves their square roots by less than 2^-62.
+constexpr double kUnder = 0x1p-60;
+// The screen takes square roots with the hardware instruction (v_sqrt_f32):
+// within 1 ulp (2u relative) for arguments of at least 2^-96, and within
+// kSqrtAbs absolutely below that (the root of such an argument is < 2^-48).
+// The FP32 value v of a candidate's effective squared distance has a
+// correctly rounded root within [e(1-8u) - tau, e(1+8u) + tau] of the exact
+// effective distance e; so its raw root r satisfies
+//   r(1 - kScr) - slack <= e <= r(1 + kScr) + slack,
+//   slack = tau(1 + 16u) + 2 kSqrtAbs,
+// and a raw root of any value below v gives a lower bound the same way.
+constexpr double kSqrtAbs = 0x1p-47;
+constexpr double kScr = 11.0 * kU32;
+
+__device__ inline float sqrt_raw(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // Squared smallest and largest effective distance from center c to the box
 // [lo, hi]; iv = 1 / influence(c).
@@ -262,7 +279,7 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
                 q[j] = C[(int64_t)j * k + c] - X[j];
                 dd += q[j] * q[j];
             }
-            const double delta = pnt + 8.0 * kU32 * (Rn + sqrt(dd) * (1.0 + kTiny));
+            const double delta = pnt + 8.0 * kU32 * (Rn + sqrt(dd) * (1.0 + kTiny)) + kUnder;
             dmax = fmax(dmax, delta);
             tau = fmax(tau, delta * iv);
             if (pos < kTileCap) {
@@ -338,7 +355,7 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
                 const double v = C[(int64_t)j * k + c] - X[j];
                 dd += v * v;
             }
-            const double delta = pnt + 8.0 * kU32 * (Rn + sqrt(dd) * (1.0 + kTiny));
+            const double delta = pnt + 8.0 * kU32 * (Rn + sqrt(dd) * (1.0 + kTiny)) + kUnder;
             dmax = fmax(dmax, delta);
             tau = fmax(tau, delta * r.clus[c].y);
         }
@@ -349,7 +366,7 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
         TileHead h;
         h.n = overflow ? 0 : cnt;
         h.overflow = overflow ? 1 : 0;
-        h.tau = tau * (1.0 + kTiny);
+        h.tau = tau * (1.0 + kTiny) + kUnder;
         h.dmax = dmax * (1.0 + kTiny);
         h.lb_out = sqrt(t.b) * (1.0 - kTiny);
         h.step[0] = step[0];
@@ -609,45 +626,49 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
         if (act) {
             double ubd, lb;
             if (F32) {
-                // the best candidate's id and FP32 squared distance, recomputed
-                // from its record exactly as in the loop
-                float bd2;
+                // the best candidate's id, FP32 effective squared distance and
+                // squared distance, recomputed from its record exactly as in
+                // the loop
+                float bd2, be2;
                 {
                     float qx, qy, qz, w2;
                     rec32(bi, bc, qx, qy, qz, w2);
-                    (void)eff32(qx, qy, qz, w2, bd2);
+                    be2 = eff32(qx, qy, qz, w2, bd2);
                 }
-                const float eb = __builtin_sqrtf(b2);
-                const float es = __builtin_sqrtf(s2);
+                // every other candidate's FP32 value is at least s2
+                const double eb = (double)sqrt_raw(be2);
+                const double es = (double)sqrt_raw(s2);
+                const double slack = hd.tau * (1.0 + 16.0 * kU32) + 2.0 * kSqrtAbs;
                 // one candidate: certain; an overflowed FP32 value: decide in FP64
                 const bool sure =
                     b2 < INFINITY &&
                     (ncand == 1 ||
                      (s2 < INFINITY &&
-                      (double)es * (1.0 - 8.0 * kU32) - (double)eb * (1.0 + 8.0 * kU32) > 2.0 * hd.tau &&
-                      (double)es - (double)eb > gap_rel * (double)es));
+                      es * (1.0 - kScr) - eb * (1.0 + kScr) > 2.0 * slack &&
+                      es - eb > gap_rel * es));
                 if (sure) {
                     cbest = bc;
-                    ubd = (double)__builtin_sqrtf(bd2) * (1.0 + 4.0 * kU32) + hd.dmax;
-                    lb = (double)es * (1.0 - 8.0 * kU32) - hd.tau;
+                    ubd = ((double)sqrt_raw(bd2) + 2.0 * kSqrtAbs) * (1.0 + 7.0 * kU32) + hd.dmax;
+                    lb = es * (1.0 - kScr) - slack;
                 } else {
                     // FP64 recheck of the candidates that can still be the best:
-                    // every FP32 value is within [e(1-8u) - tau, e(1+8u) + tau] of
-                    // exact, so the exact best has e(1-8u) <= eb(1+8u) + 2 tau
-                    // (the window), and every candidate outside it is farther
-                    // than window - tau.
+                    // every candidate's exact effective distance e lies within
+                    // [r(1-kScr) - slack, r(1+kScr) + slack] of its raw FP32
+                    // root r, so the exact best has r(1-kScr) <= eb(1+kScr) +
+                    // 2 slack (the window), and every candidate outside it is
+                    // farther than window - slack.
                     rck = true;
 #pragma unroll
                     for (int j = 0; j < D; ++j) x[j] = sorted_coord(r, j, p);
-                    const double win = (double)eb * (1.0 + 8.0 * kU32) + 2.0 * hd.tau;
+                    const double win = eb * (1.0 + kScr) + 2.0 * slack;
                     double b = kInf, s = kInf, bsq = kInf;
                     int bcc = 0x7fffffff;
                     for (int c0 = 0; c0 < ncand; ++c0) {
                         int c;
                         float qx, qy, qz, w2, d2;
                         rec32(c0, c, qx, qy, qz, w2);
-                        const float e32 = __builtin_sqrtf(eff32(qx, qy, qz, w2, d2));
-                        if (!((double)e32 * (1.0 - 8.0 * kU32) <= win)) continue;
+                        const float e32 = sqrt_raw(eff32(qx, qy, qz, w2, d2));
+                        if (!((double)e32 * (1.0 - kScr) <= win)) continue;
                         double sq;
                         const double e = eff64<D>(x, C[c], C[(int64_t)k + c],
                                                   D == 3 ? C[(int64_t)(D - 1) * k + c] : 0.0, I[c], sq);
@@ -662,7 +683,7 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
                     }
                     cbest = bcc;
                     ubd = sqrt(bsq) * (1.0 + kTiny);
-                    lb = fmin(s, win - hd.tau) * (1.0 - kTiny);
+                    lb = fmin(s, win - slack) * (1.0 - kTiny);
                 }
             } else {
                 cbest = bc;
