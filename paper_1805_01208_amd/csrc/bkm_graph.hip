@@ -392,24 +392,62 @@ __global__ __launch_bounds__(kBlock) void k_bfs_sources(int k, GraphDev g, int s
 
 // One level: every frontier vertex claims its unvisited neighbours of the
 // same block; a claimed vertex joins the next frontier and may become its
-// block's farthest vertex.
+// block's farthest vertex.  kBfsLanes lanes share a frontier vertex, each
+// taking every kBfsLanes-th entry of its row; the lanes of a wave reserve
+// their places in the next frontier with one atomic per step.
+constexpr int kBfsLanes = 8;
+
 __global__ __launch_bounds__(kBlock) void k_bfs_level(const int64_t* row_ptr, const int32_t* col,
                                                       const int32_t* A, GraphDev g,
                                                       const int32_t* frontier, int32_t fcount,
                                                       int32_t level, int32_t* dist, int32_t* next,
                                                       int32_t* ncount)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= fcount) return;
-    const int32_t u = frontier[i];
-    const int32_t a = A[u];
-    for (int64_t e = row_ptr[u]; e < row_ptr[(int64_t)u + 1]; ++e) {
-        const int32_t v = col[e];
-        if (A[v] != a || dist[v] != -1) continue;
-        if (atomicCAS(&dist[v], -1, level + 1) != -1) continue;
-        next[atomicAdd(ncount, 1)] = v;
-        atomicAdd(&g.reached[a], 1);
-        atomicMax(&g.far[a], far_key(level + 1, v));
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i = t / kBfsLanes;
+    const int lane = threadIdx.x % kWave;
+    const bool act = i < fcount;
+    int32_t u = 0, a = -1;
+    int64_t e = 0, end = 0;
+    if (act) {
+        u = frontier[i];
+        a = A[u];
+        e = row_ptr[u] + t % kBfsLanes;
+        end = row_ptr[(int64_t)u + 1];
+    }
+    const unsigned long long below = (1ULL << lane) - 1ULL;
+    while (__ballot(e < end) != 0ULL) {
+        bool claim = false;
+        int32_t v = 0;
+        if (e < end) {
+            v = col[e];
+            e += kBfsLanes;
+            claim = A[v] == a && dist[v] == -1 && atomicCAS(&dist[v], -1, level + 1) == -1;
+        }
+        const unsigned long long b = __ballot(claim);
+        if (b == 0ULL) continue;
+        int base = 0;
+        if (lane == __builtin_ctzll(b)) base = atomicAdd(ncount, (int)__popcll(b));
+        base = __shfl(base, __builtin_ctzll(b), kWave);
+        if (claim) next[base + (int)__popcll(b & below)] = v;
+        // block counters: one update per distinct block among the claims
+        unsigned long long pend = b;
+        while (pend) {
+            const int leader = __builtin_ctzll(pend);
+            const int la = __shfl(a, leader, kWave);
+            const bool mine = claim && a == la;
+            const unsigned long long mm = __ballot(mine);
+            unsigned long long key = mine ? far_key(level + 1, v) : 0ULL;
+            for (int m = kWave / 2; m > 0; m >>= 1) {
+                const unsigned long long o = __shfl_xor(key, m, kWave);
+                key = o > key ? o : key;
+            }
+            if (lane == leader) {
+                atomicAdd(&g.reached[la], (int)__popcll(mm));
+                atomicMax(&g.far[la], key);
+            }
+            pend &= ~mm;
+        }
     }
 }
 
@@ -584,8 +622,8 @@ hipError_t launch_bfs_level(const int64_t* row_ptr, const int32_t* col, const in
                             int32_t level, int32_t* dist, int32_t* next, int32_t* ncount,
                             hipStream_t s)
 {
-    k_bfs_level<<<nblocks(fcount, kBlock), kBlock, 0, s>>>(row_ptr, col, A, g, frontier, fcount,
-                                                           level, dist, next, ncount);
+    k_bfs_level<<<nblocks((int64_t)fcount * kBfsLanes, kBlock), kBlock, 0, s>>>(
+        row_ptr, col, A, g, frontier, fcount, level, dist, next, ncount);
     return hipGetLastError();
 }
 
