@@ -97,6 +97,18 @@ DevState* host_state()
     return h;
 }
 
+// Pinned two-entry ring the round loop copies the state records into (one
+// per thread, kept for the process: pinned allocations are slow).
+DevState* loop_ring()
+{
+    thread_local DevState* h = nullptr;
+    if (!h) {
+        if (hipHostMalloc((void**)&h, 2 * sizeof(DevState), hipHostMallocDefault) != hipSuccess)
+            h = nullptr;
+    }
+    return h;
+}
+
 int check_points(const bkm_points* pts)
 {
     if (!pts) return fail(BKM_EINVAL, "points is NULL");
@@ -476,10 +488,10 @@ int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_i
             for (auto& row : ev)
                 for (auto e : row)
                     if (e) (void)hipEventDestroy(e);
-            if (ring) (void)hipHostFree(ring);
         }
     } lr{s};
-    HIPCHK(hipHostMalloc((void**)&lr.ring, 2 * sizeof(DevState), hipHostMallocDefault));
+    lr.ring = loop_ring();
+    if (!lr.ring) return fail(BKM_ENOMEM, "pinned host buffer unavailable");
     for (auto& row : lr.ev) {
         for (int i = 0; i < 6; ++i)
             if (timing) HIPCHK(hipEventCreate(&row[i]));

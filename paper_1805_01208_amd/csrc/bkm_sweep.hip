@@ -593,8 +593,8 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
             bc = better ? c : bc;
             be = better ? e : be;
         };
-        if (__ballot(act) != 0ULL) {
-            if (!hd.overflow) {
+        if (!hd.overflow) {
+            if (__ballot(act) != 0ULL) {
                 for (int c0 = 0; c0 < ncand; ++c0) {
                     const int c = s_cid[c0];
                     if (F32) {
@@ -605,17 +605,39 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
                                    s_c64[F32 ? 0 : 2][F32 ? 0 : c0], s_c64[F32 ? 0 : 3][F32 ? 0 : c0]);
                     }
                 }
-            } else {
-                for (int c0 = 0; c0 < ncand; ++c0) {
-                    const int c = sl[c0];
+            }
+        } else {
+            // overflowed tile: the super-tile's list, staged through LDS in
+            // chunks of kTileCap records that every wave of the block helps
+            // to build (the loop is block-uniform)
+            for (int cb = 0; cb < ncand; cb += kTileCap) {
+                const int m = min(kTileCap, ncand - cb);
+                __syncthreads();   // the previous chunk is consumed
+                if (tid < m) {
+                    const int c = sl[cb + tid];
+                    s_cid[tid] = c;
                     if (F32) {
                         int cc;
                         float qx, qy, qz, w2;
-                        rec32(c0, cc, qx, qy, qz, w2);
-                        consider32(c0, qx, qy, qz, w2);
+                        rec32(cb + tid, cc, qx, qy, qz, w2);
+                        s_q[tid] = make_float4(qx, qy, qz, w2);
                     } else {
-                        consider64(c, C[c], C[(int64_t)k + c],
-                                   D == 3 ? C[(int64_t)(D - 1) * k + c] : 0.0, I[c]);
+                        s_c64[0][F32 ? 0 : tid] = C[c];
+                        s_c64[F32 ? 0 : 1][F32 ? 0 : tid] = C[(int64_t)k + c];
+                        s_c64[F32 ? 0 : 2][F32 ? 0 : tid] = D == 3 ? C[(int64_t)(D - 1) * k + c] : 0.0;
+                        s_c64[F32 ? 0 : 3][F32 ? 0 : tid] = I[c];
+                    }
+                }
+                __syncthreads();
+                if (__ballot(act) != 0ULL) {
+                    for (int c0 = 0; c0 < m; ++c0) {
+                        if (F32) {
+                            const float4 qv = s_q[c0];
+                            consider32(cb + c0, qv.x, qv.y, qv.z, qv.w);
+                        } else {
+                            consider64(s_cid[c0], s_c64[0][F32 ? 0 : c0], s_c64[F32 ? 0 : 1][F32 ? 0 : c0],
+                                       s_c64[F32 ? 0 : 2][F32 ? 0 : c0], s_c64[F32 ? 0 : 3][F32 ? 0 : c0]);
+                        }
                     }
                 }
             }

@@ -154,12 +154,16 @@ struct RoundTable {
     double box[kHashSlots][2 * D];               // D minima, D maxima
 };
 
-// Slot of `key` in the table (inserted if new), or -1 when the table is full.
+// Slot of `key` in the table (inserted if new), or -1 when kProbes probes
+// find neither it nor a free slot (the caller then goes to the global
+// arrays, which is always valid: the table only batches updates).
+constexpr int kProbes = 16;
+
 template <int D>
 __device__ inline int table_slot(RoundTable<D>& t, int key)
 {
     int slot = (int)(((unsigned)key * 2654435761u) >> 24) & (kHashSlots - 1);
-    for (int probe = 0; probe < kHashSlots; ++probe) {
+    for (int probe = 0; probe < kProbes; ++probe) {
         const int old = atomicCAS(&t.key[slot], -1, key);
         if (old == -1 || old == key) return slot;
         slot = (slot + 1) & (kHashSlots - 1);
