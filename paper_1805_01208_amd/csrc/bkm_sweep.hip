@@ -237,7 +237,6 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
 {
     const DevState* st = r.st;
     if (st->done || st->round_done) return;
-    constexpr bool F32 = PREC == BKM_PREC_F32_RECHECK;
     constexpr int kCpl = 4;   // candidates a lane keeps in registers between passes
     const int lane = threadIdx.x % kWave;
     const int tile = bid * (kBlock / kWave) + threadIdx.x / kWave;
@@ -342,24 +341,9 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
             emit(keep, c);
         }
     }
+    // an overflowed tile is swept in FP64 over the super-tile list (its
+    // FP32 bounds are not used)
     const bool overflow = cnt > kTileCap;
-    if (overflow && F32) {
-        // the sweep will scan the whole super-tile list: bound its error
-        tau = 0.0;
-        dmax = 0.0;
-        for (int i = lane; i < L; i += kWave) {
-            const int c = sl[i];
-            double dd = 0.0;
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                const double v = C[(int64_t)j * k + c] - X[j];
-                dd += v * v;
-            }
-            const double delta = pnt + 8.0 * kU32 * (Rn + sqrt(dd) * (1.0 + kTiny)) + kUnder;
-            dmax = fmax(dmax, delta);
-            tau = fmax(tau, delta * r.clus[c].y);
-        }
-    }
     tau = wave_max_d(tau);
     dmax = wave_max_d(dmax);
     if (lane == 0) {
@@ -415,7 +399,7 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
     __shared__ int s_gdirty[T / kWave]; // per 64-point group: a point of it changed block
     __shared__ float4 s_q[kTileCap];
     __shared__ int s_cid[kTileCap];
-    __shared__ double s_c64[F32 ? 1 : 4][F32 ? 1 : kTileCap];
+    __shared__ double s_c64[4][kTileCap];   // FP64 centers and influences (FP64 sweep, overflow)
     __shared__ int s_nl;
     __shared__ unsigned long long s_cnt[kBlock / kWave][5];   // counters of each wave
 
@@ -450,10 +434,10 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
         if (F32) {
             s_q[tid] = make_float4(rec.qx, rec.qy, rec.qz, rec.w2);
         } else {
-            s_c64[0][F32 ? 0 : tid] = C[rec.id];
-            s_c64[F32 ? 0 : 1][F32 ? 0 : tid] = C[(int64_t)k + rec.id];
-            s_c64[F32 ? 0 : 2][F32 ? 0 : tid] = D == 3 ? C[(int64_t)(D - 1) * k + rec.id] : 0.0;
-            s_c64[F32 ? 0 : 3][F32 ? 0 : tid] = I[rec.id];
+            s_c64[0][tid] = C[rec.id];
+            s_c64[1][tid] = C[(int64_t)k + rec.id];
+            s_c64[2][tid] = D == 3 ? C[(int64_t)(D - 1) * k + rec.id] : 0.0;
+            s_c64[3][tid] = I[rec.id];
         }
     }
     float2 cl[PPT];
@@ -506,14 +490,11 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
     unsigned n_rechk = 0, n_chg = 0;
     const double gap_rel = r.recheck_gap;
     const double wsc = st->w_scale;
-    double X[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) X[j] = 0.0;
-    if (hd.overflow) {
-#pragma unroll
-        for (int j = 0; j < D; ++j)
-            X[j] = 0.5 * (r.tbox[(int64_t)tile * 2 * D + j] + r.tbox[(int64_t)tile * 2 * D + D + j]);
-    }
+    // an overflowed tile (more candidates than records) is swept in FP64
+    // even by the FP32 kernel: its candidates come from the super-tile list,
+    // and without a tile-sized error bound the screen would send most
+    // points to the recheck
+    const bool screen = F32 && !hd.overflow;
     for (int i0 = 0; i0 < nl; i0 += kBlock) {
         const int i = i0 + tid;
         const bool act = i < nl;
@@ -528,7 +509,7 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
             x[j] = 0.0;
         }
         if (act) {
-            if (F32) {
+            if (screen) {
                 // one load per point: its packed fixed-point offsets
                 const auto w = static_cast<const typename FixPack<D>::word*>(r.ofs)[p];
 #pragma unroll
@@ -555,24 +536,14 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
             }
             return d2 * w2;
         };
-        // the FP32 record of candidate c0 of the tile (the overflow path
-        // forms it from the centers)
+        // the FP32 record of candidate c0 of the tile
         auto rec32 = [&](int c0, int& c, float& qx, float& qy, float& qz, float& w2) {
-            if (!hd.overflow) {
-                c = s_cid[c0];
-                const float4 qv = s_q[c0];
-                qx = qv.x;
-                qy = qv.y;
-                qz = qv.z;
-                w2 = qv.w;
-            } else {
-                c = sl[c0];
-                const float fi = (float)r.clus[c].y;
-                qx = (float)(C[c] - X[0]);
-                qy = (float)(C[(int64_t)k + c] - X[1]);
-                qz = D == 3 ? (float)(C[(int64_t)(D - 1) * k + c] - X[D - 1]) : 0.0f;
-                w2 = fi * fi;
-            }
+            c = s_cid[c0];
+            const float4 qv = s_q[c0];
+            qx = qv.x;
+            qy = qv.y;
+            qz = qv.z;
+            w2 = qv.w;
         };
         // best and second-best FP32 values with b2 <= s2: the new second is
         // the median of (b2, s2, e2); only the best's record index is kept
@@ -601,44 +572,29 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
                         const float4 qv = s_q[c0];
                         consider32(c0, qv.x, qv.y, qv.z, qv.w);
                     } else {
-                        consider64(c, s_c64[0][F32 ? 0 : c0], s_c64[F32 ? 0 : 1][F32 ? 0 : c0],
-                                   s_c64[F32 ? 0 : 2][F32 ? 0 : c0], s_c64[F32 ? 0 : 3][F32 ? 0 : c0]);
+                        consider64(c, s_c64[0][c0], s_c64[1][c0], s_c64[2][c0], s_c64[3][c0]);
                     }
                 }
             }
         } else {
-            // overflowed tile: the super-tile's list, staged through LDS in
-            // chunks of kTileCap records that every wave of the block helps
-            // to build (the loop is block-uniform)
+            // overflowed tile: the super-tile's list in FP64, staged through
+            // LDS in chunks of kTileCap centers that every wave of the block
+            // helps to load (the loop is block-uniform)
             for (int cb = 0; cb < ncand; cb += kTileCap) {
                 const int m = min(kTileCap, ncand - cb);
                 __syncthreads();   // the previous chunk is consumed
                 if (tid < m) {
                     const int c = sl[cb + tid];
                     s_cid[tid] = c;
-                    if (F32) {
-                        int cc;
-                        float qx, qy, qz, w2;
-                        rec32(cb + tid, cc, qx, qy, qz, w2);
-                        s_q[tid] = make_float4(qx, qy, qz, w2);
-                    } else {
-                        s_c64[0][F32 ? 0 : tid] = C[c];
-                        s_c64[F32 ? 0 : 1][F32 ? 0 : tid] = C[(int64_t)k + c];
-                        s_c64[F32 ? 0 : 2][F32 ? 0 : tid] = D == 3 ? C[(int64_t)(D - 1) * k + c] : 0.0;
-                        s_c64[F32 ? 0 : 3][F32 ? 0 : tid] = I[c];
-                    }
+                    s_c64[0][tid] = C[c];
+                    s_c64[1][tid] = C[(int64_t)k + c];
+                    s_c64[2][tid] = D == 3 ? C[(int64_t)(D - 1) * k + c] : 0.0;
+                    s_c64[3][tid] = I[c];
                 }
                 __syncthreads();
                 if (__ballot(act) != 0ULL) {
-                    for (int c0 = 0; c0 < m; ++c0) {
-                        if (F32) {
-                            const float4 qv = s_q[c0];
-                            consider32(cb + c0, qv.x, qv.y, qv.z, qv.w);
-                        } else {
-                            consider64(s_cid[c0], s_c64[0][F32 ? 0 : c0], s_c64[F32 ? 0 : 1][F32 ? 0 : c0],
-                                       s_c64[F32 ? 0 : 2][F32 ? 0 : c0], s_c64[F32 ? 0 : 3][F32 ? 0 : c0]);
-                        }
-                    }
+                    for (int c0 = 0; c0 < m; ++c0)
+                        consider64(s_cid[c0], s_c64[0][c0], s_c64[1][c0], s_c64[2][c0], s_c64[3][c0]);
                 }
             }
         }
@@ -647,7 +603,7 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
         long long wh = 1, wl = 0;
         if (act) {
             double ubd, lb;
-            if (F32) {
+            if (screen) {
                 // the best candidate's id, FP32 effective squared distance and
                 // squared distance, recomputed from its record exactly as in
                 // the loop
