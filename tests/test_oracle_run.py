@@ -154,3 +154,37 @@ def test_sample_rounds_with_more_blocks_than_sample_points():
     r = oracle.balanced_kmeans(X, k, 0.05, max_iter=10, sample_keys=keys)
     assert r["info"]["sample_rounds"] == math.ceil(math.log2(n / 100))
     _check_means(X, None, r["A"], r["centers"])
+
+
+def test_sample_init_is_the_composition_of_single_rounds():
+    """The sampled run equals single one-round runs on the nested samples
+    (first 100, 200, ... points in (key, index) order), each starting from
+    the previous round's centers and influences, then the run on all points:
+    the composition is redone here in Python around the pinned single run,
+    with node weights and a finite eps so that the influences matter."""
+    rng = np.random.default_rng(35)
+    n, k = 1500, 5
+    X = [rng.random(n), rng.random(n)]
+    W = rng.lognormal(0.0, 0.5, n)
+    keys = workloads.splitmix64(35, n)
+    r = oracle.balanced_kmeans(X, k, 0.02, W=W, max_iter=6, sample_keys=keys, sample_start=100)
+    order = np.lexsort((np.arange(n), keys))
+    dthr = 1e-5 * max(float(x.max() - x.min()) for x in X)
+    C, _, _ = oracle.init_centers_sfc(X, k, 16)
+    I = np.ones(k)
+    s = 100
+    rounds = 0
+    while s < n:
+        idx = order[:s]
+        o = oracle.balanced_kmeans([x[idx] for x in X], k, 0.02, W=W[idx], max_iter=1,
+                                   delta_threshold=dthr, centers_init=C, influence_init=I)
+        C, I = o["centers"], o["influence"]
+        s *= 2
+        rounds += 1
+    assert not np.all(I == 1.0)          # the influences were carried, not reset
+    full = oracle.balanced_kmeans(X, k, 0.02, W=W, max_iter=6, delta_threshold=dthr,
+                                  centers_init=C, influence_init=I)
+    assert r["info"]["sample_rounds"] == rounds == 4
+    assert np.array_equal(r["A"], full["A"])
+    assert np.array_equal(r["centers"], full["centers"])
+    assert np.array_equal(r["influence"], full["influence"])
