@@ -146,7 +146,8 @@ def cpu_baseline(cfg, budget_s):
                        f"block weights, balance test): {t:.2f} s")
 
 
-def run_steps(bkm, torch, X, W, cfg, precision, steps, warmup, max_iter, tile=0, sup=0):
+def run_steps(bkm, torch, X, W, cfg, precision, steps, warmup, max_iter, tile=0, sup=0,
+              extra=None):
     n = X[0].numel()
     k = cfg["k"]
     dev = X[0].device
@@ -155,10 +156,12 @@ def run_steps(bkm, torch, X, W, cfg, precision, steps, warmup, max_iter, tile=0,
                influence=torch.empty(k, dtype=torch.float64, device=dev),
                block_weights=torch.empty(k, dtype=torch.float64, device=dev))
 
+    extra = extra or {}
+
     def one():
         return bkm.balanced_kmeans(X, k, W=W, eps=cfg["eps"], max_iter=max_iter,
                                    precision=precision, tile_points=tile, super_tiles=sup,
-                                   timing=True, out=out)
+                                   timing=True, out=out, **extra)
 
     for _ in range(warmup):
         one()
@@ -274,6 +277,10 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="measure the graph-quality evaluation instead of the partitioner")
     ap.add_argument("--knn", type=int, default=6, help="neighbours per point (--graph)")
+    ap.add_argument("--sample-init", action="store_true",
+                    help="start every run with the random-sample rounds (seed 1)")
+    ap.add_argument("--targets", action="store_true",
+                    help="non-uniform target block sizes: k log-normal(0, 0.5) relative sizes, seed 9")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for scaling the HBM byte counters)")
     args = ap.parse_args()
@@ -305,8 +312,14 @@ def main():
         graph_bench(args, torch, bkm, cfg, X)
         return
 
+    extra = {}
+    if args.sample_init:
+        extra.update(sample_init=True, seed=1)
+    if args.targets:
+        extra["target_sizes"] = torch.from_numpy(
+            np.random.default_rng(9).lognormal(0.0, 0.5, cfg["k"])).cuda()
     wall, tot, last = run_steps(bkm, torch, X, W, cfg, "f32_recheck", args.steps, args.warmup,
-                                args.max_iter, args.tile, args.super)
+                                args.max_iter, args.tile, args.super, extra)
     sweeps = tot["sweeps"]
     value = n * sweeps / wall
     ms_per_step = 1e3 * wall / args.steps
@@ -316,7 +329,7 @@ def main():
     fp64 = None
     if args.fp64_steps > 0:
         wall64, tot64, _ = run_steps(bkm, torch, X, W, cfg, "f64", args.fp64_steps, 1,
-                                     args.max_iter, args.tile, args.super)
+                                     args.max_iter, args.tile, args.super, extra)
         sweep64_s = tot64["sweep_ms"] / 1e3 / tot64["sweeps"]
         algo64 = algorithmic_bytes(tot64, d, "f64", weighted) / tot64["sweeps"]
         fp64 = {"value": n * tot64["sweeps"] / wall64, "ms_per_step": 1e3 * wall64 / args.fp64_steps,
@@ -328,7 +341,8 @@ def main():
     algo = algorithmic_bytes(tot, d, "f32_recheck", weighted) / sweeps
     achieved = algo / sweep_s / 1e9
     tile = args.tile or 1024
-    traffic = measured_traffic(cfg["name"], tile)
+    # the committed counters are for the default run only
+    traffic = None if (args.sample_init or args.targets) else measured_traffic(cfg["name"], tile)
 
     visits = tot["evaluated"] + tot["skipped"]
     line = {
@@ -347,12 +361,14 @@ def main():
         "config": {"workload": cfg["name"], "n": n, "d": d, "k": cfg["k"], "eps": cfg["eps"],
                    "weighted": weighted, "precision": "f32_recheck", "max_iter": args.max_iter,
                    "max_balance_iter": 20, "hilbert_order": 16, "tile_points": tile,
-                   "super_tiles": args.super or 16},
+                   "super_tiles": args.super or 16, "sample_init": bool(args.sample_init),
+                   "target_sizes": "lognormal(0,0.5), seed 9" if args.targets else None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_sweep", "avg_sweep_us": sweep_s * 1e6,
                      "algorithmic_bytes_per_launch": algo},
         "sweeps_per_step": sweeps / args.steps,
+        "sample_sweeps_per_step": tot["sample_sweeps"] / args.steps,   # not counted in value
         "rounds_per_step": tot["rounds"] / args.steps,
         "skip_frac": tot["skipped"] / visits,
         "recheck_frac_of_evaluated": tot["rechecked"] / max(1, tot["evaluated"]),
