@@ -46,7 +46,7 @@ def test_knn_lattice_ties_and_duplicates():
     _knn_both([g3[:, j].copy() for j in range(3)], 14, "lattice3d")
 
 
-@pytest.mark.parametrize("n,K", [(2, 1), (5, 4), (65, 1), (300, 16), (1025, 7)])
+@pytest.mark.parametrize("n,K", [(2, 1), (5, 4), (17, 16), (65, 1), (300, 16), (1025, 7)])
 def test_knn_small_and_ragged(n, K):
     _knn_both(workloads.uniform(n, 2, 68 + n), K, "small")
 

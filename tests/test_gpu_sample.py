@@ -72,6 +72,14 @@ def test_odd_start_and_tiles():
     _check_against_oracle(X, 20, 0.03, seed=10, start=37, tile_points=256)
 
 
+def test_sample_start_of_one_point():
+    """sample_start = 1: the first rounds run on 1, 2, 4, ... points with
+    all k centers (most blocks empty)."""
+    print("case sample-init start=1, n=300 2D k=8", flush=True)
+    X = workloads.uniform(300, 2, 18)
+    _check_against_oracle(X, 8, 0.05, seed=11, start=1, max_iter=8)
+
+
 def test_default_keys_are_splitmix64():
     """Without caller keys the library draws splitmix64(seed, i) itself: the
     run must equal the one given those keys explicitly."""
