@@ -445,7 +445,10 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
     for (int q = 0; q < PPT; ++q) cl[q] = r.clus32[aold[q] > 0 ? aold[q] : 0];
     // lower-bound frame in FP32, rounded so that every bound stays valid
     const float Mf = f32_down(st->M), Ef = f32_up(st->E);
-    const double M = st->M, E = st->E;
+    const double E = st->E;
+    // the lower-bound frame's scale as a reciprocal: one division per block;
+    // its rounding (a few units of 2^-53) is covered by the kTiny slack below
+    const double invM = 1.0 / st->M;
     unsigned n_eval = 0, n_skip = 0;
     __syncthreads();   // s_nl initialised
     const unsigned long long below = (1ULL << lane) - 1ULL;
@@ -675,7 +678,7 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
                 double uv = ubd - Db;
                 uv += kTiny * (fabs(ubd) + Db);
                 r.ubt[p] = f32_up(uv);
-                double lv = (lb + E) / M;
+                double lv = (lb + E) * invM;
                 lv -= kTiny * fabs(lv);
                 r.lbt[p] = (lv > 0.0) ? f32_down(lv) : 0.0f;
             }
