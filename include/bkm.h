@@ -80,6 +80,9 @@ typedef struct {
                                  with the sample's own balance target, then one center
                                  movement with erosion; they do not count towards
                                  max_iter.  Default 0 */
+    int32_t erosion;          /* 1: after each center movement that does not converge, the
+                                 influence is eroded towards 1 (Sec. 4.2); 0: the influence
+                                 is kept.  Default 1 */
     double epsilon;           /* imbalance eps >= 0 (may be +inf); default 0.03 */
     double delta_threshold;   /* absolute; < 0 selects 1e-5 * largest bounding-box extent
                                  (of all points, also in the sample rounds) */

@@ -68,10 +68,10 @@ def lib():
         L.oracle_erode.argtypes = [C.c_int, P, D, P]
         L.oracle_erode.restype = None
         L.oracle_balanced_kmeans.argtypes = [
-            I64, C.c_int, P, P, C.c_int, D, C.c_int, C.c_int, D, C.c_int,
+            I64, C.c_int, P, P, C.c_int, D, C.c_int, C.c_int, D, C.c_int, C.c_int,
             P, P, P, P, P, P, P, P, C.POINTER(OracleInfo)]
         L.oracle_balanced_kmeans_sampled.argtypes = [
-            I64, C.c_int, P, P, C.c_int, D, C.c_int, C.c_int, D, C.c_int,
+            I64, C.c_int, P, P, C.c_int, D, C.c_int, C.c_int, D, C.c_int, C.c_int,
             I64, P, P, P, P, P, P, P, C.POINTER(OracleInfo), P, P]
         L.oracle_partition_stats.argtypes = [
             I64, C.c_int, P, P, P, C.c_int, D, P, P, P, C.POINTER(OracleStats)]
@@ -259,7 +259,7 @@ def erode(delta, beta_value, influence):
 def balanced_kmeans(X, k, eps, W=None, max_iter=50, max_balance_iter=20,
                     delta_threshold=None, hilbert_order=16, centers_init=None,
                     influence_init=None, sample_keys=None, sample_start=100,
-                    target_sizes=None):
+                    target_sizes=None, erosion=True):
     """Full balanced k-means.  delta_threshold None -> 1e-5 * largest bbox extent.
     With sample_keys (one uint64 per point) the run starts with the
     random-sample initialization over the order of (key, index).
@@ -284,7 +284,8 @@ def balanced_kmeans(X, k, eps, W=None, max_iter=50, max_balance_iter=20,
         ii = None if influence_init is None else np.ascontiguousarray(influence_init, dtype=np.float64)
         _check(lib().oracle_balanced_kmeans(
             p.n, p.d, p.arr, _ptr(W), int(k), float(eps), int(max_iter), int(max_balance_iter),
-            float(delta_threshold), int(hilbert_order), _ptr(ci), _ptr(ii), _ptr(t), _ptr(A),
+            float(delta_threshold), int(hilbert_order), 1 if erosion else 0, _ptr(ci), _ptr(ii),
+            _ptr(t), _ptr(A),
             _ptr(centers), _ptr(infl), _ptr(bw), _ptr(spr), C.byref(info)), "balanced_kmeans")
     else:
         keys = np.ascontiguousarray(sample_keys, dtype=np.uint64)
@@ -292,7 +293,8 @@ def balanced_kmeans(X, k, eps, W=None, max_iter=50, max_balance_iter=20,
         ss = np.zeros(1, dtype=np.int32)
         _check(lib().oracle_balanced_kmeans_sampled(
             p.n, p.d, p.arr, _ptr(W), int(k), float(eps), int(max_iter), int(max_balance_iter),
-            float(delta_threshold), int(hilbert_order), int(sample_start), _ptr(keys), _ptr(t),
+            float(delta_threshold), int(hilbert_order), 1 if erosion else 0, int(sample_start),
+            _ptr(keys), _ptr(t),
             _ptr(A),
             _ptr(centers), _ptr(infl), _ptr(bw), _ptr(spr), C.byref(info), _ptr(sr), _ptr(ss)),
             "balanced_kmeans_sampled")

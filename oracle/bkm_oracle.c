@@ -44,7 +44,8 @@
  *   R7  beta ("average cluster diameter") = mean over non-empty blocks of the
  *       diagonal of the block's axis-aligned bounding box.
  *   R8  Erosion is applied after every movement that did not converge, before
- *       the next AssignAndBalance.  alpha = 0 when delta = 0.
+ *       the next AssignAndBalance.  alpha = 0 when delta = 0.  A switch turns
+ *       it off (the influence is then kept from round to round).
  *   R9  New centers are weighted means; an empty block keeps its center.
  *   R10 Ties in the argmin go to the lowest center index.
  *   R11 Hilbert index: Skilling's transpose algorithm (J. Skilling,
@@ -527,7 +528,7 @@ typedef struct {
  * (max_iter entries). */
 int oracle_balanced_kmeans(int64_t n, int d, const double* const* X, const double* W,
                            int k, double eps, int max_iter, int max_balance_iter,
-                           double delta_threshold, int hilbert_order,
+                           double delta_threshold, int hilbert_order, int erosion,
                            const double* centers_init, const double* influence_init,
                            const double* target_sizes, int32_t* A,
                            double* centers_out, double* influence_out, double* block_weights_out,
@@ -588,8 +589,10 @@ int oracle_balanced_kmeans(int64_t n, int d, const double* const* X, const doubl
             memcpy(C, Cn, (size_t)k * d * sizeof(double));
             break;
         }
-        double beta = oracle_beta(n, d, X, A, k);
-        oracle_erode(k, delta, beta, I);
+        if (erosion) {
+            double beta = oracle_beta(n, d, X, A, k);
+            oracle_erode(k, delta, beta, I);
+        }
         memcpy(C, Cn, (size_t)k * d * sizeof(double));
     }
 
@@ -626,7 +629,7 @@ done:
  * The sample rounds do not count towards max_iter. */
 int oracle_balanced_kmeans_sampled(int64_t n, int d, const double* const* X, const double* W,
                                    int k, double eps, int max_iter, int max_balance_iter,
-                                   double delta_threshold, int hilbert_order,
+                                   double delta_threshold, int hilbert_order, int erosion,
                                    int64_t sample_start, const uint64_t* sample_keys,
                                    const double* target_sizes, int32_t* A, double* centers_out, double* influence_out,
                                    double* block_weights_out, int32_t* sweeps_per_round,
@@ -660,8 +663,8 @@ int oracle_balanced_kmeans_sampled(int64_t n, int d, const double* const* X, con
             for (int64_t i = 0; i < s; ++i) ws[i] = W[order[i]];
         oracle_info si;
         rc = oracle_balanced_kmeans(s, d, Xs, ws, k, eps, 1, max_balance_iter, delta_threshold,
-                                    hilbert_order, C, I, target_sizes, As, C, I, NULL, NULL,
-                                    &si);
+                                    hilbert_order, erosion, C, I, target_sizes, As, C, I, NULL,
+                                    NULL, &si);
         if (rc != ORC_OK) goto done;
         rounds += 1;
         sweeps += si.sweeps;
@@ -669,7 +672,8 @@ int oracle_balanced_kmeans_sampled(int64_t n, int d, const double* const* X, con
     if (sample_rounds) *sample_rounds = rounds;
     if (sample_sweeps) *sample_sweeps = sweeps;
     rc = oracle_balanced_kmeans(n, d, X, W, k, eps, max_iter, max_balance_iter, delta_threshold,
-                                hilbert_order, C, I, target_sizes, A, centers_out, influence_out,
+                                hilbert_order, erosion, C, I, target_sizes, A, centers_out,
+                                influence_out,
                                 block_weights_out, sweeps_per_round, info);
 done:
     free(C); free(I); free(order); free(xs); free(ws); free(As);

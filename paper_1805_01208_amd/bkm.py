@@ -30,6 +30,7 @@ class Params(C.Structure):
                 ("hilbert_order", C.c_int32), ("precision", C.c_int32),
                 ("use_bounds", C.c_int32), ("tile_points", C.c_int32),
                 ("super_tiles", C.c_int32), ("timing", C.c_int32), ("sample_init", C.c_int32),
+                ("erosion", C.c_int32),
                 ("epsilon", C.c_double), ("delta_threshold", C.c_double),
                 ("recheck_rel_gap", C.c_double), ("sample_start", C.c_int64),
                 ("seed", C.c_uint64), ("sample_keys", C.c_void_p),
@@ -185,7 +186,8 @@ def balanced_kmeans(X, k, W=None, eps=0.03, max_iter=50, max_balance_iter=20,
                     delta_threshold=-1.0, hilbert_order=16, precision="f32_recheck",
                     use_bounds=True, tile_points=0, super_tiles=0, recheck_rel_gap=1e-5,
                     centers_init=None, timing=False, out=None, sample_init=False,
-                    sample_start=100, seed=0, sample_keys=None, target_sizes=None):
+                    sample_start=100, seed=0, sample_keys=None, target_sizes=None,
+                    erosion=True):
     """Balanced k-means; returns dict(A, centers, influence, block_weights, info, code).
     sample_init: start with rounds on random samples doubling from sample_start
     points (order by splitmix64(seed, index), or by sample_keys, n uint64
@@ -206,6 +208,7 @@ def balanced_kmeans(X, k, W=None, eps=0.03, max_iter=50, max_balance_iter=20,
     prm.recheck_rel_gap = float(recheck_rel_gap)
     prm.timing = 1 if timing else 0
     prm.sample_init = 1 if sample_init else 0
+    prm.erosion = 1 if erosion else 0
     prm.sample_start = int(sample_start)
     prm.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
     sk = None
@@ -237,7 +240,7 @@ def balanced_kmeans(X, k, W=None, eps=0.03, max_iter=50, max_balance_iter=20,
 def balanced_kmeans_batched(instances, eps=0.03, max_iter=50, max_balance_iter=20,
                             delta_threshold=-1.0, hilbert_order=16, precision="f32_recheck",
                             use_bounds=True, tile_points=0, super_tiles=0, recheck_rel_gap=1e-5,
-                            target_sizes=None):
+                            target_sizes=None, erosion=True):
     """Many balanced k-means runs in one call.  instances: list of (X, k) or
     (X, k, W) with X a list of d device tensors.  Scalar parameters apply to
     every instance; a list gives one value per instance (target_sizes: a
@@ -268,6 +271,7 @@ def balanced_kmeans_batched(instances, eps=0.03, max_iter=50, max_balance_iter=2
         p.tile_points = int(per(tile_points, i))
         p.super_tiles = int(per(super_tiles, i))
         p.recheck_rel_gap = float(per(recheck_rel_gap, i))
+        p.erosion = 1 if per(erosion, i) else 0
         dev = X[0].device
         ts = _targets(None if target_sizes is None else target_sizes[i], k, dev)
         keep.append(ts)

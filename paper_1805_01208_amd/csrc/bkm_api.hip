@@ -332,6 +332,7 @@ int check_run(const bkm_points* pts, const bkm_params* prm)
         return fail(BKM_EINVAL, "recheck_rel_gap must be finite and >= 0");
     if (std::isnan(p.delta_threshold)) return fail(BKM_EINVAL, "delta_threshold is NaN");
     if (p.sample_init && p.sample_start < 1) return fail(BKM_EINVAL, "sample_start must be >= 1");
+    if (p.erosion != 0 && p.erosion != 1) return fail(BKM_EINVAL, "erosion must be 0 or 1");
     return BKM_OK;
 }
 
@@ -396,6 +397,7 @@ int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_i
     RunDev r;
     plan(r, pts, p.k, T, ST, p.precision, p.use_bounds ? 1 : 0, p.recheck_rel_gap);
     r.tsz = p.target_sizes;
+    r.erosion = p.erosion;
     Arena a;
     if ((rc = alloc_run(r, a, s, true))) return rc;
 
@@ -582,6 +584,7 @@ void bkm_default_params(bkm_params* p, int32_t k)
     p->seed = 0;
     p->sample_keys = nullptr;
     p->target_sizes = nullptr;
+    p->erosion = 1;
     p->epsilon = 0.03;
     p->delta_threshold = -1.0;
     p->recheck_rel_gap = 1e-5;
@@ -957,6 +960,7 @@ int bkm_balanced_kmeans_batched(const bkm_points* pts, const bkm_params* prm, in
         plan(rs[i], &pts[i], p.k, T, p.super_tiles ? p.super_tiles : 16, p.precision,
              p.use_bounds ? 1 : 0, p.recheck_rel_gap);
         rs[i].tsz = p.target_sizes;
+        rs[i].erosion = p.erosion;
         z.total += layout(rs[i], nullptr, true);
     }
     Arena a;

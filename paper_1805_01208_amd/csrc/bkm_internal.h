@@ -86,6 +86,7 @@ struct RunDev {
     int maxjumps;
     int T, ppt, ntiles, super_tiles, nsuper, nhyper, ngroups;
     int precision, use_bounds;
+    int erosion;              // 1: erode the influence after every non-converged movement
     double recheck_gap;
 
     const void* in_x[3];      // caller's coordinates (input order)

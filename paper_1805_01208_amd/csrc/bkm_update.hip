@@ -290,9 +290,11 @@ __device__ __forceinline__ void round_end_body(RT r, const int bid)
     const int64_t g0 = (int64_t)bid * kPassGroups;
     const int64_t g = g0 + tid;
     const bool own = tid < kPassGroups;
+    // without erosion beta is not needed, and with it no box
+    const bool boxes = r.erosion != 0;
     const int f = own && g < r.ngroups ? r.gblk[g] : kPad;
     const bool dirty = own && g < r.ngroups && r.gdirty[g] != 0;
-    if (own) {
+    if (own && boxes) {
         unsigned long long mn[D], mx[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) {
@@ -321,12 +323,13 @@ __device__ __forceinline__ void round_end_body(RT r, const int bid)
     }
     // mixed groups (boxes) and groups with changed points (sums), listed
     if (own) {
-        const bool listed = f == -1 || dirty;
+        const bool mixed = boxes && f == -1;
+        const bool listed = mixed || dirty;
         const unsigned long long b = __ballot(listed);
         int pos = 0;
         if (lane == 0 && b) pos = atomicAdd(&s_n, (int)__popcll(b));
         pos = __shfl(pos, 0, kWave) + (int)__popcll(b & ((1ULL << lane) - 1ULL));
-        if (listed) s_list[pos] = tid | (f == -1 ? 0x100 : 0) | (dirty ? 0x200 : 0);
+        if (listed) s_list[pos] = tid | (mixed ? 0x100 : 0) | (dirty ? 0x200 : 0);
     }
     __syncthreads();
     const int nl = s_n;
@@ -475,13 +478,15 @@ __device__ __forceinline__ void move_body(RT r, const int bid)
             dd = sqrt(s);
 #pragma unroll
             for (int j = 0; j < D; ++j) r.C[(int64_t)j * k + c] = cn[j];
-            const unsigned long long* b = r.bb + (int64_t)c * 2 * D;
-            double e[D];
+            if (r.erosion) {   // beta, from the block's box
+                const unsigned long long* b = r.bb + (int64_t)c * 2 * D;
+                double e[D];
 #pragma unroll
-            for (int j = 0; j < D; ++j) e[j] = dec_ord(b[D + j]) - dec_ord(b[j]);
-            double q = e[0] * e[0] + e[1] * e[1];
-            if (D == 3) q = q + e[D - 1] * e[D - 1];
-            dsum += sqrt(q);
+                for (int j = 0; j < D; ++j) e[j] = dec_ord(b[D + j]) - dec_ord(b[j]);
+                double q = e[0] * e[0] + e[1] * e[1];
+                if (D == 3) q = q + e[D - 1] * e[D - 1];
+                dsum += sqrt(q);
+            }
             cnt += 1.0;
         }
         delta[c] = dd;
@@ -491,7 +496,7 @@ __device__ __forceinline__ void move_body(RT r, const int bid)
     dsum = block_reduce_1024(dsum, sh, OpAdd());
     cnt = block_reduce_1024(cnt, sh, OpAdd());
     const bool conv = dmax < st->delta_threshold;
-    const double beta = dsum / cnt;
+    const double beta = r.erosion ? dsum / cnt : 0.0;
     double mu = 1.0, emax = 0.0;
     if (!conv) {
         double m = INFINITY, e = 0.0;
@@ -499,7 +504,7 @@ __device__ __forceinline__ void move_body(RT r, const int bid)
             const double dl = delta[c];
             const double io = r.I[c];
             double in = io;
-            if (dl != 0.0) {
+            if (dl != 0.0 && r.erosion) {
                 double t = -dl / beta;
                 if (t > 0.0) t = 0.0;
                 const double alpha = 2.0 / (1.0 + exp(t)) - 1.0;

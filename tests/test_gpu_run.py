@@ -15,7 +15,7 @@ def compare_run(X, k, eps, W=None, precision="f64", **kw):
           f"{precision} {kw}", flush=True)
     Wt = None if W is None else torch.from_numpy(W).cuda()
     g = bkm.balanced_kmeans(cuda(X), k, W=Wt, eps=eps, precision=precision, **kw)
-    okw = {kk: v for kk, v in kw.items() if kk in ("max_iter", "max_balance_iter")}
+    okw = {kk: v for kk, v in kw.items() if kk in ("max_iter", "max_balance_iter", "erosion")}
     o = oracle.balanced_kmeans(widened(X), k, eps, W=W, **okw)
     A = g["A"].cpu().numpy()
     gi, oi = g["info"], o["info"]
@@ -46,6 +46,15 @@ def test_c1_uniform_2d(precision):
 def test_refined_2d_k64(precision):
     X = workloads.refined2d(120000, 2)
     compare_run(X, 64, 0.03, precision=precision, max_iter=20)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32_recheck"])
+def test_erosion_off(precision):
+    """Without erosion the influence is kept from round to round."""
+    X = workloads.gauss3d(20000, 37)
+    g, o = compare_run(X, 24, 0.02, precision=precision, max_iter=20, erosion=False)
+    e = oracle.balanced_kmeans(widened(X), 24, 0.02, max_iter=20)
+    assert not np.array_equal(o["influence"], e["influence"])
 
 
 def test_weighted_3d():

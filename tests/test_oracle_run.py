@@ -188,3 +188,35 @@ def test_sample_init_is_the_composition_of_single_rounds():
     assert np.array_equal(r["A"], full["A"])
     assert np.array_equal(r["centers"], full["centers"])
     assert np.array_equal(r["influence"], full["influence"])
+
+
+def test_erosion_off_is_the_loop_of_pinned_steps():
+    """With erosion off, the run is the loop of the pinned single steps (Alg.
+    2 around Alg. 1): assign, block weights, balance test and influence step,
+    new centers, and nothing between rounds.  Redone here in Python around
+    those steps; with erosion on, the influences differ."""
+    rng = np.random.default_rng(36)
+    n, k, eps = 3000, 7, 0.01
+    X = [rng.random(n), rng.random(n)]
+    dthr = 1e-5 * max(float(x.max() - x.min()) for x in X)
+    r = oracle.balanced_kmeans(X, k, eps, max_iter=4, max_balance_iter=3, delta_threshold=dthr,
+                               erosion=False)
+    C, _, _ = oracle.init_centers_sfc(X, k, 16)
+    I = np.ones(k)
+    lm = oracle.lmax(n, k, eps)
+    for _ in range(4):
+        for _ in range(3):
+            A, _, _ = oracle.assign(X, C, I)
+            bw = oracle.block_weights(A, None, k)
+            ok, I = oracle.balance_step(bw, 2, lm, n / k, I)
+            if ok:
+                break
+        Cn, delta = oracle.new_centers(X, None, A, C)
+        C = Cn
+        if delta.max() < dthr:
+            break
+    assert np.array_equal(r["A"], A)
+    assert np.array_equal(r["centers"], C)
+    assert np.array_equal(r["influence"], I)
+    e = oracle.balanced_kmeans(X, k, eps, max_iter=4, max_balance_iter=3, delta_threshold=dthr)
+    assert not np.array_equal(e["influence"], I)
