@@ -422,7 +422,6 @@ int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_i
         if ((rc = read_state(r, s, &h0))) return rc;
         if (dthr < 0.0) dthr = 1e-5 * h0.ext;
         const int64_t n = pts->n;
-        const size_t esz = r.in_f32 ? sizeof(float) : sizeof(double);
         Sizes z;
         z.add<double>((size_t)p.k * r.d);
         z.add<double>((size_t)p.k);
@@ -438,7 +437,6 @@ int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_i
         void* xb[3] = {nullptr, nullptr, nullptr};
         for (int j = 0; j < r.d; ++j) xb[j] = sa.take<double>((size_t)n);
         double* wb = r.weighted ? sa.take<double>((size_t)n) : nullptr;
-        (void)esz;
         if (centers_init)
             HIPCHK(hipMemcpyAsync(cbuf, centers_init, (size_t)p.k * r.d * sizeof(double),
                                   hipMemcpyDeviceToDevice, s));
