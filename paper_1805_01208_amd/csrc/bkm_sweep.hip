@@ -109,17 +109,17 @@ __device__ inline double sorted_coord(const RunDev& r, int j, int64_t p)
 // smallest distances are no smaller and its second-smallest largest distance
 // is no larger, so every center the parent drops it drops too, and the two
 // centers of its smallest largest distances are on the parent's list.
-template <int D, typename RT>
+template <int D, int NT, typename RT>
 __device__ __forceinline__ void box_filter(RT r, const double* lo, const double* hi,
                                            const int* __restrict__ list, int L, int* out,
                                            int* count_out)
 {
-    __shared__ double sa[kBlock / kWave], sb[kBlock / kWave];
+    __shared__ double sa[NT / kWave], sb[NT / kWave];
     __shared__ int cnt;
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     const int k = r.k;
     Two t{kInf, kInf};
-    for (int i = tid; i < L; i += kBlock) {
+    for (int i = tid; i < L; i += NT) {
         const int c = list ? list[i] : i;
         double lo2, hi2;
         box_eff2<D>(lo, hi, r.C, k, c, r.clus[c].y, lo2, hi2);
@@ -133,10 +133,10 @@ __device__ __forceinline__ void box_filter(RT r, const double* lo, const double*
     if (tid == 0) cnt = 0;
     __syncthreads();
     Two all{sa[0], sb[0]};
-    for (int w = 1; w < kBlock / kWave; ++w) all = merge_two(all, Two{sa[w], sb[w]});
+    for (int w = 1; w < NT / kWave; ++w) all = merge_two(all, Two{sa[w], sb[w]});
     const double thr2 = all.b * (1.0 + 2.0 * kCandSlack);
     const unsigned long long below = (1ULL << lane) - 1ULL;
-    for (int i0 = 0; i0 < L; i0 += kBlock) {
+    for (int i0 = 0; i0 < L; i0 += NT) {
         const int i = i0 + tid;
         int c = 0;
         bool keep = false;
@@ -156,7 +156,10 @@ __device__ __forceinline__ void box_filter(RT r, const double* lo, const double*
     if (tid == 0) *count_out = cnt;
 }
 
-// Hyper-tiles (kHyper super-tiles) against all k centers.
+// Hyper-tiles (kHyper super-tiles) against all k centers: few blocks with
+// long lists, so each block has kHyperThreads threads.
+constexpr int kHyperThreads = 1024;
+
 template <int D, typename RT>
 __device__ __forceinline__ void hypercand_body(RT r, const int bid)
 {
@@ -168,17 +171,17 @@ __device__ __forceinline__ void hypercand_body(RT r, const int bid)
         lo[j] = r.hbox[(int64_t)bid * 2 * D + j];
         hi[j] = r.hbox[(int64_t)bid * 2 * D + D + j];
     }
-    box_filter<D, RT>(r, lo, hi, nullptr, r.k, r.hlist + (int64_t)bid * r.k, r.hcount + bid);
+    box_filter<D, kHyperThreads, RT>(r, lo, hi, nullptr, r.k, r.hlist + (int64_t)bid * r.k, r.hcount + bid);
 }
 
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_hypercand(RunDev r)
+__global__ __launch_bounds__(kHyperThreads) void k_hypercand(RunDev r)
 {
     hypercand_body<D, const RunDev>(r, blockIdx.x);
 }
 
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_hypercand_multi(const RunDev* rs, const int2* map)
+__global__ __launch_bounds__(kHyperThreads) void k_hypercand_multi(const RunDev* rs, const int2* map)
 {
     const int2 m = map[blockIdx.x];
     hypercand_body<D, const RunDev&>(rs[m.x], m.y);
@@ -197,7 +200,7 @@ __device__ __forceinline__ void supercand_body(RT r, const int bid)
         hi[j] = r.sbox[(int64_t)bid * 2 * D + D + j];
     }
     const int h = bid / kHyper;
-    box_filter<D, RT>(r, lo, hi, r.hlist + (int64_t)h * r.k, r.hcount[h],
+    box_filter<D, kBlock, RT>(r, lo, hi, r.hlist + (int64_t)h * r.k, r.hcount[h],
                       r.slist + (int64_t)bid * r.k, r.scount + bid);
 }
 
@@ -239,7 +242,8 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
     if (st->done || st->round_done) return;
     constexpr int kCpl = 4;   // candidates a lane keeps in registers between passes
     const int lane = threadIdx.x % kWave;
-    const int tile = bid * (kBlock / kWave) + threadIdx.x / kWave;
+    // wave-uniform: the tile box, its frame and the list bounds live in scalar registers
+    const int tile = __builtin_amdgcn_readfirstlane(bid * (kBlock / kWave) + (int)threadIdx.x / kWave);
     if (tile >= r.ntiles) return;
     const int k = r.k;
     const double* __restrict__ C = r.C;
@@ -795,10 +799,10 @@ hipError_t sweep_p(const RunDev& r, hipStream_t s)
 hipError_t launch_supercand(const RunDev& r, hipStream_t s)
 {
     if (r.d == 2) {
-        k_hypercand<2><<<r.nhyper, kBlock, 0, s>>>(r);
+        k_hypercand<2><<<r.nhyper, kHyperThreads, 0, s>>>(r);
         k_supercand<2><<<r.nsuper, kBlock, 0, s>>>(r);
     } else {
-        k_hypercand<3><<<r.nhyper, kBlock, 0, s>>>(r);
+        k_hypercand<3><<<r.nhyper, kHyperThreads, 0, s>>>(r);
         k_supercand<3><<<r.nsuper, kBlock, 0, s>>>(r);
     }
     return hipGetLastError();
@@ -837,7 +841,7 @@ hipError_t sweep_multi_ppt(const MultiSet& m, hipStream_t s)
 template <int D, int PREC>
 hipError_t sweep_multi_p(const MultiSet& m, hipStream_t s)
 {
-    if (m.nb_hyper) k_hypercand_multi<D><<<m.nb_hyper, kBlock, 0, s>>>(m.rs, m.map_hyper);
+    if (m.nb_hyper) k_hypercand_multi<D><<<m.nb_hyper, kHyperThreads, 0, s>>>(m.rs, m.map_hyper);
     if (m.nb_super) k_supercand_multi<D><<<m.nb_super, kBlock, 0, s>>>(m.rs, m.map_super);
     if (m.nb_quad) k_tilecand_multi<D, PREC><<<m.nb_quad, kBlock, 0, s>>>(m.rs, m.map_quad);
     if (!m.nb_tile) return hipGetLastError();
