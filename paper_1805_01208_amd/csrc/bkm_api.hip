@@ -8,6 +8,7 @@
 // host enqueues a batch (one sweep, its balance test and the round end) and
 // synchronises once per batch.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -72,18 +73,21 @@ struct Sizes {
     void add(size_t count) { total += (count * sizeof(T) + 255) & ~size_t(255); }
 };
 
+// Keep freed stream-ordered memory in the current device's default pool
+// (set once per device; devices 0..63).
 void keep_pool_memory()
 {
-    static bool done = false;
-    if (done) return;
+    static std::atomic<uint64_t> done{0};
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+    const uint64_t bit = uint64_t(1) << dev;
+    if (done.load(std::memory_order_relaxed) & bit) return;
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
         uint64_t thr = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr) == hipSuccess)
+            done.fetch_or(bit, std::memory_order_relaxed);
     }
-    done = true;
 }
 
 // Small pinned host buffer for per-round state reads.
