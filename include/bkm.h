@@ -87,7 +87,9 @@ typedef struct {
     double delta_threshold;   /* absolute; < 0 selects 1e-5 * largest bounding-box extent
                                  (of all points, also in the sample rounds) */
     double recheck_rel_gap;   /* FP64 recheck window, relative, >= 0; default 1e-5 */
-    int64_t sample_start;     /* first sample size, >= 1; default 100 */
+    int64_t sample_start;     /* first sample size, >= 1; 0 (default) = 100 * k: the paper
+                                 starts each process with 100 of its points and uses one
+                                 block per process */
     uint64_t seed;            /* random order: point i gets key splitmix64 output i of the
                                  stream seeded with `seed` (Steele, Lea, Flood 2014:
                                  z = seed + (i+1)*0x9E3779B97F4A7C15, then the mixer);

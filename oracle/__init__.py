@@ -258,11 +258,12 @@ def erode(delta, beta_value, influence):
 
 def balanced_kmeans(X, k, eps, W=None, max_iter=50, max_balance_iter=20,
                     delta_threshold=None, hilbert_order=16, centers_init=None,
-                    influence_init=None, sample_keys=None, sample_start=100,
+                    influence_init=None, sample_keys=None, sample_start=0,
                     target_sizes=None, erosion=True):
     """Full balanced k-means.  delta_threshold None -> 1e-5 * largest bbox extent.
     With sample_keys (one uint64 per point) the run starts with the
-    random-sample initialization over the order of (key, index).
+    random-sample initialization over the order of (key, index), from
+    sample_start points (0: 100 per block, 100 * k).
     target_sizes: k relative block sizes, or None for equal blocks.
 
     Returns dict(A, centers, influence, block_weights, sweeps_per_round, info)."""

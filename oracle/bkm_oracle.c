@@ -621,7 +621,9 @@ done:
  * initialization).  The points are put in a random order, given as one key
  * per point (order by (key, index)).  Starting from the SFC centers and
  * influence 1, rounds run on the first s points of that order, s =
- * sample_start and doubling after every round, each carrying centers and
+ * sample_start (0: 100 points per block, i.e. 100 * k, the paper's 100
+ * points per process with one block per process) and doubling after
+ * every round, each carrying centers and
  * influence on; once s >= n, the run on all points continues from them.
  * Each sample round is one AssignAndBalance with the sample's own balance
  * target and L_max, then one center movement with erosion (a round whose
@@ -636,8 +638,9 @@ int oracle_balanced_kmeans_sampled(int64_t n, int d, const double* const* X, con
                                    oracle_info* info, int32_t* sample_rounds,
                                    int32_t* sample_sweeps)
 {
-    if (n < 1 || d < 2 || d > 3 || k < 1 || k > n || sample_start < 1 || !sample_keys)
+    if (n < 1 || d < 2 || d > 3 || k < 1 || k > n || sample_start < 0 || !sample_keys)
         return ORC_EINVAL;
+    if (sample_start == 0) sample_start = 100 * (int64_t)k;
     int rc = ORC_OK;
     double* C = (double*)malloc((size_t)k * d * sizeof(double));
     double* I = (double*)malloc((size_t)k * sizeof(double));

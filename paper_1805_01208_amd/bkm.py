@@ -186,13 +186,13 @@ def balanced_kmeans(X, k, W=None, eps=0.03, max_iter=50, max_balance_iter=20,
                     delta_threshold=-1.0, hilbert_order=16, precision="f32_recheck",
                     use_bounds=True, tile_points=0, super_tiles=0, recheck_rel_gap=1e-5,
                     centers_init=None, timing=False, out=None, sample_init=False,
-                    sample_start=100, seed=0, sample_keys=None, target_sizes=None,
+                    sample_start=0, seed=0, sample_keys=None, target_sizes=None,
                     erosion=True):
     """Balanced k-means; returns dict(A, centers, influence, block_weights, info, code).
     sample_init: start with rounds on random samples doubling from sample_start
-    points (order by splitmix64(seed, index), or by sample_keys, n uint64
-    keys on the device).  target_sizes: k relative block sizes (device
-    tensor), or None for equal blocks."""
+    points (0: 100 per block, i.e. 100 * k), ordered by splitmix64(seed, index)
+    or by sample_keys (n uint64 keys on the device).  target_sizes: k relative
+    block sizes (device tensor), or None for equal blocks."""
     dev = X[0].device
     pts = make_points(X, W)
     prm = default_params(k)

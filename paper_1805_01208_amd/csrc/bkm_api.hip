@@ -335,7 +335,7 @@ int check_run(const bkm_points* pts, const bkm_params* prm)
     if (!(p.recheck_rel_gap >= 0.0) || !std::isfinite(p.recheck_rel_gap))
         return fail(BKM_EINVAL, "recheck_rel_gap must be finite and >= 0");
     if (std::isnan(p.delta_threshold)) return fail(BKM_EINVAL, "delta_threshold is NaN");
-    if (p.sample_init && p.sample_start < 1) return fail(BKM_EINVAL, "sample_start must be >= 1");
+    if (p.sample_init && p.sample_start < 0) return fail(BKM_EINVAL, "sample_start must be >= 0");
     if (p.erosion != 0 && p.erosion != 1) return fail(BKM_EINVAL, "erosion must be 0 or 1");
     return BKM_OK;
 }
@@ -421,7 +421,10 @@ int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_i
     const double* iinit = influence_init;
     double dthr = p.delta_threshold;
     Arena sa;
-    if (p.sample_init && p.sample_start < pts->n) {
+    // first sample size: sample_start, or 0 for 100 points per block (the
+    // paper's 100 points per process, with one block per process)
+    const int64_t s0 = p.sample_start > 0 ? p.sample_start : 100 * (int64_t)p.k;
+    if (p.sample_init && s0 < pts->n) {
         DevState h0;
         if ((rc = read_state(r, s, &h0))) return rc;
         if (dthr < 0.0) dthr = 1e-5 * h0.ext;
@@ -455,7 +458,7 @@ int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_i
         q.max_iter = 1;
         q.delta_threshold = dthr;
         q.timing = 0;
-        for (int64_t sz = p.sample_start; sz < n; sz *= 2) {
+        for (int64_t sz = s0; sz < n; sz *= 2) {
             HIPCHK(launch_gather_sample(r, sz, xb, wb, s));
             bkm_points ps = *pts;
             ps.n = sz;
@@ -582,7 +585,7 @@ void bkm_default_params(bkm_params* p, int32_t k)
     p->super_tiles = 0;
     p->timing = 0;
     p->sample_init = 0;
-    p->sample_start = 100;
+    p->sample_start = 0;
     p->seed = 0;
     p->sample_keys = nullptr;
     p->target_sizes = nullptr;

@@ -562,6 +562,22 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
             bi = better ? c0 : bi;
             b2 = better ? e2 : b2;
         };
+        // the same ranking by squared effective distance, iv2 = (1/influence)^2
+        auto consider64sq = [&](int c, double cx, double cy, double cz, double iv2) {
+            const double dx = x[0] - cx;
+            const double dy = x[1] - cy;
+            double sq = dx * dx + dy * dy;
+            if (D == 3) {
+                const double dz = x[2] - cz;
+                sq = sq + dz * dz;
+            }
+            const double e2 = sq * iv2;
+            const bool better = e2 < be || (e2 == be && c < bc);
+            se = better ? be : fmin(se, e2);
+            bs2 = better ? sq : bs2;
+            bc = better ? c : bc;
+            be = better ? e2 : be;
+        };
         auto consider64 = [&](int c, double cx, double cy, double cz, double ic) {
             double sq;
             const double e = eff64<D>(x, cx, cy, cz, ic, sq);
@@ -586,24 +602,32 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
         } else {
             // overflowed tile: the super-tile's list in FP64, staged through
             // LDS in chunks of kTileCap centers that every wave of the block
-            // helps to load (the loop is block-uniform)
+            // helps to load (the loop is block-uniform).  Candidates are
+            // compared by their squared effective distance s * (1/I)^2, with
+            // no square root or division per candidate: its rounding differs
+            // from sqrt(s) / I by a few units of 2^-53, which can only swap
+            // two candidates closer than that (a tie at the 1e-12 level), and
+            // the bounds below carry a 1e-12 slack.
             for (int cb = 0; cb < ncand; cb += kTileCap) {
                 const int m = min(kTileCap, ncand - cb);
                 __syncthreads();   // the previous chunk is consumed
                 if (tid < m) {
                     const int c = sl[cb + tid];
+                    const double iv = r.clus[c].y;
                     s_cid[tid] = c;
                     s_c64[0][tid] = C[c];
                     s_c64[1][tid] = C[(int64_t)k + c];
                     s_c64[2][tid] = D == 3 ? C[(int64_t)(D - 1) * k + c] : 0.0;
-                    s_c64[3][tid] = I[c];
+                    s_c64[3][tid] = iv * iv;
                 }
                 __syncthreads();
                 if (__ballot(act) != 0ULL) {
                     for (int c0 = 0; c0 < m; ++c0)
-                        consider64(s_cid[c0], s_c64[0][c0], s_c64[1][c0], s_c64[2][c0], s_c64[3][c0]);
+                        consider64sq(s_cid[c0], s_c64[0][c0], s_c64[1][c0], s_c64[2][c0], s_c64[3][c0]);
                 }
             }
+            // back to effective distances for the lower bound
+            se = sqrt(se);
         }
         int cbest = ao;
         bool chg = false, rck = false;

@@ -73,7 +73,7 @@ def test_default_params(bkm):
     assert (p.k, p.max_iter, p.max_balance_iter, p.hilbert_order) == (16, 50, 20, 16)
     assert p.precision == bkm.PREC_F32_RECHECK and p.use_bounds == 1
     assert p.epsilon == 0.03 and p.delta_threshold < 0 and p.recheck_rel_gap == 1e-5
-    assert (p.sample_init, p.sample_start, p.seed, p.sample_keys) == (0, 100, 0, None)
+    assert (p.sample_init, p.sample_start, p.seed, p.sample_keys) == (0, 0, 0, None)
     assert p.target_sizes is None and p.erosion == 1
 
 
@@ -99,7 +99,7 @@ def _pts(bkm, n=100, d=2, dtype=1):
     (lambda p, q: setattr(q, "precision", 5), "precision"),
     (lambda p, q: setattr(q, "tile_points", 300), "tile_points"),
     (lambda p, q: setattr(q, "recheck_rel_gap", -1.0), "recheck_rel_gap"),
-    (lambda p, q: (setattr(q, "sample_init", 1), setattr(q, "sample_start", 0)), "sample_start"),
+    (lambda p, q: (setattr(q, "sample_init", 1), setattr(q, "sample_start", -1)), "sample_start"),
     (lambda p, q: setattr(q, "erosion", 2), "erosion"),
 ])
 def test_invalid_arguments(bkm, mutate, needle):

@@ -1,5 +1,6 @@
 """Random-sample initialization (the random start described with Alg. 2):
-rounds on nested random samples doubling from 100 points, then the main
+rounds on nested random samples doubling from a first sample (by default
+100 points per block), then the main
 loop on all points.  The GPU run must equal the oracle's run with the same
 random order keys, and its own splitmix64 keys must be the published
 generator's."""
@@ -35,7 +36,8 @@ def _check_against_oracle(X, k, eps, W=None, max_iter=12, seed=0, start=100, **k
     assert (gi["sample_rounds"], gi["sample_sweeps"]) == (oi["sample_rounds"], oi["sample_sweeps"])
     assert (gi["rounds"], gi["sweeps"]) == (oi["rounds"], oi["sweeps"])
     assert gi["balanced"] == oi["balanced"]
-    assert gi["sample_rounds"] == (math.ceil(math.log2(n / start)) if n > start else 0)
+    s0 = start if start > 0 else 100 * k
+    assert gi["sample_rounds"] == (math.ceil(math.log2(n / s0)) if n > s0 else 0)
     return g
 
 
@@ -91,7 +93,16 @@ def test_default_keys_are_splitmix64():
         h = bkm.balanced_kmeans(X, 24, max_iter=8, sample_init=True,
                                 sample_keys=_keys_dev(workloads.splitmix64(seed, 12000)))
         assert torch.equal(g["A"], h["A"]) and torch.equal(g["centers"], h["centers"])
-        assert g["info"]["sample_rounds"] == 7
+        assert g["info"]["sample_rounds"] == 3   # from 100 * 24 points: 2400, 4800, 9600
+
+
+def test_default_start_is_100_points_per_block():
+    """sample_start = 0 (the default): the first sample has 100 * k points,
+    as the oracle reads it too."""
+    print("case sample-init default start, n=40000 2D k=25", flush=True)
+    X = workloads.refined2d(40000, 19)
+    g = _check_against_oracle(X, 25, 0.03, seed=12, start=0, max_iter=10)
+    assert g["info"]["sample_rounds"] == 4   # 2500, 5000, 10000, 20000
 
 
 def test_sample_covering_all_points_is_plain_run():

@@ -136,7 +136,7 @@ def test_sample_init_finishes_balanced_with_block_means():
     X = [rng.random(n) for _ in range(3)]
     W = rng.lognormal(0.0, 0.5, n)
     keys = rng.integers(0, 2**63, n, dtype=np.uint64)
-    r = oracle.balanced_kmeans(X, k, 0.05, W=W, max_iter=30, sample_keys=keys)
+    r = oracle.balanced_kmeans(X, k, 0.05, W=W, max_iter=30, sample_keys=keys, sample_start=100)
     assert r["info"]["sample_rounds"] == math.ceil(math.log2(n / 100))
     assert r["info"]["balanced"] == 1
     assert r["block_weights"].max() <= r["info"]["lmax"]
@@ -151,9 +151,28 @@ def test_sample_rounds_with_more_blocks_than_sample_points():
     n, k = 6000, 300
     X = [rng.random(n), rng.random(n)]
     keys = rng.integers(0, 2**63, n, dtype=np.uint64)
-    r = oracle.balanced_kmeans(X, k, 0.05, max_iter=10, sample_keys=keys)
+    r = oracle.balanced_kmeans(X, k, 0.05, max_iter=10, sample_keys=keys, sample_start=100)
     assert r["info"]["sample_rounds"] == math.ceil(math.log2(n / 100))
     _check_means(X, None, r["A"], r["centers"])
+
+
+def test_default_first_sample_is_100_points_per_block():
+    """sample_start = 0 (the default) starts from 100 points per block,
+    100 * k: the paper starts every process with 100 of its points and runs
+    one block per process, so the number of sample rounds is
+    ceil(log2(n_local / 100)) with n_local = n / k."""
+    rng = np.random.default_rng(35)
+    n, k = 20000, 16
+    X = [rng.random(n), rng.random(n)]
+    keys = rng.integers(0, 2**63, n, dtype=np.uint64)
+    a = oracle.balanced_kmeans(X, k, 0.03, max_iter=8, sample_keys=keys)
+    b = oracle.balanced_kmeans(X, k, 0.03, max_iter=8, sample_keys=keys, sample_start=100 * k)
+    assert a["info"]["sample_rounds"] == math.ceil(math.log2((n / k) / 100)) == 4
+    assert a["info"]["sample_rounds"] == b["info"]["sample_rounds"]
+    assert np.array_equal(a["A"], b["A"]) and np.array_equal(a["centers"], b["centers"])
+    # n <= 100 k: no sample round at all
+    c = oracle.balanced_kmeans(X, 200, 0.03, max_iter=3, sample_keys=keys)
+    assert c["info"]["sample_rounds"] == 0
 
 
 def test_sample_init_is_the_composition_of_single_rounds():
