@@ -287,7 +287,10 @@ int read_counters(const RunDev& r, hipStream_t s, unsigned long long out[kCntWor
 // SFC bootstrap: bounding box (+ data checks), keys, sort, coordinates in
 // Hilbert order; with `tiles`, also the jump-aligned padded layout and the
 // tile, group and super-tile boxes.
-int bootstrap(RunDev& r, int order, hipStream_t s, bool tiles, double eps = 0.0)
+// presorted: the points already come in a spatially coherent order (a sample
+// taken from a Hilbert layout), which is kept instead of sorting by key.
+int bootstrap(RunDev& r, int order, hipStream_t s, bool tiles, double eps = 0.0,
+              bool presorted = false)
 {
     HIPCHK(launch_bbox(r, order, s));
     if (r.tsz) HIPCHK(launch_target_prep(r, eps, s));
@@ -299,8 +302,12 @@ int bootstrap(RunDev& r, int order, hipStream_t s, bool tiles, double eps = 0.0)
     if (h.bad_data)
         return fail(BKM_EDATA, r.weighted ? "non-finite coordinate or weight <= 0 / non-finite"
                                           : "non-finite coordinate");
-    HIPCHK(launch_keys(r, order, r.sperm, s));
-    HIPCHK(radix_sort_pairs(r, r.keys, r.sperm, r.d * order, s));
+    if (presorted) {
+        HIPCHK(launch_iota(r.sperm, r.n, s));
+    } else {
+        HIPCHK(launch_keys(r, order, r.sperm, s));
+        HIPCHK(radix_sort_pairs(r, r.keys, r.sperm, r.d * order, s));
+    }
     HIPCHK(launch_permute(r, s));
     if (!tiles) return BKM_OK;
     HIPCHK(launch_jump_plan(r, s));
@@ -391,9 +398,11 @@ struct BatchRes {
 // One balanced k-means run (Alg. 2 around Alg. 1) on checked arguments.
 // centers_init ([k][d]) and influence_init ([k]) may be NULL (SFC centers,
 // influence 1); with centers given, k may exceed n (a sample round).
+// presorted: the points come in Hilbert order already (a sample round).
 int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_init,
              const double* influence_init, int32_t* assignment_out, double* centers_out,
-             double* influence_out, double* block_weights_out, bkm_info* info, hipStream_t s)
+             double* influence_out, double* block_weights_out, bkm_info* info, hipStream_t s,
+             bool presorted = false)
 {
     int rc;
     const int T = p.tile_points ? p.tile_points : auto_tile(pts->n, p.k);
@@ -410,7 +419,7 @@ int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_i
     struct EvFree { hipEvent_t* e; ~EvFree() { for (int i = 0; i < 3; ++i) (void)hipEventDestroy(e[i]); } } evf{ev};
     HIPCHK(hipEventRecord(ev[0], s));
 
-    if ((rc = bootstrap(r, p.hilbert_order, s, true, p.epsilon))) return rc;
+    if ((rc = bootstrap(r, p.hilbert_order, s, true, p.epsilon, presorted))) return rc;
 
     // random-sample initialization: rounds on the first sz points of a random
     // order, sz doubling, each one AssignAndBalance and one center movement
@@ -435,6 +444,8 @@ int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_i
         z.add<int32_t>((size_t)n);
         for (int j = 0; j < r.d; ++j) z.add<double>((size_t)n);   // room for either dtype
         if (r.weighted) z.add<double>((size_t)n);
+        z.add<int32_t>((size_t)n);         // rank of each point in the random order
+        z.add<int32_t>((size_t)r.npad);    // rank of the point at each layout position
         sa.s = s;
         HIPCHK(hipMallocAsync((void**)&sa.base, z.total, s));
         sa.cap = z.total;
@@ -444,6 +455,8 @@ int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_i
         void* xb[3] = {nullptr, nullptr, nullptr};
         for (int j = 0; j < r.d; ++j) xb[j] = sa.take<double>((size_t)n);
         double* wb = r.weighted ? sa.take<double>((size_t)n) : nullptr;
+        int32_t* rank = sa.take<int32_t>((size_t)n);
+        int32_t* rk = sa.take<int32_t>((size_t)r.npad);
         if (centers_init)
             HIPCHK(hipMemcpyAsync(cbuf, centers_init, (size_t)p.k * r.d * sizeof(double),
                                   hipMemcpyDeviceToDevice, s));
@@ -453,20 +466,22 @@ int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_i
             HIPCHK(hipMemcpyAsync(ibuf, influence_init, (size_t)p.k * sizeof(double),
                                   hipMemcpyDeviceToDevice, s));
         HIPCHK(launch_sample_order(r, p.seed, p.sample_keys, s));
+        HIPCHK(launch_sample_layout_rank(r, rank, rk, s));
         bkm_params q = p;
         q.sample_init = 0;
         q.max_iter = 1;
         q.delta_threshold = dthr;
         q.timing = 0;
         for (int64_t sz = s0; sz < n; sz *= 2) {
-            HIPCHK(launch_gather_sample(r, sz, xb, wb, s));
+            // the sample's points in the layout's Hilbert order
+            HIPCHK(launch_sample_compact(r, rk, sz, xb, wb, s));
             bkm_points ps = *pts;
             ps.n = sz;
             for (int j = 0; j < r.d; ++j) ps.coords[j] = xb[j];
             ps.weights = wb;
             bkm_info si;
             rc = run_core(&ps, q, cbuf, (sample_rounds || influence_init) ? ibuf : nullptr, abuf,
-                          cbuf, ibuf, nullptr, &si, s);
+                          cbuf, ibuf, nullptr, &si, s, true);
             if (rc < 0) return rc;
             sample_rounds += 1;
             sample_sweeps += si.sweeps;

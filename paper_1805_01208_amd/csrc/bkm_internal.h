@@ -364,11 +364,15 @@ hipError_t launch_init_run(const RunDev& r, const double* centers_init_rowmajor,
                            const double* influence_init, int max_iter, int max_balance_iter,
                            double eps, double delta_threshold, hipStream_t s);
 // random-sample initialization: order of the points by (key, index), keys from
-// splitmix64 or given; the first `count` points of it gathered
+// splitmix64 or given (in sperm); then the rank of the point at every layout
+// position, and per sample the layout positions of rank below `count`, in
+// layout order, with their coordinates and weights
 hipError_t launch_sample_order(const RunDev& r, uint64_t seed, const uint64_t* given,
                                hipStream_t s);
-hipError_t launch_gather_sample(const RunDev& r, int64_t count, void* const* x, double* w,
-                                hipStream_t s);
+hipError_t launch_sample_layout_rank(const RunDev& r, int32_t* rank, int32_t* rk, hipStream_t s);
+hipError_t launch_sample_compact(const RunDev& r, const int32_t* rk, int64_t count, void* const* x,
+                                 double* w, hipStream_t s);
+hipError_t launch_iota(int32_t* v, int64_t n, hipStream_t s);
 hipError_t launch_knn(const RunDev& r, int K, int32_t* nbr, unsigned long long* visits,
                       hipStream_t s);
 hipError_t launch_sym_count(int64_t n, int K, const int32_t* nbr, int32_t* extra, int* bad,

@@ -807,21 +807,6 @@ __global__ __launch_bounds__(kBlock) void k_sample_keys(RunDev r, uint64_t seed,
     r.sperm[i] = (int32_t)i;
 }
 
-// The first s points of the random order, gathered in that order.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gather_sample(RunDev r, int64_t s, T* x0, T* x1,
-                                                          T* x2, double* w)
-{
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= s) return;
-    const int64_t o = r.sperm[i];
-    const T* const* in = reinterpret_cast<const T* const*>(r.in_x);
-    x0[i] = in[0][o];
-    x1[i] = in[1][o];
-    if (r.d == 3) x2[i] = in[2][o];
-    if (w) w[i] = r.in_w[o];
-}
-
 hipError_t launch_sample_order(const RunDev& r, uint64_t seed, const uint64_t* given,
                                hipStream_t s)
 {
@@ -831,15 +816,133 @@ hipError_t launch_sample_order(const RunDev& r, uint64_t seed, const uint64_t* g
     return radix_sort_pairs(r, r.keys, r.sperm, 64, s);
 }
 
-hipError_t launch_gather_sample(const RunDev& r, int64_t count, void* const* x, double* w,
-                                hipStream_t s)
+// ---------------------------------------------- samples in Hilbert order
+// A sample round only needs its points in some spatially coherent order (its
+// results do not depend on the order), so the nested samples are taken from
+// the full run's Hilbert layout instead of being sorted again: the layout
+// positions whose point ranks below s in the random order, kept in layout
+// order.
+
+// rank[order[j]] = j: every point's position in the random order
+__global__ __launch_bounds__(kBlock) void k_sample_rank(const int32_t* order, int64_t n,
+                                                       int32_t* rank)
 {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j < n) rank[order[j]] = (int32_t)j;
+}
+
+// rank of the point at each layout position; INT32_MAX for padding
+__global__ __launch_bounds__(kBlock) void k_sample_layout_rank(RunDev r, const int32_t* rank,
+                                                              int32_t* rk)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= r.npad) return;
+    const int32_t src = r.perm[p];
+    rk[p] = src >= 0 ? rank[src] : INT32_MAX;
+}
+
+// per chunk of kChunk layout positions (each thread kSortIpt consecutive
+// ones): how many rank below s
+__global__ __launch_bounds__(kBlock) void k_sample_count(const int32_t* rk, int64_t npad,
+                                                        int64_t s, uint32_t* cnt)
+{
+    __shared__ uint32_t sh[kBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kSortIpt;
+    uint32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < kSortIpt; ++q) {
+        const int64_t p = base + q;
+        c += (p < npad && rk[p] < s) ? 1u : 0u;
+    }
+    for (int m = kWave / 2; m > 0; m >>= 1) c += __shfl_xor(c, m, kWave);
+    if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) t += sh[w];
+        cnt[blockIdx.x] = t;
+    }
+}
+
+// stable compaction: the kept positions of each chunk, in layout order, from
+// the chunk's scanned offset on; their coordinates and weights gathered
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sample_scatter(RunDev r, const int32_t* rk, int64_t s,
+                                                          const uint32_t* off, T* x0, T* x1,
+                                                          T* x2, double* w)
+{
+    __shared__ uint32_t sh[kBlock];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)tid * kSortIpt;
+    bool keep[kSortIpt];
+    uint32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < kSortIpt; ++q) {
+        const int64_t p = base + q;
+        keep[q] = p < r.npad && rk[p] < s;
+        c += keep[q] ? 1u : 0u;
+    }
+    // exclusive scan of the threads' counts
+    sh[tid] = c;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {
+        const uint32_t v = tid >= o ? sh[tid - o] : 0u;
+        __syncthreads();
+        sh[tid] += v;
+        __syncthreads();
+    }
+    int64_t t = (int64_t)off[blockIdx.x] + sh[tid] - c;
+    T* const xo[3] = {x0, x1, x2};
+#pragma unroll
+    for (int q = 0; q < kSortIpt; ++q) {
+        if (!keep[q]) continue;
+        const int64_t p = base + q;
+        for (int j = 0; j < r.d; ++j) {
+            if (r.in_f32)
+                reinterpret_cast<float*>(xo[j])[t] = r.xs32[j][p];
+            else
+                reinterpret_cast<double*>(xo[j])[t] = r.xs64[j][p];
+        }
+        if (w) w[t] = r.ws[p];
+        ++t;
+    }
+}
+
+// identity permutation: the points are taken in their given order
+__global__ __launch_bounds__(kBlock) void k_iota(int32_t* v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) v[i] = (int32_t)i;
+}
+
+hipError_t launch_sample_layout_rank(const RunDev& r, int32_t* rank, int32_t* rk, hipStream_t s)
+{
+    k_sample_rank<<<nblocks(r.n, kBlock), kBlock, 0, s>>>(r.sperm, r.n, rank);
+    k_sample_layout_rank<<<nblocks(r.npad, kBlock), kBlock, 0, s>>>(r, rank, rk);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_compact(const RunDev& r, const int32_t* rk, int64_t count, void* const* x,
+                                 double* w, hipStream_t s)
+{
+    const int nch = (int)nblocks(r.npad, kChunk);
+    const int nseg = (nch + kScanSeg - 1) / kScanSeg;
+    k_sample_count<<<nch, kBlock, 0, s>>>(rk, r.npad, count, r.hist);
+    k_scan_reduce<<<nseg, kBlock, 0, s>>>(r.hist, nch, r.part);
+    k_scan_top<<<1, 1024, 0, s>>>(r.part, nseg);
+    k_scan_down<<<nseg, kBlock, 0, s>>>(r.hist, nch, r.part);
     if (r.in_f32)
-        k_gather_sample<float><<<nblocks(count, kBlock), kBlock, 0, s>>>(
-            r, count, (float*)x[0], (float*)x[1], (float*)x[2], w);
+        k_sample_scatter<float><<<nch, kBlock, 0, s>>>(r, rk, count, r.hist, (float*)x[0],
+                                                       (float*)x[1], (float*)x[2], w);
     else
-        k_gather_sample<double><<<nblocks(count, kBlock), kBlock, 0, s>>>(
-            r, count, (double*)x[0], (double*)x[1], (double*)x[2], w);
+        k_sample_scatter<double><<<nch, kBlock, 0, s>>>(r, rk, count, r.hist, (double*)x[0],
+                                                        (double*)x[1], (double*)x[2], w);
+    return hipGetLastError();
+}
+
+hipError_t launch_iota(int32_t* v, int64_t n, hipStream_t s)
+{
+    k_iota<<<nblocks(n, kBlock), kBlock, 0, s>>>(v, n);
     return hipGetLastError();
 }
 
