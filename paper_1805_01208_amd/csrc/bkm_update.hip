@@ -143,8 +143,12 @@ __global__ __launch_bounds__(1024) void k_balance_multi(const RunDev* rs, const 
 // Integer sums and min/max of the order-preserving encoding are exact and
 // order-independent, so nothing depends on scheduling.
 constexpr int kPassGroups = kBlock;      // one group per thread in the uniform step
-constexpr int kHashSlots = 256;
-constexpr int kMixBatch = 4;             // listed groups a wave has in flight
+// A pass block (16K points) meets far fewer than 128 blocks unless blocks
+// hold only a few hundred points, and a full table falls back to the global
+// arrays; with 128 slots and two listed groups in flight per wave, 8 waves
+// per SIMD fit in LDS and registers.
+constexpr int kHashSlots = 128;
+constexpr int kMixBatch = 2;             // listed groups a wave has in flight
 constexpr int kRoundThreadsMulti = 1024; // threads per block of the many-instance round end
 
 template <int D>
@@ -434,7 +438,7 @@ __device__ __forceinline__ void round_end_body(RT r, const int bid)
 }
 
 template <int D, bool WEIGHTED>
-__global__ __launch_bounds__(kBlock, 6) void k_round_end(RunDev r)
+__global__ __launch_bounds__(kBlock, 8) void k_round_end(RunDev r)
 {
     round_end_body<D, WEIGHTED, kBlock, const RunDev>(r, blockIdx.x);
 }
