@@ -187,7 +187,9 @@ __global__ __launch_bounds__(kHyperThreads) void k_hypercand_multi(const RunDev*
     hypercand_body<D, const RunDev&>(rs[m.x], m.y);
 }
 
-// Super-tiles against their hyper-tile's list.
+// Super-tiles against their hyper-tile's list, kSuperThreads threads each.
+constexpr int kSuperThreads = 512;
+
 template <int D, typename RT>
 __device__ __forceinline__ void supercand_body(RT r, const int bid)
 {
@@ -200,12 +202,12 @@ __device__ __forceinline__ void supercand_body(RT r, const int bid)
         hi[j] = r.sbox[(int64_t)bid * 2 * D + D + j];
     }
     const int h = bid / kHyper;
-    box_filter<D, kBlock, RT>(r, lo, hi, r.hlist + (int64_t)h * r.k, r.hcount[h],
+    box_filter<D, kSuperThreads, RT>(r, lo, hi, r.hlist + (int64_t)h * r.k, r.hcount[h],
                       r.slist + (int64_t)bid * r.k, r.scount + bid);
 }
 
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_supercand(RunDev r)
+__global__ __launch_bounds__(kSuperThreads) void k_supercand(RunDev r)
 {
     supercand_body<D, const RunDev>(r, blockIdx.x);
 }
@@ -213,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_supercand(RunDev r)
 // Many instances in one launch: block b works on instance map[b].x as its
 // block map[b].y.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_supercand_multi(const RunDev* rs, const int2* map)
+__global__ __launch_bounds__(kSuperThreads) void k_supercand_multi(const RunDev* rs, const int2* map)
 {
     const int2 m = map[blockIdx.x];
     supercand_body<D, const RunDev&>(rs[m.x], m.y);
@@ -824,10 +826,10 @@ hipError_t launch_supercand(const RunDev& r, hipStream_t s)
 {
     if (r.d == 2) {
         k_hypercand<2><<<r.nhyper, kHyperThreads, 0, s>>>(r);
-        k_supercand<2><<<r.nsuper, kBlock, 0, s>>>(r);
+        k_supercand<2><<<r.nsuper, kSuperThreads, 0, s>>>(r);
     } else {
         k_hypercand<3><<<r.nhyper, kHyperThreads, 0, s>>>(r);
-        k_supercand<3><<<r.nsuper, kBlock, 0, s>>>(r);
+        k_supercand<3><<<r.nsuper, kSuperThreads, 0, s>>>(r);
     }
     return hipGetLastError();
 }
@@ -866,7 +868,7 @@ template <int D, int PREC>
 hipError_t sweep_multi_p(const MultiSet& m, hipStream_t s)
 {
     if (m.nb_hyper) k_hypercand_multi<D><<<m.nb_hyper, kHyperThreads, 0, s>>>(m.rs, m.map_hyper);
-    if (m.nb_super) k_supercand_multi<D><<<m.nb_super, kBlock, 0, s>>>(m.rs, m.map_super);
+    if (m.nb_super) k_supercand_multi<D><<<m.nb_super, kSuperThreads, 0, s>>>(m.rs, m.map_super);
     if (m.nb_quad) k_tilecand_multi<D, PREC><<<m.nb_quad, kBlock, 0, s>>>(m.rs, m.map_quad);
     if (!m.nb_tile) return hipGetLastError();
     return m.weighted ? sweep_multi_ppt<D, PREC, true>(m, s) : sweep_multi_ppt<D, PREC, false>(m, s);
