@@ -54,6 +54,9 @@ struct DevState {
     double wmax;
     double beta, max_delta, max_weight, total_weight;
     double max_ratio;         // largest weight / target over the blocks at the last balance test
+    // the sweep's copies of the frame, refreshed wherever M or E change
+    double invM;              // 1 / M
+    float Mf, Ef;             // M rounded down and E rounded up to FP32
 };
 
 // Sweep counters, summed over the kCntSlots slots by the host.
@@ -333,6 +336,17 @@ __host__ __device__ inline double fix_value(long long hi, long long lo)
 // Directed conversions FP64 -> FP32.
 __device__ inline float f32_up(double x) { return __double2float_ru(x); }
 __device__ inline float f32_down(double x) { return __double2float_rd(x); }
+
+// The sweep's copies of the lower-bound frame (M, E): FP32 values rounded so
+// that every bound stays valid, and the reciprocal of M (its rounding, a few
+// units of 2^-53, is covered by the sweep's 1e-12 slack).  Called by the one
+// thread that has just changed M or E.
+__device__ inline void frame_copies(DevState* st)
+{
+    st->Mf = f32_down(st->M);
+    st->Ef = f32_up(st->E);
+    st->invM = 1.0 / st->M;
+}
 
 // ------------------------------------------------------------- launchers
 // Each returns the hipError_t of its last launch.

@@ -449,12 +449,11 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
     float2 cl[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) cl[q] = r.clus32[aold[q] > 0 ? aold[q] : 0];
-    // lower-bound frame in FP32, rounded so that every bound stays valid
-    const float Mf = f32_down(st->M), Ef = f32_up(st->E);
+    // lower-bound frame in FP32, rounded so that every bound stays valid, and
+    // the reciprocal of its scale (precomputed by whoever changed the frame)
+    const float Mf = st->Mf, Ef = st->Ef;
     const double E = st->E;
-    // the lower-bound frame's scale as a reciprocal: one division per block;
-    // its rounding (a few units of 2^-53) is covered by the kTiny slack below
-    const double invM = 1.0 / st->M;
+    const double invM = st->invM;
     unsigned n_eval = 0, n_skip = 0;
     __syncthreads();   // s_nl initialised
     const unsigned long long below = (1ULL << lane) - 1ULL;

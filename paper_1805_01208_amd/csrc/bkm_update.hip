@@ -105,6 +105,7 @@ __device__ __forceinline__ void balance_body(RT r, const int bid)
             // lower bounds shrink with the largest relative influence growth
             st->M = st->M * mu * kDown;
             st->E = st->E * mu * kUp;
+            frame_copies(st);
             if (sweep_no >= st->max_balance_iter) st->round_done = 1;
         }
     }
@@ -536,6 +537,7 @@ __device__ __forceinline__ void move_body(RT r, const int bid)
         } else {
             st->M = st->M * mu * kDown;
             st->E = (st->E * mu + emax) * kUp;
+            frame_copies(st);
         }
         if (st->rounds >= st->max_iter) st->done = 1;
         st->round_done = 0;
@@ -660,6 +662,7 @@ __global__ __launch_bounds__(kBlock) void k_init_clusters(RunDev r, const double
         st->max_balance_iter = max_bal;
         st->M = 1.0;
         st->E = 0.0;
+        frame_copies(st);
         const double W = st->total_weight;
         if (!r.tsz) {   // with target sizes, the prep left the largest limit here
             if (r.weighted) {
@@ -715,6 +718,7 @@ __global__ __launch_bounds__(1024) void k_set_step(RunDev r, const double* crm,
             st->M = st->M * m * kDown;
             st->E = (st->E * m + e) * kUp;
         }
+        frame_copies(st);
         st->done = 0;
         st->round_done = 0;
     }
