@@ -897,12 +897,8 @@ __global__ __launch_bounds__(kBlock) void k_sample_scatter(RunDev r, const int32
     for (int q = 0; q < kSortIpt; ++q) {
         if (!keep[q]) continue;
         const int64_t p = base + q;
-        for (int j = 0; j < r.d; ++j) {
-            if (r.in_f32)
-                reinterpret_cast<float*>(xo[j])[t] = r.xs32[j][p];
-            else
-                reinterpret_cast<double*>(xo[j])[t] = r.xs64[j][p];
-        }
+        // T is the layout's own type (float for FP32 input), so no conversion
+        for (int j = 0; j < r.d; ++j) xo[j][t] = r.in_f32 ? (T)r.xs32[j][p] : (T)r.xs64[j][p];
         if (w) w[t] = r.ws[p];
         ++t;
     }
