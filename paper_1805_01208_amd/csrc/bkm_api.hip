@@ -707,7 +707,7 @@ int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int3
     for (int i = 0; i < 4; ++i) z.add<int32_t>((size_t)k);
     z.add<unsigned long long>((size_t)k);
     z.add<long long>(4);
-    z.add<int>(4);
+    z.add<int>(8);
     z.add<double>(8);
     for (int i = 0; i < 3; ++i) z.add<int32_t>((size_t)n);
     Arena a;
@@ -724,9 +724,10 @@ int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int3
     long long* sc = a.take<long long>(4);
     g.cut2 = sc;
     g.sums = sc + 1;
-    int* ints = a.take<int>(4);
+    int* ints = a.take<int>(8);
     g.bad = ints;
-    int32_t* cnt = ints + 1;   // frontier counts
+    int32_t* cnt = ints + 1;       // frontier counts, three in rotation
+    int32_t* nlevels = ints + 4;   // levels with a non-empty frontier
     double* summary = a.take<double>(8);
     int32_t* dist = a.take<int32_t>((size_t)n);
     int32_t* qa = a.take<int32_t>((size_t)n);
@@ -735,37 +736,39 @@ int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int3
     HIPCHK(hipMemsetAsync(g.size, 0, (size_t)k * sizeof(int32_t), s));
     HIPCHK(launch_fill_i32(g.seed, k, INT32_MAX, s));
     HIPCHK(hipMemsetAsync(sc, 0, 4 * sizeof(long long), s));
-    HIPCHK(hipMemsetAsync(ints, 0, 4 * sizeof(int), s));
+    HIPCHK(hipMemsetAsync(ints, 0, 8 * sizeof(int), s));
     HIPCHK(launch_gm_vertex(n, nnz, row_ptr, col, assignment, k, g, s));
     int hb = 0;
     HIPCHK(hipMemcpyAsync(&hb, g.bad, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (hb) return fail(BKM_EINVAL, "assignment outside [0, k), or row_ptr/col outside the graph");
 
-    // two breadth-first sweeps over all blocks at once; the host reads the
-    // frontier size after every level
-    int levels = 0;
+    // two breadth-first sweeps over all blocks at once.  Levels are enqueued
+    // in batches of kBfsBatch, each reading its frontier size on the device;
+    // the host reads the size left after a batch, and the levels past the
+    // end of a search do nothing.
+    constexpr int kBfsBatch = 32;
     for (int sweep = 0; sweep < 2; ++sweep) {
         HIPCHK(launch_fill_i32(dist, n, -1, s));
-        HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t), s));
+        HIPCHK(hipMemsetAsync(cnt, 0, 3 * sizeof(int32_t), s));
         HIPCHK(launch_bfs_sources(k, g, sweep, dist, qa, cnt, s));
-        int32_t f = 0;
-        HIPCHK(hipMemcpyAsync(&f, cnt, sizeof(f), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        int32_t* cur = qa;
-        int32_t* nxt = qb;
-        for (int32_t level = 0; f > 0; ++level) {
-            if (level >= n) return fail(BKM_EHIP, "breadth-first search did not end");
-            HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t), s));
-            HIPCHK(launch_bfs_level(row_ptr, col, assignment, g, cur, f, level, dist, nxt, cnt, s));
-            HIPCHK(hipMemcpyAsync(&f, cnt, sizeof(f), hipMemcpyDeviceToHost, s));
+        int32_t f = 1;
+        for (int64_t level = 0; f > 0;) {
+            if (level >= n + kBfsBatch) return fail(BKM_EHIP, "breadth-first search did not end");
+            for (int b = 0; b < kBfsBatch; ++b, ++level) {
+                int32_t* cur = (level & 1) ? qb : qa;
+                int32_t* nxt = (level & 1) ? qa : qb;
+                HIPCHK(launch_bfs_level(row_ptr, col, assignment, g, cur, cnt, (int32_t)level, dist,
+                                        nxt, nlevels, n, s));
+            }
+            HIPCHK(hipMemcpyAsync(&f, cnt + level % 3, sizeof(f), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             if (f < 0 || f > n) return fail(BKM_EHIP, "frontier of %d vertices", f);
-            std::swap(cur, nxt);
-            ++levels;
         }
         if (sweep == 0) HIPCHK(launch_gm_connected(k, g, s));
     }
+    int levels = 0;
+    HIPCHK(hipMemcpyAsync(&levels, nlevels, sizeof(levels), hipMemcpyDeviceToHost, s));
     HIPCHK(launch_gm_final(k, g, diameter_out, comm_out, summary, s));
     double hs[8];
     long long hl[4];

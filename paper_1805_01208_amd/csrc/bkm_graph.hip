@@ -22,6 +22,8 @@
 //     them all), two sweeps.
 #include <climits>
 
+#include <algorithm>
+
 #include "bkm_internal.h"
 
 namespace bkm {
@@ -397,56 +399,72 @@ __global__ __launch_bounds__(kBlock) void k_bfs_sources(int k, GraphDev g, int s
 // their places in the next frontier with one atomic per step.
 constexpr int kBfsLanes = 8;
 
+// The frontier size comes from device memory (counts[level % 3]), so the
+// host can enqueue many levels without reading it: a fixed grid walks the
+// frontier, and a level whose frontier is empty does nothing.  The level
+// adds to counts[(level + 1) % 3], which the level before cleared, and
+// clears counts[(level + 2) % 3] for the level after; `levels` counts the
+// levels with a non-empty frontier.
 __global__ __launch_bounds__(kBlock) void k_bfs_level(const int64_t* row_ptr, const int32_t* col,
                                                       const int32_t* A, GraphDev g,
-                                                      const int32_t* frontier, int32_t fcount,
+                                                      const int32_t* frontier, int32_t* counts,
                                                       int32_t level, int32_t* dist, int32_t* next,
-                                                      int32_t* ncount)
+                                                      int32_t* levels)
 {
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t i = t / kBfsLanes;
-    const int lane = threadIdx.x % kWave;
-    const bool act = i < fcount;
-    int32_t u = 0, a = -1;
-    int64_t e = 0, end = 0;
-    if (act) {
-        u = frontier[i];
-        a = A[u];
-        e = row_ptr[u] + t % kBfsLanes;
-        end = row_ptr[(int64_t)u + 1];
+    const int32_t fcount = counts[level % 3];
+    int32_t* ncount = counts + (level + 1) % 3;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        counts[(level + 2) % 3] = 0;
+        if (fcount > 0) atomicAdd(levels, 1);
     }
+    const int lane = threadIdx.x % kWave;
     const unsigned long long below = (1ULL << lane) - 1ULL;
-    while (__ballot(e < end) != 0ULL) {
-        bool claim = false;
-        int32_t v = 0;
-        if (e < end) {
-            v = col[e];
-            e += kBfsLanes;
-            claim = A[v] == a && dist[v] == -1 && atomicCAS(&dist[v], -1, level + 1) == -1;
+    const int64_t per_block = kBlock / kBfsLanes;
+    // block-uniform walk over the frontier, kBlock / kBfsLanes vertices per block and step
+    for (int64_t i0 = (int64_t)blockIdx.x * per_block; i0 < fcount;
+         i0 += (int64_t)gridDim.x * per_block) {
+        const int64_t i = i0 + threadIdx.x / kBfsLanes;
+        const bool act = i < fcount;
+        int32_t u = 0, a = -1;
+        int64_t e = 0, end = 0;
+        if (act) {
+            u = frontier[i];
+            a = A[u];
+            e = row_ptr[u] + threadIdx.x % kBfsLanes;
+            end = row_ptr[(int64_t)u + 1];
         }
-        const unsigned long long b = __ballot(claim);
-        if (b == 0ULL) continue;
-        int base = 0;
-        if (lane == __builtin_ctzll(b)) base = atomicAdd(ncount, (int)__popcll(b));
-        base = __shfl(base, __builtin_ctzll(b), kWave);
-        if (claim) next[base + (int)__popcll(b & below)] = v;
-        // block counters: one update per distinct block among the claims
-        unsigned long long pend = b;
-        while (pend) {
-            const int leader = __builtin_ctzll(pend);
-            const int la = __shfl(a, leader, kWave);
-            const bool mine = claim && a == la;
-            const unsigned long long mm = __ballot(mine);
-            unsigned long long key = mine ? far_key(level + 1, v) : 0ULL;
-            for (int m = kWave / 2; m > 0; m >>= 1) {
-                const unsigned long long o = __shfl_xor(key, m, kWave);
-                key = o > key ? o : key;
+        while (__ballot(e < end) != 0ULL) {
+            bool claim = false;
+            int32_t v = 0;
+            if (e < end) {
+                v = col[e];
+                e += kBfsLanes;
+                claim = A[v] == a && dist[v] == -1 && atomicCAS(&dist[v], -1, level + 1) == -1;
             }
-            if (lane == leader) {
-                atomicAdd(&g.reached[la], (int)__popcll(mm));
-                atomicMax(&g.far[la], key);
+            const unsigned long long b = __ballot(claim);
+            if (b == 0ULL) continue;
+            int base = 0;
+            if (lane == __builtin_ctzll(b)) base = atomicAdd(ncount, (int)__popcll(b));
+            base = __shfl(base, __builtin_ctzll(b), kWave);
+            if (claim) next[base + (int)__popcll(b & below)] = v;
+            // block counters: one update per distinct block among the claims
+            unsigned long long pend = b;
+            while (pend) {
+                const int leader = __builtin_ctzll(pend);
+                const int la = __shfl(a, leader, kWave);
+                const bool mine = claim && a == la;
+                const unsigned long long mm = __ballot(mine);
+                unsigned long long key = mine ? far_key(level + 1, v) : 0ULL;
+                for (int m = kWave / 2; m > 0; m >>= 1) {
+                    const unsigned long long o = __shfl_xor(key, m, kWave);
+                    key = o > key ? o : key;
+                }
+                if (lane == leader) {
+                    atomicAdd(&g.reached[la], (int)__popcll(mm));
+                    atomicMax(&g.far[la], key);
+                }
+                pend &= ~mm;
             }
-            pend &= ~mm;
         }
     }
 }
@@ -618,12 +636,14 @@ hipError_t launch_bfs_sources(int k, const GraphDev& g, int second, int32_t* dis
 }
 
 hipError_t launch_bfs_level(const int64_t* row_ptr, const int32_t* col, const int32_t* A,
-                            const GraphDev& g, const int32_t* frontier, int32_t fcount,
-                            int32_t level, int32_t* dist, int32_t* next, int32_t* ncount,
-                            hipStream_t s)
+                            const GraphDev& g, const int32_t* frontier, int32_t* counts,
+                            int32_t level, int32_t* dist, int32_t* next, int32_t* levels,
+                            int64_t n, hipStream_t s)
 {
-    k_bfs_level<<<nblocks((int64_t)fcount * kBfsLanes, kBlock), kBlock, 0, s>>>(
-        row_ptr, col, A, g, frontier, fcount, level, dist, next, ncount);
+    // enough blocks for a frontier of n vertices in one step, at most 2048
+    const unsigned grid = (unsigned)std::min<int64_t>(2048, nblocks(n * kBfsLanes, kBlock));
+    k_bfs_level<<<grid, kBlock, 0, s>>>(row_ptr, col, A, g, frontier, counts, level, dist, next,
+                                        levels);
     return hipGetLastError();
 }
 

@@ -401,10 +401,11 @@ hipError_t launch_gm_vertex(int64_t n, int64_t nnz, const int64_t* row_ptr, cons
                             const int32_t* A, int k, const GraphDev& g, hipStream_t s);
 hipError_t launch_bfs_sources(int k, const GraphDev& g, int second, int32_t* dist,
                               int32_t* queue, int32_t* count, hipStream_t s);
+// one breadth-first level; its frontier size is counts[level % 3] on the device
 hipError_t launch_bfs_level(const int64_t* row_ptr, const int32_t* col, const int32_t* A,
-                            const GraphDev& g, const int32_t* frontier, int32_t fcount,
-                            int32_t level, int32_t* dist, int32_t* next, int32_t* ncount,
-                            hipStream_t s);
+                            const GraphDev& g, const int32_t* frontier, int32_t* counts,
+                            int32_t level, int32_t* dist, int32_t* next, int32_t* levels,
+                            int64_t n, hipStream_t s);
 hipError_t launch_gm_connected(int k, const GraphDev& g, hipStream_t s);
 hipError_t launch_gm_final(int k, const GraphDev& g, int32_t* diam_out, int64_t* comm_out,
                            double* summary, hipStream_t s);
