@@ -286,7 +286,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design, not part of this build).", file=sys.stderr)
+              "(the library has no multi-GPU sharding; it is described as a design only).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
