@@ -239,3 +239,50 @@ def test_erosion_off_is_the_loop_of_pinned_steps():
     assert np.array_equal(r["influence"], I)
     e = oracle.balanced_kmeans(X, k, eps, max_iter=4, max_balance_iter=3, delta_threshold=dthr)
     assert not np.array_equal(e["influence"], I)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_erosion_on_is_the_loop_of_pinned_steps(weighted):
+    """With erosion on (the default of every run), the run is the loop of the
+    pinned single steps with erosion placed as Sec. 4.2 and Alg. 2 read:
+    AssignAndBalance, new centers; on convergence the new centers are
+    returned as they are; otherwise beta is taken from the round's final
+    assignment, the influence is eroded by the round's movements, and only
+    then do the new centers replace the old ones.  Redone here in Python
+    around those steps, for unit and node weights, bit for bit."""
+    rng = np.random.default_rng(37 + weighted)
+    n, k, eps, rounds, sweeps = 3000, 7, 0.01, 50, 3
+    X = [rng.random(n), rng.random(n)]
+    W = rng.lognormal(0.0, 0.5, n) if weighted else None
+    # a threshold the run meets with a movement that is not zero, so that an
+    # erosion on the converged round would change the returned influence
+    dthr = 1e-3
+    r = oracle.balanced_kmeans(X, k, eps, W=W, max_iter=rounds, max_balance_iter=sweeps,
+                               delta_threshold=dthr)
+    C, _, _ = oracle.init_centers_sfc(X, k, 16)
+    I = np.ones(k)
+    lm = oracle.lmax(n, k, eps, W)
+    target = oracle.total_weight(n, W) / k
+    eroded = made = 0
+    for _ in range(rounds):
+        made += 1
+        for _ in range(sweeps):
+            A, _, _ = oracle.assign(X, C, I)
+            bw = oracle.block_weights(A, W, k)
+            ok, I = oracle.balance_step(bw, 2, lm, target, I)
+            if ok:
+                break
+        Cn, delta = oracle.new_centers(X, W, A, C)
+        if delta.max() < dthr:
+            assert delta.max() > 0.0
+            C = Cn
+            break
+        I = oracle.erode(delta, oracle.beta(X, A, k), I)
+        eroded += 1
+        C = Cn
+    assert eroded >= 2                       # erosion acted between rounds
+    assert np.array_equal(r["A"], A)
+    assert np.array_equal(r["centers"], C)
+    assert np.array_equal(r["influence"], I)
+    assert r["info"]["rounds"] == made < rounds
+    assert r["info"]["converged"] == 1       # the last round returned without erosion
