@@ -48,7 +48,7 @@ def run_and_compare(X, k, precision, use_bounds, tile, steps=6, seed=0):
     Xw = widened(X)
     for s in range(steps):
         Ao, best, second = oracle.assign(Xw, Cs[s], Is[s])
-        assert_assignment_parity(A[s], Ao, best, second, f"step {s}")
+        assert_assignment_parity(A[s], Ao, best, second, f"step {s}", Xw, Cs[s], Is[s])
         assert np.array_equal(bw[s], np.bincount(A[s], minlength=k).astype(np.float64))
     return info
 
@@ -122,3 +122,69 @@ def test_sweep_far_apart_clusters(d):
     for prec in ("f64", "f32_recheck"):
         info = run_and_compare(X, 60, prec, True, 1024, steps=4, seed=d)
         assert info["overflow_tiles"] == 0
+
+
+def near_tie_cloud(d, n_tie, n_bg, k, seed):
+    """Random points and centers, plus n_tie points placed next to the
+    bisector of two nearby centers (unit influence) at relative gaps
+    (second - best) / best drawn log-uniformly from [1e-9, 1e-6]: inside the
+    window where the FP32 screen must hand the decision to FP64 (Sec. 4.2
+    argmin; the recheck threshold is a 1e-5 relative gap)."""
+    rng = np.random.default_rng(seed)
+    C = rng.random((k, d))
+    C[1] = C[0] + 0.02 * rng.normal(size=d)
+    h = 0.5 * np.linalg.norm(C[1] - C[0])
+    nvec = (C[1] - C[0]) / (2.0 * h)
+    mid = 0.5 * (C[0] + C[1])
+    g = np.exp(rng.uniform(np.log(1e-9), np.log(1e-6), n_tie)) * rng.choice([-1.0, 1.0], n_tie)
+    # a random offset perpendicular to the axis of the two centers
+    u = rng.normal(size=(n_tie, d))
+    u -= np.outer(u @ nvec, nvec)
+    u *= (rng.uniform(0.0, 0.01, n_tie) / np.linalg.norm(u, axis=1))[:, None]
+    dist2 = h * h + np.sum(u * u, axis=1)
+    t = g * dist2 / (2.0 * h)          # (d1 - d0) / d0 ~= 2 t h / dist^2
+    P = mid + u + t[:, None] * nvec
+    bg = rng.random((n_bg, d))
+    X = [np.concatenate([P[:, j], bg[:, j]]) for j in range(d)]
+    return X, C
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("precision", ["f64", "f32_recheck"])
+def test_sweep_near_ties_recheck(d, precision):
+    """Points at relative gaps of 1e-9..1e-6 between their two nearest centers
+    get the oracle's exact assignment; with the FP32 screen they must go
+    through the FP64 recheck."""
+    from paper_1805_01208_amd import bkm
+    X, C = near_tie_cloud(d, 3000, 20000, 32, 70 + d)
+    k = C.shape[0]
+    Is = np.ones((1, k))
+    print(f"case near ties d={d} {precision}", flush=True)
+    A, _, info = bkm.assign_sweeps(cuda(X), torch.from_numpy(C[None]), torch.from_numpy(Is),
+                                   precision=precision)
+    Ao, best, second = oracle.assign(X, C, Is[0])
+    gap = (second - best) / best
+    tie = np.flatnonzero(gap < 1e-5)
+    assert tie.size > 2000 and gap.min() > 1e-12
+    assert np.array_equal(A[0].cpu().numpy(), Ao)
+    if precision == "f32_recheck":
+        assert info["rechecked"] >= tie.size
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32_recheck"])
+def test_sweep_overflowed_tiles(precision):
+    """k far above the 128 candidate records a tile keeps: tiles overflow and
+    are swept in FP64 over their super-tile list; results stay exact."""
+    rng = np.random.default_rng(5)
+    n = 40000
+    X = [rng.random(n), rng.random(n)]
+    from paper_1805_01208_amd import bkm
+    Cs, Is = state_sequence(X, 4000, 3, 11)
+    print(f"case overflow {precision}", flush=True)
+    A, _, info = bkm.assign_sweeps(cuda(X), torch.from_numpy(Cs), torch.from_numpy(Is),
+                                   precision=precision, tile_points=1024)
+    assert info["overflow_tiles"] > 0
+    A = A.cpu().numpy()
+    for s in range(3):
+        Ao, best, second = oracle.assign(X, Cs[s], Is[s])
+        assert_assignment_parity(A[s], Ao, best, second, f"step {s}", X, Cs[s], Is[s])
