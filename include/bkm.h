@@ -250,6 +250,23 @@ int bkm_partition_stats(const bkm_points* pts, const int32_t* assignment, int32_
                         double epsilon, const double* target_sizes, double* block_weights_out,
                         double* centers_out, bkm_stats* out, void* stream);
 
+/* bkm_partition_stats without any device or host allocation, for callers
+ * that cannot allocate: code under stream capture into a HIP graph, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, results
+ * and errors as bkm_partition_stats, plus BKM_EINVAL for k above
+ * BKM_NOALLOC_MAX_K.  Its workspace is one static device array of
+ * BKM_NOALLOC_SCRATCH_BYTES per device, held from the first call on a device
+ * until the process ends; every call on a device shares it, so calls that
+ * overlap on one device (different streams or threads) race and must be
+ * serialised by the caller.  The call returns after the stream has finished
+ * (it fills a host struct). */
+#define BKM_NOALLOC_MAX_K 65536
+#define BKM_NOALLOC_SCRATCH_BYTES (8 << 20)
+int bkm_partition_stats_noalloc(const bkm_points* pts, const int32_t* assignment, int32_t k,
+                                double epsilon, const double* target_sizes,
+                                double* block_weights_out, double* centers_out, bkm_stats* out,
+                                void* stream);
+
 /* ---------------------------------------------------------------------------
  * Graph-quality evaluation (Sec. 2, the block measures; Sec. 5.2, Metrics).
  * The paper measures partitions on the meshes' graphs; these calls build

@@ -75,7 +75,7 @@ class BkmError(RuntimeError):
 _LIB = None
 FUNCTIONS = ("bkm_default_params", "bkm_init_centers_sfc", "bkm_balanced_kmeans",
              "bkm_balanced_kmeans_batched", "bkm_assign_sweeps", "bkm_partition_stats",
-             "bkm_knn", "bkm_knn_graph", "bkm_graph_metrics", "bkm_last_error")
+             "bkm_partition_stats_noalloc", "bkm_knn", "bkm_knn_graph", "bkm_graph_metrics", "bkm_last_error")
 
 
 def lib():
@@ -96,6 +96,7 @@ def lib():
                                         C.c_int32, C.c_int32, P, P, C.POINTER(Info), P]
         L.bkm_partition_stats.argtypes = [C.POINTER(Points), P, C.c_int32, C.c_double, P, P, P,
                                           C.POINTER(Stats), P]
+        L.bkm_partition_stats_noalloc.argtypes = L.bkm_partition_stats.argtypes
         L.bkm_balanced_kmeans_batched.argtypes = [C.POINTER(Points), C.POINTER(Params), C.c_int32,
                                                   C.POINTER(P), C.POINTER(P), C.POINTER(Info), P]
         L.bkm_knn.argtypes = [C.POINTER(Points), C.c_int32, P, C.POINTER(KnnInfo), P]
@@ -105,7 +106,8 @@ def lib():
         L.bkm_last_error.argtypes = []
         L.bkm_last_error.restype = C.c_char_p
         for f in ("bkm_init_centers_sfc", "bkm_balanced_kmeans", "bkm_assign_sweeps",
-                  "bkm_partition_stats", "bkm_balanced_kmeans_batched", "bkm_knn",
+                  "bkm_partition_stats", "bkm_partition_stats_noalloc",
+                  "bkm_balanced_kmeans_batched", "bkm_knn",
                   "bkm_knn_graph", "bkm_graph_metrics"):
             getattr(L, f).restype = C.c_int
         _LIB = L
@@ -316,6 +318,25 @@ def partition_stats(X, A, k, eps=0.03, W=None, target_sizes=None):
     st = Stats()
     _check(lib().bkm_partition_stats(C.byref(pts), _ptr(A.contiguous()), int(k), float(eps),
                                      _ptr(ts), _ptr(bw), _ptr(cen), C.byref(st), _stream()))
+    res = {f: getattr(st, f) for f, _ in Stats._fields_}
+    res.update(block_weights=bw, centers=cen)
+    return res
+
+
+def partition_stats_noalloc(X, A, k, eps=0.03, W=None, target_sizes=None, bw=None, cen=None):
+    """partition_stats through the no-allocation entry point; bw [k] and cen
+    [k, d] float64 device tensors may be passed in (allocated here if not)."""
+    dev = X[0].device
+    pts = make_points(X, W)
+    ts = _targets(target_sizes, k, dev)
+    if bw is None:
+        bw = torch.empty(k, dtype=torch.float64, device=dev)
+    if cen is None:
+        cen = torch.empty((k, pts.d), dtype=torch.float64, device=dev)
+    st = Stats()
+    _check(lib().bkm_partition_stats_noalloc(C.byref(pts), _ptr(A.contiguous()), int(k),
+                                             float(eps), _ptr(ts), _ptr(bw), _ptr(cen),
+                                             C.byref(st), _stream()))
     res = {f: getattr(st, f) for f, _ in Stats._fields_}
     res.update(block_weights=bw, centers=cen)
     return res

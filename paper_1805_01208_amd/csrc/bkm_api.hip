@@ -73,6 +73,28 @@ struct Sizes {
     void add(size_t count) { total += (count * sizeof(T) + 255) & ~size_t(255); }
 };
 
+// Static workspace of the no-allocation entry points: every device the
+// library runs on holds one copy until the process ends.  Host code never
+// uses the symbol itself as an address (on the host it is only a stand-in):
+// its device address is looked up once per device and kept.
+static __device__ __align__(256) unsigned char scratch[BKM_NOALLOC_SCRATCH_BYTES];
+
+int scratch_address(char** out)
+{
+    static std::atomic<char*> addr[64];
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(BKM_EINVAL, "device %d outside [0, 64)", dev);
+    char* p = addr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        HIPCHK(hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(BKM_EHIP, "hipGetSymbolAddress returned NULL");
+        addr[dev].store(p, std::memory_order_release);
+    }
+    *out = p;
+    return BKM_OK;
+}
+
 // Keep freed stream-ordered memory in the current device's default pool
 // (set once per device; devices 0..63).
 void keep_pool_memory()
@@ -584,6 +606,89 @@ int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_i
 
 }  // namespace
 
+// ------------------------------------------------------- partition stats
+int check_stats_args(const bkm_points* pts, const int32_t* assignment, int32_t k, double eps,
+                     const bkm_stats* out)
+{
+    int rc = check_points(pts);
+    if (rc) return rc;
+    if (k < 1) return fail(BKM_EINVAL, "k = %d < 1", k);
+    if (!assignment || !out) return fail(BKM_EINVAL, "assignment/out is NULL");
+    if (!(eps >= 0.0)) return fail(BKM_EINVAL, "epsilon must be >= 0");
+    return BKM_OK;
+}
+
+// Device workspace of the statistics: state, reduction buffer (bounding-box
+// and objective partials of at most 1024 blocks), centers, fixed-point sums,
+// the six results and, with target sizes, per-block targets and limits.
+size_t stats_workspace(int k, int d, bool targets)
+{
+    Sizes z;
+    z.add<DevState>(1);
+    z.add<double>(std::max<int64_t>(8192, k));
+    z.add<double>((size_t)k * d);
+    z.add<long long>((size_t)k * kAcc);
+    z.add<double>(8);
+    if (targets) {
+        z.add<double>((size_t)k);
+        z.add<double>((size_t)k);
+        z.add<double>((size_t)k + 1);
+    }
+    return z.total;
+}
+
+// The statistics on a workspace of stats_workspace() bytes at `ws`.  With
+// `noalloc` nothing is allocated: the state is cleared by a fill kernel and
+// read back into a stack copy (no pinned staging buffer).
+int stats_core(const bkm_points* pts, const int32_t* assignment, int32_t k, double epsilon,
+               const double* target_sizes, double* block_weights_out, double* centers_out,
+               bkm_stats* out, hipStream_t s, char* ws, bool noalloc)
+{
+    RunDev r;
+    plan(r, pts, k, 1024, 16, BKM_PREC_F64, 0, 0.0);
+    Arena a;   // carves only: base is handed back before it would be freed
+    a.base = ws;
+    r.st = a.take<DevState>(1);
+    r.red = a.take<double>(std::max<int64_t>(8192, k));
+    r.C = a.take<double>((size_t)k * r.d);
+    r.acc = a.take<long long>((size_t)k * kAcc);
+    double* out6 = a.take<double>(8);
+    if (target_sizes) {
+        r.tsz = target_sizes;
+        r.tT = a.take<double>((size_t)k);
+        r.tL = a.take<double>((size_t)k);
+        r.tpre = a.take<double>((size_t)k + 1);
+    }
+    a.base = nullptr;
+    static_assert(sizeof(DevState) % 4 == 0, "state is cleared as 32-bit words");
+    HIPCHK(launch_fill_i32((int32_t*)r.st, (int64_t)(sizeof(DevState) / 4), 0, s));
+    HIPCHK(launch_fill_i32((int32_t*)r.acc, (int64_t)k * kAcc * 2, 0, s));
+    HIPCHK(launch_bbox(r, 16, s));
+    if (r.tsz) HIPCHK(launch_target_prep(r, epsilon, s));
+    HIPCHK(launch_stats(r, assignment, epsilon, block_weights_out, centers_out, out6, s));
+    double h6[8];
+    HIPCHK(hipMemcpyAsync(h6, out6, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+    DevState h;
+    if (noalloc) {
+        HIPCHK(hipMemcpyAsync(&h, r.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    } else {
+        HIPCHK(hipStreamSynchronize(s));
+        int rc = read_state(r, s, &h);
+        if (rc) return rc;
+    }
+    if (h.bad_data & 4)
+        return fail(BKM_EINVAL, "target_sizes must be finite and > 0, with a finite sum");
+    if (h.bad_data & 2) return fail(BKM_EINVAL, "assignment outside [0, k)");
+    if (h.bad_data & 1) return fail(BKM_EDATA, "non-finite coordinate or bad weight");
+    out->imbalance = h6[0];
+    out->objective = h6[1];
+    out->l_max = h6[2];
+    out->empty_blocks = (int32_t)h6[3];
+    out->overloaded_blocks = (int32_t)h6[4];
+    return BKM_OK;
+}
+
 extern "C" {
 
 void bkm_default_params(bkm_params* p, int32_t k)
@@ -886,61 +991,36 @@ int bkm_partition_stats(const bkm_points* pts, const int32_t* assignment, int32_
                         double* centers_out, bkm_stats* out, void* stream)
 {
     g_err.clear();
-    int rc = check_points(pts);
+    int rc = check_stats_args(pts, assignment, k, epsilon, out);
     if (rc) return rc;
-    if (k < 1) return fail(BKM_EINVAL, "k = %d < 1", k);
-    if (!assignment || !out) return fail(BKM_EINVAL, "assignment/out is NULL");
-    if (!(epsilon >= 0.0)) return fail(BKM_EINVAL, "epsilon must be >= 0");
     hipStream_t s = (hipStream_t)stream;
     keep_pool_memory();
-    RunDev r;
-    plan(r, pts, k, 1024, 16, BKM_PREC_F64, 0, 0.0);
-    // statistics need only the state, the reduction buffer, centers and sums
-    Sizes z;
-    z.add<DevState>(1);
-    z.add<double>(std::max<int64_t>(8192, k));
-    z.add<double>((size_t)k * r.d);
-    z.add<long long>((size_t)k * kAcc);
-    z.add<double>(8);
-    if (target_sizes) {
-        z.add<double>((size_t)k);
-        z.add<double>((size_t)k);
-        z.add<double>((size_t)k + 1);
-    }
+    const size_t bytes = stats_workspace(k, pts->d, target_sizes != nullptr);
     Arena a;
     a.s = s;
-    HIPCHK(hipMallocAsync((void**)&a.base, z.total, s));
-    r.st = a.take<DevState>(1);
-    r.red = a.take<double>(std::max<int64_t>(8192, k));
-    r.C = a.take<double>((size_t)k * r.d);
-    r.acc = a.take<long long>((size_t)k * kAcc);
-    double* out6 = a.take<double>(8);
-    if (target_sizes) {
-        r.tsz = target_sizes;
-        r.tT = a.take<double>((size_t)k);
-        r.tL = a.take<double>((size_t)k);
-        r.tpre = a.take<double>((size_t)k + 1);
-    }
-    HIPCHK(hipMemsetAsync(r.st, 0, sizeof(DevState), s));
-    HIPCHK(hipMemsetAsync(r.acc, 0, (size_t)k * kAcc * sizeof(long long), s));
-    HIPCHK(launch_bbox(r, 16, s));
-    if (r.tsz) HIPCHK(launch_target_prep(r, epsilon, s));
-    HIPCHK(launch_stats(r, assignment, epsilon, block_weights_out, centers_out, out6, s));
-    double h6[8];
-    HIPCHK(hipMemcpyAsync(h6, out6, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    DevState h;
-    if ((rc = read_state(r, s, &h))) return rc;
-    if (h.bad_data & 4)
-        return fail(BKM_EINVAL, "target_sizes must be finite and > 0, with a finite sum");
-    if (h.bad_data & 2) return fail(BKM_EINVAL, "assignment outside [0, k)");
-    if (h.bad_data & 1) return fail(BKM_EDATA, "non-finite coordinate or bad weight");
-    out->imbalance = h6[0];
-    out->objective = h6[1];
-    out->l_max = h6[2];
-    out->empty_blocks = (int32_t)h6[3];
-    out->overloaded_blocks = (int32_t)h6[4];
-    return BKM_OK;
+    HIPCHK(hipMallocAsync((void**)&a.base, bytes, s));
+    return stats_core(pts, assignment, k, epsilon, target_sizes, block_weights_out, centers_out,
+                      out, s, a.base, false);
+}
+
+int bkm_partition_stats_noalloc(const bkm_points* pts, const int32_t* assignment, int32_t k,
+                                double epsilon, const double* target_sizes,
+                                double* block_weights_out, double* centers_out, bkm_stats* out,
+                                void* stream)
+{
+    g_err.clear();
+    int rc = check_stats_args(pts, assignment, k, epsilon, out);
+    if (rc) return rc;
+    if (k > BKM_NOALLOC_MAX_K)
+        return fail(BKM_EINVAL, "k = %d above the no-allocation limit %d", k, BKM_NOALLOC_MAX_K);
+    const size_t bytes = stats_workspace(k, pts->d, target_sizes != nullptr);
+    if (bytes > sizeof(scratch))
+        return fail(BKM_EINVAL, "workspace of %zu bytes exceeds the static %zu", bytes,
+                    sizeof(scratch));
+    char* ws = nullptr;
+    if ((rc = scratch_address(&ws))) return rc;
+    return stats_core(pts, assignment, k, epsilon, target_sizes, block_weights_out, centers_out,
+                      out, (hipStream_t)stream, ws, true);
 }
 
 int bkm_balanced_kmeans_batched(const bkm_points* pts, const bkm_params* prm, int32_t count,
