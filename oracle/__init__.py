@@ -36,7 +36,7 @@ class OracleGraphStats(C.Structure):
     _fields_ = [
         ("edge_cut", C.c_int64), ("max_comm", C.c_int64), ("total_comm", C.c_int64),
         ("max_diameter", C.c_int32), ("disconnected_blocks", C.c_int32),
-        ("harmonic_diameter", C.c_double),
+        ("exact_blocks", C.c_int32), ("harmonic_diameter", C.c_double),
     ]
 
 
@@ -78,8 +78,9 @@ def lib():
         L.oracle_knn.argtypes = [I64, C.c_int, P, C.c_int, P]
         L.oracle_knn_of.argtypes = [I64, C.c_int, P, C.c_int, I64, P, P]
         L.oracle_knn_symmetrize.argtypes = [I64, C.c_int, P, P, P, P]
-        L.oracle_graph_metrics.argtypes = [I64, P, P, P, C.c_int, P, P,
+        L.oracle_graph_metrics.argtypes = [I64, P, P, P, C.c_int, P, P, P,
                                            C.POINTER(OracleGraphStats)]
+        L.oracle_ifub_trace.argtypes = [I64, P, P, P]
         L.oracle_num_threads.argtypes = []
         _ = I32
         _LIB = L
@@ -359,9 +360,23 @@ def graph_metrics(row_ptr, col, A, k):
     n = A.shape[0]
     comm = np.empty(k, dtype=np.int64)
     diam = np.empty(k, dtype=np.int32)
+    dub = np.empty(k, dtype=np.int32)
     st = OracleGraphStats()
     _check(lib().oracle_graph_metrics(n, _ptr(row_ptr), _ptr(col), _ptr(A), int(k), _ptr(comm),
-                                      _ptr(diam), C.byref(st)), "graph_metrics")
+                                      _ptr(diam), _ptr(dub), C.byref(st)), "graph_metrics")
     out = {f: getattr(st, f) for f, _ in OracleGraphStats._fields_}
-    out.update(comm=comm, diameter=diam)
+    out.update(comm=comm, diameter=diam, diameter_ub=dub)
     return out
+
+
+def ifub_trace(row_ptr, col):
+    """The steps of the diameter bound (4-sweep, then up to 3 iFUB rounds) on
+    a connected graph taken as one block: dict of a1, b1, r2, a2, b2, u, l,
+    rounds, lb, ub."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    t = np.zeros(10, dtype=np.int64)
+    _check(lib().oracle_ifub_trace(row_ptr.shape[0] - 1, _ptr(row_ptr), _ptr(col), _ptr(t)),
+           "ifub_trace")
+    return dict(zip(("a1", "b1", "r2", "a2", "b2", "u", "l", "rounds", "lb", "ub"),
+                    (int(v) for v in t)))

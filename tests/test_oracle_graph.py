@@ -147,7 +147,11 @@ def test_metrics_match_networkx_on_a_knn_graph():
             continue
         exact = nx.diameter(H)
         assert exact >= m["diameter"][b] >= math.ceil(exact / 2)
-        # the double sweep itself, with scipy's breadth-first distances
+        assert m["diameter_ub"][b] >= exact
+        if m["diameter_ub"][b] == m["diameter"][b]:
+            assert m["diameter"][b] == exact
+        # never below the double sweep from the block's lowest vertex, with
+        # scipy's breadth-first distances
         idx = sorted(blocks[b])
         pos = {v: i for i, v in enumerate(idx)}
         rows = [pos[u] for u in idx for v in G[u] if v in pos]
@@ -155,7 +159,84 @@ def test_metrics_match_networkx_on_a_knn_graph():
         M = csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(len(idx), len(idx)))
         d0 = shortest_path(M, unweighted=True, indices=0)
         far = int(np.flatnonzero(d0 == d0.max())[0])
-        assert m["diameter"][b] == int(shortest_path(M, unweighted=True, indices=far).max())
+        assert m["diameter"][b] >= int(shortest_path(M, unweighted=True, indices=far).max())
+
+
+def _edges_csr(n, edges):
+    rows = [[] for _ in range(n)]
+    for u, v in edges:
+        rows[u].append(v)
+        rows[v].append(u)
+    rp = np.zeros(n + 1, dtype=np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    return rp, np.array([v for r in rows for v in sorted(r)], dtype=np.int32)
+
+
+def _golden_traces():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "ifub_traces.txt")
+    out = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        out[f[0]] = dict(zip(("a1", "b1", "r2", "a2", "b2", "u", "l", "rounds", "lb", "ub"),
+                             map(int, f[1:])))
+    return out
+
+
+def test_diameter_bound_hand_traces():
+    """4-sweep and iFUB rounds (Sec. 5.2, Metrics) traced by hand on three
+    graphs: one where the double sweep from vertex 0 misses the diameter and
+    one round closes the gap, a cycle that becomes exact in its third round,
+    and a cycle still open after three rounds."""
+    gold = _golden_traces()
+    graphs = {
+        "g7": _edges_csr(7, [(0, 4), (0, 6), (1, 4), (1, 6), (2, 6), (3, 6), (5, 6)]),
+        "c12": _edges_csr(12, [(i, (i + 1) % 12) for i in range(12)]),
+        "c14": _edges_csr(14, [(i, (i + 1) % 14) for i in range(14)]),
+    }
+    for name, (rp, col) in graphs.items():
+        assert oracle.ifub_trace(rp, col) == gold[name], name
+        m = oracle.graph_metrics(rp, col, np.zeros(len(rp) - 1, np.int32), 1)
+        assert (m["diameter"][0], m["diameter_ub"][0]) == (gold[name]["lb"], gold[name]["ub"])
+        assert m["exact_blocks"] == (1 if gold[name]["lb"] == gold[name]["ub"] else 0)
+
+
+def test_diameter_bound_exact_on_paths_trees_grids_and_bounds_on_random_graphs():
+    """Equal to the exact diameter (networkx) on paths, random trees and grids,
+    where the first sweeps already reach it; on random connected graphs
+    between the double sweep and the exact value, at most the proven upper
+    bound, and exact whenever lower and upper bound meet."""
+    import networkx as nx
+    rng = np.random.default_rng(44)
+    cases = [nx.path_graph(17), nx.grid_2d_graph(6, 9), nx.grid_2d_graph(1, 5)]
+    cases += [nx.random_labeled_tree(int(rng.integers(2, 60)), seed=int(rng.integers(1 << 30)))
+              for _ in range(20)]
+    for G in cases:
+        G = nx.convert_node_labels_to_integers(G, ordering="sorted")
+        n = G.number_of_nodes()
+        rp, col = _edges_csr(n, list(G.edges()))
+        m = oracle.graph_metrics(rp, col, np.zeros(n, np.int32), 1)
+        assert m["diameter"][0] == nx.diameter(G)
+    seen_gap = 0
+    for t in range(300):
+        n = int(rng.integers(6, 40))
+        G = nx.gnp_random_graph(n, float(rng.uniform(0.06, 0.3)), seed=int(rng.integers(1 << 30)))
+        if not nx.is_connected(G):
+            continue
+        rp, col = _edges_csr(n, list(G.edges()))
+        m = oracle.graph_metrics(rp, col, np.zeros(n, np.int32), 1)
+        exact = nx.diameter(G)
+        lb, ub = int(m["diameter"][0]), int(m["diameter_ub"][0])
+        d0 = nx.single_source_shortest_path_length(G, 0)
+        far = min(v for v in d0 if d0[v] == max(d0.values()))
+        dsweep = max(nx.single_source_shortest_path_length(G, far).values())
+        assert dsweep <= lb <= exact <= ub
+        if lb == ub:
+            assert lb == exact
+        seen_gap += dsweep < exact
+    assert seen_gap > 0
 
 
 def test_invalid_graph_inputs():
