@@ -254,7 +254,8 @@ def graph_bench(args, torch, bkm, cfg, X):
         "graph": {"nnz": nnz, "edge_cut": m["edge_cut"], "max_comm": m["max_comm"],
                   "total_comm": m["total_comm"], "max_diameter": m["max_diameter"],
                   "disconnected_blocks": m["disconnected_blocks"],
-                  "harmonic_diameter": m["harmonic_diameter"], "bfs_levels": m["bfs_levels"]},
+                  "harmonic_diameter": m["harmonic_diameter"], "bfs_levels": m["bfs_levels"],
+                  "exact_blocks": m["exact_blocks"]},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = graph_cpu_baseline(cfg, K, args.cpu_seconds)

@@ -312,30 +312,40 @@ typedef struct {
     double harmonic_diameter;   /* harmonic mean of the bounds over blocks of >= 2
                                    vertices (1/inf = 0); inf if all are disconnected,
                                    0 if there are none */
-    int32_t bfs_levels;         /* breadth-first levels run (both sweeps) */
-    int32_t pad;
+    int32_t bfs_levels;         /* breadth-first levels run (all searches) */
+    int32_t exact_blocks;       /* non-empty connected blocks whose bound is proven exact */
 } bkm_graph_stats;
 
 /* Edge cut, communication volume and block diameters of a partition of an
  * undirected graph (Sec. 2 definitions):
  *   comm(V_i) = sum over v in V_i of the number of blocks other than V_i
  *   holding a neighbour of v;
- *   the diameter of a block is bounded from below by a double sweep of
- *   breadth-first searches inside the block (Sec. 5.2 uses such a bound,
- *   within a factor 2 of the exact value): from the block's lowest vertex to
- *   the farthest vertex found (largest distance, lowest index on ties),
- *   whose eccentricity is the bound; -1 if the block is disconnected, 0 if
- *   it is empty.
+ *   the diameter of a block is bounded from below as in Sec. 5.2 (Metrics),
+ *   by the first 3 rounds of the iFUB algorithm (Crescenzi et al., Theor.
+ *   Comput. Sci. 514, 2013) inside the block, started from a 4-sweep:
+ *   r1 = the block's lowest vertex; a1, b1 = farthest from r1, a1; r2 = the
+ *   vertex at distance floor(ecc(a1)/2) from a1 on the a1-b1 path; a2, b2 =
+ *   farthest from r2, a2; u = the vertex at distance floor(ecc(a2)/2) from
+ *   a2 on the a2-b2 path; l = max(ecc(a1), ecc(a2)).  Farthest = largest
+ *   hop distance, lowest index on ties; a path is walked back from its far
+ *   end, each step to the lowest-index neighbour one level closer.  iFUB
+ *   from u: i = ecc(u), lb = max(l, i), ub = 2i; each round (while ub > lb,
+ *   at most 3) takes B = the largest eccentricity of the vertices at
+ *   distance i from u; if max(lb, B) > 2(i-1) then lb = ub = max(lb, B),
+ *   else lb = max(lb, B), ub = 2(i-1), i = i-1.  The bound is lb (exact
+ *   when lb == ub); -1 if the block is disconnected, 0 if it is empty.
  *   row_ptr [device] n+1 int64, col [device] nnz int32: CSR holding both
  *           directions of every edge.
  *   assignment [device] n int32 in [0, k).
- *   comm_out [device] k int64, diameter_out [device] k int32, or NULL.
+ *   comm_out [device] k int64; diameter_out, diameter_ub_out [device] k
+ *   int32 (lower bound lb and proven upper bound ub); each may be NULL.
  *   out [host] required.
  * Errors: BKM_EINVAL (also for an assignment, row pointer or column out of
  * range), BKM_ENOMEM, BKM_EHIP. */
 int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
                       const int32_t* assignment, int32_t k, int64_t* comm_out,
-                      int32_t* diameter_out, bkm_graph_stats* out, void* stream);
+                      int32_t* diameter_out, int32_t* diameter_ub_out, bkm_graph_stats* out,
+                      void* stream);
 
 /* Message of the last nonzero return on the calling thread ("" if none). */
 const char* bkm_last_error(void);

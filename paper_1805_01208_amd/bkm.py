@@ -59,7 +59,7 @@ class GraphStats(C.Structure):
     _fields_ = [("edge_cut", C.c_int64), ("max_comm", C.c_int64), ("total_comm", C.c_int64),
                 ("max_diameter", C.c_int32), ("disconnected_blocks", C.c_int32),
                 ("harmonic_diameter", C.c_double), ("bfs_levels", C.c_int32),
-                ("pad", C.c_int32)]
+                ("exact_blocks", C.c_int32)]
 
 
 class KnnInfo(C.Structure):
@@ -75,7 +75,8 @@ class BkmError(RuntimeError):
 _LIB = None
 FUNCTIONS = ("bkm_default_params", "bkm_init_centers_sfc", "bkm_balanced_kmeans",
              "bkm_balanced_kmeans_batched", "bkm_assign_sweeps", "bkm_partition_stats",
-             "bkm_partition_stats_noalloc", "bkm_knn", "bkm_knn_graph", "bkm_graph_metrics", "bkm_last_error")
+             "bkm_partition_stats_noalloc", "bkm_knn", "bkm_knn_graph", "bkm_graph_metrics",
+             "bkm_last_error")
 
 
 def lib():
@@ -101,7 +102,7 @@ def lib():
                                                   C.POINTER(P), C.POINTER(P), C.POINTER(Info), P]
         L.bkm_knn.argtypes = [C.POINTER(Points), C.c_int32, P, C.POINTER(KnnInfo), P]
         L.bkm_knn_graph.argtypes = [C.c_int64, C.c_int32, P, P, P, C.POINTER(C.c_int64), P]
-        L.bkm_graph_metrics.argtypes = [C.c_int64, C.c_int64, P, P, P, C.c_int32, P, P,
+        L.bkm_graph_metrics.argtypes = [C.c_int64, C.c_int64, P, P, P, C.c_int32, P, P, P,
                                         C.POINTER(GraphStats), P]
         L.bkm_last_error.argtypes = []
         L.bkm_last_error.restype = C.c_char_p
@@ -372,10 +373,11 @@ def graph_metrics(row_ptr, col, A, k):
     n = A.numel()
     comm = torch.empty(k, dtype=torch.int64, device=dev)
     diam = torch.empty(k, dtype=torch.int32, device=dev)
+    dub = torch.empty(k, dtype=torch.int32, device=dev)
     st = GraphStats()
     _check(lib().bkm_graph_metrics(n, col.numel(), _ptr(row_ptr.contiguous()),
                                    _ptr(col.contiguous()), _ptr(A.contiguous()), int(k),
-                                   _ptr(comm), _ptr(diam), C.byref(st), _stream()))
-    res = {f: getattr(st, f) for f, _ in GraphStats._fields_ if f != "pad"}
-    res.update(comm=comm, diameter=diam)
+                                   _ptr(comm), _ptr(diam), _ptr(dub), C.byref(st), _stream()))
+    res = {f: getattr(st, f) for f, _ in GraphStats._fields_}
+    res.update(comm=comm, diameter=diam, diameter_ub=dub)
     return res

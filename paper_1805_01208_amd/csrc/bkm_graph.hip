@@ -16,10 +16,15 @@
 //     exact ones.
 //   * symmetrisation: a directed entry p -> q that has no partner q -> p adds
 //     p to q's row; rows are then sorted by index.
-//   * metrics: one thread per vertex for cut and communication volume;
-//     breadth-first searches for the diameter bounds run level-synchronously
-//     over all blocks at once (blocks are disjoint, so one frontier serves
-//     them all), two sweeps.
+//   * metrics: one thread per vertex for cut and communication volume.  The
+//     diameter bound (Sec. 5.2, Metrics: the first 3 rounds of iFUB, from a
+//     4-sweep) runs every block at once: blocks are disjoint, so one
+//     level-synchronous frontier serves them all.  The 4-sweep and the
+//     search from its middle vertex u are five single-source searches per
+//     block; a round's fringe (the vertices at distance i from u) is searched
+//     bit-parallel, 64 sources per block and pass, each vertex holding a
+//     64-bit mask of the sources that reached it, and the deepest level any
+//     source reaches is the largest eccentricity of the fringe.
 #include <climits>
 
 #include <algorithm>
@@ -368,21 +373,92 @@ __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t* p, int64_t n, int3
     if (i < n) p[i] = v;
 }
 
-// Sources of a sweep: the lowest vertex of every non-empty block (first
-// sweep), or the farthest vertex of the first sweep of every connected block
-// (second sweep).
-__global__ __launch_bounds__(kBlock) void k_bfs_sources(int k, GraphDev g, int second,
-                                                        int32_t* dist, int32_t* queue,
-                                                        int32_t* count)
+__global__ __launch_bounds__(kBlock) void k_fill_u64(unsigned long long* p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0ULL;
+}
+
+__device__ inline int32_t far_vertex(unsigned long long key)
+{
+    return (int32_t)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
+}
+
+__device__ inline int32_t far_level(unsigned long long key) { return (int32_t)(key >> 32); }
+
+// With dist from a search of block b whose far end x lies `steps` levels or
+// more from its source: the vertex `steps` levels closer to the source on
+// the path back from x, each step to the lowest-index neighbour of the
+// block one level closer.
+__device__ int32_t walk_back(const int64_t* row_ptr, const int32_t* col, const int32_t* A,
+                             const int32_t* dist, int32_t b, int32_t x, int32_t steps)
+{
+    for (int32_t t = 0; t < steps && x >= 0; ++t) {
+        const int32_t want = dist[x] - 1;
+        int32_t nx = -1;
+        for (int64_t e = row_ptr[x]; e < row_ptr[(int64_t)x + 1]; ++e) {
+            const int32_t y = col[e];
+            if (A[y] == b && dist[y] == want && (nx < 0 || y < nx)) nx = y;
+        }
+        x = nx;
+    }
+    return x;
+}
+
+// Per-block bookkeeping between the single-source searches of the diameter
+// bound, from the results of the search just finished (far, reached, dist):
+//   stage 0: source r1 = the lowest vertex;
+//   stage 1: connected iff the search reached the whole block; source a1;
+//   stage 2: ecc(a1); source r2, floor(ecc/2) from a1 on the path from b1;
+//   stage 3: source a2;
+//   stage 4: l = max(ecc(a1), ecc(a2)); source u, floor(ecc/2) from a2 on
+//            the path from b2;
+//   stage 5: iFUB start from ecc(u): i, lb, ub; counts the blocks left open.
+__global__ __launch_bounds__(kBlock) void k_diam_stage(int k, GraphDev g, int stage,
+                                                       const int64_t* row_ptr, const int32_t* col,
+                                                       const int32_t* A, const int32_t* dist)
 {
     const int b = blockIdx.x * kBlock + threadIdx.x;
     if (b >= k) return;
     int32_t src = -1;
-    if (!second) {
+    const unsigned long long key = g.far[b];
+    if (stage == 0) {
+        g.conn[b] = 0;
         if (g.size[b] > 0) src = g.seed[b];
-    } else if (g.size[b] > 0 && g.reached[b] == g.size[b]) {
-        src = (int32_t)(0xFFFFFFFFu - (unsigned)(g.far[b] & 0xFFFFFFFFull));
+    } else if (stage == 1) {
+        const int c = g.size[b] > 0 && g.reached[b] == g.size[b] ? 1 : 0;
+        g.conn[b] = c;
+        if (c) src = far_vertex(key);
+    } else if (g.conn[b]) {
+        const int32_t e = far_level(key);
+        if (stage == 2) {
+            g.ecc1[b] = e;
+            src = walk_back(row_ptr, col, A, dist, b, far_vertex(key), e - e / 2);
+        } else if (stage == 3) {
+            src = far_vertex(key);
+        } else if (stage == 4) {
+            g.lval[b] = max(g.ecc1[b], e);
+            src = walk_back(row_ptr, col, A, dist, b, far_vertex(key), e - e / 2);
+        } else {
+            g.fi[b] = e;
+            g.lb[b] = max(g.lval[b], e);
+            g.ub[b] = 2 * e;
+            g.fcnt[b] = 0;
+            g.blast[b] = -1;
+            if (g.ub[b] > g.lb[b]) atomicAdd(&g.ctl[0], 1);
+        }
     }
+    g.src[b] = src;
+}
+
+// Seeds the next single-source search from g.src (resets every block's
+// reached count and farthest vertex).
+__global__ __launch_bounds__(kBlock) void k_bfs_sources(int k, GraphDev g, int32_t* dist,
+                                                        int32_t* queue, int32_t* count)
+{
+    const int b = blockIdx.x * kBlock + threadIdx.x;
+    if (b >= k) return;
+    const int32_t src = g.src[b];
     g.reached[b] = 0;
     g.far[b] = 0;
     if (src < 0) return;
@@ -390,6 +466,66 @@ __global__ __launch_bounds__(kBlock) void k_bfs_sources(int k, GraphDev g, int s
     g.reached[b] = 1;
     g.far[b] = far_key(0, src);
     queue[atomicAdd(count, 1)] = src;
+}
+
+// iFUB round, fringe: every vertex of an open block at distance i from u
+// gets its rank in the block's fringe (the order does not matter: a round
+// takes the largest eccentricity over the whole fringe); the largest fringe
+// goes to ctl[1].
+__global__ __launch_bounds__(kBlock) void k_fringe_rank(int64_t n, const int32_t* A,
+                                                        const int32_t* du, GraphDev g,
+                                                        int32_t* frank)
+{
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= n) return;
+    const int32_t b = A[v];
+    int32_t r = -1;
+    if (g.conn[b] && g.ub[b] > g.lb[b] && du[v] == g.fi[b]) {
+        r = atomicAdd(&g.fcnt[b], 1);
+        atomicMax(&g.ctl[1], r + 1);
+    }
+    frank[v] = r;
+}
+
+// Sources of batch `batch`: fringe ranks 64*batch .. 64*batch + 63 of every
+// block, each with its own bit.
+__global__ __launch_bounds__(kBlock) void k_mbfs_seed(int64_t n, const int32_t* frank, int batch,
+                                                      unsigned long long* arrive, int32_t* queue,
+                                                      int32_t* count)
+{
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x % kWave;
+    const int32_t r = v < n ? frank[v] - 64 * batch : -1;
+    const bool src = r >= 0 && r < 64;
+    if (src) arrive[v] = 1ULL << r;
+    const unsigned long long b = __ballot(src);
+    if (b == 0ULL) return;
+    int base = 0;
+    if (lane == __builtin_ctzll(b)) base = atomicAdd(count, (int)__popcll(b));
+    base = __shfl(base, __builtin_ctzll(b), kWave);
+    if (src) queue[base + (int)__popcll(b & ((1ULL << lane) - 1ULL))] = (int32_t)v;
+}
+
+// Round end: B = the deepest level the fringe's searches reached.  If
+// max(lb, B) > 2(i - 1) the bound is exact (lb = ub), else lb = max(lb, B),
+// ub = 2(i - 1) and the next round looks one level closer to u.
+__global__ __launch_bounds__(kBlock) void k_ifub_round(int k, GraphDev g)
+{
+    const int b = blockIdx.x * kBlock + threadIdx.x;
+    if (b >= k || !g.conn[b] || g.ub[b] <= g.lb[b]) return;
+    const int32_t i = g.fi[b];
+    const int32_t m = max(g.lb[b], g.blast[b]);
+    if (m > 2 * (i - 1)) {
+        g.lb[b] = m;
+        g.ub[b] = m;
+    } else {
+        g.lb[b] = m;
+        g.ub[b] = 2 * (i - 1);
+        g.fi[b] = i - 1;
+    }
+    g.fcnt[b] = 0;
+    g.blast[b] = -1;
+    if (g.ub[b] > g.lb[b]) atomicAdd(&g.ctl[0], 1);
 }
 
 // One level: every frontier vertex claims its unvisited neighbours of the
@@ -469,27 +605,102 @@ __global__ __launch_bounds__(kBlock) void k_bfs_level(const int64_t* row_ptr, co
     }
 }
 
-// Block results after both sweeps, and the summary (one block).
+// One level of the bit-parallel search: a frontier vertex takes the bits
+// that first reached it at this level (its arrival mask minus the bits it
+// has seen), records the level as its block's deepest, and offers them to
+// its neighbours of the same block; a neighbour whose arrival mask for the
+// next level was empty joins the next frontier.  A neighbour read while it
+// is itself updating its seen mask may be offered bits it already has: it
+// drops them at the next level, so every bit arrives at every vertex at its
+// true distance from the source.  Frontier sizes rotate as in k_bfs_level.
+__global__ __launch_bounds__(kBlock) void k_mbfs_level(const int64_t* row_ptr, const int32_t* col,
+                                                       const int32_t* A, GraphDev g,
+                                                       const int32_t* frontier, int32_t* counts,
+                                                       int32_t level, unsigned long long* seen,
+                                                       unsigned long long* cur,
+                                                       unsigned long long* nxt, int32_t* next,
+                                                       int32_t* levels)
+{
+    const int32_t fcount = counts[level % 3];
+    int32_t* ncount = counts + (level + 1) % 3;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        counts[(level + 2) % 3] = 0;
+        if (fcount > 0) atomicAdd(levels, 1);
+    }
+    const int lane = threadIdx.x % kWave;
+    const unsigned long long below = (1ULL << lane) - 1ULL;
+    const int64_t per_block = kBlock / kBfsLanes;
+    for (int64_t i0 = (int64_t)blockIdx.x * per_block; i0 < fcount;
+         i0 += (int64_t)gridDim.x * per_block) {
+        const int64_t i = i0 + threadIdx.x / kBfsLanes;
+        const bool act = i < fcount;
+        int32_t u = 0, a = -1;
+        int64_t e = 0, end = 0;
+        unsigned long long m = 0ULL;
+        if (act) {
+            u = frontier[i];
+            a = A[u];
+            const unsigned long long sn = seen[u];
+            m = cur[u] & ~sn;
+            // the lanes of u's group all read cur and seen above (same wave)
+            if (threadIdx.x % kBfsLanes == 0) {
+                cur[u] = 0ULL;
+                if (m) {
+                    seen[u] = sn | m;
+                    atomicMax(&g.blast[a], level);
+                }
+            }
+            if (m) {
+                e = row_ptr[u] + threadIdx.x % kBfsLanes;
+                end = row_ptr[(int64_t)u + 1];
+            }
+        }
+        while (__ballot(e < end) != 0ULL) {
+            bool app = false;
+            int32_t v = 0;
+            if (e < end) {
+                v = col[e];
+                e += kBfsLanes;
+                if (A[v] == a) {
+                    const unsigned long long add = m & ~seen[v];
+                    if (add) app = atomicOr(&nxt[v], add) == 0ULL;
+                }
+            }
+            const unsigned long long b = __ballot(app);
+            if (b == 0ULL) continue;
+            int base = 0;
+            if (lane == __builtin_ctzll(b)) base = atomicAdd(ncount, (int)__popcll(b));
+            base = __shfl(base, __builtin_ctzll(b), kWave);
+            if (app) next[base + (int)__popcll(b & below)] = v;
+        }
+    }
+}
+
+// Block results after the searches, and the summary (one block).
 __global__ __launch_bounds__(1024) void k_gm_final(int k, GraphDev g, int32_t* diam_out,
-                                                   int64_t* comm_out, double* summary)
+                                                   int32_t* diam_ub_out, int64_t* comm_out,
+                                                   double* summary)
 {
     __shared__ double sh[1024 / kWave];
     __shared__ long long shl[3][1024 / kWave];
     long long mxc = 0, tot = 0, disc = 0;
-    double mxd = 0.0, inv = 0.0, counted = 0.0;
+    double mxd = 0.0, inv = 0.0, counted = 0.0, exact = 0.0;
     for (int b = threadIdx.x; b < k; b += 1024) {
         const long long c = g.comm[b];
         mxc = c > mxc ? c : mxc;
         tot += c;
-        int32_t dm;
+        int32_t dm, du;
         if (g.size[b] == 0) {
-            dm = 0;
+            dm = du = 0;
         } else if (g.conn[b] == 0) {
-            dm = -1;
+            dm = du = -1;
             ++disc;
         } else {
-            dm = (int32_t)(g.far[b] >> 32);
+            dm = g.lb[b];
+            du = g.ub[b];
+            if (dm == du) exact += 1.0;
         }
+        if (diam_ub_out) diam_ub_out[b] = du;
         if (g.size[b] >= 2) {
             counted += 1.0;
             if (dm > 0) inv += 1.0 / (double)dm;
@@ -513,6 +724,7 @@ __global__ __launch_bounds__(1024) void k_gm_final(int k, GraphDev g, int32_t* d
     mxd = wave_max_d(mxd);
     inv = wave_sum_d(inv);
     counted = wave_sum_d(counted);
+    exact = wave_sum_d(exact);
     __syncthreads();
     if (threadIdx.x == 0) {
         long long a = 0, t = 0, dsc = 0;
@@ -551,14 +763,14 @@ __global__ __launch_bounds__(1024) void k_gm_final(int k, GraphDev g, int32_t* d
         for (int w = 0; w < 1024 / kWave; ++w) s += sh[w];
         summary[5] = s;
     }
-}
-
-// After the first sweep: a block is connected when the sweep reached all of
-// its vertices.
-__global__ __launch_bounds__(kBlock) void k_gm_connected(int k, GraphDev g)
-{
-    const int b = blockIdx.x * kBlock + threadIdx.x;
-    if (b < k) g.conn[b] = g.size[b] > 0 && g.reached[b] == g.size[b] ? 1 : 0;
+    __syncthreads();
+    if (lane == 0) sh[wv] = exact;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < 1024 / kWave; ++w) s += sh[w];
+        summary[6] = s;
+    }
 }
 
 template <int D>
@@ -628,10 +840,57 @@ hipError_t launch_gm_vertex(int64_t n, int64_t nnz, const int64_t* row_ptr, cons
     return hipGetLastError();
 }
 
-hipError_t launch_bfs_sources(int k, const GraphDev& g, int second, int32_t* dist,
-                              int32_t* queue, int32_t* count, hipStream_t s)
+hipError_t launch_diam_stage(int k, const GraphDev& g, int stage, const int64_t* row_ptr,
+                             const int32_t* col, const int32_t* A, const int32_t* dist,
+                             hipStream_t s)
 {
-    k_bfs_sources<<<nblocks(k, kBlock), kBlock, 0, s>>>(k, g, second, dist, queue, count);
+    k_diam_stage<<<nblocks(k, kBlock), kBlock, 0, s>>>(k, g, stage, row_ptr, col, A, dist);
+    return hipGetLastError();
+}
+
+hipError_t launch_bfs_sources(int k, const GraphDev& g, int32_t* dist, int32_t* queue,
+                              int32_t* count, hipStream_t s)
+{
+    k_bfs_sources<<<nblocks(k, kBlock), kBlock, 0, s>>>(k, g, dist, queue, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_fringe_rank(int64_t n, const int32_t* A, const int32_t* du, const GraphDev& g,
+                              int32_t* frank, hipStream_t s)
+{
+    k_fringe_rank<<<nblocks(n, kBlock), kBlock, 0, s>>>(n, A, du, g, frank);
+    return hipGetLastError();
+}
+
+hipError_t launch_mbfs_seed(int64_t n, const int32_t* frank, int batch,
+                            unsigned long long* arrive, int32_t* queue, int32_t* count,
+                            hipStream_t s)
+{
+    k_mbfs_seed<<<nblocks(n, kBlock), kBlock, 0, s>>>(n, frank, batch, arrive, queue, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_mbfs_level(const int64_t* row_ptr, const int32_t* col, const int32_t* A,
+                             const GraphDev& g, const int32_t* frontier, int32_t* counts,
+                             int32_t level, unsigned long long* seen, unsigned long long* cur,
+                             unsigned long long* nxt, int32_t* next, int32_t* levels, int64_t n,
+                             hipStream_t s)
+{
+    const unsigned grid = (unsigned)std::min<int64_t>(2048, nblocks(n * kBfsLanes, kBlock));
+    k_mbfs_level<<<grid, kBlock, 0, s>>>(row_ptr, col, A, g, frontier, counts, level, seen, cur,
+                                         nxt, next, levels);
+    return hipGetLastError();
+}
+
+hipError_t launch_ifub_round(int k, const GraphDev& g, hipStream_t s)
+{
+    k_ifub_round<<<nblocks(k, kBlock), kBlock, 0, s>>>(k, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s)
+{
+    if (n > 0) k_fill_u64<<<nblocks(n, kBlock), kBlock, 0, s>>>(p, n);
     return hipGetLastError();
 }
 
@@ -647,16 +906,10 @@ hipError_t launch_bfs_level(const int64_t* row_ptr, const int32_t* col, const in
     return hipGetLastError();
 }
 
-hipError_t launch_gm_connected(int k, const GraphDev& g, hipStream_t s)
+hipError_t launch_gm_final(int k, const GraphDev& g, int32_t* diam_out, int32_t* diam_ub_out,
+                           int64_t* comm_out, double* summary, hipStream_t s)
 {
-    k_gm_connected<<<nblocks(k, kBlock), kBlock, 0, s>>>(k, g);
-    return hipGetLastError();
-}
-
-hipError_t launch_gm_final(int k, const GraphDev& g, int32_t* diam_out, int64_t* comm_out,
-                           double* summary, hipStream_t s)
-{
-    k_gm_final<<<1, 1024, 0, s>>>(k, g, diam_out, comm_out, summary);
+    k_gm_final<<<1, 1024, 0, s>>>(k, g, diam_out, diam_ub_out, comm_out, summary);
     return hipGetLastError();
 }
 

@@ -143,12 +143,14 @@ def test_graph_argument_errors(bkm):
     assert L.bkm_knn_graph(10, 10, C.c_void_p(0x2000), C.c_void_p(0x3000), C.c_void_p(0x4000),
                            None, None) == bkm.BKM_EINVAL
     st = bkm.GraphStats()
-    assert L.bkm_graph_metrics(10, 5, None, None, None, 2, None, None, C.byref(st),
+    assert L.bkm_graph_metrics(10, 5, None, None, None, 2, None, None, None, C.byref(st),
                                None) == bkm.BKM_EINVAL
     assert L.bkm_graph_metrics(10, -1, C.c_void_p(0x2000), C.c_void_p(0x3000),
-                               C.c_void_p(0x4000), 2, None, None, C.byref(st), None) == bkm.BKM_EINVAL
+                               C.c_void_p(0x4000), 2, None, None, None, C.byref(st),
+                               None) == bkm.BKM_EINVAL
     assert L.bkm_graph_metrics(10, 5, C.c_void_p(0x2000), C.c_void_p(0x3000),
-                               C.c_void_p(0x4000), 0, None, None, C.byref(st), None) == bkm.BKM_EINVAL
+                               C.c_void_p(0x4000), 0, None, None, None, C.byref(st),
+                               None) == bkm.BKM_EINVAL
 
 
 def test_batched_argument_errors(bkm):

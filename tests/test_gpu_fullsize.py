@@ -170,9 +170,11 @@ def check_knn_graph(cfg, X, K, A=None, k=None):
         print(f"case full-size graph metrics {cfg['name']} k={k}", flush=True)
         g = bkm.graph_metrics(rp, col, A, k)
         o = oracle.graph_metrics(rph, colh, A.cpu().numpy(), k)
-        for key in ("edge_cut", "max_comm", "total_comm", "max_diameter", "disconnected_blocks"):
+        for key in ("edge_cut", "max_comm", "total_comm", "max_diameter", "disconnected_blocks",
+                    "exact_blocks"):
             assert g[key] == o[key], key
         assert np.array_equal(g["diameter"].cpu().numpy(), o["diameter"])
+        assert np.array_equal(g["diameter_ub"].cpu().numpy(), o["diameter_ub"])
     return info
 
 

@@ -66,10 +66,12 @@ def _metrics_both(rp, col, A, k, what):
     print(f"case graph metrics {what} k={k}", flush=True)
     g = bkm.graph_metrics(rp, col, A, k)
     o = oracle.graph_metrics(rp.cpu().numpy(), col.cpu().numpy(), A.cpu().numpy(), k)
-    for key in ("edge_cut", "max_comm", "total_comm", "max_diameter", "disconnected_blocks"):
+    for key in ("edge_cut", "max_comm", "total_comm", "max_diameter", "disconnected_blocks",
+                "exact_blocks"):
         assert g[key] == o[key], (what, key)
     assert np.array_equal(g["comm"].cpu().numpy(), o["comm"])
     assert np.array_equal(g["diameter"].cpu().numpy(), o["diameter"])
+    assert np.array_equal(g["diameter_ub"].cpu().numpy(), o["diameter_ub"])
     if np.isfinite(o["harmonic_diameter"]):
         assert g["harmonic_diameter"] == pytest.approx(o["harmonic_diameter"], rel=1e-12)
     else:
@@ -108,6 +110,53 @@ def test_metrics_on_a_grid_graph():
     A = torch.tensor([(v % a) // w for v in range(a * b)], dtype=torch.int32).cuda()
     g = _metrics_both(rp, col, A, s, "grid strips")
     assert g["edge_cut"] == (s - 1) * b and g["max_diameter"] == (w - 1) + (b - 1)
+
+
+def _csr_of_edges(n, edges):
+    rows = [[] for _ in range(n)]
+    for u, v in edges:
+        rows[u].append(v)
+        rows[v].append(u)
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    col = np.array([v for r in rows for v in sorted(r)], dtype=np.int32)
+    return torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda()
+
+
+def test_diameter_rounds_with_large_fringes():
+    """Blocks that stay open through all three iFUB rounds, with fringes of
+    up to 199 vertices (several 64-source passes): products of a cycle and
+    a complete graph (every vertex has the same eccentricity), a long cycle
+    (still open after three rounds), a path, and random sparse blocks; the
+    bounds, upper bounds and exact counts must equal the oracle's."""
+    import networkx as nx
+    rng = np.random.default_rng(73)
+    parts = [nx.cartesian_product(nx.cycle_graph(10), nx.complete_graph(100)),
+             nx.cartesian_product(nx.cycle_graph(14), nx.complete_graph(80)),
+             nx.cycle_graph(40), nx.path_graph(33)]
+    parts += [nx.gnp_random_graph(int(rng.integers(20, 200)), 0.05, seed=int(rng.integers(1 << 30)))
+              for _ in range(12)]
+    edges, A, base = [], [], 0
+    for b, G in enumerate(parts):
+        G = nx.convert_node_labels_to_integers(G, ordering="sorted")
+        edges += [(u + base, v + base) for u, v in G.edges()]
+        A += [b] * G.number_of_nodes()
+        base += G.number_of_nodes()
+    # shuffle vertex ids so that blocks interleave in the index order
+    perm = rng.permutation(base)
+    edges = [(int(perm[u]), int(perm[v])) for u, v in edges]
+    Ap = np.empty(base, dtype=np.int32)
+    Ap[perm] = np.array(A, dtype=np.int32)
+    # a few edges between blocks (they only add to the cut)
+    for _ in range(30):
+        u, v = rng.integers(0, base, 2)
+        if Ap[u] != Ap[v]:
+            edges.append((int(u), int(v)))
+    rp, col = _csr_of_edges(base, edges)
+    g = _metrics_both(rp, col, torch.from_numpy(Ap).cuda(), len(parts), "large fringes")
+    d = g["diameter"].cpu().numpy()
+    dub = g["diameter_ub"].cpu().numpy()
+    assert (d[0], dub[0]) == (6, 6) and (d[1], dub[1]) == (8, 10)
+    assert (d[2], dub[2]) == (20, 34)
 
 
 def test_invalid_graph_inputs_are_rejected():
