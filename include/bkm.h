@@ -37,6 +37,8 @@ extern "C" {
 #define BKM_EDATA (-2)       /* non-finite coordinate, or weight <= 0 / non-finite */
 #define BKM_ENOMEM (-3)      /* device allocation failed */
 #define BKM_EHIP (-4)        /* a HIP runtime call failed (message names it) */
+#define BKM_EINTERNAL (-5)   /* an internal consistency check failed (a sweep decision
+                                produced no valid block); outputs are not valid */
 #define BKM_WUNBALANCED 1    /* outputs valid, but the last AssignAndBalance call
                                 ran out of sweeps before meeting L_max */
 

@@ -13,7 +13,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbkm.so")
 
-BKM_OK, BKM_EINVAL, BKM_EDATA, BKM_ENOMEM, BKM_EHIP = 0, -1, -2, -3, -4
+BKM_OK, BKM_EINVAL, BKM_EDATA, BKM_ENOMEM, BKM_EHIP, BKM_EINTERNAL = 0, -1, -2, -3, -4, -5
 BKM_WUNBALANCED = 1
 BKM_F32, BKM_F64 = 0, 1
 PREC_F64, PREC_F32_RECHECK = 0, 1

@@ -238,8 +238,7 @@ size_t layout(RunDev& r, Arena* a, bool full)
             both((uint32_t*)nullptr, (size_t)np * (d == 3 ? 2 : 1), *reinterpret_cast<uint32_t**>(&r.ofs));
         if (r.weighted) both((double*)nullptr, np, r.ws);
         both((int32_t*)nullptr, np, r.A);
-        both((float*)nullptr, np, r.ubt);
-        both((float*)nullptr, np, r.lbt);
+        both((float2*)nullptr, np, r.bnd);
         both((double*)nullptr, (size_t)ntiles * 2 * d, r.tbox);
         both((double*)nullptr, (size_t)(np / kWave) * 2 * d, r.gbox);
         const int64_t nhyper = (nsuper + kHyper - 1) / kHyper;
@@ -258,7 +257,7 @@ size_t layout(RunDev& r, Arena* a, bool full)
             both((double*)nullptr, (size_t)k + 1, r.tpre);
         }
         both((double2*)nullptr, (size_t)k, r.clus);
-        both((float2*)nullptr, (size_t)k, r.clus32);
+        both((float4*)nullptr, (size_t)k, r.clus32);
         both((int32_t*)nullptr, (size_t)(np / kWave), r.gblk);
         both((int32_t*)nullptr, (size_t)(np / kWave), r.gdirty);
         both((int32_t*)nullptr, np, r.Aprev);
@@ -587,6 +586,9 @@ int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_i
     if ((rc = read_state(r, s, &h))) return rc;
     unsigned long long cnt[kCntWords];
     if ((rc = read_counters(r, s, cnt))) return rc;
+    if (cnt[kCntInvalid])
+        return fail(BKM_EINTERNAL, "%llu sweep decisions produced no valid block",
+                    (unsigned long long)cnt[kCntInvalid]);
 
     if (info) {
         fill_info(info, h, cnt);
@@ -1031,6 +1033,9 @@ int bkm_assign_sweeps(const bkm_points* pts, int32_t k, int32_t steps, const dou
     }
     unsigned long long cnt[kCntWords];
     if ((rc = read_counters(r, s, cnt))) return rc;
+    if (cnt[kCntInvalid])
+        return fail(BKM_EINTERNAL, "%llu sweep decisions produced no valid block",
+                    (unsigned long long)cnt[kCntInvalid]);
     if (info) {
         std::memset(info, 0, sizeof(*info));
         info->sweeps = steps;
@@ -1391,12 +1396,15 @@ int bkm_balanced_kmeans_batched(const bkm_points* pts, const bkm_params* prm, in
     (void)hipEventElapsedTime(&tot_ms, t0, t2);
     for (int i = 0; i < count; ++i) {
         balanced = balanced && res.hstates[i].balanced;
-        if (!info) continue;
         unsigned long long cnt[kCntWords];
         for (int j = 0; j < kCntWords; ++j) {
             cnt[j] = 0;
             for (int q = 0; q < kCntSlots; ++q) cnt[j] += res.hcnt[(size_t)i * kCntSlots * kCntWords + q * kCntWords + j];
         }
+        if (cnt[kCntInvalid])
+            return fail(BKM_EINTERNAL, "instance %d: %llu sweep decisions produced no valid block",
+                        i, (unsigned long long)cnt[kCntInvalid]);
+        if (!info) continue;
         fill_info(&info[i], res.hstates[i], cnt);
         info[i].bootstrap_ms = boot_ms;
         info[i].total_ms = tot_ms;

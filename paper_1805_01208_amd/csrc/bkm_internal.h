@@ -28,9 +28,10 @@ constexpr int kSortChunk = kBlock * kSortIpt;   // items per block per pass
 // of a round read it to decide whether they still have work (a finished
 // AssignAndBalance call or a finished run turns later launches into no-ops),
 // so the host only synchronises once per round.
-struct DevState {
+struct alignas(16) DevState {
     int32_t done;             // run finished (converged or out of rounds)
-    int32_t round_done;       // current AssignAndBalance call finished
+    int32_t round_done;       // current AssignAndBalance call finished (right after done:
+                              // both are read as one 8-byte word)
     int32_t balanced;         // result of the last balance test
     int32_t converged;
     int32_t rounds;           // AssignAndBalance calls completed
@@ -57,28 +58,46 @@ struct DevState {
     // the sweep's copies of the frame, refreshed wherever M or E change
     double invM;              // 1 / M
     float Mf, Ef;             // M rounded down and E rounded up to FP32
+    float Edn, invMdn;        // E rounded down; 1/M times (1 - 2^-21), rounded down
+    int32_t pad;
 };
 
+// The run or the current AssignAndBalance call is over: one 8-byte load of
+// the two adjacent flags.
+__device__ inline bool round_over(const DevState* st)
+{
+    const int2 f = *reinterpret_cast<const int2*>(&st->done);
+    return (f.x | f.y) != 0;
+}
+
 // Sweep counters, summed over the kCntSlots slots by the host.
-enum { kCntEvaluated = 0, kCntSkipped, kCntRechecked, kCntChanged, kCntCandEvals, kCntOverflow };
+enum {
+    kCntEvaluated = 0, kCntSkipped, kCntRechecked, kCntChanged, kCntCandEvals, kCntOverflow,
+    kCntInvalid   // decisions that produced no valid block (an internal error)
+};
 
 // Candidates of one tile for the current sweep, written by k_tilecand.
 struct TileHead {
     int32_t n;                // records in use
     int32_t overflow;         // 1: more than kTileCap candidates; sweep the super-tile list
     float step[3];            // FP32 value of one unit of the tile's fixed-point offsets, per axis
-    float pad;
+    float slack32;            // FP32 screen slack: tau(1 + 16u) + 2^-46, rounded up
     double tau;               // bound on |FP32 effective distance - exact| over the candidates
     double dmax;              // bound on |FP32 distance - exact| over the candidates
     double lb_out;            // lower bound on the effective distance of every center left out
+    float ubadd32;            // dmax + 2^-46 (1 + 7u), rounded up: the upper bound's additive term
+    float lbout32;            // lb_out rounded down
 };
 
 // One candidate center of a tile: FP32 offset of the center from the tile
-// anchor and squared FP32 inverse influence, for the FP32 screen.
+// anchor and squared FP32 inverse influence, for the FP32 screen, and a lower
+// bound on the value the screen (or the FP64 sweep) can compute for this
+// center at any point of the tile.  A tile's records are sorted by that key.
 struct alignas(32) CandRec {
     float qx, qy, qz, w2;
     int32_t id;
-    int32_t pad0, pad1, pad2;
+    float key;
+    int32_t pad1, pad2;
 };
 
 // Everything a run keeps on the device.  Point arrays are in Hilbert (sorted)
@@ -109,8 +128,8 @@ struct RunDev {
     int32_t* jumps;           // [maxjumps] first point after each jump, sorted by the plan
     int64_t* jshift;          // [maxjumps] layout shift of the points from jumps[j] on
     int32_t* A;               // current block of each sorted point (-1: none yet)
-    float* ubt;               // stored upper bounds (distance frame)
-    float* lbt;               // stored lower bounds (lazy frame)
+    float2* bnd;              // stored bounds of each point: x upper (distance frame),
+                              // y lower (lazy frame), one 8-byte record
     double* tbox;             // [ntiles][2d] lo..., hi...
     double* gbox;             // [ngroups][2d] boxes of 64-point groups
     double* hbox;             // [nhyper][2d] boxes of hyper-tiles (kHyper super-tiles)
@@ -127,7 +146,8 @@ struct RunDev {
     double* tL;               // [k] weight limit of each block (with target sizes)
     double* tpre;             // [k+1] prefix sums of the target sizes in index order; [k] = total
     double2* clus;            // [k] (accumulated movement, 1/influence)
-    float2* clus32;           // [k] the same rounded up to FP32, for the Hamerly test
+    float4* clus32;           // [k] FP32 copies: movement rounded up, 1/influence rounded
+                              // up (Hamerly test), movement rounded down (bound stores)
     int32_t* Aprev;           // [npad] block of each point at the previous round end
     int32_t* gdirty;          // [ngroups] 1 if a point of the group changed block in this round
     int32_t* gblk;            // [ngroups] block of every point of the group after the last
@@ -212,17 +232,21 @@ __device__ inline typename FixPack<D>::word fix_pack(const long long* q)
 }
 
 // Field j of a packed word, sign-extended, as FP32 (exact: |field| < 2^21).
+// Each field is taken out with 32-bit shifts (a 3D field may straddle the two
+// halves of the word), so the conversion is a 32-bit one.
 template <int D>
 __device__ inline float fix_field(typename FixPack<D>::word w, int j)
 {
     constexpr int b = FixPack<D>::kBits;
-    constexpr int nb = 8 * (int)sizeof(w);
-    using S = std::conditional_t<D == 3, long long, int>;
-    const S v = (S)(w << (nb - b * (j + 1))) >> (nb - b);
-    return (float)v;
+    const uint32_t x = (uint32_t)(w >> (b * j));
+    return (float)((int32_t)(x << (32 - b)) >> (32 - b));
 }
 
 // ------------------------------------------------------------------ helpers
+// Lanes of the wave for which p holds (the condition's own lane mask, with
+// no detour through a 0/1 register).
+__device__ inline unsigned long long wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
 __device__ inline double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, kWave); }
 
 __device__ inline long long shfl_xor_ll(long long v, int m) { return __shfl_xor(v, m, kWave); }
@@ -346,6 +370,8 @@ __device__ inline void frame_copies(DevState* st)
     st->Mf = f32_down(st->M);
     st->Ef = f32_up(st->E);
     st->invM = 1.0 / st->M;
+    st->Edn = f32_down(st->E);
+    st->invMdn = f32_down(st->invM * (1.0 - 0x1p-21));
 }
 
 // ------------------------------------------------------------- launchers

@@ -146,7 +146,7 @@ __device__ __forceinline__ void box_filter(RT r, const double* lo, const double*
             box_eff2<D>(lo, hi, r.C, k, c, r.clus[c].y, lo2, hi2);
             keep = lo2 <= thr2;
         }
-        const unsigned long long b = __ballot(keep);
+        const unsigned long long b = wave_ballot(keep);
         int off = 0;
         if (lane == 0 && b) off = atomicAdd(&cnt, (int)__popcll(b));
         off = __shfl(off, 0, kWave);
@@ -164,7 +164,7 @@ template <int D, typename RT>
 __device__ __forceinline__ void hypercand_body(RT r, const int bid)
 {
     const DevState* st = r.st;
-    if (st->done || st->round_done) return;
+    if (round_over(st)) return;
     double lo[D], hi[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -194,7 +194,7 @@ template <int D, typename RT>
 __device__ __forceinline__ void supercand_body(RT r, const int bid)
 {
     const DevState* st = r.st;
-    if (st->done || st->round_done) return;
+    if (round_over(st)) return;
     double lo[D], hi[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -237,13 +237,27 @@ __global__ __launch_bounds__(kSuperThreads) void k_supercand_multi(const RunDev*
 // multiply-adds and a square root) add at most 3.6*u*(Rn + r_c).  dmax uses
 // Rn/(2M)*1.0001 + 8*u*(Rn + r_c), and tau that times 1/influence(c),
 // maximised over the candidates.
+//
+// Sort key.  For a point of the tile, the correctly rounded root of the
+// screen's value for c is at least e(1 - 8u) - tau_c (tau_c: c's own term of
+// tau), e its exact effective distance, and e is at least lo_c, the smallest
+// effective distance from the tile box to c; so the value itself is at least
+// key_c = (lo_c(1 - 10u) - tau_c)^2 (1 - 4u) (0 when negative), rounded down.
+// The FP64 sweep's value s*(1/I)^2 of a point inside the box exceeds it too.
+// Records are written in ascending key order, so a sweep may stop at the
+// first record whose key is at least every lane's current second-best value
+// (Alg. 1 breaks the same way once the box distance passes the second-best):
+// no later record can change a lane's best or second-best.
 template <int D, int PREC, typename RT>
 __device__ __forceinline__ void tilecand_body(RT r, const int bid)
 {
     const DevState* st = r.st;
-    if (st->done || st->round_done) return;
+    if (round_over(st)) return;
     constexpr int kCpl = 4;   // candidates a lane keeps in registers between passes
+    __shared__ CandRec s_rec[kBlock / kWave][kTileCap];
+    __shared__ float s_key[kBlock / kWave][kTileCap];
     const int lane = threadIdx.x % kWave;
+    const int wv = threadIdx.x / kWave;
     // wave-uniform: the tile box, its frame and the list bounds live in scalar registers
     const int tile = __builtin_amdgcn_readfirstlane(bid * (kBlock / kWave) + (int)threadIdx.x / kWave);
     if (tile >= r.ntiles) return;
@@ -272,9 +286,10 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
 
     int cnt = 0;
     double tau = 0.0, dmax = 0.0;
-    // error bounds of one candidate; the record itself when it fits
-    auto emit = [&](bool keep, int c) {
-        const unsigned long long b = __ballot(keep);
+    // error bounds of one candidate; the record itself (staged in LDS for the
+    // sort) when it fits; lo2 = squared smallest effective box distance
+    auto emit = [&](bool keep, int c, double lo2) {
+        const unsigned long long b = wave_ballot(keep);
         const int pos = cnt + (int)__popcll(b & below);
         if (keep) {
             const double iv = r.clus[c].y;
@@ -285,9 +300,11 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
                 dd += q[j] * q[j];
             }
             const double delta = pnt + 8.0 * kU32 * (Rn + sqrt(dd) * (1.0 + kTiny)) + kUnder;
+            const double tc = delta * iv;
             dmax = fmax(dmax, delta);
-            tau = fmax(tau, delta * iv);
+            tau = fmax(tau, tc);
             if (pos < kTileCap) {
+                const double lk = sqrt(lo2) * (1.0 - 10.0 * kU32) - tc * (1.0 + kTiny);
                 CandRec rec;
                 rec.qx = (float)q[0];
                 rec.qy = (float)q[1];
@@ -295,8 +312,10 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
                 const float fi = (float)iv;
                 rec.w2 = fi * fi;
                 rec.id = c;
-                rec.pad0 = rec.pad1 = rec.pad2 = 0;
-                out[pos] = rec;
+                rec.key = lk > 0.0 ? f32_down(lk * lk * (1.0 - 4.0 * kU32)) : 0.0f;
+                rec.pad1 = rec.pad2 = 0;
+                s_rec[wv][pos] = rec;
+                s_key[wv][pos] = rec.key;
             }
         }
         cnt += (int)__popcll(b);
@@ -324,7 +343,7 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
         t = wave_two(t);
         thr2 = t.b * (1.0 + 2.0 * kCandSlack);
 #pragma unroll
-        for (int u = 0; u < kCpl; ++u) emit(cc[u] >= 0 && clo[u] <= thr2, cc[u]);
+        for (int u = 0; u < kCpl; ++u) emit(cc[u] >= 0 && clo[u] <= thr2, cc[u], clo[u]);
     } else {
         for (int i = lane; i < L; i += kWave) {
             const int c = sl[i];
@@ -338,18 +357,36 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
             const int i = i0 + lane;
             int c = 0;
             bool keep = false;
+            double lo2 = 0.0;
             if (i < L) {
                 c = sl[i];
-                double lo2, hi2;
+                double hi2;
                 box_eff2<D>(blo, bhi, C, k, c, r.clus[c].y, lo2, hi2);
                 keep = lo2 <= thr2;
             }
-            emit(keep, c);
+            emit(keep, c, lo2);
         }
     }
     // an overflowed tile is swept in FP64 over the super-tile list (its
     // FP32 bounds are not used)
     const bool overflow = cnt > kTileCap;
+    // the records in ascending key order (ties by staging position): each
+    // lane ranks its staged records against all of them (the wave's own LDS
+    // rows, so a wave-level fence orders the writes before the reads)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (!overflow) {
+        for (int i = lane; i < cnt; i += kWave) {
+            const float ki = s_key[wv][i];
+            int rank = 0;
+            for (int j = 0; j < cnt; ++j) {
+                const float kj = s_key[wv][j];
+                rank += (kj < ki || (kj == ki && j < i)) ? 1 : 0;
+            }
+            out[rank] = s_rec[wv][i];
+        }
+    }
     tau = wave_max_d(tau);
     dmax = wave_max_d(dmax);
     if (lane == 0) {
@@ -362,7 +399,9 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
         h.step[0] = step[0];
         h.step[1] = step[1];
         h.step[2] = step[2];
-        h.pad = 0.0f;
+        h.slack32 = f32_up((h.tau * (1.0 + 16.0 * kU32) + 2.0 * kSqrtAbs) * (1.0 + 0x1p-20));
+        h.ubadd32 = f32_up((h.dmax + 2.0 * kSqrtAbs * (1.0 + 7.0 * kU32)) * (1.0 + 0x1p-20));
+        h.lbout32 = f32_down(h.lb_out);
         r.thead[tile] = h;
     }
 }
@@ -386,17 +425,58 @@ __global__ __launch_bounds__(kBlock) void k_tilecand_multi(const RunDev* rs, con
 // Block = one tile of T = 256 * PPT consecutive Hilbert-ordered points.
 // Phase 1 streams every point of the tile (thread t, points base + t + 256 q,
 // so each wave reads 64 consecutive points and every access is coalesced):
-// block id, stored bounds, Hamerly test.  The points the bounds cannot
-// decide are compacted into an LDS work list, and phase 2 gives each of them
-// a full lane for the candidate scan (records staged in LDS), the decision
-// and the block-weight bookkeeping, so skipped points cost no candidate
-// arithmetic.  The coordinate sums of the center update are not touched
-// here: the round-end pass rebuilds them from the final assignment.
+// block id, stored bounds (one 8-byte record), Hamerly test.  The points the
+// bounds cannot decide are compacted into an LDS work list, and phase 2
+// gives each of them a full lane for the candidate scan (records staged in
+// LDS, in ascending key order, so the scan stops once no later record can
+// matter to any lane of the wave), the decision and the block-weight
+// bookkeeping, so skipped points cost no candidate arithmetic.  The
+// coordinate sums of the center update are not touched here: the round-end
+// pass rebuilds them from the final assignment.
+//
+// FP32 arithmetic of the decision and the stored bounds.  With u = 2^-24 and
+// RN the FP32 rounding, every quantity below is rounded in the safe
+// direction:
+//   * Hamerly test: U = (ub + D) / I, L = M lb - E with the stored ub, lb,
+//     the movement D and 1/I rounded up (clus32.x, .y), M rounded down, E
+//     up; RN(RN(ub + D) * (1/I)) >= U (1 - u)^2, and RN(M lb - E) (one
+//     fused multiply-add) <= L (1 + u) when positive; the point is skipped
+//     when RN(ubf (1 + 2^-20) + 2^-100) < lbf, which then implies U < L.
+//   * sure decision: with kM <= 1 - kScr - 4u and kP >= 1 + kScr + 4u,
+//     RN(es kM - eb kP) > 2 slack32 implies the exact-arithmetic test
+//     es (1 - kScr) - eb (1 + kScr) > 2 slack (slack32 >= slack, the
+//     rounding of es kM and of the fused difference is within the 4u).
+//   * bounds of a sure point: RN(sqrt_raw(d2) (1 + 10u) + ubadd32) >= the
+//     FP64 form (sqrt_raw(d2) + 2^-46)(1 + 7u) + dmax; RN(es kM - slack32)
+//     <= es (1 - kScr) - slack for both signs of the result.
+//   * stored upper bound: t = RN(ubf - Ddn) with the movement rounded down;
+//     RN(|t| 2^-22 + (t + 2^-120)) >= ubf - Ddn.
+//   * stored lower bound: RN(RN(lbf + Edn) invMdn) <= (lb + E) / M when
+//     lbf + Edn >= 0 (Edn <= E, invMdn <= (1 - 2^-22) / M); a negative
+//     value is stored as 0, which is always valid.
+// FP64 results (recheck, plain FP64 sweep) enter the same stores through
+// f32_up_q / f32_dn_q: RN(RN(x)(1 + 2^-22) + 2^-120) >= x and, for x >= 0,
+// RN(RN(x)(1 - 2^-22)) <= x (flushed to 0 below 2^-100).
+__device__ inline float f32_up_q(double x)
+{
+    return __builtin_fmaf((float)x, 1.0f + 0x1p-22f, 0x1p-120f);
+}
+
+__device__ inline float f32_dn_q(double x)
+{
+    const float y = (float)x * (1.0f - 0x1p-22f);
+    return y < 0x1p-100f ? 0.0f : y;
+}
+
+constexpr float kM32 = 1.0f - 15.0f * 0x1p-24f;   // <= 1 - kScr - 4u
+constexpr float kP32 = 1.0f + 16.0f * 0x1p-24f;   // >= 1 + kScr + 4u
+constexpr float kUb32 = 1.0f + 10.0f * 0x1p-24f;  // 1 + 10u
+
 template <int D, int PREC, int PPT, bool WEIGHTED, typename RT>
 __device__ __forceinline__ void sweep_body(RT r, const int bid)
 {
     DevState* st = r.st;
-    if (st->done || st->round_done) return;
+    if (round_over(st)) return;
     constexpr bool F32 = PREC == BKM_PREC_F32_RECHECK;
     constexpr int T = kBlock * PPT;
     __shared__ int s_off[T];      // tile offsets of the points to evaluate
@@ -404,8 +484,9 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
     __shared__ int s_gflag[T / kWave];  // per 64-point group: common block, or -1
     __shared__ int s_gdirty[T / kWave]; // per 64-point group: a point of it changed block
     __shared__ float4 s_q[kTileCap];
+    __shared__ float s_key[kTileCap];
     __shared__ int s_cid[kTileCap];
-    __shared__ double s_c64[4][kTileCap];   // FP64 centers and influences (FP64 sweep, overflow)
+    __shared__ double s_c64[4][kTileCap];   // FP64 centers and (1/I)^2 (FP64 sweep, overflow)
     __shared__ int s_nl;
     __shared__ unsigned long long s_cnt[kBlock / kWave][5];   // counters of each wave
 
@@ -415,88 +496,102 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
     const int k = r.k;
     const double* __restrict__ C = r.C;
     const double* __restrict__ I = r.I;
+    // per-tile views: a 32-bit offset from a wave-uniform base per access
+    int32_t* __restrict__ At = r.A + base;
+    float2* __restrict__ Bt = r.bnd + base;
     if (tid == 0) s_nl = 0;
     if (tid < T / kWave) s_gdirty[tid] = 0;
 
     // ---- phase 1: block ids and stored bounds (arrays are padded to whole tiles)
     int aold[PPT];
-    float ut[PPT], lt[PPT];
+    float2 bd[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
-        const int64_t p = base + (int64_t)q * kBlock + tid;
-        aold[q] = r.A[p];
-        ut[q] = r.use_bounds ? r.ubt[p] : 0.0f;
-        lt[q] = r.use_bounds ? r.lbt[p] : 0.0f;
+        const unsigned i = (unsigned)(q * kBlock + tid);
+        aold[q] = At[i];
+        bd[q] = Bt[i];
     }
     const TileHead hd = r.thead[tile];
     const int sidx = tile / r.super_tiles;
     const int* __restrict__ sl = r.slist + (int64_t)sidx * k;
     const CandRec* __restrict__ cr = r.tcand + (int64_t)tile * kTileCap;
     const int ncand = hd.overflow ? r.scount[sidx] : hd.n;
-    // the tile's candidate records into LDS
-    if (!hd.overflow && tid < hd.n) {
-        const CandRec rec = cr[tid];
-        s_cid[tid] = rec.id;
-        if (F32) {
-            s_q[tid] = make_float4(rec.qx, rec.qy, rec.qz, rec.w2);
-        } else {
-            s_c64[0][tid] = C[rec.id];
-            s_c64[1][tid] = C[(int64_t)k + rec.id];
-            s_c64[2][tid] = D == 3 ? C[(int64_t)(D - 1) * k + rec.id] : 0.0;
-            s_c64[3][tid] = I[rec.id];
+    // the tile's candidate records into LDS; an odd count is padded with a
+    // record no point can pick (its values are +inf), so the scan can take
+    // the records two at a time
+    if (!hd.overflow && tid <= hd.n) {
+        if (tid < hd.n) {
+            const CandRec rec = cr[tid];
+            s_cid[tid] = rec.id;
+            s_key[tid] = rec.key;
+            if (F32) {
+                s_q[tid] = make_float4(rec.qx, rec.qy, rec.qz, rec.w2);
+            } else {
+                const double iv = r.clus[rec.id].y;
+                s_c64[0][tid] = C[rec.id];
+                s_c64[1][tid] = C[(int64_t)k + rec.id];
+                s_c64[2][tid] = D == 3 ? C[(int64_t)(D - 1) * k + rec.id] : 0.0;
+                s_c64[3][tid] = iv * iv;
+            }
+        } else if ((hd.n & 1) && tid < kTileCap) {
+            s_cid[tid] = 0;
+            s_key[tid] = INFINITY;
+            s_q[tid] = make_float4(0x1p120f, 0x1p120f, 0x1p120f, 1.0f);
+            s_c64[0][tid] = s_c64[1][tid] = s_c64[2][tid] = 0x1p600;
+            s_c64[3][tid] = 1.0;
         }
     }
-    float2 cl[PPT];
+    float4 cl[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) cl[q] = r.clus32[aold[q] > 0 ? aold[q] : 0];
-    // lower-bound frame in FP32, rounded so that every bound stays valid, and
-    // the reciprocal of its scale (precomputed by whoever changed the frame)
-    const float Mf = st->Mf, Ef = st->Ef;
-    const double E = st->E;
-    const double invM = st->invM;
-    unsigned n_eval = 0, n_skip = 0;
-    __syncthreads();   // s_nl initialised
+    // lower-bound frame in FP32, rounded so that every bound stays valid;
+    // without bounds the test below can never pass (its lower bound is -inf)
+    const float Mf = r.use_bounds ? st->Mf : 0.0f;
+    const float Ef = r.use_bounds ? st->Ef : INFINITY;
+    const float Edn = st->Edn, invMdn = st->invMdn;
     const unsigned long long below = (1ULL << lane) - 1ULL;
+    // Hamerly test (Sec. 4.3) of every point: upper bound on the own
+    // effective distance below the lower bound on the second-best one (a
+    // point without a block yet has an infinite upper bound)
+    unsigned long long bq[PPT];
+    unsigned n_eval = 0, n_skip = 0;
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
-        bool ev = aold[q] != kPad && ncand > 0;
-        bool sk = false;
-        if (ev && r.use_bounds && aold[q] >= 0) {
-            // Hamerly test (Sec. 4.3): upper bound on the own effective
-            // distance below the lower bound on the second-best one.  FP32
-            // with absolute slack covering every rounding.
-            float sub = ut[q] + cl[q].x;
-            sub += 0x1p-21f * (fabsf(ut[q]) + cl[q].x);
-            const float ub = sub * cl[q].y * (1.0f + 0x1p-20f);
-            const float m = Mf * lt[q];
-            const float lb = (m - Ef) - 0x1p-20f * (m + Ef);
-            if (ub < lb) {
-                ev = false;
-                sk = true;
-            }
-        }
-        const unsigned long long b = __ballot(ev);
-        // counters are wave-uniform: popcounts of ballots
-        n_skip += (unsigned)__popcll(__ballot(sk));
-        n_eval += (unsigned)__popcll(b);
-        int pos = 0;
-        if (lane == 0 && b) pos = atomicAdd(&s_nl, (int)__popcll(b));
-        pos = __shfl(pos, 0, kWave) + (int)__popcll(b & below);
-        if (ev) {
+        const bool real = aold[q] != kPad && ncand > 0;
+        const float ub = (bd[q].x + cl[q].x) * cl[q].y;
+        const float lb = __builtin_fmaf(Mf, bd[q].y, -Ef);
+        const bool skip = __builtin_fmaf(ub, 1.0f + 0x1p-20f, 0x1p-100f) < lb;
+        bq[q] = wave_ballot(real & !skip);
+        const unsigned nr = (unsigned)__popcll(wave_ballot(real));
+        const unsigned ne = (unsigned)__popcll(bq[q]);
+        n_eval += ne;
+        n_skip += nr - ne;
+    }
+    // one LDS reservation per wave for all its points to evaluate
+    __syncthreads();   // s_nl initialised
+    int run = 0;
+    if (lane == 0 && n_eval) run = atomicAdd(&s_nl, (int)n_eval);
+    run = __builtin_amdgcn_readfirstlane(run);
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        if ((bq[q] >> lane) & 1ULL) {
+            const int pos = run + (int)__popcll(bq[q] & below);
             s_off[pos] = q * kBlock + tid;
             s_aold[pos] = aold[q];
         }
+        run += (int)__popcll(bq[q]);
         // the wave holds one whole 64-point group here: its common block
-        const int a0 = __shfl(aold[q], 0, kWave);
-        const bool same = __ballot(aold[q] != a0) == 0ULL;
+        const int a0 = __builtin_amdgcn_readfirstlane(aold[q]);
+        const bool same = wave_ballot(aold[q] != a0) == 0ULL;
         if (lane == 0) s_gflag[q * (kBlock / kWave) + tid / kWave] = same ? a0 : -1;
     }
     __syncthreads();
     const int nl = s_nl;
 
     // ---- phase 2: one lane per undecided point
-    unsigned n_rechk = 0, n_chg = 0;
-    const double gap_rel = r.recheck_gap;
+    unsigned n_rechk = 0, n_chg = 0, n_bad = 0;
+    unsigned long long n_cand = 0;
+    const float gap32 = (float)r.recheck_gap;
     const double wsc = st->w_scale;
     // an overflowed tile (more candidates than records) is swept in FP64
     // even by the FP32 kernel: its candidates come from the super-tile list,
@@ -527,6 +622,7 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
                 for (int j = 0; j < D; ++j) x[j] = sorted_coord(r, j, p);
             }
         }
+        const unsigned nact = (unsigned)__popcll(wave_ballot(act));
         // best and second-best over the tile's candidates
         float b2 = INFINITY, s2 = INFINITY;
         int bi = 0;
@@ -563,7 +659,11 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
             bi = better ? c0 : bi;
             b2 = better ? e2 : b2;
         };
-        // the same ranking by squared effective distance, iv2 = (1/influence)^2
+        // the ranking by squared effective distance s * (1/I)^2, iv2 = (1/I)^2,
+        // ties to the lower center index.  Its rounding differs from
+        // sqrt(s) / I by a few units of 2^-53, which can only swap two
+        // candidates closer than that (a tie at the 1e-12 level), and the
+        // bounds below carry a 1e-12 slack.
         auto consider64sq = [&](int c, double cx, double cy, double cz, double iv2) {
             const double dx = x[0] - cx;
             const double dy = x[1] - cy;
@@ -579,36 +679,37 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
             bc = better ? c : bc;
             be = better ? e2 : be;
         };
-        auto consider64 = [&](int c, double cx, double cy, double cz, double ic) {
-            double sq;
-            const double e = eff64<D>(x, cx, cy, cz, ic, sq);
-            const bool better = e < be || (e == be && c < bc);
-            se = better ? be : fmin(se, e);
-            bs2 = better ? sq : bs2;
-            bc = better ? c : bc;
-            be = better ? e : be;
-        };
         if (!hd.overflow) {
-            if (__ballot(act) != 0ULL) {
-                for (int c0 = 0; c0 < ncand; ++c0) {
-                    const int c = s_cid[c0];
+            if (nact) {
+                // records in ascending key order, taken two at a time: stop
+                // once every active lane's second-best value is at most the
+                // next key -- no later record can change its best or
+                // second-best (for FP64 the key is strictly above it)
+                int c0 = 0;
+                for (; c0 < ncand; c0 += 2) {
+                    const float key = s_key[c0];
                     if (F32) {
-                        const float4 qv = s_q[c0];
-                        consider32(c0, qv.x, qv.y, qv.z, qv.w);
+                        if (wave_ballot(act & (s2 > key)) == 0ULL) break;
+                        const float4 qa = s_q[c0];
+                        const float4 qb = s_q[c0 + 1];
+                        consider32(c0, qa.x, qa.y, qa.z, qa.w);
+                        consider32(c0 + 1, qb.x, qb.y, qb.z, qb.w);
                     } else {
-                        consider64(c, s_c64[0][c0], s_c64[1][c0], s_c64[2][c0], s_c64[3][c0]);
+                        if (wave_ballot(act & !(se < (double)key)) == 0ULL) break;
+                        consider64sq(s_cid[c0], s_c64[0][c0], s_c64[1][c0], s_c64[2][c0],
+                                     s_c64[3][c0]);
+                        if (c0 + 1 < ncand)
+                            consider64sq(s_cid[c0 + 1], s_c64[0][c0 + 1], s_c64[1][c0 + 1],
+                                         s_c64[2][c0 + 1], s_c64[3][c0 + 1]);
                     }
                 }
+                n_cand += (unsigned long long)nact * (unsigned)min(c0, ncand);
             }
+            if (!F32) se = sqrt(se);
         } else {
             // overflowed tile: the super-tile's list in FP64, staged through
             // LDS in chunks of kTileCap centers that every wave of the block
-            // helps to load (the loop is block-uniform).  Candidates are
-            // compared by their squared effective distance s * (1/I)^2, with
-            // no square root or division per candidate: its rounding differs
-            // from sqrt(s) / I by a few units of 2^-53, which can only swap
-            // two candidates closer than that (a tie at the 1e-12 level), and
-            // the bounds below carry a 1e-12 slack.
+            // helps to load (the loop is block-uniform)
             for (int cb = 0; cb < ncand; cb += kTileCap) {
                 const int m = min(kTileCap, ncand - cb);
                 __syncthreads();   // the previous chunk is consumed
@@ -622,19 +723,20 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
                     s_c64[3][tid] = iv * iv;
                 }
                 __syncthreads();
-                if (__ballot(act) != 0ULL) {
+                if (nact) {
                     for (int c0 = 0; c0 < m; ++c0)
                         consider64sq(s_cid[c0], s_c64[0][c0], s_c64[1][c0], s_c64[2][c0], s_c64[3][c0]);
                 }
             }
+            n_cand += (unsigned long long)nact * (unsigned)ncand;
             // back to effective distances for the lower bound
             se = sqrt(se);
         }
         int cbest = ao;
-        bool chg = false, rck = false;
+        bool chg = false, rck = false, bad = false;
         long long wh = 1, wl = 0;
         if (act) {
-            double ubd, lb;
+            float ubf, lbf;   // upper bound on the own distance, lower bound on the second-best
             if (screen) {
                 // the best candidate's id, FP32 effective squared distance and
                 // squared distance, recomputed from its record exactly as in
@@ -646,20 +748,19 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
                     be2 = eff32(qx, qy, qz, w2, bd2);
                 }
                 // every other candidate's FP32 value is at least s2
-                const double eb = (double)sqrt_raw(be2);
-                const double es = (double)sqrt_raw(s2);
-                const double slack = hd.tau * (1.0 + 16.0 * kU32) + 2.0 * kSqrtAbs;
+                const float eb = sqrt_raw(be2);
+                const float es = sqrt_raw(s2);
+                const float sl32 = hd.slack32;
                 // one candidate: certain; an overflowed FP32 value: decide in FP64
                 const bool sure =
                     b2 < INFINITY &&
                     (ncand == 1 ||
-                     (s2 < INFINITY &&
-                      es * (1.0 - kScr) - eb * (1.0 + kScr) > 2.0 * slack &&
-                      es - eb > gap_rel * es));
+                     (s2 < INFINITY && __builtin_fmaf(-eb, kP32, es * kM32) > 2.0f * sl32 &&
+                      es - eb > gap32 * es));
                 if (sure) {
                     cbest = bc;
-                    ubd = ((double)sqrt_raw(bd2) + 2.0 * kSqrtAbs) * (1.0 + 7.0 * kU32) + hd.dmax;
-                    lb = es * (1.0 - kScr) - slack;
+                    ubf = __builtin_fmaf(sqrt_raw(bd2), kUb32, hd.ubadd32);
+                    lbf = __builtin_fmaf(es, kM32, -sl32);
                 } else {
                     // FP64 recheck of the candidates that can still be the best:
                     // every candidate's exact effective distance e lies within
@@ -670,7 +771,8 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
                     rck = true;
 #pragma unroll
                     for (int j = 0; j < D; ++j) x[j] = sorted_coord(r, j, p);
-                    const double win = eb * (1.0 + kScr) + 2.0 * slack;
+                    const double slack = hd.tau * (1.0 + 16.0 * kU32) + 2.0 * kSqrtAbs;
+                    const double win = (double)eb * (1.0 + kScr) + 2.0 * slack;
                     double b = kInf, s = kInf, bsq = kInf;
                     int bcc = 0x7fffffff;
                     for (int c0 = 0; c0 < ncand; ++c0) {
@@ -692,43 +794,46 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
                         }
                     }
                     cbest = bcc;
-                    ubd = sqrt(bsq) * (1.0 + kTiny);
-                    lb = fmin(s, win - slack) * (1.0 - kTiny);
+                    ubf = f32_up_q(sqrt(bsq) * (1.0 + kTiny));
+                    lbf = f32_dn_q(fmin(s, win - slack) * (1.0 - kTiny));
                 }
             } else {
                 cbest = bc;
-                ubd = sqrt(bs2) * (1.0 + kTiny);
-                lb = se * (1.0 - kTiny);
+                ubf = f32_up_q(sqrt(bs2) * (1.0 + kTiny));
+                lbf = f32_dn_q(se * (1.0 - kTiny));
             }
-            if (cbest < 0 || cbest >= k) cbest = ao >= 0 ? ao : (hd.overflow ? sl[0] : s_cid[0]);
-            lb = fmin(lb, hd.lb_out);
-            if (r.use_bounds) {
-                const double Db = r.clus[cbest].x;
-                double uv = ubd - Db;
-                uv += kTiny * (fabs(ubd) + Db);
-                r.ubt[p] = f32_up(uv);
-                double lv = (lb + E) * invM;
-                lv -= kTiny * fabs(lv);
-                r.lbt[p] = (lv > 0.0) ? f32_down(lv) : 0.0f;
+            // a decision without a valid block is an internal error: it is
+            // counted (the call then fails) and the point keeps a valid block
+            if (cbest < 0 || cbest >= k) {
+                bad = true;
+                cbest = ao >= 0 ? ao : 0;
+            }
+            lbf = fminf(lbf, hd.lbout32);
+            {
+                const float t = ubf - r.clus32[cbest].z;
+                const float ut = __builtin_fmaf(fabsf(t), 0x1p-22f, t + 0x1p-120f);
+                const float lt = (lbf + Edn) * invMdn;
+                Bt[off] = make_float2(ut, fmaxf(lt, 0.0f));
             }
             if (cbest != ao) {
                 chg = true;
-                r.A[p] = cbest;
+                At[off] = cbest;
                 s_gflag[off / kWave] = -1;   // conservatively mixed from now on
                 s_gdirty[off / kWave] = 1;
                 if (WEIGHTED) fix_split(r.ws[p] * wsc, wh, wl);
             }
         }
-        n_rechk += (unsigned)__popcll(__ballot(rck));
+        n_rechk += (unsigned)__popcll(wave_ballot(rck));
+        n_bad += (unsigned)__popcll(wave_ballot(bad));
         // wave-aggregated transfer of the point's weight from the old to the new block
-        unsigned long long pend = __ballot(chg);
+        unsigned long long pend = wave_ballot(chg);
         n_chg += (unsigned)__popcll(pend);
         while (pend) {
             const int leader = __builtin_ctzll(pend);
             const int ka = __shfl(ao, leader, kWave);
             const int kb = __shfl(cbest, leader, kWave);
             const bool mine = chg && ao == ka && cbest == kb;
-            const unsigned long long mm = __ballot(mine);
+            const unsigned long long mm = wave_ballot(mine);
             long long vh, vl = 0;
             if (WEIGHTED) {
                 vh = wave_sum_ll(mine ? wh : 0);
@@ -757,7 +862,11 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
         s_cnt[wv][1] = n_skip;
         s_cnt[wv][2] = n_rechk;
         s_cnt[wv][3] = n_chg;
-        s_cnt[wv][4] = (unsigned long long)n_eval * (unsigned long long)ncand;
+        s_cnt[wv][4] = n_cand;
+        if (n_bad) {
+            unsigned long long* slot = r.cnt + (int64_t)(tile % kCntSlots) * kCntWords;
+            atomicAdd(slot + kCntInvalid, (unsigned long long)n_bad);
+        }
     }
     __syncthreads();
     // per 64-point group: the common block of its points (or -1, also when a

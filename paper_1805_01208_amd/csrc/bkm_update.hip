@@ -48,7 +48,7 @@ template <int D, typename RT>
 __device__ __forceinline__ void balance_body(RT r, const int bid)
 {
     DevState* st = r.st;
-    if (st->done || st->round_done) return;
+    if (round_over(st)) return;
     __shared__ double sh[1024 / kWave];
     const int k = r.k;
     const bool per_block = r.tsz != nullptr;
@@ -518,7 +518,7 @@ __device__ __forceinline__ void move_body(RT r, const int bid)
             r.I[c] = in;
             const double dacc = (r.clus[c].x + dl) * kUp;
             r.clus[c] = make_double2(dacc, 1.0 / in);
-            r.clus32[c] = make_float2(f32_up(dacc), f32_up(1.0 / in));
+            r.clus32[c] = make_float4(f32_up(dacc), f32_up(1.0 / in), f32_down(dacc), 0.0f);
             m = fmin(m, io / in);
             e = fmax(e, dl / in);
         }
@@ -568,8 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_init_points(RunDev r)
     if (i >= r.npad) return;
     r.A[i] = r.perm[i] >= 0 ? -1 : kPad;
     r.Aprev[i] = r.A[i];
-    r.ubt[i] = INFINITY;
-    r.lbt[i] = 0.0f;
+    r.bnd[i] = make_float2(INFINITY, 0.0f);
     if (i < r.ngroups) r.gdirty[i] = 0;
 }
 
@@ -645,7 +644,7 @@ __global__ __launch_bounds__(kBlock) void k_init_clusters(RunDev r, const double
         const double in = iinit ? iinit[c] : 1.0;
         r.I[c] = in;
         r.clus[c] = make_double2(0.0, 1.0 / in);
-        r.clus32[c] = make_float2(0.0f, f32_up(1.0 / in));
+        r.clus32[c] = make_float4(0.0f, f32_up(1.0 / in), 0.0f, 0.0f);
         for (int a = 0; a < kAcc; ++a) r.acc[(int64_t)c * kAcc + a] = 0;
         for (int j = 0; j < 2 * D; ++j) r.bb[(int64_t)c * 2 * D + j] = j < D ? ~0ULL : 0ULL;
     }
@@ -703,7 +702,7 @@ __global__ __launch_bounds__(1024) void k_set_step(RunDev r, const double* crm,
         r.I[c] = in;
         const double dacc = first ? 0.0 : (r.clus[c].x + dl) * kUp;
         r.clus[c] = make_double2(dacc, 1.0 / in);
-        r.clus32[c] = make_float2(f32_up(dacc), f32_up(1.0 / in));
+        r.clus32[c] = make_float4(f32_up(dacc), f32_up(1.0 / in), f32_down(dacc), 0.0f);
         m = fmin(m, io / in);
         e = fmax(e, dl / in);
     }
