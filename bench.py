@@ -173,7 +173,42 @@ def run_steps(bkm, torch, X, W, cfg, precision, steps, warmup, max_iter, tile=0,
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     tot = {key: sum(i[key] for i in infos) for key in infos[0]}
-    return wall, tot, infos[-1]
+    return wall, tot, infos[-1], out
+
+
+def error_vs_oracle(bkm, torch, X, Xh, W, cfg, out, samples=20000):
+    """Error of the last timed run against the oracle: its centers against
+    the exact weighted means of its blocks (all points, on the host), and one
+    fresh FP32+recheck sweep on its final centers and influence against the
+    oracle's brute-force argmin on a random sample of points (mismatches
+    outside and inside the 1e-12 tie gap)."""
+    import numpy as np
+    import oracle
+    k = cfg["k"]
+    A = out["A"].cpu().numpy()
+    C = out["centers"].cpu().numpy()
+    Wh = cfg["W"]
+    wsum = np.bincount(A, weights=Wh, minlength=k) if Wh is not None else \
+        np.bincount(A, minlength=k).astype(np.float64)
+    ne = wsum > 0
+    err = 0.0
+    for j, x in enumerate(Xh):
+        xs = np.asarray(x, dtype=np.float64)
+        ref = np.bincount(A, weights=xs if Wh is None else Wh * xs, minlength=k)[ne] / wsum[ne]
+        scale = max(float(np.max(np.abs(ref))), float(xs.max() - xs.min()))
+        err = max(err, float(np.max(np.abs(C[ne, j] - ref))) / scale)
+    I = out["influence"].cpu().numpy()
+    As, _, _ = bkm.assign_sweeps(X, torch.from_numpy(C[None]), torch.from_numpy(I[None]),
+                                 precision="f32_recheck")
+    rng = np.random.default_rng(4242)
+    idx = np.sort(rng.choice(len(A), size=min(samples, len(A)), replace=False))
+    Ao, best, second = oracle.assign([np.asarray(x[idx], dtype=np.float64) for x in Xh], C, I)
+    bad = As[0].cpu().numpy()[idx] != Ao
+    tie = (second - best) / np.maximum(best, 1e-300) < 1e-12
+    return {"sample_points": int(len(idx)), "assignment_mismatches": int(np.sum(bad & ~tie)),
+            "mismatches_at_ties": int(np.sum(bad & tie)), "max_center_rel_err": err,
+            "block_weights_exact": bool(Wh is not None or np.array_equal(
+                out["block_weights"].cpu().numpy(), wsum))}
 
 
 FP64_PEAK_TFLOPS = 78.6
@@ -270,8 +305,9 @@ def main():
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c5"])
     ap.add_argument("--n", type=int, default=None, help="override the workload size")
     ap.add_argument("--max-iter", type=int, default=50)
-    ap.add_argument("--tile", type=int, default=0, help="points per tile (0: library default)")
-    ap.add_argument("--super", type=int, default=0, help="tiles per super-tile (0: default)")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="points per tile (0: the library's autotuner, -1: the n/k rule)")
+    ap.add_argument("--super", type=int, default=0, help="tiles per super-tile (0: tuned/default)")
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -313,14 +349,28 @@ def main():
         graph_bench(args, torch, bkm, cfg, X)
         return
 
+    # the tiling: the autotuner's choice (measured here once, before the timed
+    # steps, or taken from its cache), unless fixed on the command line
+    tune = None
+    tile, sup = args.tile, args.super
+    if tile == 0:
+        t_tune = time.perf_counter()
+        tune = bkm.autotune(X, cfg["k"], W=W, precision="f32_recheck", super_tiles=sup)
+        tune["seconds"] = time.perf_counter() - t_tune
+        print(f"[bench] autotuned tiling: {tune}", file=sys.stderr, flush=True)
+        tile, sup = tune["tile_points"], tune["super_tiles"]
+    elif tile < 0:
+        tile = 1024 if n / cfg["k"] >= 2048 else 512 if n / cfg["k"] >= 512 else 256
+    sup = sup or 16
+
     extra = {}
     if args.sample_init:
         extra.update(sample_init=True, seed=1)
     if args.targets:
         extra["target_sizes"] = torch.from_numpy(
             np.random.default_rng(9).lognormal(0.0, 0.5, cfg["k"])).cuda()
-    wall, tot, last = run_steps(bkm, torch, X, W, cfg, "f32_recheck", args.steps, args.warmup,
-                                args.max_iter, args.tile, args.super, extra)
+    wall, tot, last, outs = run_steps(bkm, torch, X, W, cfg, "f32_recheck", args.steps,
+                                      args.warmup, args.max_iter, tile, sup, extra)
     sweeps = tot["sweeps"]
     value = n * sweeps / wall
     ms_per_step = 1e3 * wall / args.steps
@@ -329,8 +379,8 @@ def main():
 
     fp64 = None
     if args.fp64_steps > 0:
-        wall64, tot64, _ = run_steps(bkm, torch, X, W, cfg, "f64", args.fp64_steps, 1,
-                                     args.max_iter, args.tile, args.super, extra)
+        wall64, tot64, _, _ = run_steps(bkm, torch, X, W, cfg, "f64", args.fp64_steps, 1,
+                                     args.max_iter, tile, sup, extra)
         sweep64_s = tot64["sweep_ms"] / 1e3 / tot64["sweeps"]
         algo64 = algorithmic_bytes(tot64, d, "f64", weighted) / tot64["sweeps"]
         fp64 = {"value": n * tot64["sweeps"] / wall64, "ms_per_step": 1e3 * wall64 / args.fp64_steps,
@@ -341,7 +391,6 @@ def main():
     sweep_s = tot["sweep_ms"] / 1e3 / sweeps
     algo = algorithmic_bytes(tot, d, "f32_recheck", weighted) / sweeps
     achieved = algo / sweep_s / 1e9
-    tile = args.tile or 1024
     # the committed counters are for the default run only
     traffic = None if (args.sample_init or args.targets) else measured_traffic(cfg["name"], tile)
 
@@ -357,12 +406,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32_screen+f64_recheck",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "n": n, "d": d, "k": cfg["k"], "eps": cfg["eps"],
                    "weighted": weighted, "precision": "f32_recheck", "max_iter": args.max_iter,
                    "max_balance_iter": 20, "hilbert_order": 16, "tile_points": tile,
-                   "super_tiles": args.super or 16, "sample_init": bool(args.sample_init),
+                   "super_tiles": sup, "sample_init": bool(args.sample_init),
                    "target_sizes": "lognormal(0,0.5), seed 9" if args.targets else None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -379,6 +428,8 @@ def main():
                                 "bootstrap_ms", "total_ms")},
         "balanced": last["balanced"],
         "imbalance": last["imbalance"],
+        "autotune": tune,
+        "error_vs_oracle": error_vs_oracle(bkm, torch, X, Xh, W, cfg, outs),
     }
     if fp64 is not None:
         line["fp64_plain"] = fp64

@@ -70,8 +70,11 @@ typedef struct {
     int32_t precision;        /* bkm_precision; default BKM_PREC_F32_RECHECK */
     int32_t use_bounds;       /* 1: Hamerly upper/lower bounds skip points (Sec. 4.3); default 1 */
     int32_t tile_points;      /* points per tile of the sweep: 256, 512 or 1024; 0 = chosen
-                                 from the mean number of points per block */
-    int32_t super_tiles;      /* tiles per candidate super-tile, >= 1; 0 = default */
+                                 by the autotuner (bkm_autotune: cached, or measured on
+                                 first use); -1 = chosen from the mean number of points
+                                 per block (1024 from 2048 up, 512 from 512, else 256) */
+    int32_t super_tiles;      /* tiles per candidate super-tile, >= 1; 0 = the tuned value
+                                 with tile_points = 0, else 16 */
     int32_t timing;           /* 1: time every kernel of the round loop with HIP events on
                                  `stream` and report the sums in bkm_info; default 0 */
     int32_t sample_init;      /* 1: random-sample initialization before the main loop (the
@@ -238,6 +241,40 @@ int bkm_assign_sweeps(const bkm_points* pts, int32_t k, int32_t steps,
                       int32_t precision, int32_t use_bounds, int32_t tile_points,
                       int32_t* assignment_out, double* block_weights_out,
                       bkm_info* info, void* stream);
+
+/* Autotuner of the sweep's tiling.  Tile size (256, 512, 1024) and tiles per
+ * super-tile (8, 16, 24, 32) are chosen by timing short balanced k-means runs
+ * (3 rounds, twice each, the faster counts) of every combination on a
+ * strided sample of at most 2^23 of the points, with k scaled to keep the
+ * mean number of points per block; the objective is the device time of the
+ * candidate filters and the sweep per sweep.  Choices are cached per (device
+ * architecture, d, precision, weighting, half-octave of n/k, octave of n up
+ * to 2^23): in the process, and, when the environment variable
+ * BKM_TUNE_CACHE names a file, in that file (read once, appended to).
+ * bkm_balanced_kmeans and bkm_balanced_kmeans_batched use it for
+ * tile_points = 0 (the batched call per instance); the random-sample rounds
+ * take the n/k rule.  Results never depend on the tiling, only the time.
+ *   force  1: measure even if cached (the new choice replaces the old).
+ *   out    [host] the choice and, when measured, the timings.
+ * Errors as bkm_balanced_kmeans. */
+typedef struct {
+    int32_t tile_points;      /* chosen tile size */
+    int32_t super_tiles;      /* chosen tiles per super-tile (params.super_tiles if set) */
+    int32_t from_cache;       /* 1: taken from the cache, nothing measured */
+    int32_t candidates;       /* configurations timed */
+    double best_us;           /* per-sweep time of the choice on the sample (us) */
+    double default_us;        /* per-sweep time of the n/k rule with 16 tiles per super-tile */
+    int64_t sample_points;    /* points of the sample */
+    int32_t sample_k;         /* blocks of the sample runs */
+    int32_t pad;
+} bkm_tune_result;
+
+int bkm_autotune(const bkm_points* pts, const bkm_params* prm, int32_t force,
+                 bkm_tune_result* out, void* stream);
+
+/* Forgets every cached tuning choice of this process (the cache file is not
+ * touched). */
+void bkm_autotune_clear(void);
 
 /* Statistics of a given assignment (Sec. 2): block weights, weighted block
  * means (NaN for an empty block), imbalance, k-means objective, empty and

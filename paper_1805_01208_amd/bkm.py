@@ -62,6 +62,13 @@ class GraphStats(C.Structure):
                 ("exact_blocks", C.c_int32)]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("tile_points", C.c_int32), ("super_tiles", C.c_int32),
+                ("from_cache", C.c_int32), ("candidates", C.c_int32), ("best_us", C.c_double),
+                ("default_us", C.c_double), ("sample_points", C.c_int64),
+                ("sample_k", C.c_int32), ("pad", C.c_int32)]
+
+
 class KnnInfo(C.Structure):
     _fields_ = [("group_visits", C.c_int64), ("layout_ms", C.c_double), ("search_ms", C.c_double)]
 
@@ -76,7 +83,7 @@ _LIB = None
 FUNCTIONS = ("bkm_default_params", "bkm_init_centers_sfc", "bkm_balanced_kmeans",
              "bkm_balanced_kmeans_batched", "bkm_assign_sweeps", "bkm_partition_stats",
              "bkm_partition_stats_noalloc", "bkm_knn", "bkm_knn_graph", "bkm_graph_metrics",
-             "bkm_last_error")
+             "bkm_autotune", "bkm_autotune_clear", "bkm_last_error")
 
 
 def lib():
@@ -104,12 +111,16 @@ def lib():
         L.bkm_knn_graph.argtypes = [C.c_int64, C.c_int32, P, P, P, C.POINTER(C.c_int64), P]
         L.bkm_graph_metrics.argtypes = [C.c_int64, C.c_int64, P, P, P, C.c_int32, P, P, P,
                                         C.POINTER(GraphStats), P]
+        L.bkm_autotune.argtypes = [C.POINTER(Points), C.POINTER(Params), C.c_int32,
+                                   C.POINTER(TuneResult), P]
+        L.bkm_autotune_clear.argtypes = []
+        L.bkm_autotune_clear.restype = None
         L.bkm_last_error.argtypes = []
         L.bkm_last_error.restype = C.c_char_p
         for f in ("bkm_init_centers_sfc", "bkm_balanced_kmeans", "bkm_assign_sweeps",
                   "bkm_partition_stats", "bkm_partition_stats_noalloc",
                   "bkm_balanced_kmeans_batched", "bkm_knn",
-                  "bkm_knn_graph", "bkm_graph_metrics"):
+                  "bkm_knn_graph", "bkm_graph_metrics", "bkm_autotune"):
             getattr(L, f).restype = C.c_int
         _LIB = L
     return _LIB
@@ -308,6 +319,25 @@ def assign_sweeps(X, centers_seq, influence_seq, precision="f32_recheck", use_bo
                                    1 if use_bounds else 0, int(tile_points), _ptr(A), _ptr(bw),
                                    C.byref(info), _stream()))
     return A, bw, info_dict(info)
+
+
+def autotune(X, k, W=None, precision="f32_recheck", force=False, super_tiles=0, **kw):
+    """The autotuner's tiling for these points (cached, or measured now):
+    dict of the bkm_tune_result fields."""
+    pts = make_points(X, W)
+    prm = default_params(k)
+    prm.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    prm.super_tiles = int(super_tiles)
+    for f, v in kw.items():
+        setattr(prm, f, v)
+    res = TuneResult()
+    _check(lib().bkm_autotune(C.byref(pts), C.byref(prm), 1 if force else 0, C.byref(res),
+                              _stream()))
+    return {f: getattr(res, f) for f, _ in TuneResult._fields_ if f != "pad"}
+
+
+def autotune_clear():
+    lib().bkm_autotune_clear()
 
 
 def partition_stats(X, A, k, eps=0.03, W=None, target_sizes=None):

@@ -12,7 +12,10 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -342,7 +345,7 @@ int bootstrap(RunDev& r, int order, hipStream_t s, bool tiles, double eps = 0.0,
     return BKM_OK;
 }
 
-int check_tile(int T) { return T == 0 || T == 256 || T == 512 || T == 1024; }
+int check_tile(int T) { return T == -1 || T == 0 || T == 256 || T == 512 || T == 1024; }
 
 // Arguments of one balanced k-means run.
 int check_run(const bkm_points* pts, const bkm_params* prm)
@@ -358,7 +361,8 @@ int check_run(const bkm_points* pts, const bkm_params* prm)
     if ((rc = check_order(pts->d, p.hilbert_order))) return rc;
     if (p.precision != BKM_PREC_F64 && p.precision != BKM_PREC_F32_RECHECK)
         return fail(BKM_EINVAL, "precision %d unknown", p.precision);
-    if (!check_tile(p.tile_points)) return fail(BKM_EINVAL, "tile_points %d not 0/256/512/1024", p.tile_points);
+    if (!check_tile(p.tile_points))
+        return fail(BKM_EINVAL, "tile_points %d not -1/0/256/512/1024", p.tile_points);
     if (p.super_tiles < 0) return fail(BKM_EINVAL, "super_tiles must be >= 0");
     if (!(p.recheck_rel_gap >= 0.0) || !std::isfinite(p.recheck_rel_gap))
         return fail(BKM_EINVAL, "recheck_rel_gap must be finite and >= 0");
@@ -368,7 +372,7 @@ int check_run(const bkm_points* pts, const bkm_params* prm)
     return BKM_OK;
 }
 
-// Tile size for tile_points = 0, from the mean number of points per block:
+// Tile size for tile_points = -1, from the mean number of points per block:
 // smaller blocks want smaller tiles, whose boxes keep fewer candidates.
 int auto_tile(int64_t n, int k)
 {
@@ -416,6 +420,212 @@ struct BatchRes {
     }
 };
 
+int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_init,
+             const double* influence_init, int32_t* assignment_out, double* centers_out,
+             double* influence_out, double* block_weights_out, bkm_info* info, hipStream_t s,
+             bool presorted = false);
+
+// ------------------------------------------------------------- autotuner
+// Tile size and tiles per super-tile of the sweep, chosen by measurement.
+// A configuration is timed by short balanced k-means runs (kTuneRounds
+// rounds, twice, the faster counts) on a strided sample of at most
+// kTuneSample points with k scaled to keep the mean points per block; the
+// objective is the device time of the candidate filters and the sweep per
+// sweep.  Choices are cached per (device architecture, d, precision,
+// weighting, half-octave of n/k, octave of n capped at the sample size),
+// in the process and, when the environment names a file in BKM_TUNE_CACHE,
+// in that file (one line per key, read once, appended on every new entry).
+constexpr int kTuneTiles[] = {256, 512, 1024};
+constexpr int kTuneSupers[] = {8, 16, 24, 32};
+constexpr int64_t kTuneSample = int64_t(1) << 23;
+constexpr int kTuneRounds = 3;
+
+struct TuneEntry {
+    int T, ST;
+    double us;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(const bkm_points* pts, const bkm_params& p)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t c = arch.find(':');
+        if (c != std::string::npos) arch = arch.substr(0, c);
+    }
+    const int ppb = (int)std::lround(2.0 * std::log2((double)pts->n / (double)p.k));
+    const int nb = (int)std::min<double>(std::floor(std::log2((double)pts->n)),
+                                         std::log2((double)kTuneSample));
+    char buf[160];
+    snprintf(buf, sizeof(buf), "%s d%d p%d w%d ppb%d n%d", arch.c_str(), pts->d, p.precision,
+             pts->weights ? 1 : 0, ppb, nb);
+    return buf;
+}
+
+// Reads the cache file once (lines "key... | T ST us"); the mutex is held.
+void tune_load_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("BKM_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char line[256];
+    while (std::fgets(line, sizeof(line), f)) {
+        char* bar = std::strchr(line, '|');
+        if (!bar) continue;
+        *bar = 0;
+        std::string key(line);
+        while (!key.empty() && key.back() == ' ') key.pop_back();
+        TuneEntry e;
+        if (std::sscanf(bar + 1, "%d %d %lf", &e.T, &e.ST, &e.us) == 3 && check_tile(e.T) &&
+            e.T > 0 && e.ST >= 1)
+            g_tune[key] = e;
+    }
+    std::fclose(f);
+}
+
+void tune_store_locked(const std::string& key, const TuneEntry& e)
+{
+    g_tune[key] = e;
+    const char* path = std::getenv("BKM_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s | %d %d %.3f\n", key.c_str(), e.T, e.ST, e.us);
+    std::fclose(f);
+}
+
+// Device time per sweep of the candidate filters and the sweep for one
+// configuration on the sample (the faster of two short runs).
+int tune_time(const bkm_points* ps, const bkm_params& p, int T, int ST, int32_t* abuf,
+              double* cbuf, hipStream_t s, double* us)
+{
+    bkm_params q = p;
+    q.tile_points = T;
+    q.super_tiles = ST;
+    q.timing = 1;
+    q.sample_init = 0;
+    q.target_sizes = nullptr;
+    q.max_iter = kTuneRounds;
+    *us = INFINITY;
+    for (int rep = 0; rep < 2; ++rep) {
+        bkm_info info;
+        const int rc = run_core(ps, q, nullptr, nullptr, abuf, cbuf, nullptr, nullptr, &info, s);
+        if (rc < 0) return rc;
+        if (info.sweeps > 0)
+            *us = std::min(*us, 1e3 * (info.cand_ms + info.sweep_ms) / info.sweeps);
+    }
+    return BKM_OK;
+}
+
+// Measures every configuration on a strided sample of the points.
+int tune_measure(const bkm_points* pts, const bkm_params& p, hipStream_t s, TuneEntry* best,
+                 bkm_tune_result* res)
+{
+    const int64_t n = pts->n;
+    const int64_t stride = std::max<int64_t>(1, (n + kTuneSample - 1) / kTuneSample);
+    const int64_t ns = (n + stride - 1) / stride;
+    const int ks = (int)std::max<int64_t>(1, std::min<int64_t>(ns, std::llround((double)p.k * ns / n)));
+    const size_t es = pts->dtype == BKM_F32 ? sizeof(float) : sizeof(double);
+    Sizes z;
+    for (int j = 0; j < pts->d; ++j) z.add<char>((size_t)ns * es);
+    if (pts->weights) z.add<double>((size_t)ns);
+    z.add<int32_t>((size_t)ns);
+    z.add<double>((size_t)ks * pts->d);
+    Arena a;
+    a.s = s;
+    HIPCHK(hipMallocAsync((void**)&a.base, z.total, s));
+    bkm_points ps = *pts;
+    ps.n = ns;
+    for (int j = 0; j < pts->d; ++j) {
+        char* dst = a.take<char>((size_t)ns * es);
+        HIPCHK(hipMemcpy2DAsync(dst, es, pts->coords[j], es * stride, es, ns,
+                                hipMemcpyDeviceToDevice, s));
+        ps.coords[j] = dst;
+    }
+    if (pts->weights) {
+        double* w = a.take<double>((size_t)ns);
+        HIPCHK(hipMemcpy2DAsync(w, sizeof(double), pts->weights, sizeof(double) * stride,
+                                sizeof(double), ns, hipMemcpyDeviceToDevice, s));
+        ps.weights = w;
+    }
+    int32_t* abuf = a.take<int32_t>((size_t)ns);
+    double* cbuf = a.take<double>((size_t)ks * pts->d);
+    bkm_params q = p;
+    q.k = ks;
+    best->us = INFINITY;
+    best->T = auto_tile(n, p.k);
+    best->ST = 16;
+    int timed = 0;
+    double def_us = 0.0;
+    for (int T : kTuneTiles) {
+        for (int ST : kTuneSupers) {
+            double us;
+            const int rc = tune_time(&ps, q, T, ST, abuf, cbuf, s, &us);
+            if (rc < 0) return rc;
+            ++timed;
+            if (T == auto_tile(n, p.k) && ST == 16) def_us = us;
+            if (us < best->us) *best = TuneEntry{T, ST, us};
+        }
+    }
+    if (res) {
+        res->candidates = timed;
+        res->default_us = def_us;
+        res->sample_points = ns;
+        res->sample_k = ks;
+    }
+    return BKM_OK;
+}
+
+// The tuned configuration for these points and parameters: from the cache,
+// or measured now (and cached).
+int tuned_tiles(const bkm_points* pts, const bkm_params& p, hipStream_t s, int* T, int* ST,
+                bkm_tune_result* res, bool force = false)
+{
+    const std::string key = tune_key(pts, p);
+    if (res) std::memset(res, 0, sizeof(*res));
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find(key);
+        if (!force && it != g_tune.end()) {
+            *T = it->second.T;
+            *ST = p.super_tiles ? p.super_tiles : it->second.ST;
+            if (res) {
+                res->tile_points = *T;
+                res->super_tiles = *ST;
+                res->from_cache = 1;
+                res->best_us = it->second.us;
+            }
+            return BKM_OK;
+        }
+    }
+    TuneEntry e;
+    const int rc = tune_measure(pts, p, s, &e, res);
+    if (rc < 0) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_store_locked(key, e);
+    }
+    *T = e.T;
+    *ST = p.super_tiles ? p.super_tiles : e.ST;
+    if (res) {
+        res->tile_points = *T;
+        res->super_tiles = *ST;
+        res->from_cache = 0;
+        res->best_us = e.us;
+    }
+    return BKM_OK;
+}
+
 // One balanced k-means run (Alg. 2 around Alg. 1) on checked arguments.
 // centers_init ([k][d]) and influence_init ([k]) may be NULL (SFC centers,
 // influence 1); with centers given, k may exceed n (a sample round).
@@ -423,11 +633,12 @@ struct BatchRes {
 int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_init,
              const double* influence_init, int32_t* assignment_out, double* centers_out,
              double* influence_out, double* block_weights_out, bkm_info* info, hipStream_t s,
-             bool presorted = false)
+             bool presorted)
 {
     int rc;
-    const int T = p.tile_points ? p.tile_points : auto_tile(pts->n, p.k);
-    const int ST = p.super_tiles ? p.super_tiles : 16;
+    int T = p.tile_points > 0 ? p.tile_points : auto_tile(pts->n, p.k);
+    int ST = p.super_tiles ? p.super_tiles : 16;
+    if (p.tile_points == 0 && (rc = tuned_tiles(pts, p, s, &T, &ST, nullptr)) < 0) return rc;
     RunDev r;
     plan(r, pts, p.k, T, ST, p.precision, p.use_bounds ? 1 : 0, p.recheck_rel_gap);
     r.tsz = p.target_sizes;
@@ -491,6 +702,9 @@ int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_i
         bkm_params q = p;
         q.sample_init = 0;
         q.max_iter = 1;
+        // the short sample rounds take the n/k rule rather than tuning
+        // every sample size
+        if (q.tile_points == 0) q.tile_points = -1;
         q.delta_threshold = dthr;
         q.timing = 0;
         for (int64_t sz = s0; sz < n; sz *= 2) {
@@ -954,6 +1168,25 @@ int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int3
 
 const char* bkm_last_error(void) { return g_err.c_str(); }
 
+int bkm_autotune(const bkm_points* pts, const bkm_params* prm, int32_t force,
+                 bkm_tune_result* out, void* stream)
+{
+    g_err.clear();
+    int rc = check_run(pts, prm);
+    if (rc) return rc;
+    if (!out) return fail(BKM_EINVAL, "out is NULL");
+    keep_pool_memory();
+    int T = 0, ST = 0;
+    rc = tuned_tiles(pts, *prm, (hipStream_t)stream, &T, &ST, out, force != 0);
+    return rc < 0 ? rc : BKM_OK;
+}
+
+void bkm_autotune_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+}
+
 int bkm_init_centers_sfc(const bkm_points* pts, int32_t k, int32_t hilbert_order,
                          double* centers_out, int32_t* perm_out, uint64_t* keys_out,
                          void* stream)
@@ -1122,9 +1355,13 @@ int bkm_balanced_kmeans_batched(const bkm_points* pts, const bkm_params* prm, in
     z.add<DevState>(count);
     for (int i = 0; i < count; ++i) {
         const bkm_params& p = prm[i];
-        const int T = p.tile_points ? p.tile_points : auto_tile(pts[i].n, p.k);
-        plan(rs[i], &pts[i], p.k, T, p.super_tiles ? p.super_tiles : 16, p.precision,
-             p.use_bounds ? 1 : 0, p.recheck_rel_gap);
+        int T = p.tile_points > 0 ? p.tile_points : auto_tile(pts[i].n, p.k);
+        int ST = p.super_tiles ? p.super_tiles : 16;
+        if (p.tile_points == 0) {
+            const int rc = tuned_tiles(&pts[i], p, s, &T, &ST, nullptr);
+            if (rc < 0) return rc;
+        }
+        plan(rs[i], &pts[i], p.k, T, ST, p.precision, p.use_bounds ? 1 : 0, p.recheck_rel_gap);
         rs[i].tsz = p.target_sizes;
         rs[i].erosion = p.erosion;
         z.total += layout(rs[i], nullptr, true);

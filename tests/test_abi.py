@@ -45,7 +45,7 @@ def test_struct_layouts_match_header(bkm, tmp_path):
     header, compiled by the host C compiler."""
     structs = {"bkm_points": bkm.Points, "bkm_params": bkm.Params, "bkm_info": bkm.Info,
                "bkm_stats": bkm.Stats, "bkm_graph_stats": bkm.GraphStats,
-               "bkm_knn_info": bkm.KnnInfo}
+               "bkm_knn_info": bkm.KnnInfo, "bkm_tune_result": bkm.TuneResult}
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "bkm.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
