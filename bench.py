@@ -311,6 +311,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-error-check", action="store_true",
+                    help="skip the check against the oracle (profiling runs)")
     ap.add_argument("--graph", action="store_true",
                     help="measure the graph-quality evaluation instead of the partitioner")
     ap.add_argument("--knn", type=int, default=6, help="neighbours per point (--graph)")
@@ -429,7 +431,8 @@ def main():
         "balanced": last["balanced"],
         "imbalance": last["imbalance"],
         "autotune": tune,
-        "error_vs_oracle": error_vs_oracle(bkm, torch, X, Xh, W, cfg, outs),
+        "error_vs_oracle": None if args.no_error_check else
+        error_vs_oracle(bkm, torch, X, Xh, W, cfg, outs),
     }
     if fp64 is not None:
         line["fp64_plain"] = fp64

@@ -260,7 +260,8 @@ size_t layout(RunDev& r, Arena* a, bool full)
             both((double*)nullptr, (size_t)k + 1, r.tpre);
         }
         both((double2*)nullptr, (size_t)k, r.clus);
-        both((float4*)nullptr, (size_t)k, r.clus32);
+        both((float2*)nullptr, (size_t)k, r.clus32);
+        both((float*)nullptr, (size_t)k, r.clusdn);
         both((int32_t*)nullptr, (size_t)(np / kWave), r.gblk);
         both((int32_t*)nullptr, (size_t)(np / kWave), r.gdirty);
         both((int32_t*)nullptr, np, r.Aprev);

@@ -146,8 +146,9 @@ struct RunDev {
     double* tL;               // [k] weight limit of each block (with target sizes)
     double* tpre;             // [k+1] prefix sums of the target sizes in index order; [k] = total
     double2* clus;            // [k] (accumulated movement, 1/influence)
-    float4* clus32;           // [k] FP32 copies: movement rounded up, 1/influence rounded
-                              // up (Hamerly test), movement rounded down (bound stores)
+    float2* clus32;           // [k] FP32 copies for the Hamerly test: movement and
+                              // 1/influence, both rounded up
+    float* clusdn;            // [k] movement rounded down to FP32 (bound stores)
     int32_t* Aprev;           // [npad] block of each point at the previous round end
     int32_t* gdirty;          // [ngroups] 1 if a point of the group changed block in this round
     int32_t* gblk;            // [ngroups] block of every point of the group after the last

@@ -449,7 +449,8 @@ __global__ __launch_bounds__(kBlock) void k_tilecand_multi(const RunDev* rs, con
 //   * bounds of a sure point: RN(sqrt_raw(d2) (1 + 10u) + ubadd32) >= the
 //     FP64 form (sqrt_raw(d2) + 2^-46)(1 + 7u) + dmax; RN(es kM - slack32)
 //     <= es (1 - kScr) - slack for both signs of the result.
-//   * stored upper bound: t = RN(ubf - Ddn) with the movement rounded down;
+//   * stored upper bound: t = RN(ubf - Ddn) with the movement rounded down
+//     (clusdn);
 //     RN(|t| 2^-22 + (t + 2^-120)) >= ubf - Ddn.
 //   * stored lower bound: RN(RN(lbf + Edn) invMdn) <= (lb + E) / M when
 //     lbf + Edn >= 0 (Edn <= E, invMdn <= (1 - 2^-22) / M); a negative
@@ -541,7 +542,7 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
             s_c64[3][tid] = 1.0;
         }
     }
-    float4 cl[PPT];
+    float2 cl[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) cl[q] = r.clus32[aold[q] > 0 ? aold[q] : 0];
     // lower-bound frame in FP32, rounded so that every bound stays valid;
@@ -810,7 +811,7 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
             }
             lbf = fminf(lbf, hd.lbout32);
             {
-                const float t = ubf - r.clus32[cbest].z;
+                const float t = ubf - r.clusdn[cbest];
                 const float ut = __builtin_fmaf(fabsf(t), 0x1p-22f, t + 0x1p-120f);
                 const float lt = (lbf + Edn) * invMdn;
                 Bt[off] = make_float2(ut, fmaxf(lt, 0.0f));

@@ -518,7 +518,8 @@ __device__ __forceinline__ void move_body(RT r, const int bid)
             r.I[c] = in;
             const double dacc = (r.clus[c].x + dl) * kUp;
             r.clus[c] = make_double2(dacc, 1.0 / in);
-            r.clus32[c] = make_float4(f32_up(dacc), f32_up(1.0 / in), f32_down(dacc), 0.0f);
+            r.clus32[c] = make_float2(f32_up(dacc), f32_up(1.0 / in));
+            r.clusdn[c] = f32_down(dacc);
             m = fmin(m, io / in);
             e = fmax(e, dl / in);
         }
@@ -644,7 +645,8 @@ __global__ __launch_bounds__(kBlock) void k_init_clusters(RunDev r, const double
         const double in = iinit ? iinit[c] : 1.0;
         r.I[c] = in;
         r.clus[c] = make_double2(0.0, 1.0 / in);
-        r.clus32[c] = make_float4(0.0f, f32_up(1.0 / in), 0.0f, 0.0f);
+        r.clus32[c] = make_float2(0.0f, f32_up(1.0 / in));
+        r.clusdn[c] = 0.0f;
         for (int a = 0; a < kAcc; ++a) r.acc[(int64_t)c * kAcc + a] = 0;
         for (int j = 0; j < 2 * D; ++j) r.bb[(int64_t)c * 2 * D + j] = j < D ? ~0ULL : 0ULL;
     }
@@ -702,7 +704,8 @@ __global__ __launch_bounds__(1024) void k_set_step(RunDev r, const double* crm,
         r.I[c] = in;
         const double dacc = first ? 0.0 : (r.clus[c].x + dl) * kUp;
         r.clus[c] = make_double2(dacc, 1.0 / in);
-        r.clus32[c] = make_float4(f32_up(dacc), f32_up(1.0 / in), f32_down(dacc), 0.0f);
+        r.clus32[c] = make_float2(f32_up(dacc), f32_up(1.0 / in));
+        r.clusdn[c] = f32_down(dacc);
         m = fmin(m, io / in);
         e = fmax(e, dl / in);
     }
