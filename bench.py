@@ -146,6 +146,65 @@ def cpu_baseline(cfg, budget_s):
                        f"block weights, balance test): {t:.2f} s")
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_pruned(cfg, budget_s):
+    """The pruned FP64 CPU baseline (Hamerly bounds + bounding-box candidates,
+    OpenMP; equal to the oracle bit for bit) running the whole balanced k-means
+    on a random sample of the workload with k scaled to keep the mean block
+    size; points per second per sweep (sample size x sweeps / time in sweeps),
+    median of 5 runs, on all host threads and on one thread."""
+    import numpy as np
+    import baseline
+    import oracle
+    X = cfg["X"]
+    n = len(X[0])
+    k = cfg["k"]
+    rng = np.random.default_rng(2468)
+
+    def sample(m):
+        idx = np.sort(rng.choice(n, size=m, replace=False))
+        Xs = [np.asarray(x[idx], dtype=np.float64) for x in X]
+        ks = max(1, min(m, int(round(k * m / n))))
+        C0, _, _ = oracle.init_centers_sfc(Xs, ks, 16)
+        return Xs, ks, C0
+
+    def runs(m, reps):
+        Xs, ks, C0 = sample(m)
+        vals, last = [], None
+        for _ in range(reps):
+            last = baseline.balanced_kmeans(Xs, ks, cfg["eps"], C0)["info"]
+            vals.append(m * last["sweeps"] / max(last["sweep_seconds"], 1e-9))
+        return float(np.median(vals)), ks, last
+
+    out = {}
+    all_threads = baseline.num_threads()
+    for label, threads in (("all_threads", all_threads), ("one_thread", 1)):
+        baseline.set_threads(threads)
+        m0 = min(n, 100_000)
+        _, _, pilot = runs(m0, 1)
+        per_run = budget_s / 10.0
+        m = int(min(n, max(m0, m0 * per_run / max(pilot["total_seconds"], 1e-6))))
+        v, ks, last = runs(m, 5)
+        out[label] = {"value": v, "unit": "points/s", "cores": threads,
+                      "sample": f"{m} random points, k={ks}, a whole balanced k-means run "
+                                f"({last['sweeps']} sweeps, skip {last['skipped'] / max(1, last['skipped'] + last['evaluated']):.3f}), "
+                                f"median of 5"}
+    baseline.set_threads(all_threads)
+    out["kind"] = "pruned FP64 (Hamerly + box candidates), equal to the oracle"
+    out["cpu_model"] = cpu_model()
+    return out
+
+
 def run_steps(bkm, torch, X, W, cfg, precision, steps, warmup, max_iter, tile=0, sup=0,
               extra=None):
     n = X[0].numel()
@@ -440,6 +499,9 @@ def main():
         line["sweep_speedup_vs_fp64"] = fp64["avg_sweep_us"] / (sweep_s * 1e6)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+        line["cpu_baseline"]["cpu_model"] = cpu_model()
+        if W is None:
+            line["cpu_pruned"] = cpu_pruned(cfg, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 

@@ -7,9 +7,15 @@ shell cloud is 2.6e11 distance evaluations), so the checks are:
   * Hilbert keys of every point against the oracle's keys (bit-exact), the
     sort order and the initial centers against their definitions (Alg. 2);
   * sweeps with injected states (Alg. 1, bounds carried across steps):
-    assignments of a random sample of points against the oracle's
-    brute-force argmin computed for those points alone (Sec. 4.2), block
-    weights of every step against an exact count;
+    assignments against the oracle's brute-force argmin (Sec. 4.2) -- of
+    every point of the 2D refined cloud (16M, both precisions), of an 8M
+    random sample of the 3D shell cloud and a 1M sample of the 250M cloud
+    (the oracle takes about 2e9 point-center pairs per second on 16 host
+    threads; all 64M x 4096 pairs would take over two minutes per step) --
+    block weights of every step against an exact count;
+  * the batched workload's full recipe (256 instances of up to 2M points):
+    every instance identical to its separate run, the smallest ones also to
+    the oracle's run;
   * full runs: block weights against an exact recount, centers against the
     weighted means of their blocks (Alg. 2), the balance bound when balanced.
 """
@@ -22,7 +28,8 @@ from paper_1805_01208_amd import workloads
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow, pytest.mark.timeout(900)]
 
-SAMPLE = 20000
+SAMPLE_C3 = 8_000_000
+SAMPLE_C5 = 1_000_000
 
 
 @pytest.fixture(scope="module")
@@ -65,7 +72,7 @@ def check_bootstrap(cfg, X):
     return ref
 
 
-def check_sweeps(cfg, X, C0, precision, seed):
+def check_sweeps(cfg, X, C0, precision, seed, sample=None):
     from paper_1805_01208_amd import bkm
     k = cfg["k"]
     Xw = widened(cfg["X"])
@@ -80,11 +87,12 @@ def check_sweeps(cfg, X, C0, precision, seed):
                                     precision=precision)
     A = A.cpu().numpy()
     bw = bw.cpu().numpy()
-    idx = np.sort(rng.choice(n, size=SAMPLE, replace=False))
-    Xs = [x[idx] for x in Xw]
+    idx = np.arange(n) if sample is None else np.sort(rng.choice(n, size=sample, replace=False))
+    Xs = Xw if sample is None else [x[idx] for x in Xw]
     for s in range(len(Cs)):
+        print(f"  step {s}: oracle on {len(idx)} points", flush=True)
         Ao, best, second = oracle.assign(Xs, Cs[s], Is[s])
-        assert_assignment_parity(A[s][idx], Ao, best, second, f"step {s}")
+        assert_assignment_parity(A[s][idx], Ao, best, second, f"step {s}", Xs, Cs[s], Is[s])
         assert np.array_equal(bw[s], np.bincount(A[s], minlength=k).astype(np.float64))
     assert info["skipped"] > 0
     return info
@@ -131,7 +139,7 @@ def test_c2_refined2d_16M(c2):
 def test_c3_shells3d_64M(c3):
     cfg, X = c3
     C0 = check_bootstrap(cfg, X)
-    check_sweeps(cfg, X, C0, "f32_recheck", 31)
+    check_sweeps(cfg, X, C0, "f32_recheck", 31, SAMPLE_C3)
     g = check_run(cfg, X)
     assert g["info"]["balanced"] == 1
 
@@ -139,7 +147,7 @@ def test_c3_shells3d_64M(c3):
 def test_c5_radial2d_250M_weighted(c5):
     cfg, X, W = c5
     C0 = check_bootstrap(cfg, X)
-    check_sweeps(cfg, X, C0, "f32_recheck", 51)
+    check_sweeps(cfg, X, C0, "f32_recheck", 51, SAMPLE_C5)
     check_run(cfg, X, W=W)
 
 
@@ -188,3 +196,32 @@ def test_c2_knn_graph_and_metrics(c2):
 def test_c3_knn(c3):
     cfg, X = c3
     check_knn_graph(cfg, X, 10)
+
+
+def test_c4_batched_full_recipe():
+    """The batched workload as the benchmark defines it: 256 instances, n
+    log-uniform in [1e4, 2e6], k log-uniform in [8, 512], even ids 2D
+    uniform, odd ids 3D Gaussian clusters, FP32+recheck, tiles from the
+    autotuner.  Every instance must equal its separate run; the four
+    smallest also the oracle's run."""
+    from paper_1805_01208_amd import bkm
+    cfgs = workloads.c4()
+    insts = [(cuda(c["X"]), c["k"]) for c in cfgs]
+    print(f"case full-size batched C4: {len(insts)} instances, "
+          f"{sum(len(c['X'][0]) for c in cfgs)} points", flush=True)
+    outs, rc = bkm.balanced_kmeans_batched(insts, max_iter=50)
+    assert rc in (0, 1)
+    for i, (inst, res) in enumerate(zip(insts, outs)):
+        g = bkm.balanced_kmeans(inst[0], inst[1], max_iter=50)
+        assert torch.equal(res["A"], g["A"]), f"instance {i}"
+        assert torch.equal(res["centers"], g["centers"]), f"instance {i}"
+        assert (res["info"]["rounds"], res["info"]["sweeps"]) == (g["info"]["rounds"],
+                                                                  g["info"]["sweeps"])
+    small = sorted(range(len(cfgs)), key=lambda i: len(cfgs[i]["X"][0]))[:4]
+    for i in small:
+        c = cfgs[i]
+        print(f"  oracle instance {i}: n={len(c['X'][0])} k={c['k']}", flush=True)
+        o = oracle.balanced_kmeans(widened(c["X"]), c["k"], 0.03, max_iter=50)
+        assert np.array_equal(outs[i]["A"].cpu().numpy(), o["A"]), f"instance {i}"
+        assert (outs[i]["info"]["rounds"], outs[i]["info"]["sweeps"]) == (o["info"]["rounds"],
+                                                                          o["info"]["sweeps"])
