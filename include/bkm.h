@@ -110,6 +110,16 @@ typedef struct {
                                      floor(n*S_c/tsum) + floor(n*t_c/(2*tsum)) (S_c the sum
                                      of the sizes before c), at most n-1.  Invalid sizes
                                      give BKM_EINVAL after the bounding box is taken */
+    int32_t debug_checks;     /* 0: off (default).  1: after every sweep and every center
+                                 move, check sampled points against a brute-force FP64
+                                 evaluation over all k centers: the stored Hamerly upper
+                                 bound covers the distance to the own center, the lower
+                                 bound is below the effective distance to every other
+                                 center, and after a sweep the block is an argmin (ties
+                                 within 1e-12); about 2^26 point-center pairs per check.
+                                 2: the same on every point.  Any violation fails the call
+                                 with BKM_EINTERNAL.  Ignored by the batched call. */
+    int32_t pad_;
 } bkm_params;
 
 /* Counters of one bkm_balanced_kmeans call (host struct). */
@@ -140,6 +150,8 @@ typedef struct {
     double move_ms;           /* center move + erosion, one per round */
     int32_t sample_rounds;    /* rounds of the random-sample initialization */
     int32_t sample_sweeps;    /* sweeps made in them */
+    int64_t debug_checked;    /* with params.debug_checks: points checked, over all checks */
+    int64_t debug_violations; /* and those that failed (the call then fails) */
 } bkm_info;
 
 typedef struct {

@@ -34,7 +34,7 @@ class Params(C.Structure):
                 ("epsilon", C.c_double), ("delta_threshold", C.c_double),
                 ("recheck_rel_gap", C.c_double), ("sample_start", C.c_int64),
                 ("seed", C.c_uint64), ("sample_keys", C.c_void_p),
-                ("target_sizes", C.c_void_p)]
+                ("target_sizes", C.c_void_p), ("debug_checks", C.c_int32), ("pad_", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -47,7 +47,8 @@ class Info(C.Structure):
                 ("bootstrap_ms", C.c_double), ("total_ms", C.c_double),
                 ("cand_ms", C.c_double), ("sweep_ms", C.c_double), ("balance_ms", C.c_double),
                 ("boxes_ms", C.c_double), ("move_ms", C.c_double),
-                ("sample_rounds", C.c_int32), ("sample_sweeps", C.c_int32)]
+                ("sample_rounds", C.c_int32), ("sample_sweeps", C.c_int32),
+                ("debug_checked", C.c_int64), ("debug_violations", C.c_int64)]
 
 
 class Stats(C.Structure):
@@ -201,7 +202,7 @@ def balanced_kmeans(X, k, W=None, eps=0.03, max_iter=50, max_balance_iter=20,
                     use_bounds=True, tile_points=0, super_tiles=0, recheck_rel_gap=1e-5,
                     centers_init=None, timing=False, out=None, sample_init=False,
                     sample_start=0, seed=0, sample_keys=None, target_sizes=None,
-                    erosion=True):
+                    erosion=True, debug_checks=0):
     """Balanced k-means; returns dict(A, centers, influence, block_weights, info, code).
     sample_init: start with rounds on random samples doubling from sample_start
     points (0: 100 per block, i.e. 100 * k), ordered by splitmix64(seed, index)
@@ -223,6 +224,7 @@ def balanced_kmeans(X, k, W=None, eps=0.03, max_iter=50, max_balance_iter=20,
     prm.timing = 1 if timing else 0
     prm.sample_init = 1 if sample_init else 0
     prm.erosion = 1 if erosion else 0
+    prm.debug_checks = int(debug_checks)
     prm.sample_start = int(sample_start)
     prm.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
     sk = None

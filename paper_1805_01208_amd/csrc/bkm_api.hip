@@ -370,6 +370,8 @@ int check_run(const bkm_points* pts, const bkm_params* prm)
     if (std::isnan(p.delta_threshold)) return fail(BKM_EINVAL, "delta_threshold is NaN");
     if (p.sample_init && p.sample_start < 0) return fail(BKM_EINVAL, "sample_start must be >= 0");
     if (p.erosion != 0 && p.erosion != 1) return fail(BKM_EINVAL, "erosion must be 0 or 1");
+    if (p.debug_checks < 0 || p.debug_checks > 2)
+        return fail(BKM_EINVAL, "debug_checks must be 0, 1 or 2");
     return BKM_OK;
 }
 
@@ -397,6 +399,8 @@ void fill_info(bkm_info* info, const DevState& h, const unsigned long long* cnt)
     info->changed = (int64_t)cnt[kCntChanged];
     info->candidate_evals = (int64_t)cnt[kCntCandEvals];
     info->overflow_tiles = (int64_t)cnt[kCntOverflow];
+    info->debug_checked = (int64_t)cnt[kCntDebugChecked];
+    info->debug_violations = (int64_t)cnt[kCntDebugViolated];
 }
 
 // Owned HIP objects of a batched call, released on every return path.
@@ -644,6 +648,12 @@ int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_i
     plan(r, pts, p.k, T, ST, p.precision, p.use_bounds ? 1 : 0, p.recheck_rel_gap);
     r.tsz = p.target_sizes;
     r.erosion = p.erosion;
+    // debug checks: every point, or a stride that keeps a check near 2^26
+    // point-center pairs
+    if (p.debug_checks == 2)
+        r.debug_stride = 1;
+    else if (p.debug_checks == 1)
+        r.debug_stride = (int)std::max<int64_t>(1, ((int64_t)r.npad_cap * p.k) >> 26);
     Arena a;
     if ((rc = alloc_run(r, a, s, true))) return rc;
 
@@ -764,12 +774,14 @@ int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_i
         HIPCHK(launch_tilecand(r, s));
         HIPCHK(mark(1));
         HIPCHK(launch_sweep(r, s));
+        HIPCHK(launch_check_bounds(r, 1, s));
         HIPCHK(mark(2));
         HIPCHK(launch_balance(r, s));
         HIPCHK(mark(3));
         HIPCHK(launch_block_boxes(r, s));
         HIPCHK(mark(4));
         HIPCHK(launch_move(r, s));
+        HIPCHK(launch_check_bounds(r, 0, s));
         HIPCHK(mark(5));
         HIPCHK(hipMemcpyAsync(&lr.ring[nb & 1], r.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
         HIPCHK(hipEventRecord(ev[6], s));
@@ -804,6 +816,10 @@ int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_i
     if (cnt[kCntInvalid])
         return fail(BKM_EINTERNAL, "%llu sweep decisions produced no valid block",
                     (unsigned long long)cnt[kCntInvalid]);
+    if (cnt[kCntDebugViolated])
+        return fail(BKM_EINTERNAL, "debug checks: %llu of %llu checked points violate a bound "
+                    "or are not at an argmin", (unsigned long long)cnt[kCntDebugViolated],
+                    (unsigned long long)cnt[kCntDebugChecked]);
 
     if (info) {
         fill_info(info, h, cnt);

@@ -20,7 +20,7 @@ constexpr int kPad = -2;             // block id of a padding point (never evalu
 constexpr int kMaxJumps = 8192;      // jumps between Hilbert-consecutive points realigned to tiles
 constexpr int kGapBins = 128;        // log2 histogram of gaps between consecutive points
 constexpr int kCntSlots = 64;        // sweep counters spread over this many cache lines
-constexpr int kCntWords = 8;         // counters per slot (one 64-byte line)
+constexpr int kCntWords = 16;        // counters per slot (one 128-byte line)
 constexpr int kSortIpt = 8;          // radix sort: items per thread per pass
 constexpr int kSortChunk = kBlock * kSortIpt;   // items per block per pass
 
@@ -73,7 +73,9 @@ __device__ inline bool round_over(const DevState* st)
 // Sweep counters, summed over the kCntSlots slots by the host.
 enum {
     kCntEvaluated = 0, kCntSkipped, kCntRechecked, kCntChanged, kCntCandEvals, kCntOverflow,
-    kCntInvalid   // decisions that produced no valid block (an internal error)
+    kCntInvalid,      // decisions that produced no valid block (an internal error)
+    kCntDebugChecked, // debug checks: points checked
+    kCntDebugViolated // debug checks: points whose bounds or block failed the check
 };
 
 // Candidates of one tile for the current sweep, written by k_tilecand.
@@ -109,6 +111,8 @@ struct RunDev {
     int T, ppt, ntiles, super_tiles, nsuper, nhyper, ngroups;
     int precision, use_bounds;
     int erosion;              // 1: erode the influence after every non-converged movement
+    int debug_stride;         // > 0: check every debug_stride-th layout slot after each
+                              // sweep and each move (bounds, block) against brute force
     double recheck_gap;
 
     const void* in_x[3];      // caller's coordinates (input order)
@@ -490,6 +494,10 @@ constexpr int kPassGroupsHost = 256;   // groups per block of the round-end pass
 hipError_t launch_sweep_multi(const MultiSet& m, hipStream_t s);    // candidates + sweep
 hipError_t launch_update_multi(const MultiSet& m, hipStream_t s);   // balance + round end + move
 hipError_t launch_move(const RunDev& r, hipStream_t s);
+// debug checks of the stored bounds (and, after a sweep, the block) of every
+// debug_stride-th point against a brute-force FP64 evaluation; after_sweep
+// selects the check of the block as the argmin
+hipError_t launch_check_bounds(const RunDev& r, int after_sweep, hipStream_t s);
 hipError_t launch_set_step(const RunDev& r, const double* centers_rm, const double* infl,
                            int first, hipStream_t s);
 hipError_t launch_finish(const RunDev& r, int32_t* assignment_out, double* centers_out,

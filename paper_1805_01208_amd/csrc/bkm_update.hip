@@ -943,6 +943,80 @@ hipError_t launch_block_boxes(const RunDev& r, hipStream_t s)
     return hipGetLastError();
 }
 
+// Debug check of the Hamerly invariants (Sec. 4.3) on sampled points, all in
+// exact FP64 against every center: the stored upper bound plus the movement
+// of the point's center is at least its distance to that center; the lower
+// bound in its affine frame (M * stored - E) is at most the effective
+// distance to every other center; and, right after a sweep, the point's
+// block is an argmin of the effective distance (within the 1e-12 tie gap).
+// Relative slack 1e-12 on each side.  Violations are counted, not trapped.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_check_bounds(RunDev r, int after_sweep)
+{
+    const DevState* st = r.st;
+    if (after_sweep ? round_over(st) : st->done != 0) return;
+    const int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * r.debug_stride;
+    bool checked = false, bad = false;
+    if (i < r.npad) {
+        const int a = r.A[i];
+        if (a != kPad) {
+            checked = true;
+            if (a < 0 || a >= r.k) {
+                bad = true;
+            } else {
+                double x[D];
+#pragma unroll
+                for (int j = 0; j < D; ++j)
+                    x[j] = r.in_f32 ? (double)r.xs32[j][i] : r.xs64[j][i];
+                const int k = r.k;
+                double own = 0.0, own_sq = 0.0, other = INFINITY, best = INFINITY;
+                for (int c = 0; c < k; ++c) {
+                    const double dx = x[0] - r.C[c];
+                    const double dy = x[1] - r.C[(int64_t)k + c];
+                    double sq = dx * dx + dy * dy;
+                    if (D == 3) {
+                        const double dz = x[2] - r.C[(int64_t)(D - 1) * k + c];
+                        sq = sq + dz * dz;
+                    }
+                    const double e = sqrt(sq) / r.I[c];
+                    best = fmin(best, e);
+                    if (c == a) {
+                        own = e;
+                        own_sq = sq;
+                    } else {
+                        other = fmin(other, e);
+                    }
+                }
+                const float2 b = r.bnd[i];
+                const double ub = (double)b.x + r.clus[a].x;
+                const double lb = st->M * (double)b.y - st->E;
+                if (ub < sqrt(own_sq) * (1.0 - 1e-12)) bad = true;
+                if (lb > other * (1.0 + 1e-12)) bad = true;
+                if (after_sweep && own > best * (1.0 + 1e-12)) bad = true;
+            }
+        }
+    }
+    const unsigned long long nc = __popcll(wave_ballot(checked));
+    const unsigned long long nb = __popcll(wave_ballot(bad));
+    if (threadIdx.x % kWave == 0 && nc) {
+        unsigned long long* slot = r.cnt + (int64_t)(blockIdx.x % kCntSlots) * kCntWords;
+        atomicAdd(slot + kCntDebugChecked, nc);
+        if (nb) atomicAdd(slot + kCntDebugViolated, nb);
+    }
+}
+
+hipError_t launch_check_bounds(const RunDev& r, int after_sweep, hipStream_t s)
+{
+    if (r.debug_stride <= 0) return hipSuccess;
+    const int64_t m = (r.npad + r.debug_stride - 1) / r.debug_stride;
+    const unsigned g = nblocks(m, kBlock);
+    if (r.d == 2)
+        k_check_bounds<2><<<g, kBlock, 0, s>>>(r, after_sweep);
+    else
+        k_check_bounds<3><<<g, kBlock, 0, s>>>(r, after_sweep);
+    return hipGetLastError();
+}
+
 hipError_t launch_move(const RunDev& r, hipStream_t s)
 {
     if (r.d == 2)
