@@ -270,6 +270,63 @@ def error_vs_oracle(bkm, torch, X, Xh, W, cfg, out, samples=20000):
                 out["block_weights"].cpu().numpy(), wsum))}
 
 
+def extra_workloads(bkm, torch):
+    """The other workloads, one figure each (points assigned per second per
+    sweep over whole calls, inputs resident): C2 with the plain FP64 sweep,
+    the 256-instance batch C4 in one batched call, and C5 (250M weighted
+    FP32 points).  Tilings from the autotuner."""
+    import numpy as np
+    out = {}
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [fn() for _ in range(steps)]
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, res[-1]
+
+    cfg = make_workload("c2")
+    X = [torch.from_numpy(x).cuda() for x in cfg["X"]]
+    n = len(cfg["X"][0])
+    dt, g = timed(lambda: bkm.balanced_kmeans(X, cfg["k"], eps=cfg["eps"], precision="f64",
+                                              timing=True), 3, 1)
+    i = g["info"]
+    out["c2_refined2d_fp64"] = {"value": n * i["sweeps"] / dt, "unit": "points/s",
+                                "ms_per_call": 1e3 * dt, "sweeps": i["sweeps"],
+                                "avg_sweep_us": 1e3 * i["sweep_ms"] / i["sweeps"],
+                                "n": n, "k": cfg["k"], "precision": "f64"}
+    del X
+    print(f"[bench] c2 fp64: {out['c2_refined2d_fp64']}", file=sys.stderr, flush=True)
+
+    cfgs = make_workload("c4")
+    insts = [([torch.from_numpy(x).cuda() for x in c["X"]], c["k"]) for c in cfgs]
+    npts = sum(len(c["X"][0]) for c in cfgs)
+    dt, (res, rc) = timed(lambda: bkm.balanced_kmeans_batched(insts), 2, 1)
+    sweeps = sum(o["info"]["sweeps"] for o in res)
+    pts_sweeps = sum(len(c["X"][0]) * o["info"]["sweeps"] for c, o in zip(cfgs, res))
+    out["c4_batched"] = {"value": pts_sweeps / dt, "unit": "points/s", "ms_per_call": 1e3 * dt,
+                         "instances": len(cfgs), "points": npts, "sweeps": sweeps,
+                         "return_code": rc, "precision": "f32_recheck"}
+    del insts
+    print(f"[bench] c4 batched: {out['c4_batched']}", file=sys.stderr, flush=True)
+
+    cfg = make_workload("c5")
+    X = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in cfg["X"]]
+    W = torch.from_numpy(cfg["W"]).cuda()
+    n = len(cfg["X"][0])
+    dt, g = timed(lambda: bkm.balanced_kmeans(X, cfg["k"], W=W, eps=cfg["eps"], timing=True), 2, 1)
+    i = g["info"]
+    out["c5_radial2d_weighted"] = {"value": n * i["sweeps"] / dt, "unit": "points/s",
+                                   "ms_per_call": 1e3 * dt, "sweeps": i["sweeps"],
+                                   "avg_sweep_us": 1e3 * i["sweep_ms"] / i["sweeps"],
+                                   "n": n, "k": cfg["k"], "precision": "f32_recheck",
+                                   "balanced": i["balanced"]}
+    print(f"[bench] c5: {out['c5_radial2d_weighted']}", file=sys.stderr, flush=True)
+    return out
+
+
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -372,6 +429,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error-check", action="store_true",
                     help="skip the check against the oracle (profiling runs)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads' figures (C2 plain FP64, C4 batched, C5)")
     ap.add_argument("--graph", action="store_true",
                     help="measure the graph-quality evaluation instead of the partitioner")
     ap.add_argument("--knn", type=int, default=6, help="neighbours per point (--graph)")
@@ -502,6 +561,10 @@ def main():
         line["cpu_baseline"]["cpu_model"] = cpu_model()
         if W is None:
             line["cpu_pruned"] = cpu_pruned(cfg, args.cpu_seconds)
+    if not args.no_extras and args.config == "c3" and args.n is None:
+        del X, W, outs
+        torch.cuda.empty_cache()
+        line["other_workloads"] = extra_workloads(bkm, torch)
     print(json.dumps(line), flush=True)
 
 

@@ -260,8 +260,8 @@ int bkm_assign_sweeps(const bkm_points* pts, int32_t k, int32_t steps,
  * strided sample of at most 2^23 of the points, with k scaled to keep the
  * mean number of points per block; the objective is the device time of the
  * candidate filters and the sweep per sweep.  Choices are cached per (device
- * architecture, d, precision, weighting, half-octave of n/k, octave of n up
- * to 2^23): in the process, and, when the environment variable
+ * architecture, d, precision, weighting, octave of n/k, size class of n:
+ * below 2^17, 2^20, 2^23, or above): in the process, and, when the environment variable
  * BKM_TUNE_CACHE names a file, in that file (read once, appended to).
  * bkm_balanced_kmeans and bkm_balanced_kmeans_batched use it for
  * tile_points = 0 (the batched call per instance); the random-sample rounds

@@ -437,7 +437,7 @@ int run_core(const bkm_points* pts, const bkm_params& p, const double* centers_i
 // kTuneSample points with k scaled to keep the mean points per block; the
 // objective is the device time of the candidate filters and the sweep per
 // sweep.  Choices are cached per (device architecture, d, precision,
-// weighting, half-octave of n/k, octave of n capped at the sample size),
+// weighting, octave of n/k, size class of n: below 2^17, 2^20, 2^23, above),
 // in the process and, when the environment names a file in BKM_TUNE_CACHE,
 // in that file (one line per key, read once, appended on every new entry).
 constexpr int kTuneTiles[] = {256, 512, 1024};
@@ -464,9 +464,9 @@ std::string tune_key(const bkm_points* pts, const bkm_params& p)
         const size_t c = arch.find(':');
         if (c != std::string::npos) arch = arch.substr(0, c);
     }
-    const int ppb = (int)std::lround(2.0 * std::log2((double)pts->n / (double)p.k));
-    const int nb = (int)std::min<double>(std::floor(std::log2((double)pts->n)),
-                                         std::log2((double)kTuneSample));
+    const int ppb = (int)std::lround(std::log2((double)pts->n / (double)p.k));
+    const int nb = pts->n < (int64_t(1) << 17) ? 0 : pts->n < (int64_t(1) << 20) ? 1
+                 : pts->n < kTuneSample ? 2 : 3;
     char buf[160];
     snprintf(buf, sizeof(buf), "%s d%d p%d w%d ppb%d n%d", arch.c_str(), pts->d, p.precision,
              pts->weights ? 1 : 0, ppb, nb);
