@@ -73,9 +73,9 @@ def sweep_source_digest():
 
 
 def measured_traffic(workload, tile):
-    """HBM bytes per sweep launch from the committed counter summary, or None
-    when it is missing, was taken on another workload, or the sweep kernel's
-    source has changed since."""
+    """HBM bytes per sweep launch from the committed counter summary (memory-side
+    requests by size), as (total, read, write), or None when it is missing, was
+    taken on another workload, or the sweep kernel's source has changed since."""
     try:
         with open(TRAFFIC_FILE) as fh:
             kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith(" "))
@@ -87,7 +87,8 @@ def measured_traffic(workload, tile):
     if kv.get("workload") != workload or kv.get("tile_points") != str(tile):
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return (float(kv["hbm_bytes_per_launch"]), float(kv["read_bytes_per_launch"]),
+                float(kv["write_bytes_per_launch"]))
     except (KeyError, ValueError):
         return None
 
@@ -534,7 +535,12 @@ def main():
                    "super_tiles": sup, "sample_init": bool(args.sample_init),
                    "target_sizes": "lognormal(0,0.5), seed 9" if args.targets else None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None if traffic is None else traffic[0],
+                     "traffic_read": None if traffic is None else traffic[1],
+                     "traffic_write": None if traffic is None else traffic[2],
+                     "traffic_frac": None if traffic is None else
+                     traffic[0] / sweep_s / 1e9 / HBM_PEAK_GBS,
                      "kernel": "k_sweep", "avg_sweep_us": sweep_s * 1e6,
                      "algorithmic_bytes_per_launch": algo},
         "sweeps_per_step": sweeps / args.steps,
