@@ -152,6 +152,9 @@ typedef struct {
     int32_t sample_sweeps;    /* sweeps made in them */
     int64_t debug_checked;    /* with params.debug_checks: points checked, over all checks */
     int64_t debug_violations; /* and those that failed (the call then fails) */
+    int64_t list_builds;      /* sweeps that built the candidate lists; the others kept the
+                                 lists of the last build (the influences had moved within
+                                 the lists' margin) */
 } bkm_info;
 
 typedef struct {

@@ -48,7 +48,8 @@ class Info(C.Structure):
                 ("cand_ms", C.c_double), ("sweep_ms", C.c_double), ("balance_ms", C.c_double),
                 ("boxes_ms", C.c_double), ("move_ms", C.c_double),
                 ("sample_rounds", C.c_int32), ("sample_sweeps", C.c_int32),
-                ("debug_checked", C.c_int64), ("debug_violations", C.c_int64)]
+                ("debug_checked", C.c_int64), ("debug_violations", C.c_int64),
+                ("list_builds", C.c_int64)]
 
 
 class Stats(C.Structure):

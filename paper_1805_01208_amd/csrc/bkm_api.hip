@@ -243,6 +243,7 @@ size_t layout(RunDev& r, Arena* a, bool full)
         both((int32_t*)nullptr, np, r.A);
         both((float2*)nullptr, np, r.bnd);
         both((double*)nullptr, (size_t)ntiles * 2 * d, r.tbox);
+        both((TileFrame*)nullptr, (size_t)ntiles, r.tframe);
         both((double*)nullptr, (size_t)(np / kWave) * 2 * d, r.gbox);
         const int64_t nhyper = (nsuper + kHyper - 1) / kHyper;
         both((double*)nullptr, (size_t)nhyper * 2 * d, r.hbox);
@@ -262,6 +263,7 @@ size_t layout(RunDev& r, Arena* a, bool full)
         both((double2*)nullptr, (size_t)k, r.clus);
         both((float2*)nullptr, (size_t)k, r.clus32);
         both((float*)nullptr, (size_t)k, r.clusdn);
+        both((double*)nullptr, (size_t)k, r.ivb);
         both((int32_t*)nullptr, (size_t)(np / kWave), r.gblk);
         both((int32_t*)nullptr, (size_t)(np / kWave), r.gdirty);
         both((int32_t*)nullptr, np, r.Aprev);
@@ -401,6 +403,7 @@ void fill_info(bkm_info* info, const DevState& h, const unsigned long long* cnt)
     info->overflow_tiles = (int64_t)cnt[kCntOverflow];
     info->debug_checked = (int64_t)cnt[kCntDebugChecked];
     info->debug_violations = (int64_t)cnt[kCntDebugViolated];
+    info->list_builds = (int64_t)cnt[kCntListBuilds];
 }
 
 // Owned HIP objects of a batched call, released on every return path.

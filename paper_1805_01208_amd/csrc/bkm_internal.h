@@ -14,6 +14,12 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;          // threads per block of the point kernels
 constexpr int kTileCap = 128;        // candidate records kept per tile
 constexpr int kHyper = 16;           // super-tiles per hyper-tile of the candidate hierarchy
+// Squared margin of the candidate filters (Sec. 4.4 filter, widened): a
+// list keeps every center whose smallest effective distance to the box is
+// within sqrt(kListMargin2) of the second-smallest largest one, so it stays
+// complete while every center's 1/influence moves by a ratio in [G, F]
+// with F <= G sqrt(kListMargin2); the lists are then kept.
+constexpr double kListMargin2 = 1.3125;
 constexpr int kFixShift = 30;        // fixed-point sums: term = hi * 2^30 + lo
 constexpr long long kFixLoMask = (1LL << kFixShift) - 1;
 constexpr int kPad = -2;             // block id of a padding point (never evaluated)
@@ -55,11 +61,17 @@ struct alignas(16) DevState {
     double wmax;
     double beta, max_delta, max_weight, total_weight;
     double max_ratio;         // largest weight / target over the blocks at the last balance test
+    // Candidate lists are built with a margin and kept while the influences
+    // move within it: listG and listF bound (1/I now) / (1/I at the last
+    // build) over all centers from below and above; the balance step keeps
+    // them (they mean something only while lists_ok is set).
+    double listG, listF;
     // the sweep's copies of the frame, refreshed wherever M or E change
     double invM;              // 1 / M
     float Mf, Ef;             // M rounded down and E rounded up to FP32
     float Edn, invMdn;        // E rounded down; 1/M times (1 - 2^-21), rounded down
-    int32_t pad;
+    int32_t lists_ok;         // 1: the next sweep keeps the candidate lists of the last build;
+                              // 0: they are rebuilt
 };
 
 // The run or the current AssignAndBalance call is over: one 8-byte load of
@@ -75,7 +87,8 @@ enum {
     kCntEvaluated = 0, kCntSkipped, kCntRechecked, kCntChanged, kCntCandEvals, kCntOverflow,
     kCntInvalid,      // decisions that produced no valid block (an internal error)
     kCntDebugChecked, // debug checks: points checked
-    kCntDebugViolated // debug checks: points whose bounds or block failed the check
+    kCntDebugViolated, // debug checks: points whose bounds or block failed the check
+    kCntListBuilds    // sweeps that built the candidate lists (the others kept them)
 };
 
 // Candidates of one tile for the current sweep, written by k_tilecand.
@@ -89,17 +102,31 @@ struct TileHead {
     double lb_out;            // lower bound on the effective distance of every center left out
     float ubadd32;            // dmax + 2^-46 (1 + 7u), rounded up: the upper bound's additive term
     float lbout32;            // lb_out rounded down
+    double lb_build;          // lb_out at the build
+};
+
+// Static frame of a tile, fixed by its box at the layout: the anchor X (box
+// center) of the packed offsets, the norm of the box half-extents, and the
+// FP32 value of one unit of the offsets per axis.
+struct TileFrame {
+    double X[3];
+    double hnorm;
+    float step[3];
+    float pad;
 };
 
 // One candidate center of a tile: FP32 offset of the center from the tile
 // anchor and squared FP32 inverse influence, for the FP32 screen, and a lower
-// bound on the value the screen (or the FP64 sweep) can compute for this
-// center at any point of the tile.  A tile's records are sorted by that key.
+// bound (key) on the value the screen (or the FP64 sweep) can compute for
+// this center at any point of the tile.  A tile's records are sorted by that
+// key.  dlt and key0 keep what the build knew: the center's term of the FP32
+// error bound before 1/influence (rounded up) and the key, from which a
+// sweep that keeps the lists refreshes w2, key and the tile's bounds.
 struct alignas(32) CandRec {
     float qx, qy, qz, w2;
     int32_t id;
     float key;
-    int32_t pad1, pad2;
+    float dlt, key0;
 };
 
 // Everything a run keeps on the device.  Point arrays are in Hilbert (sorted)
@@ -135,6 +162,7 @@ struct RunDev {
     float2* bnd;              // stored bounds of each point: x upper (distance frame),
                               // y lower (lazy frame), one 8-byte record
     double* tbox;             // [ntiles][2d] lo..., hi...
+    TileFrame* tframe;        // [ntiles]
     double* gbox;             // [ngroups][2d] boxes of 64-point groups
     double* hbox;             // [nhyper][2d] boxes of hyper-tiles (kHyper super-tiles)
     int32_t* hlist;           // [nhyper][k] candidate centers of each hyper-tile
@@ -150,6 +178,7 @@ struct RunDev {
     double* tL;               // [k] weight limit of each block (with target sizes)
     double* tpre;             // [k+1] prefix sums of the target sizes in index order; [k] = total
     double2* clus;            // [k] (accumulated movement, 1/influence)
+    double* ivb;              // [k] 1/influence at the last candidate-list build
     float2* clus32;           // [k] FP32 copies for the Hamerly test: movement and
                               // 1/influence, both rounded up
     float* clusdn;            // [k] movement rounded down to FP32 (bound stores)
@@ -272,6 +301,14 @@ __host__ __device__ inline double dec_ord(unsigned long long e)
     return v.d;
 }
 
+// The FP32 screen's squared inverse influence: 1/I rounded to FP32, squared
+// in FP32.
+__device__ inline float screen_w2(double iv)
+{
+    const float fi = (float)iv;
+    return fi * fi;
+}
+
 // Smallest two values of a set (a <= b), merged pairwise.
 struct Two { double a, b; };
 
@@ -327,6 +364,62 @@ __device__ inline unsigned long long dpp_u64(unsigned long long v)
     const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, ROWS, 0xf, false);
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, ROWS, 0xf, false);
     return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+// Reductions of FP64 values over the wave through the same network: an
+// inclusive scan whose last lane holds the result, read back as a
+// wave-uniform value.  `idle` is the neutral element the network feeds to
+// lanes without a source.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_d(double v, double idle)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned long long z = (unsigned long long)__double_as_longlong(idle);
+    const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)z, (int)(unsigned)u, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(z >> 32), (int)(unsigned)(u >> 32), CTRL,
+                                               ROWS, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ inline double readlane_last_d(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, kWave - 1);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), kWave - 1);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Largest of two values per lane over the wave (both reductions interleaved).
+__device__ inline void wave_max2_dpp(double& a, double& b)
+{
+    const double ninf = -INFINITY;
+    a = fmax(a, dpp_d<0x111, 0xf>(a, ninf)); b = fmax(b, dpp_d<0x111, 0xf>(b, ninf));   // row_shr:1
+    a = fmax(a, dpp_d<0x112, 0xf>(a, ninf)); b = fmax(b, dpp_d<0x112, 0xf>(b, ninf));   // row_shr:2
+    a = fmax(a, dpp_d<0x114, 0xf>(a, ninf)); b = fmax(b, dpp_d<0x114, 0xf>(b, ninf));   // row_shr:4
+    a = fmax(a, dpp_d<0x118, 0xf>(a, ninf)); b = fmax(b, dpp_d<0x118, 0xf>(b, ninf));   // row_shr:8
+    a = fmax(a, dpp_d<0x142, 0xa>(a, ninf)); b = fmax(b, dpp_d<0x142, 0xa>(b, ninf));   // row_bcast:15
+    a = fmax(a, dpp_d<0x143, 0xc>(a, ninf)); b = fmax(b, dpp_d<0x143, 0xc>(b, ninf));   // row_bcast:31
+    a = readlane_last_d(a);
+    b = readlane_last_d(b);
+}
+
+template <int CTRL, int ROWS>
+__device__ inline Two two_step_dpp(Two t)
+{
+    const Two o{dpp_d<CTRL, ROWS>(t.a, INFINITY), dpp_d<CTRL, ROWS>(t.b, INFINITY)};
+    return merge_two(t, o);
+}
+
+// The two smallest values over the wave (as wave_two), wave-uniform.
+__device__ inline Two wave_two_dpp(Two t)
+{
+    t = two_step_dpp<0x111, 0xf>(t);
+    t = two_step_dpp<0x112, 0xf>(t);
+    t = two_step_dpp<0x114, 0xf>(t);
+    t = two_step_dpp<0x118, 0xf>(t);
+    t = two_step_dpp<0x142, 0xa>(t);
+    t = two_step_dpp<0x143, 0xc>(t);
+    return Two{readlane_last_d(t.a), readlane_last_d(t.b)};
 }
 
 // Sum of a 64-bit integer over the wave, returned on every lane: an

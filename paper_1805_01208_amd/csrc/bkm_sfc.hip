@@ -584,6 +584,27 @@ __global__ __launch_bounds__(kBlock) void k_tile_prep(RunDev r)
         r.tbox[(int64_t)blockIdx.x * 2 * D + j] = v;
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        // the frame of the packed offsets below and of the candidate filter
+        TileFrame f;
+        double rn2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            f.X[j] = 0.0;
+            f.step[j] = 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const double X = 0.5 * (box[j] + box[D + j]);
+            const double h = fmax(box[D + j] - X, X - box[j]);
+            rn2 += h * h;
+            f.X[j] = X;
+            f.step[j] = (float)(h / FixPack<D>::kMax);
+        }
+        f.hnorm = sqrt(rn2);
+        f.pad = 0.0f;
+        r.tframe[blockIdx.x] = f;
+    }
     if (r.precision == BKM_PREC_F32_RECHECK) {
         double X[D], h[D];
 #pragma unroll

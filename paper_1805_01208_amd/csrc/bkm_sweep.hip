@@ -12,6 +12,10 @@
 //     super-tile's list (k_tilecand, one wave each), which writes the
 //     surviving centers as compact records: FP32 offset from the tile anchor
 //     and squared FP32 inverse influence.
+//     The filters keep a margin, so the lists of a round's first sweep stay
+//     complete through its balance sweeps while the influences move little
+//     (the balance step checks the bound); such sweeps only refresh each
+//     tile's records and error bounds for the new influences.
 //   * points (Sec. 4.3, Hamerly): a point whose upper bound on the effective
 //     distance to its own center is below its lower bound on the second-best
 //     effective distance keeps its block without evaluating anything.  The
@@ -104,7 +108,8 @@ __device__ inline double sorted_coord(const RunDev& r, int j, int64_t p)
 // Candidate filter of one box [lo, hi] against the centers of `list` (all k
 // centers when list is NULL): c stays iff its smallest effective distance to
 // the box is at most the second-smallest largest one (Sec. 4.4: no point of
-// the box can have c as best or second-best otherwise).  A box inside a
+// the box can have c as best or second-best otherwise), widened by the list
+// margin so that the list outlives small influence changes.  A box inside a
 // parent box may filter the parent's list instead of all centers: its
 // smallest distances are no smaller and its second-smallest largest distance
 // is no larger, so every center the parent drops it drops too, and the two
@@ -134,7 +139,7 @@ __device__ __forceinline__ void box_filter(RT r, const double* lo, const double*
     __syncthreads();
     Two all{sa[0], sb[0]};
     for (int w = 1; w < NT / kWave; ++w) all = merge_two(all, Two{sa[w], sb[w]});
-    const double thr2 = all.b * (1.0 + 2.0 * kCandSlack);
+    const double thr2 = all.b * (1.0 + 2.0 * kCandSlack) * kListMargin2;
     const unsigned long long below = (1ULL << lane) - 1ULL;
     for (int i0 = 0; i0 < L; i0 += NT) {
         const int i = i0 + tid;
@@ -164,7 +169,10 @@ template <int D, typename RT>
 __device__ __forceinline__ void hypercand_body(RT r, const int bid)
 {
     const DevState* st = r.st;
-    if (round_over(st)) return;
+    if (round_over(st) || st->lists_ok) return;
+    // the influences the lists are built for, for the balance step's test
+    for (int c = bid * kHyperThreads + (int)threadIdx.x; c < r.k; c += r.nhyper * kHyperThreads)
+        r.ivb[c] = r.clus[c].y;
     double lo[D], hi[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -194,7 +202,7 @@ template <int D, typename RT>
 __device__ __forceinline__ void supercand_body(RT r, const int bid)
 {
     const DevState* st = r.st;
-    if (round_over(st)) return;
+    if (round_over(st) || st->lists_ok) return;
     double lo[D], hi[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -248,35 +256,85 @@ __global__ __launch_bounds__(kSuperThreads) void k_supercand_multi(const RunDev*
 // first record whose key is at least every lane's current second-best value
 // (Alg. 1 breaks the same way once the box distance passes the second-best):
 // no later record can change a lane's best or second-best.
+// FP32 screen slack of a tile from its tau: tau(1 + 16u) + 2^-46, rounded up.
+__device__ inline float screen_slack32(double tau)
+{
+    return f32_up((tau * (1.0 + 16.0 * kU32) + 2.0 * kSqrtAbs) * (1.0 + 0x1p-20));
+}
+
+// A sweep that keeps the lists of the last build (every 1/influence within
+// [G, F] times its value then, F <= G sqrt(kListMargin2)) brings the tile's
+// records and bounds to the current influences: each record's FP32 squared
+// inverse influence, recomputed as the build computes it; its key, a lower
+// bound on the screen's value for its center at any point of the tile, which
+// scales with the center's 1/influence (its distance and error terms both
+// do), so key0 G^2 is one and the order stays; tau, retaken from the
+// records' error terms; and the bound on every center left out at the
+// build, lb_build G.
+template <typename RT>
+__device__ inline void refresh_tile(RT r, int tile, int lane)
+{
+    TileHead* __restrict__ hp = r.thead + tile;
+    const int n = hp->n;   // 0 for an overflowed tile
+    const double G = r.st->listG;
+    const double G2 = G * G * (1.0 - 0x1p-50);
+    CandRec* __restrict__ cr = r.tcand + (int64_t)tile * kTileCap;
+    double tau = 0.0, unused = 0.0;
+    for (int i = lane; i < n; i += kWave) {
+        CandRec rec = cr[i];
+        const double iv = r.clus[rec.id].y;
+        rec.w2 = screen_w2(iv);
+        rec.key = f32_down((double)rec.key0 * G2);
+        tau = fmax(tau, (double)rec.dlt * iv);
+        cr[i] = rec;
+    }
+    wave_max2_dpp(tau, unused);
+    if (lane == 0) {
+        const double lb = hp->lb_build * G * (1.0 - kTiny);
+        hp->lb_out = lb;
+        hp->lbout32 = f32_down(lb);
+        if (!hp->overflow) {
+            hp->tau = tau * (1.0 + kTiny) + kUnder;
+            hp->slack32 = screen_slack32(hp->tau);
+        }
+    }
+}
+
 template <int D, int PREC, typename RT>
 __device__ __forceinline__ void tilecand_body(RT r, const int bid)
 {
     const DevState* st = r.st;
     if (round_over(st)) return;
-    constexpr int kCpl = 4;   // candidates a lane keeps in registers between passes
-    __shared__ CandRec s_rec[kBlock / kWave][kTileCap];
+    constexpr int kCpl = 4;   // list entries a lane keeps in registers between passes
+    // per wave: the kept candidates (center, squared smallest effective box
+    // distance), then in the same slot the candidate's record
+    union Slot {
+        CandRec rec;
+        struct { double lo2; int c; } k;
+    };
+    __shared__ Slot s_slot[kBlock / kWave][kTileCap];
     __shared__ float s_key[kBlock / kWave][kTileCap];
     const int lane = threadIdx.x % kWave;
     const int wv = threadIdx.x / kWave;
     // wave-uniform: the tile box, its frame and the list bounds live in scalar registers
     const int tile = __builtin_amdgcn_readfirstlane(bid * (kBlock / kWave) + (int)threadIdx.x / kWave);
     if (tile >= r.ntiles) return;
+    if (st->lists_ok) {
+        // the sweep keeps the lists of the last build
+        refresh_tile(r, tile, lane);
+        return;
+    }
     const int k = r.k;
     const double* __restrict__ C = r.C;
 
     double blo[D], bhi[D], X[D];
-    double rn2 = 0.0;
-    float step[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int j = 0; j < D; ++j) {
         blo[j] = r.tbox[(int64_t)tile * 2 * D + j];
         bhi[j] = r.tbox[(int64_t)tile * 2 * D + D + j];
-        X[j] = 0.5 * (blo[j] + bhi[j]);
-        const double h = fmax(bhi[j] - X[j], X[j] - blo[j]);
-        rn2 += h * h;
-        step[j] = (float)(h / FixPack<D>::kMax);
+        X[j] = r.tframe[tile].X[j];
     }
-    const double Rn = sqrt(rn2) * (1.0 + kTiny);
+    const double Rn = r.tframe[tile].hnorm * (1.0 + kTiny);
     const double pnt = (D == 3 ? kFixPt3 : kFixPt2) * Rn;   // fixed-point term of the bound
     const int sidx = tile / r.super_tiles;
     const int L = r.scount[sidx];
@@ -284,43 +342,18 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
     CandRec* __restrict__ out = r.tcand + (int64_t)tile * kTileCap;
     const unsigned long long below = (1ULL << lane) - 1ULL;
 
+    // candidates that pass the filter, compacted into the wave's slots
+    // (their count goes on beyond kTileCap: the tile then overflows)
     int cnt = 0;
-    double tau = 0.0, dmax = 0.0;
-    // error bounds of one candidate; the record itself (staged in LDS for the
-    // sort) when it fits; lo2 = squared smallest effective box distance
-    auto emit = [&](bool keep, int c, double lo2) {
+    auto keep_if = [&](bool keep, int c, double lo2) {
         const unsigned long long b = wave_ballot(keep);
         const int pos = cnt + (int)__popcll(b & below);
-        if (keep) {
-            const double iv = r.clus[c].y;
-            double dd = 0.0, q[D];
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                q[j] = C[(int64_t)j * k + c] - X[j];
-                dd += q[j] * q[j];
-            }
-            const double delta = pnt + 8.0 * kU32 * (Rn + sqrt(dd) * (1.0 + kTiny)) + kUnder;
-            const double tc = delta * iv;
-            dmax = fmax(dmax, delta);
-            tau = fmax(tau, tc);
-            if (pos < kTileCap) {
-                const double lk = sqrt(lo2) * (1.0 - 10.0 * kU32) - tc * (1.0 + kTiny);
-                CandRec rec;
-                rec.qx = (float)q[0];
-                rec.qy = (float)q[1];
-                rec.qz = D == 3 ? (float)q[D - 1] : 0.0f;
-                const float fi = (float)iv;
-                rec.w2 = fi * fi;
-                rec.id = c;
-                rec.key = lk > 0.0 ? f32_down(lk * lk * (1.0 - 4.0 * kU32)) : 0.0f;
-                rec.pad1 = rec.pad2 = 0;
-                s_rec[wv][pos] = rec;
-                s_key[wv][pos] = rec.key;
-            }
+        if (keep && pos < kTileCap) {
+            s_slot[wv][pos].k.lo2 = lo2;
+            s_slot[wv][pos].k.c = c;
         }
         cnt += (int)__popcll(b);
     };
-
     Two t{kInf, kInf};
     double thr2;
     if (L <= kCpl * kWave) {
@@ -340,10 +373,11 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
                 t = merge_two(t, Two{hi2, kInf});
             }
         }
-        t = wave_two(t);
-        thr2 = t.b * (1.0 + 2.0 * kCandSlack);
+        t = wave_two_dpp(t);
+        thr2 = t.b * (1.0 + 2.0 * kCandSlack) * kListMargin2;
 #pragma unroll
-        for (int u = 0; u < kCpl; ++u) emit(cc[u] >= 0 && clo[u] <= thr2, cc[u], clo[u]);
+        for (int u = 0; u < kCpl; ++u)
+            if (u * kWave < L) keep_if(cc[u] >= 0 && clo[u] <= thr2, cc[u], clo[u]);
     } else {
         for (int i = lane; i < L; i += kWave) {
             const int c = sl[i];
@@ -351,8 +385,8 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
             box_eff2<D>(blo, bhi, C, k, c, r.clus[c].y, lo2, hi2);
             t = merge_two(t, Two{hi2, kInf});
         }
-        t = wave_two(t);
-        thr2 = t.b * (1.0 + 2.0 * kCandSlack);
+        t = wave_two_dpp(t);
+        thr2 = t.b * (1.0 + 2.0 * kCandSlack) * kListMargin2;
         for (int i0 = 0; i0 < L; i0 += kWave) {
             const int i = i0 + lane;
             int c = 0;
@@ -364,45 +398,81 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
                 box_eff2<D>(blo, bhi, C, k, c, r.clus[c].y, lo2, hi2);
                 keep = lo2 <= thr2;
             }
-            emit(keep, c, lo2);
+            keep_if(keep, c, lo2);
         }
     }
     // an overflowed tile is swept in FP64 over the super-tile list (its
     // FP32 bounds are not used)
     const bool overflow = cnt > kTileCap;
-    // the records in ascending key order (ties by staging position): each
-    // lane ranks its staged records against all of them (the wave's own LDS
-    // rows, so a wave-level fence orders the writes before the reads)
+    const int nrec = min(cnt, kTileCap);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // error bounds of every kept candidate and its record (one lane each,
+    // in place of its slot)
+    double tau = 0.0, dmax = 0.0;
+    for (int i = lane; i < nrec; i += kWave) {
+        const double lo2 = s_slot[wv][i].k.lo2;
+        const int c = s_slot[wv][i].k.c;
+        const double iv = r.clus[c].y;
+        double dd = 0.0, q[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            q[j] = C[(int64_t)j * k + c] - X[j];
+            dd += q[j] * q[j];
+        }
+        const double delta = pnt + 8.0 * kU32 * (Rn + sqrt(dd) * (1.0 + kTiny)) + kUnder;
+        const double tc = delta * iv;
+        dmax = fmax(dmax, delta);
+        tau = fmax(tau, tc);
+        const double lk = sqrt(lo2) * (1.0 - 10.0 * kU32) - tc * (1.0 + kTiny);
+        CandRec rec;
+        rec.qx = (float)q[0];
+        rec.qy = (float)q[1];
+        rec.qz = D == 3 ? (float)q[D - 1] : 0.0f;
+        rec.w2 = screen_w2(iv);
+        rec.id = c;
+        rec.key = lk > 0.0 ? f32_down(lk * lk * (1.0 - 4.0 * kU32)) : 0.0f;
+        rec.dlt = f32_up(delta);
+        rec.key0 = rec.key;
+        s_slot[wv][i].rec = rec;
+        s_key[wv][i] = rec.key;
+    }
+    wave_max2_dpp(tau, dmax);
+    // the records in ascending key order (ties by slot): each lane ranks its
+    // records against all of them (the wave's own LDS rows, so a wave-level
+    // fence orders the writes before the reads)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (!overflow) {
-        for (int i = lane; i < cnt; i += kWave) {
+        for (int i = lane; i < nrec; i += kWave) {
             const float ki = s_key[wv][i];
             int rank = 0;
-            for (int j = 0; j < cnt; ++j) {
+            for (int j = 0; j < nrec; ++j) {
                 const float kj = s_key[wv][j];
                 rank += (kj < ki || (kj == ki && j < i)) ? 1 : 0;
             }
-            out[rank] = s_rec[wv][i];
+            out[rank] = s_slot[wv][i].rec;
         }
     }
-    tau = wave_max_d(tau);
-    dmax = wave_max_d(dmax);
     if (lane == 0) {
+        const TileFrame& fr = r.tframe[tile];
         TileHead h;
         h.n = overflow ? 0 : cnt;
         h.overflow = overflow ? 1 : 0;
         h.tau = tau * (1.0 + kTiny) + kUnder;
         h.dmax = dmax * (1.0 + kTiny);
-        h.lb_out = sqrt(t.b) * (1.0 - kTiny);
-        h.step[0] = step[0];
-        h.step[1] = step[1];
-        h.step[2] = step[2];
-        h.slack32 = f32_up((h.tau * (1.0 + 16.0 * kU32) + 2.0 * kSqrtAbs) * (1.0 + 0x1p-20));
+        h.lb_out = sqrt(t.b * kListMargin2) * (1.0 - kTiny);
+        h.lb_build = h.lb_out;
+        h.step[0] = fr.step[0];
+        h.step[1] = fr.step[1];
+        h.step[2] = fr.step[2];
+        h.slack32 = screen_slack32(h.tau);
         h.ubadd32 = f32_up((h.dmax + 2.0 * kSqrtAbs * (1.0 + 7.0 * kU32)) * (1.0 + 0x1p-20));
         h.lbout32 = f32_down(h.lb_out);
         r.thead[tile] = h;
+        if (tile == 0) atomicAdd(r.cnt + kCntListBuilds, 1ULL);
     }
 }
 

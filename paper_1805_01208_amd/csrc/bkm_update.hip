@@ -69,9 +69,12 @@ __device__ __forceinline__ void balance_body(RT r, const int bid)
     // balanced: every block within its limit (one common limit, or its own)
     const bool bal = per_block ? over == 0.0 : mx <= st->lmax;
     const int sweep_no = st->sweep_in_round + 1;
-    double mu = 1.0;
+    double mu = 1.0, lg = 1.0, lf = 1.0;
     if (!bal) {
-        double m = INFINITY;
+        // m: smallest ratio old/new influence (the lower-bound frame); qlo,
+        // qhi: smallest and largest ratio of 1/influence to its value at the
+        // last candidate-list build
+        double m = INFINITY, qlo = INFINITY, qhi = 0.0;
         for (int c = threadIdx.x; c < k; c += 1024) {
             const double s = block_weight(r, c);
             double f;
@@ -85,12 +88,18 @@ __device__ __forceinline__ void balance_body(RT r, const int bid)
             }
             const double io = r.I[c];
             const double in = io * f;
+            const double iv = 1.0 / in;
             r.I[c] = in;
-            r.clus[c].y = 1.0 / in;
-            r.clus32[c].y = f32_up(1.0 / in);
+            r.clus[c].y = iv;
+            r.clus32[c].y = f32_up(iv);
             m = fmin(m, io / in);
+            const double q = iv / r.ivb[c];
+            qlo = fmin(qlo, q);
+            qhi = fmax(qhi, q);
         }
         mu = block_reduce_1024(m, sh, OpMin());
+        lg = block_reduce_1024(qlo, sh, OpMin()) * kDown;
+        lf = block_reduce_1024(qhi, sh, OpMax()) * kUp;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -106,6 +115,10 @@ __device__ __forceinline__ void balance_body(RT r, const int bid)
             st->M = st->M * mu * kDown;
             st->E = st->E * mu * kUp;
             frame_copies(st);
+            // the lists stay complete while F <= G sqrt(kListMargin2)
+            st->listG = lg;
+            st->listF = lf;
+            st->lists_ok = lf * lf <= kListMargin2 * (lg * lg) * kDown ? 1 : 0;
             if (sweep_no >= st->max_balance_iter) st->round_done = 1;
         }
     }
@@ -543,6 +556,7 @@ __device__ __forceinline__ void move_body(RT r, const int bid)
         if (st->rounds >= st->max_iter) st->done = 1;
         st->round_done = 0;
         st->sweep_in_round = 0;
+        st->lists_ok = 0;   // the centers moved: the next sweep rebuilds the lists
     }
     for (int i = threadIdx.x; i < k * 2 * D; i += 1024) r.bb[i] = (i % (2 * D)) < D ? ~0ULL : 0ULL;
 }
@@ -664,6 +678,9 @@ __global__ __launch_bounds__(kBlock) void k_init_clusters(RunDev r, const double
         st->M = 1.0;
         st->E = 0.0;
         frame_copies(st);
+        st->lists_ok = 0;
+        st->listG = 1.0;
+        st->listF = 1.0;
         const double W = st->total_weight;
         if (!r.tsz) {   // with target sizes, the prep left the largest limit here
             if (r.weighted) {
@@ -723,6 +740,7 @@ __global__ __launch_bounds__(1024) void k_set_step(RunDev r, const double* crm,
         frame_copies(st);
         st->done = 0;
         st->round_done = 0;
+        st->lists_ok = 0;
     }
 }
 

@@ -111,3 +111,16 @@ def test_partition_stats_matches_oracle():
     bad[5] = k
     with pytest.raises(bkm.BkmError):
         bkm.partition_stats(cuda(X), torch.from_numpy(bad).cuda(), k)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32_recheck"])
+def test_kept_candidate_lists(precision):
+    """Balance sweeps keep the candidate lists of a round's first sweep while
+    the influences move within the lists' margin (Sec. 4.4 filter, widened):
+    a run that keeps them in some sweeps and rebuilds them in others equals
+    the oracle's run."""
+    X = workloads.shells3d(400000, 5)
+    g, _ = compare_run(X, 96, 0.01, precision=precision, max_iter=15)
+    gi = g["info"]
+    print(f"  sweeps {gi['sweeps']}, list builds {gi['list_builds']}", flush=True)
+    assert gi["rounds"] <= gi["list_builds"] < gi["sweeps"]
