@@ -244,6 +244,8 @@ size_t layout(RunDev& r, Arena* a, bool full)
         both((float2*)nullptr, np, r.bnd);
         both((double*)nullptr, (size_t)ntiles * 2 * d, r.tbox);
         both((TileFrame*)nullptr, (size_t)ntiles, r.tframe);
+        both((TileBound*)nullptr, (size_t)ntiles, r.tbnd);
+        both((double2*)nullptr, (size_t)k, r.cdec);
         both((double*)nullptr, (size_t)(np / kWave) * 2 * d, r.gbox);
         const int64_t nhyper = (nsuper + kHyper - 1) / kHyper;
         both((double*)nullptr, (size_t)nhyper * 2 * d, r.hbox);

@@ -66,6 +66,9 @@ struct alignas(16) DevState {
     // build) over all centers from below and above; the balance step keeps
     // them (they mean something only while lists_ok is set).
     double listG, listF;
+    // (r, s) over all centers for the last interval between sweeps (the
+    // debug check after a center move relaxes the tile bounds with them)
+    double imu, ie;
     // the sweep's copies of the frame, refreshed wherever M or E change
     double invM;              // 1 / M
     float Mf, Ef;             // M rounded down and E rounded up to FP32
@@ -103,6 +106,25 @@ struct TileHead {
     float ubadd32;            // dmax + 2^-46 (1 + 7u), rounded up: the upper bound's additive term
     float lbout32;            // lb_out rounded down
     double lb_build;          // lb_out at the build
+};
+
+// Lower-bound frame of a tile (Sec. 4.3 bounds, relaxed per tile).  The
+// points of a tile store their Hamerly lower bound lb as s = (lb + E) / M.
+// Between two sweeps every center's effective distances change by at least
+// a ratio r_c (influence) and a shift s_c (movement); the second-best
+// center of a point of the tile is then one of the tile's candidates (their
+// ratios and shifts bound the change) or a center left out of its list
+// (whose distance is at least the list's fresh lb_out), so the bound of the
+// next sweep is min(m lb - e, lb_out) with m, e the smallest ratio and
+// largest shift over the tile's candidates: the frame takes M <- m M,
+// E <- m E + e, and the sweep lowers a stored s above lam = (lb_out + E) / M
+// to lam.  FP32 copies are rounded so that every bound stays valid.
+struct TileBound {
+    double M, E;
+    float Mf, Ef;             // M rounded down, E rounded up
+    float Edn, invMdn;        // E rounded down; 1/M times (1 - 2^-21), rounded down
+    float lam;                // lam rounded down
+    float pad;
 };
 
 // Static frame of a tile, fixed by its box at the layout: the anchor X (box
@@ -163,6 +185,9 @@ struct RunDev {
                               // y lower (lazy frame), one 8-byte record
     double* tbox;             // [ntiles][2d] lo..., hi...
     TileFrame* tframe;        // [ntiles]
+    TileBound* tbnd;          // [ntiles] lower-bound frames
+    double2* cdec;            // [k] (r_c, s_c): smallest ratio and largest shift of the center's
+                              // effective distances since the last sweep
     double* gbox;             // [ngroups][2d] boxes of 64-point groups
     double* hbox;             // [nhyper][2d] boxes of hyper-tiles (kHyper super-tiles)
     int32_t* hlist;           // [nhyper][k] candidate centers of each hyper-tile
@@ -389,18 +414,26 @@ __device__ inline double readlane_last_d(double v)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Largest of two values per lane over the wave (both reductions interleaved).
-__device__ inline void wave_max2_dpp(double& a, double& b)
+// Largest of N values per lane over the wave (the reductions interleaved),
+// wave-uniform.
+template <int CTRL, int ROWS, int N>
+__device__ inline void max_step_dpp(double* v)
 {
-    const double ninf = -INFINITY;
-    a = fmax(a, dpp_d<0x111, 0xf>(a, ninf)); b = fmax(b, dpp_d<0x111, 0xf>(b, ninf));   // row_shr:1
-    a = fmax(a, dpp_d<0x112, 0xf>(a, ninf)); b = fmax(b, dpp_d<0x112, 0xf>(b, ninf));   // row_shr:2
-    a = fmax(a, dpp_d<0x114, 0xf>(a, ninf)); b = fmax(b, dpp_d<0x114, 0xf>(b, ninf));   // row_shr:4
-    a = fmax(a, dpp_d<0x118, 0xf>(a, ninf)); b = fmax(b, dpp_d<0x118, 0xf>(b, ninf));   // row_shr:8
-    a = fmax(a, dpp_d<0x142, 0xa>(a, ninf)); b = fmax(b, dpp_d<0x142, 0xa>(b, ninf));   // row_bcast:15
-    a = fmax(a, dpp_d<0x143, 0xc>(a, ninf)); b = fmax(b, dpp_d<0x143, 0xc>(b, ninf));   // row_bcast:31
-    a = readlane_last_d(a);
-    b = readlane_last_d(b);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = fmax(v[i], dpp_d<CTRL, ROWS>(v[i], -INFINITY));
+}
+
+template <int N>
+__device__ inline void wave_max_dpp(double* v)
+{
+    max_step_dpp<0x111, 0xf, N>(v);   // row_shr:1
+    max_step_dpp<0x112, 0xf, N>(v);   // row_shr:2
+    max_step_dpp<0x114, 0xf, N>(v);   // row_shr:4
+    max_step_dpp<0x118, 0xf, N>(v);   // row_shr:8
+    max_step_dpp<0x142, 0xa, N>(v);   // row_bcast:15
+    max_step_dpp<0x143, 0xc, N>(v);   // row_bcast:31
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = readlane_last_d(v[i]);
 }
 
 template <int CTRL, int ROWS>
@@ -463,6 +496,19 @@ __device__ inline float f32_down(double x) { return __double2float_rd(x); }
 // that every bound stays valid, and the reciprocal of M (its rounding, a few
 // units of 2^-53, is covered by the sweep's 1e-12 slack).  Called by the one
 // thread that has just changed M or E.
+// One relaxation step of a tile's lower-bound frame: m, e the smallest ratio
+// and largest shift over its candidates, lb_out the bound on the rest.
+__device__ inline void tile_bound_step(TileBound& f, double m, double e, double lb_out)
+{
+    f.M = f.M * m * (1.0 - 0x1p-50);
+    f.E = (f.E * m + e) * (1.0 + 0x1p-50);
+    f.Mf = f32_down(f.M);
+    f.Ef = f32_up(f.E);
+    f.Edn = f32_down(f.E);
+    f.invMdn = f32_down((1.0 / f.M) * (1.0 - 0x1p-21));
+    f.lam = f32_down((lb_out + f.E) / f.M * (1.0 - 0x1p-50));
+}
+
 __device__ inline void frame_copies(DevState* st)
 {
     st->Mf = f32_down(st->M);

@@ -271,26 +271,61 @@ __device__ inline float screen_slack32(double tau)
 // do), so key0 G^2 is one and the order stays; tau, retaken from the
 // records' error terms; and the bound on every center left out at the
 // build, lb_build G.
+// The smallest ratio and largest shift (r_c, s_c) over the super-tile list
+// of an overflowed tile (its candidates), per lane; m starts at 1 (a larger
+// ratio only tightens, so 1 is always valid).
+template <typename RT>
+__device__ inline void decay_over_super(RT r, int tile, int lane, double& m, double& e)
+{
+    const int sidx = tile / r.super_tiles;
+    const int L = r.scount[sidx];
+    const int* __restrict__ sl = r.slist + (int64_t)sidx * r.k;
+    for (int i = lane; i < L; i += kWave) {
+        const double2 d = r.cdec[sl[i]];
+        m = fmin(m, d.x);
+        e = fmax(e, d.y);
+    }
+}
+
+// The tile's lower-bound frame f (as loaded) relaxed by (m, e) for this
+// sweep (wave-uniform values).
+template <typename RT>
+__device__ inline void relax_tile_bound(RT r, int tile, int lane, TileBound f, double m, double e,
+                                        double lb_out)
+{
+    if (lane == 0) {
+        tile_bound_step(f, m, e, lb_out);
+        r.tbnd[tile] = f;
+    }
+}
+
 template <typename RT>
 __device__ inline void refresh_tile(RT r, int tile, int lane)
 {
     TileHead* __restrict__ hp = r.thead + tile;
+    const TileBound f0 = r.tbnd[tile];
     const int n = hp->n;   // 0 for an overflowed tile
     const double G = r.st->listG;
     const double G2 = G * G * (1.0 - 0x1p-50);
     CandRec* __restrict__ cr = r.tcand + (int64_t)tile * kTileCap;
-    double tau = 0.0, unused = 0.0;
+    double tau = 0.0, m = 1.0, e = 0.0;
     for (int i = lane; i < n; i += kWave) {
         CandRec rec = cr[i];
         const double iv = r.clus[rec.id].y;
+        const double2 d = r.cdec[rec.id];
+        m = fmin(m, d.x);
+        e = fmax(e, d.y);
         rec.w2 = screen_w2(iv);
         rec.key = f32_down((double)rec.key0 * G2);
         tau = fmax(tau, (double)rec.dlt * iv);
         cr[i] = rec;
     }
-    wave_max2_dpp(tau, unused);
+    if (hp->overflow) decay_over_super(r, tile, lane, m, e);
+    double v[3] = {tau, -m, e};
+    wave_max_dpp<3>(v);
+    tau = v[0];
+    const double lb = hp->lb_build * G * (1.0 - kTiny);
     if (lane == 0) {
-        const double lb = hp->lb_build * G * (1.0 - kTiny);
         hp->lb_out = lb;
         hp->lbout32 = f32_down(lb);
         if (!hp->overflow) {
@@ -298,6 +333,7 @@ __device__ inline void refresh_tile(RT r, int tile, int lane)
             hp->slack32 = screen_slack32(hp->tau);
         }
     }
+    relax_tile_bound(r, tile, lane, f0, -v[1], v[2], lb);
 }
 
 template <int D, int PREC, typename RT>
@@ -324,6 +360,7 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
         refresh_tile(r, tile, lane);
         return;
     }
+    const TileBound f0 = r.tbnd[tile];
     const int k = r.k;
     const double* __restrict__ C = r.C;
 
@@ -410,11 +447,14 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // error bounds of every kept candidate and its record (one lane each,
     // in place of its slot)
-    double tau = 0.0, dmax = 0.0;
+    double tau = 0.0, dmax = 0.0, m = 1.0, e = 0.0;
     for (int i = lane; i < nrec; i += kWave) {
         const double lo2 = s_slot[wv][i].k.lo2;
         const int c = s_slot[wv][i].k.c;
         const double iv = r.clus[c].y;
+        const double2 dc = r.cdec[c];
+        m = fmin(m, dc.x);
+        e = fmax(e, dc.y);
         double dd = 0.0, q[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) {
@@ -438,7 +478,15 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
         s_slot[wv][i].rec = rec;
         s_key[wv][i] = rec.key;
     }
-    wave_max2_dpp(tau, dmax);
+    if (overflow) decay_over_super(r, tile, lane, m, e);
+    {
+        double v[4] = {tau, dmax, -m, e};
+        wave_max_dpp<4>(v);
+        tau = v[0];
+        dmax = v[1];
+        m = -v[2];
+        e = v[3];
+    }
     // the records in ascending key order (ties by slot): each lane ranks its
     // records against all of them (the wave's own LDS rows, so a wave-level
     // fence orders the writes before the reads)
@@ -474,6 +522,7 @@ __device__ __forceinline__ void tilecand_body(RT r, const int bid)
         r.thead[tile] = h;
         if (tile == 0) atomicAdd(r.cnt + kCntListBuilds, 1ULL);
     }
+    relax_tile_bound(r, tile, lane, f0, m, e, sqrt(t.b * kListMargin2) * (1.0 - kTiny));
 }
 
 template <int D, int PREC>
@@ -615,11 +664,13 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
     float2 cl[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) cl[q] = r.clus32[aold[q] > 0 ? aold[q] : 0];
-    // lower-bound frame in FP32, rounded so that every bound stays valid;
-    // without bounds the test below can never pass (its lower bound is -inf)
-    const float Mf = r.use_bounds ? st->Mf : 0.0f;
-    const float Ef = r.use_bounds ? st->Ef : INFINITY;
-    const float Edn = st->Edn, invMdn = st->invMdn;
+    // the tile's lower-bound frame in FP32, rounded so that every bound
+    // stays valid; without bounds the test below can never pass (its lower
+    // bound is -inf)
+    const TileBound tb = r.tbnd[tile];
+    const float Mf = r.use_bounds ? tb.Mf : 0.0f;
+    const float Ef = r.use_bounds ? tb.Ef : INFINITY;
+    const float Edn = tb.Edn, invMdn = tb.invMdn, lam = tb.lam;
     const unsigned long long below = (1ULL << lane) - 1ULL;
     // Hamerly test (Sec. 4.3) of every point: upper bound on the own
     // effective distance below the lower bound on the second-best one (a
@@ -630,8 +681,12 @@ __device__ __forceinline__ void sweep_body(RT r, const int bid)
     for (int q = 0; q < PPT; ++q) {
         const bool real = aold[q] != kPad && ncand > 0;
         const float ub = (bd[q].x + cl[q].x) * cl[q].y;
-        const float lb = __builtin_fmaf(Mf, bd[q].y, -Ef);
+        // the stored bound, lowered to the tile's floor for the centers
+        // left out of its list (a skipped point keeps the lowered value)
+        const float sq = fminf(bd[q].y, lam);
+        const float lb = __builtin_fmaf(Mf, sq, -Ef);
         const bool skip = __builtin_fmaf(ub, 1.0f + 0x1p-20f, 0x1p-100f) < lb;
+        if (real && skip && sq < bd[q].y) Bt[q * kBlock + tid].y = sq;
         bq[q] = wave_ballot(real & !skip);
         const unsigned nr = (unsigned)__popcll(wave_ballot(real));
         const unsigned ne = (unsigned)__popcll(bq[q]);

@@ -96,13 +96,18 @@ __device__ __forceinline__ void balance_body(RT r, const int bid)
             const double q = iv / r.ivb[c];
             qlo = fmin(qlo, q);
             qhi = fmax(qhi, q);
+            r.cdec[c] = make_double2(io / in, 0.0);
         }
         mu = block_reduce_1024(m, sh, OpMin());
         lg = block_reduce_1024(qlo, sh, OpMin()) * kDown;
         lf = block_reduce_1024(qhi, sh, OpMax()) * kUp;
     }
+    if (bal)
+        for (int c = threadIdx.x; c < k; c += 1024) r.cdec[c] = make_double2(1.0, 0.0);
     __syncthreads();
     if (threadIdx.x == 0) {
+        st->imu = mu;
+        st->ie = 0.0;
         st->sweep_in_round = sweep_no;
         st->sweeps += 1;
         st->balanced = bal ? 1 : 0;
@@ -535,6 +540,8 @@ __device__ __forceinline__ void move_body(RT r, const int bid)
             r.clusdn[c] = f32_down(dacc);
             m = fmin(m, io / in);
             e = fmax(e, dl / in);
+            // after the balance step of the same interval
+            r.cdec[c] = make_double2(r.cdec[c].x * (io / in), dl / in);
         }
         mu = block_reduce_1024(m, sh, OpMin());
         emax = block_reduce_1024(e, sh, OpMax());
@@ -552,6 +559,8 @@ __device__ __forceinline__ void move_body(RT r, const int bid)
             st->M = st->M * mu * kDown;
             st->E = (st->E * mu + emax) * kUp;
             frame_copies(st);
+            st->imu = st->imu * mu;
+            st->ie = emax;
         }
         if (st->rounds >= st->max_iter) st->done = 1;
         st->round_done = 0;
@@ -585,6 +594,18 @@ __global__ __launch_bounds__(kBlock) void k_init_points(RunDev r)
     r.Aprev[i] = r.A[i];
     r.bnd[i] = make_float2(INFINITY, 0.0f);
     if (i < r.ngroups) r.gdirty[i] = 0;
+    if (i < r.ntiles) {
+        TileBound f;
+        f.M = 1.0;
+        f.E = 0.0;
+        f.Mf = 1.0f;
+        f.Ef = 0.0f;
+        f.Edn = 0.0f;
+        f.invMdn = f32_down(1.0 - 0x1p-21);
+        f.lam = INFINITY;
+        f.pad = 0.0f;
+        r.tbnd[i] = f;
+    }
 }
 
 // Non-uniform target sizes (the footnote to the objective at the start of
@@ -661,6 +682,7 @@ __global__ __launch_bounds__(kBlock) void k_init_clusters(RunDev r, const double
         r.clus[c] = make_double2(0.0, 1.0 / in);
         r.clus32[c] = make_float2(0.0f, f32_up(1.0 / in));
         r.clusdn[c] = 0.0f;
+        r.cdec[c] = make_double2(1.0, 0.0);
         for (int a = 0; a < kAcc; ++a) r.acc[(int64_t)c * kAcc + a] = 0;
         for (int j = 0; j < 2 * D; ++j) r.bb[(int64_t)c * 2 * D + j] = j < D ? ~0ULL : 0ULL;
     }
@@ -681,6 +703,8 @@ __global__ __launch_bounds__(kBlock) void k_init_clusters(RunDev r, const double
         st->lists_ok = 0;
         st->listG = 1.0;
         st->listF = 1.0;
+        st->imu = 1.0;
+        st->ie = 0.0;
         const double W = st->total_weight;
         if (!r.tsz) {   // with target sizes, the prep left the largest limit here
             if (r.weighted) {
@@ -723,6 +747,7 @@ __global__ __launch_bounds__(1024) void k_set_step(RunDev r, const double* crm,
         r.clus[c] = make_double2(dacc, 1.0 / in);
         r.clus32[c] = make_float2(f32_up(dacc), f32_up(1.0 / in));
         r.clusdn[c] = f32_down(dacc);
+        r.cdec[c] = make_double2(io / in, dl / in);
         m = fmin(m, io / in);
         e = fmax(e, dl / in);
     }
@@ -738,6 +763,8 @@ __global__ __launch_bounds__(1024) void k_set_step(RunDev r, const double* crm,
             st->E = (st->E * m + e) * kUp;
         }
         frame_copies(st);
+        st->imu = m;
+        st->ie = e;
         st->done = 0;
         st->round_done = 0;
         st->lists_ok = 0;
@@ -1007,7 +1034,12 @@ __global__ __launch_bounds__(kBlock) void k_check_bounds(RunDev r, int after_swe
                 }
                 const float2 b = r.bnd[i];
                 const double ub = (double)b.x + r.clus[a].x;
-                const double lb = st->M * (double)b.y - st->E;
+                // the tile's frame; after a center move, with the move's
+                // relaxation over all centers (the next sweep's tile
+                // candidates apply their own)
+                const TileBound& f = r.tbnd[i / r.T];
+                double lb = f.M * fmin((double)b.y, (double)f.lam) - f.E;
+                if (!after_sweep) lb = st->imu * lb - st->ie;
                 if (ub < sqrt(own_sq) * (1.0 - 1e-12)) bad = true;
                 if (lb > other * (1.0 + 1e-12)) bad = true;
                 if (after_sweep && own > best * (1.0 + 1e-12)) bad = true;
