@@ -366,7 +366,8 @@ typedef struct {
     double harmonic_diameter;   /* harmonic mean of the bounds over blocks of >= 2
                                    vertices (1/inf = 0); inf if all are disconnected,
                                    0 if there are none */
-    int32_t bfs_levels;         /* breadth-first levels run (all searches) */
+    int32_t bfs_levels;         /* the most breadth-first levels one block's searches ran
+                                   (each block runs its own, all in one launch) */
     int32_t exact_blocks;       /* non-empty connected blocks whose bound is proven exact */
 } bkm_graph_stats;
 

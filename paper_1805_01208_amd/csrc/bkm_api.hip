@@ -1046,15 +1046,15 @@ int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int3
         return fail(BKM_EINVAL, "row_ptr/col/assignment/out is NULL");
     hipStream_t s = (hipStream_t)stream;
     keep_pool_memory();
-    constexpr int kBlockInts = 13;   // per-block int32 arrays of GraphDev
+    constexpr int kBlockInts = 9;   // per-block int32 arrays of GraphDev
     Sizes z;
     z.add<int64_t>((size_t)k);
     for (int i = 0; i < kBlockInts; ++i) z.add<int32_t>((size_t)k);
-    z.add<unsigned long long>((size_t)k);
+    z.add<int32_t>((size_t)k + 1);
     z.add<long long>(4);
     z.add<int>(16);
     z.add<double>(8);
-    for (int i = 0; i < 4; ++i) z.add<int32_t>((size_t)n);
+    for (int i = 0; i < 6; ++i) z.add<int32_t>((size_t)n);
     for (int i = 0; i < 3; ++i) z.add<unsigned long long>((size_t)n);
     Arena a;
     a.s = s;
@@ -1066,36 +1066,33 @@ int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int3
     for (int i = 0; i < kBlockInts; ++i) bi[i] = a.take<int32_t>((size_t)k);
     g.size = bi[0];
     g.seed = bi[1];
-    g.reached = bi[2];
-    g.conn = bi[3];
-    g.src = bi[4];
-    g.ecc1 = bi[5];
-    g.lval = bi[6];
-    g.fi = bi[7];
-    g.lb = bi[8];
-    g.ub = bi[9];
-    g.fcnt = bi[10];
-    g.blast = bi[11];
-    g.far = a.take<unsigned long long>((size_t)k);
+    g.conn = bi[2];
+    g.fill = bi[3];
+    g.ecc1 = bi[4];
+    g.lval = bi[5];
+    g.fi = bi[6];
+    g.lb = bi[7];
+    g.ub = bi[8];
+    g.moff = a.take<int32_t>((size_t)k + 1);
     long long* sc = a.take<long long>(4);
     g.cut2 = sc;
     g.sums = sc + 1;
     int* ints = a.take<int>(16);
     g.bad = ints;
-    int32_t* cnt = ints + 1;       // frontier counts, three in rotation
-    int32_t* nlevels = ints + 4;   // levels with a non-empty frontier
-    g.ctl = ints + 5;              // blocks left open, largest fringe
+    int32_t* nlevels = ints + 1;   // most levels of one block's searches
     double* summary = a.take<double>(8);
+    g.mem = a.take<int32_t>((size_t)n);
     int32_t* dist = a.take<int32_t>((size_t)n);
     int32_t* du = a.take<int32_t>((size_t)n);
     int32_t* qa = a.take<int32_t>((size_t)n);
     int32_t* qb = a.take<int32_t>((size_t)n);
+    int32_t* fr = a.take<int32_t>((size_t)n);   // the blocks' fringes, at their list offsets
     unsigned long long* seen = a.take<unsigned long long>((size_t)n);
-    unsigned long long* arr[2];
-    arr[0] = a.take<unsigned long long>((size_t)n);
-    arr[1] = a.take<unsigned long long>((size_t)n);
+    unsigned long long* arr0 = a.take<unsigned long long>((size_t)n);
+    unsigned long long* arr1 = a.take<unsigned long long>((size_t)n);
     HIPCHK(hipMemsetAsync(g.comm, 0, (size_t)k * sizeof(int64_t), s));
     HIPCHK(hipMemsetAsync(g.size, 0, (size_t)k * sizeof(int32_t), s));
+    HIPCHK(hipMemsetAsync(g.conn, 0, (size_t)k * sizeof(int32_t), s));
     HIPCHK(launch_fill_i32(g.seed, k, INT32_MAX, s));
     HIPCHK(hipMemsetAsync(sc, 0, 4 * sizeof(long long), s));
     HIPCHK(hipMemsetAsync(ints, 0, 16 * sizeof(int), s));
@@ -1104,69 +1101,10 @@ int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int3
     HIPCHK(hipMemcpyAsync(&hb, g.bad, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (hb) return fail(BKM_EINVAL, "assignment outside [0, k), or row_ptr/col outside the graph");
-
-    // Searches over all blocks at once.  Levels are enqueued in batches of
-    // kBfsBatch, each reading its frontier size on the device; the host reads
-    // the size left after a batch, and the levels past the end of a search do
-    // nothing.
-    constexpr int kBfsBatch = 32;
-    auto levels_loop = [&](auto&& one_level) -> int {
-        int32_t f = 1;
-        for (int64_t level = 0; f > 0;) {
-            if (level >= n + kBfsBatch) return fail(BKM_EHIP, "breadth-first search did not end");
-            for (int b = 0; b < kBfsBatch; ++b, ++level) HIPCHK(one_level(level));
-            HIPCHK(hipMemcpyAsync(&f, cnt + level % 3, sizeof(f), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            if (f < 0 || f > n) return fail(BKM_EHIP, "frontier of %d vertices", f);
-        }
-        return BKM_OK;
-    };
-    // the 4-sweep and the search from its middle vertex u: one source per block
-    int rc;
-    for (int stage = 0; stage < 5; ++stage) {
-        int32_t* d = stage == 4 ? du : dist;
-        HIPCHK(launch_diam_stage(k, g, stage, row_ptr, col, assignment, dist, s));
-        HIPCHK(launch_fill_i32(d, n, -1, s));
-        HIPCHK(hipMemsetAsync(cnt, 0, 3 * sizeof(int32_t), s));
-        HIPCHK(launch_bfs_sources(k, g, d, qa, cnt, s));
-        rc = levels_loop([&](int64_t level) {
-            int32_t* cur = (level & 1) ? qb : qa;
-            int32_t* nxt = (level & 1) ? qa : qb;
-            return launch_bfs_level(row_ptr, col, assignment, g, cur, cnt, (int32_t)level, d, nxt,
-                                    nlevels, n, s);
-        });
-        if (rc) return rc;
-    }
-    HIPCHK(hipMemsetAsync(g.ctl, 0, 2 * sizeof(int32_t), s));
-    HIPCHK(launch_diam_stage(k, g, 5, row_ptr, col, assignment, du, s));
-    // iFUB rounds: the fringe of every open block, searched 64 sources per
-    // block and pass
-    HIPCHK(launch_fill_u64(arr[0], n, s));
-    HIPCHK(launch_fill_u64(arr[1], n, s));
-    for (int round = 0; round < 3; ++round) {
-        int32_t* frank = dist;   // free after the 4-sweep
-        HIPCHK(launch_fringe_rank(n, assignment, du, g, frank, s));
-        int32_t hc[2];
-        HIPCHK(hipMemcpyAsync(hc, g.ctl, sizeof(hc), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (hc[0] == 0) break;
-        const int batches = (hc[1] + 63) / 64;
-        for (int t = 0; t < batches; ++t) {
-            HIPCHK(launch_fill_u64(seen, n, s));
-            HIPCHK(hipMemsetAsync(cnt, 0, 3 * sizeof(int32_t), s));
-            HIPCHK(launch_mbfs_seed(n, frank, t, arr[0], qa, cnt, s));
-            rc = levels_loop([&](int64_t level) {
-                int32_t* cur = (level & 1) ? qb : qa;
-                int32_t* nxt = (level & 1) ? qa : qb;
-                return launch_mbfs_level(row_ptr, col, assignment, g, cur, cnt, (int32_t)level,
-                                         seen, arr[level & 1], arr[(level + 1) & 1], nxt, nlevels,
-                                         n, s);
-            });
-            if (rc) return rc;
-        }
-        HIPCHK(hipMemsetAsync(g.ctl, 0, 2 * sizeof(int32_t), s));
-        HIPCHK(launch_ifub_round(k, g, s));
-    }
+    // the diameter bounds: one workgroup per block runs all of its searches
+    HIPCHK(launch_block_lists(n, assignment, k, g, s));
+    HIPCHK(launch_diam_blocks(row_ptr, col, assignment, k, g, dist, du, qa, qb, fr, seen, arr0,
+                              arr1, nlevels, s));
     int levels = 0;
     HIPCHK(hipMemcpyAsync(&levels, nlevels, sizeof(levels), hipMemcpyDeviceToHost, s));
     HIPCHK(launch_gm_final(k, g, diameter_out, diameter_ub_out, comm_out, summary, s));

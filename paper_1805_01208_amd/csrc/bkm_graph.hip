@@ -373,12 +373,6 @@ __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t* p, int64_t n, int3
     if (i < n) p[i] = v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_fill_u64(unsigned long long* p, int64_t n)
-{
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) p[i] = 0ULL;
-}
-
 __device__ inline int32_t far_vertex(unsigned long long key)
 {
     return (int32_t)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
@@ -405,275 +399,359 @@ __device__ int32_t walk_back(const int64_t* row_ptr, const int32_t* col, const i
     return x;
 }
 
-// Per-block bookkeeping between the single-source searches of the diameter
-// bound, from the results of the search just finished (far, reached, dist):
-//   stage 0: source r1 = the lowest vertex;
-//   stage 1: connected iff the search reached the whole block; source a1;
-//   stage 2: ecc(a1); source r2, floor(ecc/2) from a1 on the path from b1;
-//   stage 3: source a2;
-//   stage 4: l = max(ecc(a1), ecc(a2)); source u, floor(ecc/2) from a2 on
-//            the path from b2;
-//   stage 5: iFUB start from ecc(u): i, lb, ub; counts the blocks left open.
-__global__ __launch_bounds__(kBlock) void k_diam_stage(int k, GraphDev g, int stage,
-                                                       const int64_t* row_ptr, const int32_t* col,
-                                                       const int32_t* A, const int32_t* dist)
+// ------------------------------------------------------ block diameters
+// The diameter bound of a block (reading M3) lives in the block's induced
+// subgraph, so one workgroup takes one block and runs all of its searches:
+// the 4-sweep, the search from its middle vertex u, and up to three iFUB
+// rounds.  Levels are separated by workgroup barriers only: a search of any
+// length is part of one launch, and blocks proceed independently.  Each block
+// has the list of its vertices and queue space of its own size in n-sized
+// arrays (at its offset moff).
+
+constexpr int kBfsLanes = 8;   // lanes sharing a frontier vertex
+constexpr int kDiamU = 4;      // frontier vertices a lane group holds at once
+
+struct DiamShared {
+    int cnt[2];                 // frontier sizes, alternating with the level
+    int reached;                // vertices the search reached
+    int levels;                 // levels with a non-empty frontier, over all searches
+    int blast;                  // deepest level at which a fringe search reached a vertex
+    int fcount;                 // fringe size
+    int src;                    // a vertex chosen by thread 0
+    unsigned long long far;     // far_key of the farthest vertex reached
+};
+
+// Single-source search of block b from src, distances into d (every other
+// vertex of the block at -1 first); leaves the reached count and the
+// farthest vertex (largest level, lowest index) in sh.  kBfsLanes lanes
+// share a frontier vertex, each taking every kBfsLanes-th entry of its row,
+// and every lane group holds kDiamU frontier vertices at once so that their
+// loads overlap; a vertex is claimed by a CAS on its distance, and a wave
+// reserves its claims' places in the next frontier with one LDS atomic.
+template <int NT>
+__device__ void bfs_block(const int64_t* row_ptr, const int32_t* col, const int32_t* A, int32_t b,
+                          const int32_t* mem, int32_t size, int32_t src, int32_t* d, int32_t* qa,
+                          int32_t* qb, DiamShared& sh)
 {
-    const int b = blockIdx.x * kBlock + threadIdx.x;
-    if (b >= k) return;
-    int32_t src = -1;
-    const unsigned long long key = g.far[b];
-    if (stage == 0) {
-        g.conn[b] = 0;
-        if (g.size[b] > 0) src = g.seed[b];
-    } else if (stage == 1) {
-        const int c = g.size[b] > 0 && g.reached[b] == g.size[b] ? 1 : 0;
-        g.conn[b] = c;
-        if (c) src = far_vertex(key);
-    } else if (g.conn[b]) {
-        const int32_t e = far_level(key);
-        if (stage == 2) {
-            g.ecc1[b] = e;
-            src = walk_back(row_ptr, col, A, dist, b, far_vertex(key), e - e / 2);
-        } else if (stage == 3) {
-            src = far_vertex(key);
-        } else if (stage == 4) {
-            g.lval[b] = max(g.ecc1[b], e);
-            src = walk_back(row_ptr, col, A, dist, b, far_vertex(key), e - e / 2);
+    constexpr int kPer = NT / kBfsLanes;
+    const int tid = threadIdx.x, lane = tid % kWave;
+    const unsigned long long below = (1ULL << lane) - 1ULL;
+    for (int j = tid; j < size; j += NT) d[mem[j]] = -1;
+    __syncthreads();
+    if (tid == 0) {
+        d[src] = 0;
+        qa[0] = src;
+        sh.cnt[0] = 1;
+        sh.cnt[1] = 0;
+        sh.reached = 1;
+        sh.far = far_key(0, src);
+    }
+    __syncthreads();
+    int32_t* cur = qa;
+    int32_t* nxt = qb;
+    for (int level = 0;; ++level) {
+        const int ncur = sh.cnt[level & 1];
+        if (ncur == 0) break;
+        int* ncount = &sh.cnt[(level + 1) & 1];
+        for (int base = 0; base < ncur; base += kPer * kDiamU) {
+            int64_t e[kDiamU], end[kDiamU];
+#pragma unroll
+            for (int q = 0; q < kDiamU; ++q) {
+                const int i = base + q * kPer + tid / kBfsLanes;
+                e[q] = end[q] = 0;
+                if (i < ncur) {
+                    const int32_t u = cur[i];
+                    e[q] = row_ptr[u] + tid % kBfsLanes;
+                    end[q] = row_ptr[(int64_t)u + 1];
+                }
+            }
+            for (;;) {
+                bool more = false;
+#pragma unroll
+                for (int q = 0; q < kDiamU; ++q) more |= e[q] < end[q];
+                if (__ballot(more) == 0ULL) break;
+                int32_t v[kDiamU];
+                bool live[kDiamU], claim[kDiamU];
+#pragma unroll
+                for (int q = 0; q < kDiamU; ++q) {
+                    live[q] = e[q] < end[q];
+                    v[q] = live[q] ? col[e[q]] : 0;
+                    e[q] += live[q] ? kBfsLanes : 0;
+                }
+#pragma unroll
+                for (int q = 0; q < kDiamU; ++q)
+                    claim[q] = live[q] && A[v[q]] == b && d[v[q]] == -1;
+#pragma unroll
+                for (int q = 0; q < kDiamU; ++q)
+                    if (claim[q]) claim[q] = atomicCAS(&d[v[q]], -1, level + 1) == -1;
+#pragma unroll
+                for (int q = 0; q < kDiamU; ++q) {
+                    const unsigned long long bm = __ballot(claim[q]);
+                    if (bm == 0ULL) continue;
+                    const int leader = __builtin_ctzll(bm);
+                    int pos = 0;
+                    if (lane == leader) {
+                        pos = atomicAdd(ncount, (int)__popcll(bm));
+                        atomicAdd(&sh.reached, (int)__popcll(bm));
+                    }
+                    pos = __shfl(pos, leader, kWave);
+                    if (claim[q]) {
+                        nxt[pos + (int)__popcll(bm & below)] = v[q];
+                        atomicMax(&sh.far, far_key(level + 1, v[q]));
+                    }
+                }
+            }
+        }
+        __syncthreads();   // the next frontier is complete
+        if (tid == 0) {
+            sh.cnt[level & 1] = 0;   // the level after next appends here
+            sh.levels += 1;
+        }
+        __syncthreads();
+        int32_t* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+}
+
+// Searches from up to 64 sources of block b at once (an iFUB round's fringe,
+// source j with bit j): a vertex holds the sources that reached it (seen)
+// and those arriving at the current level (arr[level & 1]); it joins the next
+// frontier when the first new bit arrives.  sh.blast = the deepest level at
+// which some vertex took a new bit, the largest eccentricity of the sources.
+template <int NT>
+__device__ void mbfs_block(const int64_t* row_ptr, const int32_t* col, const int32_t* A, int32_t b,
+                           const int32_t* mem, int32_t size, const int32_t* srcs, int nsrc,
+                           unsigned long long* seen, unsigned long long* arr0,
+                           unsigned long long* arr1, int32_t* qa, int32_t* qb, DiamShared& sh)
+{
+    constexpr int kPer = NT / kBfsLanes;
+    const int tid = threadIdx.x, lane = tid % kWave;
+    const unsigned long long below = (1ULL << lane) - 1ULL;
+    for (int j = tid; j < size; j += NT) {
+        const int32_t v = mem[j];
+        seen[v] = 0ULL;
+        arr0[v] = 0ULL;
+        arr1[v] = 0ULL;
+    }
+    __syncthreads();
+    if (tid < nsrc) {
+        const int32_t v = srcs[tid];
+        arr0[v] = 1ULL << tid;
+        qa[tid] = v;
+    }
+    if (tid == 0) {
+        sh.cnt[0] = nsrc;
+        sh.cnt[1] = 0;
+        sh.blast = -1;
+    }
+    __syncthreads();
+    int32_t* cur = qa;
+    int32_t* nxt = qb;
+    for (int level = 0;; ++level) {
+        const int ncur = sh.cnt[level & 1];
+        if (ncur == 0) break;
+        int* ncount = &sh.cnt[(level + 1) & 1];
+        unsigned long long* ca = (level & 1) ? arr1 : arr0;
+        unsigned long long* na = (level & 1) ? arr0 : arr1;
+        for (int base = 0; base < ncur; base += kPer * kDiamU) {
+            int64_t e[kDiamU], end[kDiamU];
+            unsigned long long m[kDiamU];
+#pragma unroll
+            for (int q = 0; q < kDiamU; ++q) {
+                const int i = base + q * kPer + tid / kBfsLanes;
+                e[q] = end[q] = 0;
+                m[q] = 0ULL;
+                if (i < ncur) {
+                    const int32_t u = cur[i];
+                    const unsigned long long sn = seen[u];
+                    m[q] = ca[u] & ~sn;
+                    // the lanes of u's group all read ca and seen above (same wave)
+                    if (tid % kBfsLanes == 0) {
+                        ca[u] = 0ULL;
+                        if (m[q]) {
+                            seen[u] = sn | m[q];
+                            atomicMax(&sh.blast, level);
+                        }
+                    }
+                    if (m[q]) {
+                        e[q] = row_ptr[u] + tid % kBfsLanes;
+                        end[q] = row_ptr[(int64_t)u + 1];
+                    }
+                }
+            }
+            for (;;) {
+                bool more = false;
+#pragma unroll
+                for (int q = 0; q < kDiamU; ++q) more |= e[q] < end[q];
+                if (__ballot(more) == 0ULL) break;
+                int32_t v[kDiamU];
+                bool app[kDiamU];
+                unsigned long long add[kDiamU];
+#pragma unroll
+                for (int q = 0; q < kDiamU; ++q) {
+                    const bool live = e[q] < end[q];
+                    v[q] = live ? col[e[q]] : 0;
+                    e[q] += live ? kBfsLanes : 0;
+                    add[q] = live ? m[q] : 0ULL;
+                }
+#pragma unroll
+                for (int q = 0; q < kDiamU; ++q)
+                    if (add[q]) add[q] = A[v[q]] == b ? add[q] & ~seen[v[q]] : 0ULL;
+#pragma unroll
+                for (int q = 0; q < kDiamU; ++q) app[q] = add[q] && atomicOr(&na[v[q]], add[q]) == 0ULL;
+#pragma unroll
+                for (int q = 0; q < kDiamU; ++q) {
+                    const unsigned long long bm = __ballot(app[q]);
+                    if (bm == 0ULL) continue;
+                    const int leader = __builtin_ctzll(bm);
+                    int pos = 0;
+                    if (lane == leader) pos = atomicAdd(ncount, (int)__popcll(bm));
+                    pos = __shfl(pos, leader, kWave);
+                    if (app[q]) nxt[pos + (int)__popcll(bm & below)] = v[q];
+                }
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            sh.cnt[level & 1] = 0;
+            sh.levels += 1;
+        }
+        __syncthreads();
+        int32_t* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+}
+
+// One block per workgroup (reading M3):
+//   r1 = the lowest vertex; connected iff its search reaches the whole block;
+//   a1 = farthest from r1; ecc(a1), b1 = farthest from a1; r2 = floor(ecc/2)
+//   from a1 on the path back from b1; a2 = farthest from r2; ecc(a2), b2;
+//   l = max(ecc(a1), ecc(a2)); u = floor(ecc(a2)/2) from a2 on the path back
+//   from b2; i = ecc(u), lb = max(l, i), ub = 2i; then rounds while ub > lb,
+//   at most three: B = the largest eccentricity over the fringe (distance i
+//   from u, searched 64 sources at a time); if max(lb, B) > 2(i - 1) the
+//   bound is exact, else lb = max(lb, B), ub = 2(i - 1), i = i - 1.
+// `levels` takes the most levels any block's searches ran.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_diam_blocks(
+    const int64_t* row_ptr, const int32_t* col, const int32_t* A, GraphDev g, int32_t* dist,
+    int32_t* du, int32_t* qa_all, int32_t* qb_all, int32_t* fr_all, unsigned long long* seen,
+    unsigned long long* arr0, unsigned long long* arr1, int32_t* levels)
+{
+    __shared__ DiamShared sh;
+    const int32_t b = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int32_t size = g.size[b];
+    if (size == 0) return;   // reported as 0 from the size alone
+    if (tid == 0) sh.levels = 0;
+    const int32_t off = g.moff[b];
+    const int32_t* mem = g.mem + off;
+    int32_t* qa = qa_all + off;
+    int32_t* qb = qb_all + off;
+    auto search = [&](int32_t src, int32_t* d) {
+        bfs_block<NT>(row_ptr, col, A, b, mem, size, src, d, qa, qb, sh);
+    };
+    // the vertex `steps` closer to the search's source on the path back from x
+    auto back = [&](const int32_t* d, int32_t x, int32_t steps) -> int32_t {
+        if (tid == 0) sh.src = walk_back(row_ptr, col, A, d, b, x, steps);
+        __syncthreads();
+        const int32_t v = sh.src;
+        __syncthreads();
+        return v;
+    };
+    search(g.seed[b], dist);
+    if (sh.reached != size) {
+        if (tid == 0) {
+            g.conn[b] = 0;
+            atomicMax(levels, sh.levels);
+        }
+        return;
+    }
+    search(far_vertex(sh.far), dist);                    // from a1
+    const int32_t e1 = far_level(sh.far);
+    search(back(dist, far_vertex(sh.far), e1 - e1 / 2), dist);   // from r2
+    search(far_vertex(sh.far), dist);                    // from a2
+    const int32_t e2 = far_level(sh.far);
+    const int32_t lval = max(e1, e2);
+    search(back(dist, far_vertex(sh.far), e2 - e2 / 2), du);     // from u
+    int32_t i = far_level(sh.far);
+    int32_t lb = max(lval, i), ub = 2 * i;
+    int32_t* fr = fr_all + off;   // the fringe
+    for (int round = 0; round < 3 && ub > lb; ++round) {
+        if (tid == 0) sh.fcount = 0;
+        __syncthreads();
+        for (int j = tid; j < size; j += NT) {
+            const int32_t v = mem[j];
+            if (du[v] == i) fr[atomicAdd(&sh.fcount, 1)] = v;
+        }
+        __syncthreads();
+        const int nf = sh.fcount;
+        int32_t B = -1;
+        for (int t0 = 0; t0 < nf; t0 += 64) {
+            mbfs_block<NT>(row_ptr, col, A, b, mem, size, fr + t0, min(64, nf - t0), seen, arr0,
+                           arr1, qa, qb, sh);
+            B = max(B, sh.blast);
+        }
+        const int32_t m = max(lb, B);
+        if (m > 2 * (i - 1)) {
+            lb = m;
+            ub = m;
         } else {
-            g.fi[b] = e;
-            g.lb[b] = max(g.lval[b], e);
-            g.ub[b] = 2 * e;
-            g.fcnt[b] = 0;
-            g.blast[b] = -1;
-            if (g.ub[b] > g.lb[b]) atomicAdd(&g.ctl[0], 1);
+            lb = m;
+            ub = 2 * (i - 1);
+            i = i - 1;
         }
     }
-    g.src[b] = src;
+    if (tid == 0) {
+        g.conn[b] = 1;
+        g.ecc1[b] = e1;
+        g.lval[b] = lval;
+        g.fi[b] = i;
+        g.lb[b] = lb;
+        g.ub[b] = ub;
+        atomicMax(levels, sh.levels);
+    }
 }
 
-// Seeds the next single-source search from g.src (resets every block's
-// reached count and farthest vertex).
-__global__ __launch_bounds__(kBlock) void k_bfs_sources(int k, GraphDev g, int32_t* dist,
-                                                        int32_t* queue, int32_t* count)
+// Offsets of the blocks' vertex lists: exclusive prefix sums of the block
+// sizes (one block of 1024 threads, each over a contiguous segment); the
+// cursor of every list to 0.
+__global__ __launch_bounds__(1024) void k_block_offsets(int k, GraphDev g)
 {
-    const int b = blockIdx.x * kBlock + threadIdx.x;
-    if (b >= k) return;
-    const int32_t src = g.src[b];
-    g.reached[b] = 0;
-    g.far[b] = 0;
-    if (src < 0) return;
-    dist[src] = 0;
-    g.reached[b] = 1;
-    g.far[b] = far_key(0, src);
-    queue[atomicAdd(count, 1)] = src;
+    __shared__ int32_t sh[1024];
+    const int per = (k + 1023) / 1024;
+    const int b0 = (int)threadIdx.x * per;
+    int32_t s = 0;
+    for (int q = 0; q < per; ++q)
+        if (b0 + q < k) s += g.size[b0 + q];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int32_t v = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int32_t run = sh[threadIdx.x] - s;
+    for (int q = 0; q < per; ++q)
+        if (b0 + q < k) {
+            g.moff[b0 + q] = run;
+            g.fill[b0 + q] = 0;
+            run += g.size[b0 + q];
+        }
+    if (threadIdx.x == 1023) g.moff[k] = sh[1023];
 }
 
-// iFUB round, fringe: every vertex of an open block at distance i from u
-// gets its rank in the block's fringe (the order does not matter: a round
-// takes the largest eccentricity over the whole fringe); the largest fringe
-// goes to ctl[1].
-__global__ __launch_bounds__(kBlock) void k_fringe_rank(int64_t n, const int32_t* A,
-                                                        const int32_t* du, GraphDev g,
-                                                        int32_t* frank)
+// Every vertex into its block's list (order within a list is free: nothing
+// depends on it).
+__global__ __launch_bounds__(kBlock) void k_block_members(int64_t n, const int32_t* A, GraphDev g)
 {
     const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (v >= n) return;
-    const int32_t b = A[v];
-    int32_t r = -1;
-    if (g.conn[b] && g.ub[b] > g.lb[b] && du[v] == g.fi[b]) {
-        r = atomicAdd(&g.fcnt[b], 1);
-        atomicMax(&g.ctl[1], r + 1);
-    }
-    frank[v] = r;
-}
-
-// Sources of batch `batch`: fringe ranks 64*batch .. 64*batch + 63 of every
-// block, each with its own bit.
-__global__ __launch_bounds__(kBlock) void k_mbfs_seed(int64_t n, const int32_t* frank, int batch,
-                                                      unsigned long long* arrive, int32_t* queue,
-                                                      int32_t* count)
-{
-    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int lane = threadIdx.x % kWave;
-    const int32_t r = v < n ? frank[v] - 64 * batch : -1;
-    const bool src = r >= 0 && r < 64;
-    if (src) arrive[v] = 1ULL << r;
-    const unsigned long long b = __ballot(src);
-    if (b == 0ULL) return;
-    int base = 0;
-    if (lane == __builtin_ctzll(b)) base = atomicAdd(count, (int)__popcll(b));
-    base = __shfl(base, __builtin_ctzll(b), kWave);
-    if (src) queue[base + (int)__popcll(b & ((1ULL << lane) - 1ULL))] = (int32_t)v;
-}
-
-// Round end: B = the deepest level the fringe's searches reached.  If
-// max(lb, B) > 2(i - 1) the bound is exact (lb = ub), else lb = max(lb, B),
-// ub = 2(i - 1) and the next round looks one level closer to u.
-__global__ __launch_bounds__(kBlock) void k_ifub_round(int k, GraphDev g)
-{
-    const int b = blockIdx.x * kBlock + threadIdx.x;
-    if (b >= k || !g.conn[b] || g.ub[b] <= g.lb[b]) return;
-    const int32_t i = g.fi[b];
-    const int32_t m = max(g.lb[b], g.blast[b]);
-    if (m > 2 * (i - 1)) {
-        g.lb[b] = m;
-        g.ub[b] = m;
-    } else {
-        g.lb[b] = m;
-        g.ub[b] = 2 * (i - 1);
-        g.fi[b] = i - 1;
-    }
-    g.fcnt[b] = 0;
-    g.blast[b] = -1;
-    if (g.ub[b] > g.lb[b]) atomicAdd(&g.ctl[0], 1);
-}
-
-// One level: every frontier vertex claims its unvisited neighbours of the
-// same block; a claimed vertex joins the next frontier and may become its
-// block's farthest vertex.  kBfsLanes lanes share a frontier vertex, each
-// taking every kBfsLanes-th entry of its row; the lanes of a wave reserve
-// their places in the next frontier with one atomic per step.
-constexpr int kBfsLanes = 8;
-
-// The frontier size comes from device memory (counts[level % 3]), so the
-// host can enqueue many levels without reading it: a fixed grid walks the
-// frontier, and a level whose frontier is empty does nothing.  The level
-// adds to counts[(level + 1) % 3], which the level before cleared, and
-// clears counts[(level + 2) % 3] for the level after; `levels` counts the
-// levels with a non-empty frontier.
-__global__ __launch_bounds__(kBlock) void k_bfs_level(const int64_t* row_ptr, const int32_t* col,
-                                                      const int32_t* A, GraphDev g,
-                                                      const int32_t* frontier, int32_t* counts,
-                                                      int32_t level, int32_t* dist, int32_t* next,
-                                                      int32_t* levels)
-{
-    const int32_t fcount = counts[level % 3];
-    int32_t* ncount = counts + (level + 1) % 3;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        counts[(level + 2) % 3] = 0;
-        if (fcount > 0) atomicAdd(levels, 1);
-    }
-    const int lane = threadIdx.x % kWave;
-    const unsigned long long below = (1ULL << lane) - 1ULL;
-    const int64_t per_block = kBlock / kBfsLanes;
-    // block-uniform walk over the frontier, kBlock / kBfsLanes vertices per block and step
-    for (int64_t i0 = (int64_t)blockIdx.x * per_block; i0 < fcount;
-         i0 += (int64_t)gridDim.x * per_block) {
-        const int64_t i = i0 + threadIdx.x / kBfsLanes;
-        const bool act = i < fcount;
-        int32_t u = 0, a = -1;
-        int64_t e = 0, end = 0;
-        if (act) {
-            u = frontier[i];
-            a = A[u];
-            e = row_ptr[u] + threadIdx.x % kBfsLanes;
-            end = row_ptr[(int64_t)u + 1];
-        }
-        while (__ballot(e < end) != 0ULL) {
-            bool claim = false;
-            int32_t v = 0;
-            if (e < end) {
-                v = col[e];
-                e += kBfsLanes;
-                claim = A[v] == a && dist[v] == -1 && atomicCAS(&dist[v], -1, level + 1) == -1;
-            }
-            const unsigned long long b = __ballot(claim);
-            if (b == 0ULL) continue;
-            int base = 0;
-            if (lane == __builtin_ctzll(b)) base = atomicAdd(ncount, (int)__popcll(b));
-            base = __shfl(base, __builtin_ctzll(b), kWave);
-            if (claim) next[base + (int)__popcll(b & below)] = v;
-            // block counters: one update per distinct block among the claims
-            unsigned long long pend = b;
-            while (pend) {
-                const int leader = __builtin_ctzll(pend);
-                const int la = __shfl(a, leader, kWave);
-                const bool mine = claim && a == la;
-                const unsigned long long mm = __ballot(mine);
-                unsigned long long key = mine ? far_key(level + 1, v) : 0ULL;
-                for (int m = kWave / 2; m > 0; m >>= 1) {
-                    const unsigned long long o = __shfl_xor(key, m, kWave);
-                    key = o > key ? o : key;
-                }
-                if (lane == leader) {
-                    atomicAdd(&g.reached[la], (int)__popcll(mm));
-                    atomicMax(&g.far[la], key);
-                }
-                pend &= ~mm;
-            }
-        }
-    }
-}
-
-// One level of the bit-parallel search: a frontier vertex takes the bits
-// that first reached it at this level (its arrival mask minus the bits it
-// has seen), records the level as its block's deepest, and offers them to
-// its neighbours of the same block; a neighbour whose arrival mask for the
-// next level was empty joins the next frontier.  A neighbour read while it
-// is itself updating its seen mask may be offered bits it already has: it
-// drops them at the next level, so every bit arrives at every vertex at its
-// true distance from the source.  Frontier sizes rotate as in k_bfs_level.
-__global__ __launch_bounds__(kBlock) void k_mbfs_level(const int64_t* row_ptr, const int32_t* col,
-                                                       const int32_t* A, GraphDev g,
-                                                       const int32_t* frontier, int32_t* counts,
-                                                       int32_t level, unsigned long long* seen,
-                                                       unsigned long long* cur,
-                                                       unsigned long long* nxt, int32_t* next,
-                                                       int32_t* levels)
-{
-    const int32_t fcount = counts[level % 3];
-    int32_t* ncount = counts + (level + 1) % 3;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        counts[(level + 2) % 3] = 0;
-        if (fcount > 0) atomicAdd(levels, 1);
-    }
-    const int lane = threadIdx.x % kWave;
-    const unsigned long long below = (1ULL << lane) - 1ULL;
-    const int64_t per_block = kBlock / kBfsLanes;
-    for (int64_t i0 = (int64_t)blockIdx.x * per_block; i0 < fcount;
-         i0 += (int64_t)gridDim.x * per_block) {
-        const int64_t i = i0 + threadIdx.x / kBfsLanes;
-        const bool act = i < fcount;
-        int32_t u = 0, a = -1;
-        int64_t e = 0, end = 0;
-        unsigned long long m = 0ULL;
-        if (act) {
-            u = frontier[i];
-            a = A[u];
-            const unsigned long long sn = seen[u];
-            m = cur[u] & ~sn;
-            // the lanes of u's group all read cur and seen above (same wave)
-            if (threadIdx.x % kBfsLanes == 0) {
-                cur[u] = 0ULL;
-                if (m) {
-                    seen[u] = sn | m;
-                    atomicMax(&g.blast[a], level);
-                }
-            }
-            if (m) {
-                e = row_ptr[u] + threadIdx.x % kBfsLanes;
-                end = row_ptr[(int64_t)u + 1];
-            }
-        }
-        while (__ballot(e < end) != 0ULL) {
-            bool app = false;
-            int32_t v = 0;
-            if (e < end) {
-                v = col[e];
-                e += kBfsLanes;
-                if (A[v] == a) {
-                    const unsigned long long add = m & ~seen[v];
-                    if (add) app = atomicOr(&nxt[v], add) == 0ULL;
-                }
-            }
-            const unsigned long long b = __ballot(app);
-            if (b == 0ULL) continue;
-            int base = 0;
-            if (lane == __builtin_ctzll(b)) base = atomicAdd(ncount, (int)__popcll(b));
-            base = __shfl(base, __builtin_ctzll(b), kWave);
-            if (app) next[base + (int)__popcll(b & below)] = v;
-        }
-    }
+    const int32_t a = A[v];
+    g.mem[g.moff[a] + atomicAdd(&g.fill[a], 1)] = (int32_t)v;
 }
 
 // Block results after the searches, and the summary (one block).
@@ -840,69 +918,37 @@ hipError_t launch_gm_vertex(int64_t n, int64_t nnz, const int64_t* row_ptr, cons
     return hipGetLastError();
 }
 
-hipError_t launch_diam_stage(int k, const GraphDev& g, int stage, const int64_t* row_ptr,
-                             const int32_t* col, const int32_t* A, const int32_t* dist,
-                             hipStream_t s)
+hipError_t launch_block_lists(int64_t n, const int32_t* A, int k, const GraphDev& g, hipStream_t s)
 {
-    k_diam_stage<<<nblocks(k, kBlock), kBlock, 0, s>>>(k, g, stage, row_ptr, col, A, dist);
+    k_block_offsets<<<1, 1024, 0, s>>>(k, g);
+    k_block_members<<<nblocks(n, kBlock), kBlock, 0, s>>>(n, A, g);
     return hipGetLastError();
 }
 
-hipError_t launch_bfs_sources(int k, const GraphDev& g, int32_t* dist, int32_t* queue,
-                              int32_t* count, hipStream_t s)
+hipError_t launch_diam_blocks(const int64_t* row_ptr, const int32_t* col, const int32_t* A, int k,
+                              const GraphDev& g, int32_t* dist, int32_t* du, int32_t* qa,
+                              int32_t* qb, int32_t* fr, unsigned long long* seen,
+                              unsigned long long* arr0, unsigned long long* arr1, int32_t* levels,
+                              hipStream_t s)
 {
-    k_bfs_sources<<<nblocks(k, kBlock), kBlock, 0, s>>>(k, g, dist, queue, count);
-    return hipGetLastError();
-}
-
-hipError_t launch_fringe_rank(int64_t n, const int32_t* A, const int32_t* du, const GraphDev& g,
-                              int32_t* frank, hipStream_t s)
-{
-    k_fringe_rank<<<nblocks(n, kBlock), kBlock, 0, s>>>(n, A, du, g, frank);
-    return hipGetLastError();
-}
-
-hipError_t launch_mbfs_seed(int64_t n, const int32_t* frank, int batch,
-                            unsigned long long* arrive, int32_t* queue, int32_t* count,
-                            hipStream_t s)
-{
-    k_mbfs_seed<<<nblocks(n, kBlock), kBlock, 0, s>>>(n, frank, batch, arrive, queue, count);
-    return hipGetLastError();
-}
-
-hipError_t launch_mbfs_level(const int64_t* row_ptr, const int32_t* col, const int32_t* A,
-                             const GraphDev& g, const int32_t* frontier, int32_t* counts,
-                             int32_t level, unsigned long long* seen, unsigned long long* cur,
-                             unsigned long long* nxt, int32_t* next, int32_t* levels, int64_t n,
-                             hipStream_t s)
-{
-    const unsigned grid = (unsigned)std::min<int64_t>(2048, nblocks(n * kBfsLanes, kBlock));
-    k_mbfs_level<<<grid, kBlock, 0, s>>>(row_ptr, col, A, g, frontier, counts, level, seen, cur,
-                                         nxt, next, levels);
-    return hipGetLastError();
-}
-
-hipError_t launch_ifub_round(int k, const GraphDev& g, hipStream_t s)
-{
-    k_ifub_round<<<nblocks(k, kBlock), kBlock, 0, s>>>(k, g);
-    return hipGetLastError();
-}
-
-hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s)
-{
-    if (n > 0) k_fill_u64<<<nblocks(n, kBlock), kBlock, 0, s>>>(p, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_bfs_level(const int64_t* row_ptr, const int32_t* col, const int32_t* A,
-                            const GraphDev& g, const int32_t* frontier, int32_t* counts,
-                            int32_t level, int32_t* dist, int32_t* next, int32_t* levels,
-                            int64_t n, hipStream_t s)
-{
-    // enough blocks for a frontier of n vertices in one step, at most 2048
-    const unsigned grid = (unsigned)std::min<int64_t>(2048, nblocks(n * kBfsLanes, kBlock));
-    k_bfs_level<<<grid, kBlock, 0, s>>>(row_ptr, col, A, g, frontier, counts, level, dist, next,
-                                        levels);
+    // all blocks resident at once where possible (2048 threads per CU), with
+    // 64 to 1024 threads per block
+    const int64_t per = (int64_t)256 * 2048 / std::max(k, 1);
+    if (per >= 1024)
+        k_diam_blocks<1024><<<k, 1024, 0, s>>>(row_ptr, col, A, g, dist, du, qa, qb, fr, seen,
+                                               arr0, arr1, levels);
+    else if (per >= 512)
+        k_diam_blocks<512><<<k, 512, 0, s>>>(row_ptr, col, A, g, dist, du, qa, qb, fr, seen, arr0,
+                                             arr1, levels);
+    else if (per >= 256)
+        k_diam_blocks<256><<<k, 256, 0, s>>>(row_ptr, col, A, g, dist, du, qa, qb, fr, seen, arr0,
+                                             arr1, levels);
+    else if (per >= 128)
+        k_diam_blocks<128><<<k, 128, 0, s>>>(row_ptr, col, A, g, dist, du, qa, qb, fr, seen, arr0,
+                                             arr1, levels);
+    else
+        k_diam_blocks<64><<<k, 64, 0, s>>>(row_ptr, col, A, g, dist, du, qa, qb, fr, seen, arr0,
+                                           arr1, levels);
     return hipGetLastError();
 }
 

@@ -525,22 +525,20 @@ struct GraphDev {
     int64_t* comm;            // [k] communication volume
     int32_t* size;            // [k] vertices
     int32_t* seed;            // [k] lowest vertex (INT_MAX if empty)
-    int32_t* reached;         // [k] vertices reached by the current search
     int32_t* conn;            // [k] 1 if the first search reached the whole block
-    unsigned long long* far;  // [k] (level << 32) | (2^32-1 - vertex) of the farthest vertex
     long long* cut2;          // [1] cut entries (each undirected edge twice)
     long long* sums;          // [3] max comm, total comm, disconnected blocks
     int* bad;                 // [1] invalid input seen
+    // vertex lists: block b's vertices are mem[moff[b] .. moff[b+1])
+    int32_t* moff;            // [k+1]
+    int32_t* mem;             // [n]
+    int32_t* fill;            // [k] list cursor while the lists are built
     // diameter bound (4-sweep, then iFUB rounds)
-    int32_t* src;             // [k] source of the next single-source search, -1 for none
     int32_t* ecc1;            // [k] eccentricity of a1
     int32_t* lval;            // [k] l = max(ecc(a1), ecc(a2))
-    int32_t* fi;              // [k] iFUB level i
+    int32_t* fi;              // [k] iFUB level i after the rounds
     int32_t* lb;              // [k] lower bound
     int32_t* ub;              // [k] upper bound
-    int32_t* fcnt;            // [k] vertices of the current fringe
-    int32_t* blast;           // [k] deepest level reached by the current round's searches
-    int32_t* ctl;             // [2] blocks still open, largest fringe
 };
 
 hipError_t launch_bbox(const RunDev& r, int hilbert_order, hipStream_t s);
@@ -579,33 +577,14 @@ hipError_t launch_sym_fill(int64_t n, int K, const int32_t* nbr, const int64_t* 
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_gm_vertex(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
                             const int32_t* A, int k, const GraphDev& g, hipStream_t s);
-// diameter bound: per-block bookkeeping between searches (stage 0: the
-// lowest vertex; 1: connectivity, a1; 2: ecc(a1), r2; 3: a2; 4: l, u;
-// 5: iFUB start)
-hipError_t launch_diam_stage(int k, const GraphDev& g, int stage, const int64_t* row_ptr,
-                             const int32_t* col, const int32_t* A, const int32_t* dist,
-                             hipStream_t s);
-hipError_t launch_bfs_sources(int k, const GraphDev& g, int32_t* dist, int32_t* queue,
-                              int32_t* count, hipStream_t s);
-// one breadth-first level; its frontier size is counts[level % 3] on the device
-hipError_t launch_bfs_level(const int64_t* row_ptr, const int32_t* col, const int32_t* A,
-                            const GraphDev& g, const int32_t* frontier, int32_t* counts,
-                            int32_t level, int32_t* dist, int32_t* next, int32_t* levels,
-                            int64_t n, hipStream_t s);
-// iFUB rounds: fringe ranks, the sources of one batch of 64 per block, one
-// level of the bit-parallel search, and the round's update of the bounds
-hipError_t launch_fringe_rank(int64_t n, const int32_t* A, const int32_t* du, const GraphDev& g,
-                              int32_t* frank, hipStream_t s);
-hipError_t launch_mbfs_seed(int64_t n, const int32_t* frank, int batch,
-                            unsigned long long* arrive, int32_t* queue, int32_t* count,
-                            hipStream_t s);
-hipError_t launch_mbfs_level(const int64_t* row_ptr, const int32_t* col, const int32_t* A,
-                             const GraphDev& g, const int32_t* frontier, int32_t* counts,
-                             int32_t level, unsigned long long* seen, unsigned long long* cur,
-                             unsigned long long* nxt, int32_t* next, int32_t* levels, int64_t n,
-                             hipStream_t s);
-hipError_t launch_ifub_round(int k, const GraphDev& g, hipStream_t s);
-hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s);
+// diameter bounds: every block's vertex list (offsets, then members), then
+// one workgroup per block runs all its searches
+hipError_t launch_block_lists(int64_t n, const int32_t* A, int k, const GraphDev& g, hipStream_t s);
+hipError_t launch_diam_blocks(const int64_t* row_ptr, const int32_t* col, const int32_t* A, int k,
+                              const GraphDev& g, int32_t* dist, int32_t* du, int32_t* qa,
+                              int32_t* qb, int32_t* fr, unsigned long long* seen,
+                              unsigned long long* arr0, unsigned long long* arr1, int32_t* levels,
+                              hipStream_t s);
 hipError_t launch_gm_final(int k, const GraphDev& g, int32_t* diam_out, int32_t* diam_ub_out,
                            int64_t* comm_out, double* summary, hipStream_t s);
 hipError_t launch_supercand(const RunDev& r, hipStream_t s);
