@@ -212,7 +212,7 @@ size_t layout(RunDev& r, Arena* a, bool full)
     };
     both((DevState*)nullptr, 1, r.st);
     both((unsigned long long*)nullptr, kCntSlots * kCntWords, r.cnt);
-    both((double*)nullptr, std::max<int64_t>(8192, k), r.red);
+    both((double*)nullptr, std::max<int64_t>(32768, k), r.red);
     both((uint64_t*)nullptr, n, r.keys);
     both((uint64_t*)nullptr, n, r.keys2);
     both((int32_t*)nullptr, n, r.sperm);
@@ -863,7 +863,7 @@ size_t stats_workspace(int k, int d, bool targets)
 {
     Sizes z;
     z.add<DevState>(1);
-    z.add<double>(std::max<int64_t>(8192, k));
+    z.add<double>(std::max<int64_t>(32768, k));
     z.add<double>((size_t)k * d);
     z.add<long long>((size_t)k * kAcc);
     z.add<double>(8);
@@ -887,7 +887,7 @@ int stats_core(const bkm_points* pts, const int32_t* assignment, int32_t k, doub
     Arena a;   // carves only: base is handed back before it would be freed
     a.base = ws;
     r.st = a.take<DevState>(1);
-    r.red = a.take<double>(std::max<int64_t>(8192, k));
+    r.red = a.take<double>(std::max<int64_t>(32768, k));
     r.C = a.take<double>((size_t)k * r.d);
     r.acc = a.take<long long>((size_t)k * kAcc);
     double* out6 = a.take<double>(8);

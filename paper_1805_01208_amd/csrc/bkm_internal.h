@@ -66,6 +66,7 @@ struct alignas(16) DevState {
     // build) over all centers from below and above; the balance step keeps
     // them (they mean something only while lists_ok is set).
     double listG, listF;
+    double jump_thr2;         // squared gap above which consecutive points start a new tile
     // (r, s) over all centers for the last interval between sweeps (the
     // debug check after a center move relaxes the tile bounds with them)
     double imu, ie;

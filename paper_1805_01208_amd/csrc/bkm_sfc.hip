@@ -78,20 +78,38 @@ __global__ __launch_bounds__(kBlock) void k_bbox_partial(RunDev r)
     }
 }
 
+// The partials folded by all threads (thread t over parts t, t + 256, ...,
+// then a fixed tree over the threads: the weight sum's order is fixed).
 __global__ __launch_bounds__(kBlock) void k_bbox_final(RunDev r, int nparts, int m)
 {
-    __shared__ double o[8];
-    if (threadIdx.x == 0) {
-        for (int q = 0; q < 8; ++q) o[q] = r.red[q];
-        for (int b = 1; b < nparts; ++b) {
-            const double* p = r.red + (int64_t)b * 8;
-            for (int j = 0; j < 3; ++j) {
-                o[j] = fmin(o[j], p[j]);
-                o[3 + j] = fmax(o[3 + j], p[3 + j]);
-            }
-            o[6] = fmax(o[6], p[6]);
-            o[7] += p[7];
+    __shared__ double sh[kBlock][8];
+    double f[8] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nparts; b += kBlock) {
+        const double* p = r.red + (int64_t)b * 8;
+        for (int j = 0; j < 3; ++j) {
+            f[j] = fmin(f[j], p[j]);
+            f[3 + j] = fmax(f[3 + j], p[3 + j]);
         }
+        f[6] = fmax(f[6], p[6]);
+        f[7] += p[7];
+    }
+    for (int q = 0; q < 8; ++q) sh[threadIdx.x][q] = f[q];
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            double* a = sh[threadIdx.x];
+            const double* b = sh[threadIdx.x + w];
+            for (int j = 0; j < 3; ++j) {
+                a[j] = fmin(a[j], b[j]);
+                a[3 + j] = fmax(a[3 + j], b[3 + j]);
+            }
+            a[6] = fmax(a[6], b[6]);
+            a[7] += b[7];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double* o = sh[0];
         DevState* st = r.st;
         double ext = 0.0;
         for (int j = 0; j < 3; ++j) {
@@ -379,22 +397,23 @@ __device__ inline double tx_at(const RunDev& r, int j, int64_t i)
 // A tile straddling such a jump gets a huge box and a huge candidate list, so
 // the layout is padded to start a new tile after every jump.  A jump is a gap
 // between consecutive points larger than 64 times the median gap (median from
-// a log2 histogram, so the threshold is exact and order-independent).
-__device__ inline int gap_bin(double g)
+// a histogram of binary exponents of the squared gaps, so the threshold is
+// exact and order-independent; the comparisons take squared gaps).
+__device__ inline int gap_bin(double g2)
 {
-    if (!(g > 0.0)) return 0;
-    const int e = ilogb(g) + 64;
+    if (!(g2 > 0.0)) return 0;
+    const int e = (ilogb(g2) >> 1) + 64;   // the exponent of the gap, rounded down
     return e < 1 ? 1 : (e >= kGapBins ? kGapBins - 1 : e);
 }
 
-__device__ inline double gap_at(const RunDev& r, int64_t i)
+__device__ inline double gap2_at(const RunDev& r, int64_t i)
 {
     double s = 0.0;
     for (int j = 0; j < r.d; ++j) {
         const double v = tx_at(r, j, i + 1) - tx_at(r, j, i);
         s += v * v;
     }
-    return sqrt(s);
+    return s;
 }
 
 __global__ __launch_bounds__(kBlock) void k_gap_hist(RunDev r)
@@ -404,29 +423,33 @@ __global__ __launch_bounds__(kBlock) void k_gap_hist(RunDev r)
     __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i + 1 < r.n; i += stride)
-        atomicAdd(&h[gap_bin(gap_at(r, i))], 1u);
+        atomicAdd(&h[gap_bin(gap2_at(r, i))], 1u);
     __syncthreads();
     if (threadIdx.x < kGapBins && h[threadIdx.x]) atomicAdd(&r.ghist[threadIdx.x], h[threadIdx.x]);
 }
 
+// The jump threshold, squared, into the run state: the upper edge of the
+// median bin times 64 (0: no jumps).
+__global__ __launch_bounds__(kWave) void k_gap_threshold(RunDev r)
+{
+    if (threadIdx.x != 0) return;
+    unsigned long long tot = 0, acc = 0;
+    for (int b = 0; b < kGapBins; ++b) tot += r.ghist[b];
+    int med = 0;
+    for (int b = 0; b < kGapBins; ++b) {
+        acc += r.ghist[b];
+        if (2 * acc >= tot) { med = b; break; }
+    }
+    const double thr = med == 0 ? 0.0 : ldexp(1.0, med - 64 + 1 + 6);
+    r.st->jump_thr2 = thr * thr;
+}
+
 __global__ __launch_bounds__(kBlock) void k_jump_find(RunDev r)
 {
-    __shared__ double thr;
-    if (threadIdx.x == 0) {
-        // upper edge of the median bin, times 64
-        unsigned long long tot = 0, acc = 0;
-        for (int b = 0; b < kGapBins; ++b) tot += r.ghist[b];
-        int med = 0;
-        for (int b = 0; b < kGapBins; ++b) {
-            acc += r.ghist[b];
-            if (2 * acc >= tot) { med = b; break; }
-        }
-        thr = med == 0 ? 0.0 : ldexp(1.0, med - 64 + 1 + 6);
-    }
-    __syncthreads();
+    const double thr2 = r.st->jump_thr2;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i + 1 >= r.n || !(thr > 0.0)) return;
-    if (gap_at(r, i) > thr) {
+    if (i + 1 >= r.n || !(thr2 > 0.0)) return;
+    if (gap2_at(r, i) > thr2) {
         const int slot = atomicAdd(&r.st->njumps, 1);
         if (slot < r.maxjumps) r.jumps[slot] = (int32_t)(i + 1);
     }
@@ -706,7 +729,7 @@ inline unsigned nblocks(int64_t n, int per) { return (unsigned)((n + per - 1) / 
 
 hipError_t launch_bbox(const RunDev& r, int hilbert_order, hipStream_t s)
 {
-    int nparts = (int)std::min<int64_t>(1024, (r.n + kBlock - 1) / kBlock);
+    int nparts = (int)std::min<int64_t>(4096, (r.n + kBlock - 1) / kBlock);
     if (r.in_f32)
         k_bbox_partial<float><<<nparts, kBlock, 0, s>>>(r);
     else
@@ -774,6 +797,7 @@ hipError_t launch_jump_plan(const RunDev& r, hipStream_t s)
     if (e != hipSuccess) return e;
     const unsigned g = (unsigned)std::min<int64_t>(2048, nblocks(r.n, kBlock));
     k_gap_hist<<<g, kBlock, 0, s>>>(r);
+    k_gap_threshold<<<1, kWave, 0, s>>>(r);
     k_jump_find<<<nblocks(r.n, kBlock), kBlock, 0, s>>>(r);
     k_jump_plan<<<1, 1024, 0, s>>>(r);
     return hipGetLastError();

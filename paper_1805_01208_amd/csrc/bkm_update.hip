@@ -40,6 +40,32 @@ __device__ inline double block_reduce_1024(double v, double* sh, F op)
     return r;
 }
 
+// Three reductions at once (the first two minima, the third a maximum).
+__device__ inline void block_min_min_max_1024(double& a, double& b, double& c, double (*sh)[1024 / kWave])
+{
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    for (int m = kWave / 2; m > 0; m >>= 1) {
+        a = fmin(a, __shfl_xor(a, m, kWave));
+        b = fmin(b, __shfl_xor(b, m, kWave));
+        c = fmax(c, __shfl_xor(c, m, kWave));
+    }
+    __syncthreads();
+    if (lane == 0) {
+        sh[0][wv] = a;
+        sh[1][wv] = b;
+        sh[2][wv] = c;
+    }
+    __syncthreads();
+    a = sh[0][0];
+    b = sh[1][0];
+    c = sh[2][0];
+    for (int w = 1; w < 1024 / kWave; ++w) {
+        a = fmin(a, sh[0][w]);
+        b = fmin(b, sh[1][w]);
+        c = fmax(c, sh[2][w]);
+    }
+}
+
 struct OpMax { __device__ double operator()(double a, double b) const { return fmax(a, b); } };
 struct OpMin { __device__ double operator()(double a, double b) const { return fmin(a, b); } };
 struct OpAdd { __device__ double operator()(double a, double b) const { return a + b; } };
@@ -98,9 +124,11 @@ __device__ __forceinline__ void balance_body(RT r, const int bid)
             qhi = fmax(qhi, q);
             r.cdec[c] = make_double2(io / in, 0.0);
         }
-        mu = block_reduce_1024(m, sh, OpMin());
-        lg = block_reduce_1024(qlo, sh, OpMin()) * kDown;
-        lf = block_reduce_1024(qhi, sh, OpMax()) * kUp;
+        __shared__ double sh3[3][1024 / kWave];
+        block_min_min_max_1024(m, qlo, qhi, sh3);
+        mu = m;
+        lg = qlo * kDown;
+        lf = qhi * kUp;
     }
     if (bal)
         for (int c = threadIdx.x; c < k; c += 1024) r.cdec[c] = make_double2(1.0, 0.0);
