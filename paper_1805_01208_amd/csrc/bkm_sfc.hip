@@ -496,16 +496,16 @@ __global__ __launch_bounds__(1024) void k_jump_plan(RunDev r)
     }
 }
 
-// Layout shift of Hilbert position i: that of the last jump at or before i.
-__device__ inline int64_t shift_of(const RunDev& r, int nj, int64_t i)
+// Index of the first jump start after Hilbert position i (binary search).
+__device__ inline int jump_after(const RunDev& r, int nj, int64_t i)
 {
-    int lo = 0, hi = nj;  // first jump start > i
+    int lo = 0, hi = nj;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if ((int64_t)r.jumps[mid] <= i) lo = mid + 1;
         else hi = mid;
     }
-    return lo > 0 ? r.jshift[lo - 1] : 0;
+    return lo;
 }
 
 __global__ __launch_bounds__(kBlock) void k_init_layout(RunDev r)
@@ -519,12 +519,21 @@ __global__ __launch_bounds__(kBlock) void k_init_layout(RunDev r)
 // Points into the padded layout; the last point before each gap in the
 // layout also fills the gap with copies of itself, so tile and group boxes
 // are those of the real points.
+// The layout shift of Hilbert position i is that of the last jump at or
+// before it: one binary search per block for its first point, then a short
+// forward scan per thread (a block's 256 points hold few jump starts).
 __global__ __launch_bounds__(kBlock) void k_place(RunDev r)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= r.n) return;
+    __shared__ int s_j0;
+    const int64_t i0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t i = i0 + threadIdx.x;
     const int nj = r.st->njumps;
-    const int64_t pos = i + shift_of(r, nj, i);
+    if (threadIdx.x == 0) s_j0 = jump_after(r, nj, i0);
+    __syncthreads();
+    if (i >= r.n) return;
+    int j = s_j0;
+    while (j < nj && (int64_t)r.jumps[j] <= i) ++j;
+    const int64_t pos = i + (j > 0 ? r.jshift[j - 1] : 0);
     const int32_t src = r.sperm[i];
     r.perm[pos] = src;
     r.A[pos] = -1;
@@ -537,7 +546,9 @@ __global__ __launch_bounds__(kBlock) void k_place(RunDev r)
         else
             r.xs64[j][pos] = x[j];
     }
-    const int64_t next = (i + 1 < r.n) ? i + 1 + shift_of(r, nj, i + 1) : r.npad;
+    int jn = j;
+    while (jn < nj && (int64_t)r.jumps[jn] <= i + 1) ++jn;
+    const int64_t next = (i + 1 < r.n) ? i + 1 + (jn > 0 ? r.jshift[jn - 1] : 0) : r.npad;
     for (int64_t q = pos + 1; q < next; ++q) {
         for (int j = 0; j < r.d; ++j) {
             if (r.in_f32)
@@ -573,12 +584,19 @@ __global__ __launch_bounds__(kBlock) void k_tile_prep(RunDev r)
         const int64_t g0 = base + (int64_t)q * kBlock + wv * kWave;  // group start
         const int64_t i = g0 + lane;
         double gmn[D], gmx[D];
+        // the group's box: maxima of -x and x over the wave, in one pass
+        double v[2 * D];
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            const double v = xs_at(r, j, i);
-            const double w = v;
-            gmn[j] = wave_min_d(v);
-            gmx[j] = wave_max_d(w);
+            const double x = xs_at(r, j, i);
+            v[j] = -x;
+            v[D + j] = x;
+        }
+        wave_max_dpp<2 * D>(v);
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            gmn[j] = -v[j];
+            gmx[j] = v[D + j];
             tmn[j] = fmin(tmn[j], gmn[j]);
             tmx[j] = fmax(tmx[j], gmx[j]);
         }
