@@ -975,10 +975,28 @@ int bkm_knn(const bkm_points* pts, int32_t knn, int32_t* nbr_out, bkm_knn_info* 
         for (auto& e : ev) HIPCHK(hipEventCreate(&e));
     if (info) HIPCHK(hipEventRecord(ev[0], s));
     if ((rc = bootstrap(r, 16, s, true))) return rc;
+    // the search reads FP64 coordinates: an FP32 layout is widened first
+    KnnPts P{};
+    Arena wide;
+    if (r.in_f32) {
+        wide.s = s;
+        const size_t bytes = (size_t)r.npad * r.d * sizeof(double);
+        hipError_t e = hipMallocAsync((void**)&wide.base, bytes, s);
+        if (e != hipSuccess) {
+            wide.base = nullptr;
+            return fail(e == hipErrorOutOfMemory ? BKM_ENOMEM : BKM_EHIP,
+                        "hipMallocAsync(%zu bytes): %s", bytes, hipGetErrorString(e));
+        }
+        double* x = reinterpret_cast<double*>(wide.base);
+        HIPCHK(launch_knn_widen(r, x, s));
+        for (int j = 0; j < r.d; ++j) P.x[j] = x + (size_t)j * r.npad;
+    } else {
+        for (int j = 0; j < r.d; ++j) P.x[j] = r.xs64[j];
+    }
     unsigned long long* visits = reinterpret_cast<unsigned long long*>(r.red);
     HIPCHK(hipMemsetAsync(visits, 0, sizeof(unsigned long long), s));
     if (info) HIPCHK(hipEventRecord(ev[1], s));
-    HIPCHK(launch_knn(r, knn, nbr_out, visits, s));
+    HIPCHK(launch_knn(r, P, knn, nbr_out, visits, s));
     if (info) HIPCHK(hipEventRecord(ev[2], s));
     unsigned long long hv = 0;
     HIPCHK(hipMemcpyAsync(&hv, visits, sizeof(hv), hipMemcpyDeviceToHost, s));

@@ -36,11 +36,6 @@ namespace {
 
 inline unsigned nblocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
-__device__ inline double coord(const RunDev& r, int j, int64_t i)
-{
-    return r.in_f32 ? (double)r.xs32[j][i] : r.xs64[j][i];
-}
-
 // (da, ia) before (db, ib): smaller squared distance, then smaller index.
 __device__ inline bool nb_before(double da, int32_t ia, double db, int32_t ib)
 {
@@ -58,13 +53,13 @@ __device__ inline double box_gap2(const double* a, const double* b)
     return s;
 }
 
-__device__ inline double readlane_d(double v, int i)
-{
-    const unsigned long long u = __double_as_longlong(v);
-    const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, i);
-    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), i);
-    return __longlong_as_double(((long long)hi << 32) | lo);
-}
+// Scalar (wave-uniform) loads: the partner points of a visited group are the
+// same for every lane, so they are read through the scalar cache into SGPRs
+// and enter the distance arithmetic as scalar operands.
+typedef const __attribute__((address_space(4))) double* ScalarD;
+typedef const __attribute__((address_space(4))) int32_t* ScalarI;
+
+constexpr int kKnnChunk = 8;   // partners screened per wave-wide test
 
 template <int D, int K>
 struct KnnLane {
@@ -74,37 +69,58 @@ struct KnnLane {
     double kd[K];
     int32_t ki[K];
 
-    // All 64 points of group h against this lane's point.
-    __device__ inline void visit(const RunDev& r, int64_t h, int lane)
+    // Screening radius of the lane: its K-th squared distance (infinite while
+    // the list is not full), below zero for a padding lane.
+    __device__ inline double limit() const { return active ? kd[K - 1] : -1.0; }
+
+    __device__ inline void insert(double s, int32_t pi)
     {
-        const int64_t p2 = h * kWave + lane;
-        const int32_t pid = r.perm[p2];
-        double c[D];
+        kd[K - 1] = s;
+        ki[K - 1] = pi;
 #pragma unroll
-        for (int j = 0; j < D; ++j) c[j] = coord(r, j, p2);
-        for (int i = 0; i < kWave; ++i) {
-            const int32_t pi = __builtin_amdgcn_readlane(pid, i);
-            if (pi < 0) continue;   // padding (uniform)
-            double dv[D];
-#pragma unroll
-            for (int j = 0; j < D; ++j) dv[j] = q[j] - readlane_d(c[j], i);
-            double s = dv[0] * dv[0] + dv[1] * dv[1];
-            if (D == 3) s = s + dv[D - 1] * dv[D - 1];
-            if (active && pi != self && nb_before(s, pi, kd[K - 1], ki[K - 1])) {
-                kd[K - 1] = s;
-                ki[K - 1] = pi;
-#pragma unroll
-                for (int m = K - 1; m > 0; --m) {
-                    if (nb_before(kd[m], ki[m], kd[m - 1], ki[m - 1])) {
-                        const double td = kd[m];
-                        kd[m] = kd[m - 1];
-                        kd[m - 1] = td;
-                        const int32_t ti = ki[m];
-                        ki[m] = ki[m - 1];
-                        ki[m - 1] = ti;
-                    }
-                }
+        for (int m = K - 1; m > 0; --m) {
+            if (nb_before(kd[m], ki[m], kd[m - 1], ki[m - 1])) {
+                const double td = kd[m];
+                kd[m] = kd[m - 1];
+                kd[m - 1] = td;
+                const int32_t ti = ki[m];
+                ki[m] = ki[m - 1];
+                ki[m - 1] = ti;
             }
+        }
+    }
+
+    // All 64 points of group h against this lane's point.  Eight partners at
+    // a time are screened by squared distance against the lane's limit; only
+    // when some lane passes does the wave take the exact test on (squared
+    // distance, index) and insert.  A partner failing the screen fails the
+    // exact test too: the limit only shrinks.  Padding slots hold copies of
+    // a real point and are dropped by their index (-1).
+    __device__ inline void visit(const double* const* x, const int32_t* perm, int64_t h)
+    {
+        const int64_t base = h * kWave;
+        double lim = limit();
+        for (int c = 0; c < kWave; c += kKnnChunk) {
+            double s[kKnnChunk];
+            unsigned long long hit = 0;
+#pragma unroll
+            for (int u = 0; u < kKnnChunk; ++u) {
+                double dv[D];
+#pragma unroll
+                for (int j = 0; j < D; ++j) dv[j] = q[j] - ((ScalarD)x[j])[base + c + u];
+                double d2 = dv[0] * dv[0] + dv[1] * dv[1];
+                if (D == 3) d2 = d2 + dv[D - 1] * dv[D - 1];
+                s[u] = d2;
+                hit |= __ballot(d2 <= lim);
+            }
+            if (hit == 0) continue;
+#pragma unroll
+            for (int u = 0; u < kKnnChunk; ++u) {
+                const int32_t pi = ((ScalarI)perm)[base + c + u];
+                if (pi >= 0 && pi != self && s[u] <= lim && nb_before(s[u], pi, kd[K - 1], ki[K - 1]))
+                    insert(s[u], pi);
+            }
+            lim = limit();
         }
     }
 
@@ -113,8 +129,16 @@ struct KnnLane {
     __device__ inline double radius2() const { return wave_max_d(active ? kd[K - 1] : 0.0); }
 };
 
+// FP64 copy of an FP32 layout (axis j at x + j * npad) for the search.
+__global__ __launch_bounds__(kBlock) void k_knn_widen(RunDev r, double* x)
+{
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= r.npad) return;
+    for (int j = 0; j < r.d; ++j) x[j * r.npad + p] = (double)r.xs32[j][p];
+}
+
 template <int D, int K>
-__global__ __launch_bounds__(kBlock) void k_knn(RunDev r, int32_t* nbr,
+__global__ __launch_bounds__(kBlock) void k_knn(RunDev r, KnnPts P, int32_t* nbr,
                                                 unsigned long long* visits)
 {
     const int lane = threadIdx.x % kWave;
@@ -126,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_knn(RunDev r, int32_t* nbr,
     L.active = L.self >= 0;
     if (__ballot(L.active) == 0) return;   // a group of padding only
 #pragma unroll
-    for (int j = 0; j < D; ++j) L.q[j] = coord(r, j, pos);
+    for (int j = 0; j < D; ++j) L.q[j] = P.x[j][pos];
 #pragma unroll
     for (int m = 0; m < K; ++m) {
         L.kd[m] = INFINITY;
@@ -137,14 +161,14 @@ __global__ __launch_bounds__(kBlock) void k_knn(RunDev r, int32_t* nbr,
     for (int j = 0; j < 2 * D; ++j) gb[j] = r.gbox[g * 2 * D + j];
 
     long long nvis = 0;
-    L.visit(r, g, lane);
+    L.visit(P.x, r.perm, g);
     ++nvis;
     if (g > 0) {
-        L.visit(r, g - 1, lane);
+        L.visit(P.x, r.perm, g - 1);
         ++nvis;
     }
     if (g + 1 < r.ngroups) {
-        L.visit(r, g + 1, lane);
+        L.visit(P.x, r.perm, g + 1);
         ++nvis;
     }
     double R2 = L.radius2();
@@ -179,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_knn(RunDev r, int32_t* nbr,
                     while (mg) {
                         const int64_t gi = (int64_t)ti * gpt + __builtin_ctzll(mg);
                         mg &= mg - 1;
-                        L.visit(r, gi, lane);
+                        L.visit(P.x, r.perm, gi);
                         ++nvis;
                         R2 = L.radius2();
                     }
@@ -852,13 +876,13 @@ __global__ __launch_bounds__(1024) void k_gm_final(int k, GraphDev g, int32_t* d
 }
 
 template <int D>
-hipError_t launch_knn_d(const RunDev& r, int K, int32_t* nbr, unsigned long long* visits,
-                        hipStream_t s)
+hipError_t launch_knn_d(const RunDev& r, const KnnPts& P, int K, int32_t* nbr,
+                        unsigned long long* visits, hipStream_t s)
 {
     const unsigned grid = nblocks(r.ngroups, kBlock / kWave);
     switch (K) {
 #define BKM_KNN_CASE(KK) \
-    case KK: k_knn<D, KK><<<grid, kBlock, 0, s>>>(r, nbr, visits); break;
+    case KK: k_knn<D, KK><<<grid, kBlock, 0, s>>>(r, P, nbr, visits); break;
         BKM_KNN_CASE(1) BKM_KNN_CASE(2) BKM_KNN_CASE(3) BKM_KNN_CASE(4)
         BKM_KNN_CASE(5) BKM_KNN_CASE(6) BKM_KNN_CASE(7) BKM_KNN_CASE(8)
         BKM_KNN_CASE(9) BKM_KNN_CASE(10) BKM_KNN_CASE(11) BKM_KNN_CASE(12)
@@ -871,10 +895,17 @@ hipError_t launch_knn_d(const RunDev& r, int K, int32_t* nbr, unsigned long long
 
 }  // namespace
 
-hipError_t launch_knn(const RunDev& r, int K, int32_t* nbr, unsigned long long* visits,
-                      hipStream_t s)
+hipError_t launch_knn(const RunDev& r, const KnnPts& P, int K, int32_t* nbr,
+                      unsigned long long* visits, hipStream_t s)
 {
-    return r.d == 2 ? launch_knn_d<2>(r, K, nbr, visits, s) : launch_knn_d<3>(r, K, nbr, visits, s);
+    return r.d == 2 ? launch_knn_d<2>(r, P, K, nbr, visits, s)
+                    : launch_knn_d<3>(r, P, K, nbr, visits, s);
+}
+
+hipError_t launch_knn_widen(const RunDev& r, double* x, hipStream_t s)
+{
+    k_knn_widen<<<nblocks(r.npad, kBlock), kBlock, 0, s>>>(r, x);
+    return hipGetLastError();
 }
 
 hipError_t launch_sym_count(int64_t n, int K, const int32_t* nbr, int32_t* extra, int* bad,

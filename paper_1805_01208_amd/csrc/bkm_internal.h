@@ -566,8 +566,14 @@ hipError_t launch_sample_layout_rank(const RunDev& r, int32_t* rank, int32_t* rk
 hipError_t launch_sample_compact(const RunDev& r, const int32_t* rk, int64_t count, void* const* x,
                                  double* w, hipStream_t s);
 hipError_t launch_iota(int32_t* v, int64_t n, hipStream_t s);
-hipError_t launch_knn(const RunDev& r, int K, int32_t* nbr, unsigned long long* visits,
-                      hipStream_t s);
+// Points of the k-nearest-neighbour search: FP64 coordinates of the padded
+// layout, one array per axis.
+struct KnnPts {
+    const double* x[3];
+};
+hipError_t launch_knn_widen(const RunDev& r, double* x, hipStream_t s);
+hipError_t launch_knn(const RunDev& r, const KnnPts& P, int K, int32_t* nbr,
+                      unsigned long long* visits, hipStream_t s);
 hipError_t launch_sym_count(int64_t n, int K, const int32_t* nbr, int32_t* extra, int* bad,
                             hipStream_t s);
 int64_t scan_parts(int64_t n);
