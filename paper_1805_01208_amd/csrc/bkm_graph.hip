@@ -9,11 +9,15 @@
 //     curve neighbours, takes the largest K-th distance over its lanes as the
 //     search radius, and then walks the hyper-tile / super-tile / tile /
 //     group box hierarchy, visiting only groups whose box lies within the
-//     radius (which shrinks as the lists fill).  Squared distances are FP64
-//     ((dx*dx + dy*dy) + dz*dz, no contraction) and the box distance is the
-//     same expression over per-axis gaps, so by monotone rounding a group
-//     holding a point within the radius is never pruned: the lists are the
-//     exact ones.
+//     radius (which shrinks as the lists fill).  A visited group's points
+//     are the same for every lane: they arrive by scalar loads and enter the
+//     arithmetic as SGPR operands.  Four partners at a time are screened
+//     with a fused squared distance against a slightly widened K-th
+//     distance; the wave computes exact distances and inserts only when a
+//     lane passes.  Exact squared distances are FP64 ((dx*dx + dy*dy) +
+//     dz*dz, no contraction) and the box distance is the same expression
+//     over per-axis gaps, so by monotone rounding a group holding a point
+//     within the radius is never pruned: the lists are the exact ones.
 //   * symmetrisation: a directed entry p -> q that has no partner q -> p adds
 //     p to q's row; rows are then sorted by index.
 //   * metrics: one thread per vertex for cut and communication volume.  The
@@ -36,10 +40,11 @@ namespace {
 
 inline unsigned nblocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
-// (da, ia) before (db, ib): smaller squared distance, then smaller index.
+// (da, ia) before (db, ib): smaller squared distance, then smaller index
+// (bitwise operators: the compiler keeps this free of branches).
 __device__ inline bool nb_before(double da, int32_t ia, double db, int32_t ib)
 {
-    return da < db || (da == db && ia < ib);
+    return (da < db) | ((da == db) & (ia < ib));
 }
 
 template <int D>
@@ -59,7 +64,7 @@ __device__ inline double box_gap2(const double* a, const double* b)
 typedef const __attribute__((address_space(4))) double* ScalarD;
 typedef const __attribute__((address_space(4))) int32_t* ScalarI;
 
-constexpr int kKnnChunk = 8;   // partners screened per wave-wide test
+constexpr int kKnnChunk = 4;   // partners screened per wave-wide test
 
 template <int D, int K>
 struct KnnLane {
@@ -73,54 +78,80 @@ struct KnnLane {
     // the list is not full), below zero for a padding lane.
     __device__ inline double limit() const { return active ? kd[K - 1] : -1.0; }
 
+    // Insertion into the sorted list without branches: every slot compares
+    // with the new pair at once, then takes its own, its upper neighbour's
+    // or the new entry.
     __device__ inline void insert(double s, int32_t pi)
     {
-        kd[K - 1] = s;
-        ki[K - 1] = pi;
+        bool c[K];
+#pragma unroll
+        for (int m = 0; m < K; ++m) c[m] = nb_before(s, pi, kd[m], ki[m]);
 #pragma unroll
         for (int m = K - 1; m > 0; --m) {
-            if (nb_before(kd[m], ki[m], kd[m - 1], ki[m - 1])) {
-                const double td = kd[m];
-                kd[m] = kd[m - 1];
-                kd[m - 1] = td;
-                const int32_t ti = ki[m];
-                ki[m] = ki[m - 1];
-                ki[m - 1] = ti;
-            }
+            kd[m] = c[m - 1] ? kd[m - 1] : (c[m] ? s : kd[m]);
+            ki[m] = c[m - 1] ? ki[m - 1] : (c[m] ? pi : ki[m]);
         }
+        kd[0] = c[0] ? s : kd[0];
+        ki[0] = c[0] ? pi : ki[0];
     }
 
-    // All 64 points of group h against this lane's point.  Eight partners at
-    // a time are screened by squared distance against the lane's limit; only
-    // when some lane passes does the wave take the exact test on (squared
-    // distance, index) and insert.  A partner failing the screen fails the
-    // exact test too: the limit only shrinks.  Padding slots hold copies of
-    // a real point and are dropped by their index (-1).
+    // Screening limit: the limit widened by 2^-50 relative and 2^-1060
+    // absolute.  The screen's fused squared distance and the exact one
+    // ((dx*dx + dy*dy) + dz*dz) are both within a few units of 2^-53 of the
+    // true sum of the same squares, so a pair within the limit by the exact
+    // distance always passes the widened screen.
+    __device__ inline double screen_limit() const
+    {
+        const double l = limit();
+        return fma(fabs(l), 0x1p-50, l) + 0x1p-1060;
+    }
+
+    // Exact squared distance to partner slot i of the layout.
+    __device__ inline double dist2(const double* const* x, int64_t i) const
+    {
+        double dv[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) dv[j] = q[j] - ((ScalarD)x[j])[i];
+        double d2 = dv[0] * dv[0] + dv[1] * dv[1];
+        if (D == 3) d2 = d2 + dv[D - 1] * dv[D - 1];
+        return d2;
+    }
+
+    // All 64 points of group h against this lane's point.  Four partners at
+    // a time are screened by a fused squared distance against the lane's
+    // widened limit; only when some lane passes does the wave compute the
+    // exact distances, test (squared distance, index) against the K-th entry
+    // and insert.  A partner failing the screen fails the exact test too:
+    // the limit only shrinks.  Padding slots hold copies of a real point and
+    // are dropped by their index (-1).
     __device__ inline void visit(const double* const* x, const int32_t* perm, int64_t h)
     {
         const int64_t base = h * kWave;
-        double lim = limit();
+        double lim = screen_limit();
         for (int c = 0; c < kWave; c += kKnnChunk) {
-            double s[kKnnChunk];
             unsigned long long hit = 0;
 #pragma unroll
             for (int u = 0; u < kKnnChunk; ++u) {
                 double dv[D];
 #pragma unroll
                 for (int j = 0; j < D; ++j) dv[j] = q[j] - ((ScalarD)x[j])[base + c + u];
-                double d2 = dv[0] * dv[0] + dv[1] * dv[1];
-                if (D == 3) d2 = d2 + dv[D - 1] * dv[D - 1];
-                s[u] = d2;
+                double d2 = dv[0] * dv[0];
+#pragma unroll
+                for (int j = 1; j < D; ++j) d2 = fma(dv[j], dv[j], d2);
                 hit |= __ballot(d2 <= lim);
             }
             if (hit == 0) continue;
+            int32_t ids[kKnnChunk];
+#pragma unroll
+            for (int u = 0; u < kKnnChunk; ++u) ids[u] = ((ScalarI)perm)[base + c + u];
 #pragma unroll
             for (int u = 0; u < kKnnChunk; ++u) {
-                const int32_t pi = ((ScalarI)perm)[base + c + u];
-                if (pi >= 0 && pi != self && s[u] <= lim && nb_before(s[u], pi, kd[K - 1], ki[K - 1]))
-                    insert(s[u], pi);
+                const int32_t pi = ids[u];
+                const double e = dist2(x, base + c + u);
+                if (active && pi >= 0 && pi != self && nb_before(e, pi, kd[K - 1], ki[K - 1]))
+                    insert(e, pi);
             }
-            lim = limit();
+            lim = screen_limit();
         }
     }
 
@@ -142,7 +173,9 @@ __global__ __launch_bounds__(kBlock) void k_knn(RunDev r, KnnPts P, int32_t* nbr
                                                 unsigned long long* visits)
 {
     const int lane = threadIdx.x % kWave;
-    const int64_t g = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    // wave-uniform group index: the group's box and the walk live in SGPRs
+    const int64_t g = (int64_t)blockIdx.x * (kBlock / kWave) +
+                      __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     if (g >= r.ngroups) return;
     KnnLane<D, K> L;
     const int64_t pos = g * kWave + lane;

@@ -46,6 +46,22 @@ def test_knn_lattice_ties_and_duplicates():
     _knn_both([g3[:, j].copy() for j in range(3)], 14, "lattice3d")
 
 
+def test_knn_extreme_scales_and_near_ties():
+    """The search screens partners with a fused squared distance against a
+    slightly widened limit and decides with the exact one: clouds whose
+    squared distances are subnormal or near 1e300, and pairs of points one
+    unit in the last place apart, must still give the oracle's lists."""
+    rng = np.random.default_rng(71)
+    base = workloads.uniform(6000, 3, 72)
+    _knn_both([x * 1e-160 for x in base], 7, "scale 1e-160")
+    _knn_both([x * 1e150 for x in base], 7, "scale 1e150")
+    P = np.stack(workloads.uniform(3000, 2, 73), axis=1)
+    Q = np.nextafter(P, np.inf)
+    R = P + rng.choice([-1.0, 1.0], P.shape) * np.spacing(P) * rng.integers(0, 3, P.shape)
+    M = np.concatenate([P, Q, R])[rng.permutation(3 * len(P))]
+    _knn_both([M[:, 0].copy(), M[:, 1].copy()], 5, "ulp neighbours")
+
+
 @pytest.mark.parametrize("n,K", [(2, 1), (5, 4), (17, 16), (65, 1), (300, 16), (1025, 7)])
 def test_knn_small_and_ragged(n, K):
     _knn_both(workloads.uniform(n, 2, 68 + n), K, "small")
