@@ -1064,7 +1064,7 @@ int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int3
         return fail(BKM_EINVAL, "row_ptr/col/assignment/out is NULL");
     hipStream_t s = (hipStream_t)stream;
     keep_pool_memory();
-    constexpr int kBlockInts = 9;   // per-block int32 arrays of GraphDev
+    constexpr int kBlockInts = 12;  // per-block int32 arrays of GraphDev
     Sizes z;
     z.add<int64_t>((size_t)k);
     for (int i = 0; i < kBlockInts; ++i) z.add<int32_t>((size_t)k);
@@ -1091,6 +1091,9 @@ int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int3
     g.fi = bi[6];
     g.lb = bi[7];
     g.ub = bi[8];
+    g.far1 = bi[9];
+    g.nlev = bi[10];
+    g.clist = bi[11];
     g.moff = a.take<int32_t>((size_t)k + 1);
     long long* sc = a.take<long long>(4);
     g.cut2 = sc;
@@ -1098,6 +1101,7 @@ int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int3
     int* ints = a.take<int>(16);
     g.bad = ints;
     int32_t* nlevels = ints + 1;   // most levels of one block's searches
+    g.ccount = ints + 2;
     double* summary = a.take<double>(8);
     g.mem = a.take<int32_t>((size_t)n);
     int32_t* dist = a.take<int32_t>((size_t)n);
@@ -1119,10 +1123,17 @@ int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int3
     HIPCHK(hipMemcpyAsync(&hb, g.bad, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (hb) return fail(BKM_EINVAL, "assignment outside [0, k), or row_ptr/col outside the graph");
-    // the diameter bounds: one workgroup per block runs all of its searches
+    // the diameter bounds: the first search of every block, then the rest of
+    // the searches for the connected blocks, workgroups sized to their count
     HIPCHK(launch_block_lists(n, assignment, k, g, s));
-    HIPCHK(launch_diam_blocks(row_ptr, col, assignment, k, g, dist, du, qa, qb, fr, seen, arr0,
-                              arr1, nlevels, s));
+    HIPCHK(launch_diam_first(row_ptr, col, assignment, k, g, dist, qa, qb, nlevels, s));
+    int nconn = 0;
+    HIPCHK(hipMemcpyAsync(&nconn, g.ccount, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (nconn < 0 || nconn > k)
+        return fail(BKM_EHIP, "connected block count %d outside [0, %d]", nconn, k);
+    HIPCHK(launch_diam_rest(row_ptr, col, assignment, nconn, g, dist, du, qa, qb, fr, seen, arr0,
+                            arr1, nlevels, s));
     int levels = 0;
     HIPCHK(hipMemcpyAsync(&levels, nlevels, sizeof(levels), hipMemcpyDeviceToHost, s));
     HIPCHK(launch_gm_final(k, g, diameter_out, diameter_ub_out, comm_out, summary, s));

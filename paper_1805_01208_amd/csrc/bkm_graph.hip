@@ -681,7 +681,7 @@ __device__ void mbfs_block(const int64_t* row_ptr, const int32_t* col, const int
     }
 }
 
-// One block per workgroup (reading M3):
+// Diameter bounds, one block per workgroup (reading M3):
 //   r1 = the lowest vertex; connected iff its search reaches the whole block;
 //   a1 = farthest from r1; ecc(a1), b1 = farthest from a1; r2 = floor(ecc/2)
 //   from a1 on the path back from b1; a2 = farthest from r2; ecc(a2), b2;
@@ -690,19 +690,46 @@ __device__ void mbfs_block(const int64_t* row_ptr, const int32_t* col, const int
 //   at most three: B = the largest eccentricity over the fringe (distance i
 //   from u, searched 64 sources at a time); if max(lb, B) > 2(i - 1) the
 //   bound is exact, else lb = max(lb, B), ub = 2(i - 1), i = i - 1.
-// `levels` takes the most levels any block's searches ran.
+// Two launches: the first search of every block (small workgroups, all
+// blocks resident), then the rest for the connected blocks only, listed by
+// the first launch, with workgroups sized to that count (one with many
+// searches must not run on a few waves).  `levels` takes the most levels
+// any block's searches ran.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_diam_blocks(
+__global__ __launch_bounds__(NT) void k_diam_first(const int64_t* row_ptr, const int32_t* col,
+                                                   const int32_t* A, GraphDev g, int32_t* dist,
+                                                   int32_t* qa_all, int32_t* qb_all,
+                                                   int32_t* levels)
+{
+    __shared__ DiamShared sh;
+    const int32_t b = blockIdx.x;
+    const int32_t size = g.size[b];
+    if (size == 0) return;   // reported as 0 from the size alone
+    if (threadIdx.x == 0) sh.levels = 0;
+    const int32_t off = g.moff[b];
+    bfs_block<NT>(row_ptr, col, A, b, g.mem + off, size, g.seed[b], dist, qa_all + off,
+                  qb_all + off, sh);
+    if (threadIdx.x == 0) {
+        const bool conn = sh.reached == size;
+        g.conn[b] = conn ? 1 : 0;
+        g.far1[b] = far_vertex(sh.far);
+        g.nlev[b] = sh.levels;
+        if (conn) g.clist[atomicAdd(g.ccount, 1)] = b;
+        atomicMax(levels, sh.levels);
+    }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_diam_rest(
     const int64_t* row_ptr, const int32_t* col, const int32_t* A, GraphDev g, int32_t* dist,
     int32_t* du, int32_t* qa_all, int32_t* qb_all, int32_t* fr_all, unsigned long long* seen,
     unsigned long long* arr0, unsigned long long* arr1, int32_t* levels)
 {
     __shared__ DiamShared sh;
-    const int32_t b = blockIdx.x;
+    const int32_t b = g.clist[blockIdx.x];
     const int tid = threadIdx.x;
     const int32_t size = g.size[b];
-    if (size == 0) return;   // reported as 0 from the size alone
-    if (tid == 0) sh.levels = 0;
+    if (tid == 0) sh.levels = g.nlev[b];
     const int32_t off = g.moff[b];
     const int32_t* mem = g.mem + off;
     int32_t* qa = qa_all + off;
@@ -718,15 +745,7 @@ __global__ __launch_bounds__(NT) void k_diam_blocks(
         __syncthreads();
         return v;
     };
-    search(g.seed[b], dist);
-    if (sh.reached != size) {
-        if (tid == 0) {
-            g.conn[b] = 0;
-            atomicMax(levels, sh.levels);
-        }
-        return;
-    }
-    search(far_vertex(sh.far), dist);                    // from a1
+    search(g.far1[b], dist);                             // from a1
     const int32_t e1 = far_level(sh.far);
     search(back(dist, far_vertex(sh.far), e1 - e1 / 2), dist);   // from r2
     search(far_vertex(sh.far), dist);                    // from a2
@@ -762,7 +781,6 @@ __global__ __launch_bounds__(NT) void k_diam_blocks(
         }
     }
     if (tid == 0) {
-        g.conn[b] = 1;
         g.ecc1[b] = e1;
         g.lval[b] = lval;
         g.fi[b] = i;
@@ -989,30 +1007,45 @@ hipError_t launch_block_lists(int64_t n, const int32_t* A, int k, const GraphDev
     return hipGetLastError();
 }
 
-hipError_t launch_diam_blocks(const int64_t* row_ptr, const int32_t* col, const int32_t* A, int k,
-                              const GraphDev& g, int32_t* dist, int32_t* du, int32_t* qa,
-                              int32_t* qb, int32_t* fr, unsigned long long* seen,
-                              unsigned long long* arr0, unsigned long long* arr1, int32_t* levels,
-                              hipStream_t s)
+// Workgroup size for `blocks` workgroups: all resident at once where
+// possible (2048 threads per CU), 64 to 1024 threads each.
+static int diam_threads(int blocks)
 {
-    // all blocks resident at once where possible (2048 threads per CU), with
-    // 64 to 1024 threads per block
-    const int64_t per = (int64_t)256 * 2048 / std::max(k, 1);
-    if (per >= 1024)
-        k_diam_blocks<1024><<<k, 1024, 0, s>>>(row_ptr, col, A, g, dist, du, qa, qb, fr, seen,
-                                               arr0, arr1, levels);
-    else if (per >= 512)
-        k_diam_blocks<512><<<k, 512, 0, s>>>(row_ptr, col, A, g, dist, du, qa, qb, fr, seen, arr0,
-                                             arr1, levels);
-    else if (per >= 256)
-        k_diam_blocks<256><<<k, 256, 0, s>>>(row_ptr, col, A, g, dist, du, qa, qb, fr, seen, arr0,
-                                             arr1, levels);
-    else if (per >= 128)
-        k_diam_blocks<128><<<k, 128, 0, s>>>(row_ptr, col, A, g, dist, du, qa, qb, fr, seen, arr0,
-                                             arr1, levels);
-    else
-        k_diam_blocks<64><<<k, 64, 0, s>>>(row_ptr, col, A, g, dist, du, qa, qb, fr, seen, arr0,
-                                           arr1, levels);
+    const int64_t per = (int64_t)256 * 2048 / std::max(blocks, 1);
+    return per >= 1024 ? 1024 : per >= 512 ? 512 : per >= 256 ? 256 : per >= 128 ? 128 : 64;
+}
+
+hipError_t launch_diam_first(const int64_t* row_ptr, const int32_t* col, const int32_t* A, int k,
+                             const GraphDev& g, int32_t* dist, int32_t* qa, int32_t* qb,
+                             int32_t* levels, hipStream_t s)
+{
+    switch (diam_threads(k)) {
+#define BKM_DIAM_FIRST(NT) \
+    case NT: k_diam_first<NT><<<k, NT, 0, s>>>(row_ptr, col, A, g, dist, qa, qb, levels); break;
+        BKM_DIAM_FIRST(1024) BKM_DIAM_FIRST(512) BKM_DIAM_FIRST(256) BKM_DIAM_FIRST(128)
+        BKM_DIAM_FIRST(64)
+#undef BKM_DIAM_FIRST
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_diam_rest(const int64_t* row_ptr, const int32_t* col, const int32_t* A,
+                            int nconn, const GraphDev& g, int32_t* dist, int32_t* du, int32_t* qa,
+                            int32_t* qb, int32_t* fr, unsigned long long* seen,
+                            unsigned long long* arr0, unsigned long long* arr1, int32_t* levels,
+                            hipStream_t s)
+{
+    if (nconn <= 0) return hipSuccess;
+    switch (diam_threads(nconn)) {
+#define BKM_DIAM_REST(NT)                                                                   \
+    case NT:                                                                                \
+        k_diam_rest<NT><<<nconn, NT, 0, s>>>(row_ptr, col, A, g, dist, du, qa, qb, fr, seen, \
+                                             arr0, arr1, levels);                          \
+        break;
+        BKM_DIAM_REST(1024) BKM_DIAM_REST(512) BKM_DIAM_REST(256) BKM_DIAM_REST(128)
+        BKM_DIAM_REST(64)
+#undef BKM_DIAM_REST
+    }
     return hipGetLastError();
 }
 

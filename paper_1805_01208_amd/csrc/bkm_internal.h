@@ -540,6 +540,10 @@ struct GraphDev {
     int32_t* fi;              // [k] iFUB level i after the rounds
     int32_t* lb;              // [k] lower bound
     int32_t* ub;              // [k] upper bound
+    int32_t* far1;            // [k] a1, the farthest vertex of the first search
+    int32_t* nlev;            // [k] levels of the first search
+    int32_t* clist;           // [k] connected blocks, in the order found
+    int* ccount;              // [1] their count
 };
 
 hipError_t launch_bbox(const RunDev& r, int hilbert_order, hipStream_t s);
@@ -585,13 +589,16 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_gm_vertex(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
                             const int32_t* A, int k, const GraphDev& g, hipStream_t s);
 // diameter bounds: every block's vertex list (offsets, then members), then
-// one workgroup per block runs all its searches
+// the first search of every block and the rest for the connected ones
 hipError_t launch_block_lists(int64_t n, const int32_t* A, int k, const GraphDev& g, hipStream_t s);
-hipError_t launch_diam_blocks(const int64_t* row_ptr, const int32_t* col, const int32_t* A, int k,
-                              const GraphDev& g, int32_t* dist, int32_t* du, int32_t* qa,
-                              int32_t* qb, int32_t* fr, unsigned long long* seen,
-                              unsigned long long* arr0, unsigned long long* arr1, int32_t* levels,
-                              hipStream_t s);
+hipError_t launch_diam_first(const int64_t* row_ptr, const int32_t* col, const int32_t* A, int k,
+                             const GraphDev& g, int32_t* dist, int32_t* qa, int32_t* qb,
+                             int32_t* levels, hipStream_t s);
+hipError_t launch_diam_rest(const int64_t* row_ptr, const int32_t* col, const int32_t* A,
+                            int nconn, const GraphDev& g, int32_t* dist, int32_t* du, int32_t* qa,
+                            int32_t* qb, int32_t* fr, unsigned long long* seen,
+                            unsigned long long* arr0, unsigned long long* arr1, int32_t* levels,
+                            hipStream_t s);
 hipError_t launch_gm_final(int k, const GraphDev& g, int32_t* diam_out, int32_t* diam_ub_out,
                            int64_t* comm_out, double* summary, hipStream_t s);
 hipError_t launch_supercand(const RunDev& r, hipStream_t s);
