@@ -363,8 +363,8 @@ def graph_bench(args, torch, bkm, cfg, X):
     A = part["A"]
 
     def one():
-        nbr, kinfo = bkm.knn(X, K)
-        rp, col = bkm.knn_graph(nbr)
+        nbr, kinfo = bkm.knn(X, K, order=True)
+        rp, col = bkm.knn_graph(nbr, kinfo["order"])
         m = bkm.graph_metrics(rp, col, A, k)
         return kinfo, m, col.numel()
 

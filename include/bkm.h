@@ -339,23 +339,31 @@ typedef struct {
  * input index of q), nearest first.  Exact, not approximate.
  *   knn      1..16, at most n-1.
  *   nbr_out  [device] n*knn int32, [n][knn], input indices.
+ *   order_out [device] n int32 or NULL: the input indices in the Hilbert
+ *            order the search used, a spatially coherent order to pass to
+ *            bkm_knn_graph.
  *   info     [host] or NULL (then no events are recorded).
  * Errors: BKM_EINVAL, BKM_EDATA (non-finite coordinate), BKM_ENOMEM,
  * BKM_EHIP. */
-int bkm_knn(const bkm_points* pts, int32_t knn, int32_t* nbr_out, bkm_knn_info* info,
-            void* stream);
+int bkm_knn(const bkm_points* pts, int32_t knn, int32_t* nbr_out, int32_t* order_out,
+            bkm_knn_info* info, void* stream);
 
 /* The undirected graph of neighbour lists: edge {p, q} when q is in p's list
  * or p in q's; CSR with both directions, each row sorted ascending.
  *   nbr      [device] n*knn int32 from bkm_knn (or any lists without self
  *            entries).
+ *   order    [device] n int32 or NULL: the order in which the passes over
+ *            the entries take the vertices, a permutation of 0..n-1
+ *            (checked); the result does not depend on it, the speed does: in
+ *            a spatially coherent order (bkm_knn's order_out) the vertices
+ *            that reread a row come close together in time and hit in cache.
  *   row_ptr_out [device] n+1 int64.
  *   col_out  [device] room for 2*n*knn int32; the first *nnz_out are used.
  *   nnz_out  [host] or NULL.
  * Errors: BKM_EINVAL (also for an entry outside [0, n) or equal to its own
- * row), BKM_ENOMEM, BKM_EHIP. */
-int bkm_knn_graph(int64_t n, int32_t knn, const int32_t* nbr, int64_t* row_ptr_out,
-                  int32_t* col_out, int64_t* nnz_out, void* stream);
+ * row, and an order that is not a permutation), BKM_ENOMEM, BKM_EHIP. */
+int bkm_knn_graph(int64_t n, int32_t knn, const int32_t* nbr, const int32_t* order,
+                  int64_t* row_ptr_out, int32_t* col_out, int64_t* nnz_out, void* stream);
 
 typedef struct {
     int64_t edge_cut;           /* undirected edges between different blocks */
@@ -367,7 +375,9 @@ typedef struct {
                                    vertices (1/inf = 0); inf if all are disconnected,
                                    0 if there are none */
     int32_t bfs_levels;         /* the most breadth-first levels one block's searches ran
-                                   (each block runs its own, all in one launch) */
+                                   (one workgroup per block: every block's first search
+                                   in one launch, the connected blocks' others in a
+                                   second) */
     int32_t exact_blocks;       /* non-empty connected blocks whose bound is proven exact */
 } bkm_graph_stats;
 

@@ -109,8 +109,8 @@ def lib():
         L.bkm_partition_stats_noalloc.argtypes = L.bkm_partition_stats.argtypes
         L.bkm_balanced_kmeans_batched.argtypes = [C.POINTER(Points), C.POINTER(Params), C.c_int32,
                                                   C.POINTER(P), C.POINTER(P), C.POINTER(Info), P]
-        L.bkm_knn.argtypes = [C.POINTER(Points), C.c_int32, P, C.POINTER(KnnInfo), P]
-        L.bkm_knn_graph.argtypes = [C.c_int64, C.c_int32, P, P, P, C.POINTER(C.c_int64), P]
+        L.bkm_knn.argtypes = [C.POINTER(Points), C.c_int32, P, P, C.POINTER(KnnInfo), P]
+        L.bkm_knn_graph.argtypes = [C.c_int64, C.c_int32, P, P, P, P, C.POINTER(C.c_int64), P]
         L.bkm_graph_metrics.argtypes = [C.c_int64, C.c_int64, P, P, P, C.c_int32, P, P, P,
                                         C.POINTER(GraphStats), P]
         L.bkm_autotune.argtypes = [C.POINTER(Points), C.POINTER(Params), C.c_int32,
@@ -376,26 +376,34 @@ def partition_stats_noalloc(X, A, k, eps=0.03, W=None, target_sizes=None, bw=Non
     return res
 
 
-def knn(X, K):
+def knn(X, K, order=False):
     """Exact K nearest neighbours of every point: (nbr [n][K] int32 device
     tensor, input indices nearest first; dict(group_visits, layout_ms,
-    search_ms))."""
+    search_ms)).  With order=True the dict also holds "order", the input
+    indices in the search's Hilbert order (for knn_graph)."""
     dev = X[0].device
     pts = make_points(X)
     nbr = torch.empty((pts.n, int(K)), dtype=torch.int32, device=dev)
+    o = torch.empty(pts.n, dtype=torch.int32, device=dev) if order else None
     info = KnnInfo()
-    _check(lib().bkm_knn(C.byref(pts), int(K), _ptr(nbr), C.byref(info), _stream()))
-    return nbr, {f: getattr(info, f) for f, _ in KnnInfo._fields_}
+    _check(lib().bkm_knn(C.byref(pts), int(K), _ptr(nbr), _ptr(o), C.byref(info), _stream()))
+    res = {f: getattr(info, f) for f, _ in KnnInfo._fields_}
+    if order:
+        res["order"] = o
+    return nbr, res
 
 
-def knn_graph(nbr):
-    """Undirected graph of neighbour lists as CSR: (row_ptr int64, col int32)."""
+def knn_graph(nbr, order=None):
+    """Undirected graph of neighbour lists as CSR: (row_ptr int64, col int32).
+    `order` (a permutation of 0..n-1, e.g. knn's order) only sets the order
+    in which the vertices are processed."""
     n, K = nbr.shape
     dev = nbr.device
     row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
     col = torch.empty(2 * n * K, dtype=torch.int32, device=dev)
     nnz = C.c_int64(0)
-    _check(lib().bkm_knn_graph(n, K, _ptr(nbr.contiguous()), _ptr(row_ptr), _ptr(col),
+    o = None if order is None else order.to(torch.int32).contiguous()
+    _check(lib().bkm_knn_graph(n, K, _ptr(nbr.contiguous()), _ptr(o), _ptr(row_ptr), _ptr(col),
                                C.byref(nnz), _stream()))
     return row_ptr, col[:nnz.value]
 

@@ -953,8 +953,8 @@ void bkm_default_params(bkm_params* p, int32_t k)
     p->recheck_rel_gap = 1e-5;
 }
 
-int bkm_knn(const bkm_points* pts, int32_t knn, int32_t* nbr_out, bkm_knn_info* info,
-            void* stream)
+int bkm_knn(const bkm_points* pts, int32_t knn, int32_t* nbr_out, int32_t* order_out,
+            bkm_knn_info* info, void* stream)
 {
     g_err.clear();
     int rc = check_points(pts);
@@ -998,6 +998,9 @@ int bkm_knn(const bkm_points* pts, int32_t knn, int32_t* nbr_out, bkm_knn_info* 
     if (info) HIPCHK(hipEventRecord(ev[1], s));
     HIPCHK(launch_knn(r, P, knn, nbr_out, visits, s));
     if (info) HIPCHK(hipEventRecord(ev[2], s));
+    if (order_out)
+        HIPCHK(hipMemcpyAsync(order_out, r.sperm, (size_t)r.n * sizeof(int32_t),
+                              hipMemcpyDeviceToDevice, s));
     unsigned long long hv = 0;
     HIPCHK(hipMemcpyAsync(&hv, visits, sizeof(hv), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1012,8 +1015,8 @@ int bkm_knn(const bkm_points* pts, int32_t knn, int32_t* nbr_out, bkm_knn_info* 
     return BKM_OK;
 }
 
-int bkm_knn_graph(int64_t n, int32_t knn, const int32_t* nbr, int64_t* row_ptr_out,
-                  int32_t* col_out, int64_t* nnz_out, void* stream)
+int bkm_knn_graph(int64_t n, int32_t knn, const int32_t* nbr, const int32_t* order,
+                  int64_t* row_ptr_out, int32_t* col_out, int64_t* nnz_out, void* stream)
 {
     g_err.clear();
     if (n < 2 || n > INT32_MAX) return fail(BKM_EINVAL, "n = %lld outside [2, 2^31-1]", (long long)n);
@@ -1037,13 +1040,20 @@ int bkm_knn_graph(int64_t n, int32_t knn, const int32_t* nbr, int64_t* row_ptr_o
     HIPCHK(hipMemsetAsync(extra, 0, (size_t)n * sizeof(int32_t), s));
     HIPCHK(hipMemsetAsync(cursor, 0, (size_t)n * sizeof(int32_t), s));
     HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), s));
-    HIPCHK(launch_sym_count(n, knn, nbr, extra, bad, s));
     int hb = 0;
+    if (order) {
+        // cursor (zero) serves as the permutation check's marks and is zero again after it
+        HIPCHK(launch_order_check(n, order, cursor, bad, s));
+        HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (hb) return fail(BKM_EINVAL, "order is not a permutation of 0..n-1");
+    }
+    HIPCHK(launch_sym_count(n, knn, nbr, order, extra, bad, s));
     HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (hb) return fail(BKM_EINVAL, "neighbour entry outside [0, n) or pointing to its own row");
     HIPCHK(launch_sym_rows(n, knn, extra, part, row_ptr_out, s));
-    HIPCHK(launch_sym_fill(n, knn, nbr, row_ptr_out, cursor, col_out, s));
+    HIPCHK(launch_sym_fill(n, knn, nbr, order, row_ptr_out, cursor, col_out, s));
     int64_t nnz = 0;
     HIPCHK(hipMemcpyAsync(&nnz, row_ptr_out + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));

@@ -252,15 +252,46 @@ __global__ __launch_bounds__(kBlock) void k_knn(RunDev r, KnnPts P, int32_t* nbr
 }
 
 // ------------------------------------------------------------ symmetrise
+// The entry passes take their vertices in a caller's order when one is given
+// (a permutation of 0..n-1, e.g. the Hilbert order of the search): vertex t
+// of the pass is order[t].  The results do not depend on it.  Each row is
+// read again by every vertex that lists it; in a spatially coherent order
+// those vertices come close together in time, so the rereads hit in cache.
+__device__ inline int64_t vertex_at(const int32_t* order, int64_t t)
+{
+    return order ? (int64_t)order[t] : t;
+}
+
+// The order is a permutation of 0..n-1: every value in range (mark[v] = 1,
+// mark zeroed before), then every mark set (and cleared again).
+__global__ __launch_bounds__(kBlock) void k_order_mark(int64_t n, const int32_t* order,
+                                                       int32_t* mark, int* bad)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n) return;
+    const int32_t v = order[t];
+    if (v < 0 || v >= n) atomicOr(bad, 1);
+    else mark[v] = 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_order_check(int64_t n, int32_t* mark, int* bad)
+{
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= n) return;
+    if (mark[v] != 1) atomicOr(bad, 1);
+    mark[v] = 0;
+}
+
 // Directed entries p -> q (q = nbr[p][j]) without the partner q -> p: one
 // more slot in q's row.  Out-of-range neighbours set *bad.
 __global__ __launch_bounds__(kBlock) void k_sym_count(int64_t n, int K, const int32_t* nbr,
-                                                      int32_t* extra, int* bad)
+                                                      const int32_t* order, int32_t* extra,
+                                                      int* bad)
 {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= n * K) return;
-    const int64_t p = e / K;
-    const int32_t q = nbr[e];
+    const int64_t p = vertex_at(order, e / K);
+    const int32_t q = nbr[p * K + e % K];
     if (q < 0 || q >= n || q == p) {
         atomicOr(bad, 1);
         return;
@@ -348,13 +379,13 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_rows(int64_t n, int K, cons
 }
 
 __global__ __launch_bounds__(kBlock) void k_sym_fill(int64_t n, int K, const int32_t* nbr,
-                                                     const int64_t* row_ptr, int32_t* cursor,
-                                                     int32_t* col)
+                                                     const int32_t* order, const int64_t* row_ptr,
+                                                     int32_t* cursor, int32_t* col)
 {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= n * K) return;
-    const int64_t p = e / K;
-    const int32_t q = nbr[e];
+    const int64_t p = vertex_at(order, e / K);
+    const int32_t q = nbr[p * K + e % K];
     col[row_ptr[p] + e % K] = q;
     bool back = false;
     for (int i = 0; i < K; ++i) back |= nbr[(int64_t)q * K + i] == (int32_t)p;
@@ -959,10 +990,18 @@ hipError_t launch_knn_widen(const RunDev& r, double* x, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_sym_count(int64_t n, int K, const int32_t* nbr, int32_t* extra, int* bad,
-                            hipStream_t s)
+hipError_t launch_order_check(int64_t n, const int32_t* order, int32_t* mark, int* bad,
+                              hipStream_t s)
 {
-    k_sym_count<<<nblocks(n * K, kBlock), kBlock, 0, s>>>(n, K, nbr, extra, bad);
+    k_order_mark<<<nblocks(n, kBlock), kBlock, 0, s>>>(n, order, mark, bad);
+    k_order_check<<<nblocks(n, kBlock), kBlock, 0, s>>>(n, mark, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_count(int64_t n, int K, const int32_t* nbr, const int32_t* order,
+                            int32_t* extra, int* bad, hipStream_t s)
+{
+    k_sym_count<<<nblocks(n * K, kBlock), kBlock, 0, s>>>(n, K, nbr, order, extra, bad);
     return hipGetLastError();
 }
 
@@ -979,10 +1018,10 @@ hipError_t launch_sym_rows(int64_t n, int K, const int32_t* extra, int64_t* part
     return hipGetLastError();
 }
 
-hipError_t launch_sym_fill(int64_t n, int K, const int32_t* nbr, const int64_t* row_ptr,
-                           int32_t* cursor, int32_t* col, hipStream_t s)
+hipError_t launch_sym_fill(int64_t n, int K, const int32_t* nbr, const int32_t* order,
+                           const int64_t* row_ptr, int32_t* cursor, int32_t* col, hipStream_t s)
 {
-    k_sym_fill<<<nblocks(n * K, kBlock), kBlock, 0, s>>>(n, K, nbr, row_ptr, cursor, col);
+    k_sym_fill<<<nblocks(n * K, kBlock), kBlock, 0, s>>>(n, K, nbr, order, row_ptr, cursor, col);
     k_sym_sort<<<nblocks(n, kBlock), kBlock, 0, s>>>(n, row_ptr, col);
     return hipGetLastError();
 }

@@ -133,15 +133,15 @@ def test_graph_argument_errors(bkm):
     """Rejected on the host before any device work."""
     L = bkm.lib()
     p = _pts(bkm, n=10)
-    assert L.bkm_knn(C.byref(p), 0, C.c_void_p(0x2000), None, None) == bkm.BKM_EINVAL
-    assert L.bkm_knn(C.byref(p), 17, C.c_void_p(0x2000), None, None) == bkm.BKM_EINVAL
-    assert L.bkm_knn(C.byref(p), 10, C.c_void_p(0x2000), None, None) == bkm.BKM_EINVAL
+    assert L.bkm_knn(C.byref(p), 0, C.c_void_p(0x2000), None, None, None) == bkm.BKM_EINVAL
+    assert L.bkm_knn(C.byref(p), 17, C.c_void_p(0x2000), None, None, None) == bkm.BKM_EINVAL
+    assert L.bkm_knn(C.byref(p), 10, C.c_void_p(0x2000), None, None, None) == bkm.BKM_EINVAL
     assert "knn + 1" in L.bkm_last_error().decode()
-    assert L.bkm_knn(C.byref(p), 4, None, None, None) == bkm.BKM_EINVAL
-    assert L.bkm_knn_graph(1, 1, C.c_void_p(0x2000), C.c_void_p(0x3000), C.c_void_p(0x4000),
-                           None, None) == bkm.BKM_EINVAL
-    assert L.bkm_knn_graph(10, 10, C.c_void_p(0x2000), C.c_void_p(0x3000), C.c_void_p(0x4000),
-                           None, None) == bkm.BKM_EINVAL
+    assert L.bkm_knn(C.byref(p), 4, None, None, None, None) == bkm.BKM_EINVAL
+    assert L.bkm_knn_graph(1, 1, C.c_void_p(0x2000), None, C.c_void_p(0x3000),
+                           C.c_void_p(0x4000), None, None) == bkm.BKM_EINVAL
+    assert L.bkm_knn_graph(10, 10, C.c_void_p(0x2000), None, C.c_void_p(0x3000),
+                           C.c_void_p(0x4000), None, None) == bkm.BKM_EINVAL
     st = bkm.GraphStats()
     assert L.bkm_graph_metrics(10, 5, None, None, None, 2, None, None, None, C.byref(st),
                                None) == bkm.BKM_EINVAL

@@ -160,12 +160,14 @@ def check_knn_graph(cfg, X, K, A=None, k=None):
     Xw = widened(cfg["X"])
     n = len(Xw[0])
     print(f"case full-size knn graph {cfg['name']} K={K}", flush=True)
-    nbr, info = bkm.knn(X, K)
+    nbr, info = bkm.knn(X, K, order=True)
+    order = info["order"]
+    assert torch.equal(torch.sort(order.long()).values, torch.arange(n, device=order.device))
     rng = np.random.default_rng(91)
     q = np.sort(rng.choice(n, size=300, replace=False))
     nb = nbr.cpu().numpy()
     assert np.array_equal(nb[q], oracle.knn_of(Xw, K, q))
-    rp, col = bkm.knn_graph(nbr)
+    rp, col = bkm.knn_graph(nbr, order)
     rph, colh = rp.cpu().numpy(), col.cpu().numpy()
     assert rph[0] == 0 and rph[-1] == len(colh) and np.all(np.diff(rph) >= K)
     for u in q[:50]:

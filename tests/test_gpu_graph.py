@@ -71,10 +71,17 @@ def test_knn_graph_matches_oracle():
     from paper_1805_01208_amd import bkm
     X = workloads.gauss3d(12000, 69)
     nbr, ref = _knn_both(X, 9, "for graph")
-    rp, col = bkm.knn_graph(nbr)
     orp, ocol = oracle.knn_symmetrize(ref)
-    assert np.array_equal(rp.cpu().numpy(), orp)
-    assert np.array_equal(col.cpu().numpy(), ocol)
+    nb2, info = bkm.knn(cuda(X), 9, order=True)
+    assert torch.equal(nb2, nbr)
+    order = info["order"]
+    assert np.array_equal(np.sort(order.cpu().numpy()), np.arange(len(X[0])))
+    rng = np.random.default_rng(74)
+    shuffled = torch.from_numpy(rng.permutation(len(X[0])).astype(np.int32)).cuda()
+    for o in (None, order, shuffled):
+        rp, col = bkm.knn_graph(nbr, o)
+        assert np.array_equal(rp.cpu().numpy(), orp)
+        assert np.array_equal(col.cpu().numpy(), ocol)
 
 
 def _metrics_both(rp, col, A, k, what):
@@ -193,3 +200,14 @@ def test_invalid_graph_inputs_are_rejected():
     nb2[7, 2] = -1
     with pytest.raises(bkm.BkmError, match="neighbour"):
         bkm.knn_graph(nb2)
+    # vertex orders that are not permutations of 0..n-1
+    dup = torch.arange(3000, dtype=torch.int32).cuda()
+    dup[5] = 6
+    out = torch.arange(3000, dtype=torch.int32).cuda()
+    out[9] = 3000
+    for o in (dup, out):
+        with pytest.raises(bkm.BkmError, match="permutation"):
+            bkm.knn_graph(nbr, o)
+    # and the check leaves nothing behind: a valid order right after works
+    rp2, col2 = bkm.knn_graph(nbr, torch.arange(3000, dtype=torch.int32).cuda())
+    assert torch.equal(rp2, rp) and torch.equal(col2, col)
