@@ -1082,8 +1082,11 @@ int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int3
     z.add<long long>(4);
     z.add<int>(16);
     z.add<double>(8);
-    for (int i = 0; i < 6; ++i) z.add<int32_t>((size_t)n);
+    for (int i = 0; i < 8; ++i) z.add<int32_t>((size_t)n);
     for (int i = 0; i < 3; ++i) z.add<unsigned long long>((size_t)n);
+    z.add<int64_t>((size_t)n + 1);
+    z.add<int32_t>((size_t)std::max<int64_t>(nnz, 1));
+    z.add<int64_t>((size_t)scan_parts(n));
     Arena a;
     a.s = s;
     HIPCHK(hipMallocAsync((void**)&a.base, z.total, s));
@@ -1122,6 +1125,11 @@ int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int3
     unsigned long long* seen = a.take<unsigned long long>((size_t)n);
     unsigned long long* arr0 = a.take<unsigned long long>((size_t)n);
     unsigned long long* arr1 = a.take<unsigned long long>((size_t)n);
+    g.ldeg = a.take<int32_t>((size_t)n);
+    g.loc = a.take<int32_t>((size_t)n);
+    g.lrp = a.take<int64_t>((size_t)n + 1);
+    g.lcol = a.take<int32_t>((size_t)std::max<int64_t>(nnz, 1));
+    int64_t* part = a.take<int64_t>((size_t)scan_parts(n));
     HIPCHK(hipMemsetAsync(g.comm, 0, (size_t)k * sizeof(int64_t), s));
     HIPCHK(hipMemsetAsync(g.size, 0, (size_t)k * sizeof(int32_t), s));
     HIPCHK(hipMemsetAsync(g.conn, 0, (size_t)k * sizeof(int32_t), s));
@@ -1133,17 +1141,19 @@ int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int3
     HIPCHK(hipMemcpyAsync(&hb, g.bad, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (hb) return fail(BKM_EINVAL, "assignment outside [0, k), or row_ptr/col outside the graph");
-    // the diameter bounds: the first search of every block, then the rest of
-    // the searches for the connected blocks, workgroups sized to their count
+    // the diameter bounds: the block lists and the relabelled block subgraphs
+    // (qb holds the local degrees until the searches), the first search of
+    // every block, then the rest of the searches for the connected blocks,
+    // workgroups sized to their count
     HIPCHK(launch_block_lists(n, assignment, k, g, s));
-    HIPCHK(launch_diam_first(row_ptr, col, assignment, k, g, dist, qa, qb, nlevels, s));
+    HIPCHK(launch_local_rows(n, row_ptr, col, assignment, g, qb, part, s));
+    HIPCHK(launch_diam_first(k, g, dist, qa, qb, nlevels, s));
     int nconn = 0;
     HIPCHK(hipMemcpyAsync(&nconn, g.ccount, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (nconn < 0 || nconn > k)
         return fail(BKM_EHIP, "connected block count %d outside [0, %d]", nconn, k);
-    HIPCHK(launch_diam_rest(row_ptr, col, assignment, nconn, g, dist, du, qa, qb, fr, seen, arr0,
-                            arr1, nlevels, s));
+    HIPCHK(launch_diam_rest(nconn, g, dist, du, qa, qb, fr, seen, arr0, arr1, nlevels, s));
     int levels = 0;
     HIPCHK(hipMemcpyAsync(&levels, nlevels, sizeof(levels), hipMemcpyDeviceToHost, s));
     HIPCHK(launch_gm_final(k, g, diameter_out, diameter_ub_out, comm_out, summary, s));

@@ -433,14 +433,19 @@ __global__ __launch_bounds__(kBlock) void k_gm_vertex(int64_t n, int64_t nnz, co
             atomicOr(g.bad, 1);
         } else {
             long long vol = 0;
+            int32_t own = 0;
             for (int64_t e = rs; e < re; ++e) {
                 const int32_t b = A[col[e]];
-                if (b == a) continue;
+                if (b == a) {
+                    ++own;
+                    continue;
+                }
                 ++cut;
                 bool dup = false;
                 for (int64_t f = rs; f < e && !dup; ++f) dup = A[col[f]] == b;
                 if (!dup) ++vol;
             }
+            g.ldeg[u] = own;
             if (vol) atomicAdd((unsigned long long*)&g.comm[a], (unsigned long long)vol);
             atomicAdd(&g.size[a], 1);
             atomicMin(&g.seed[a], (int32_t)u);
@@ -468,19 +473,21 @@ __device__ inline int32_t far_vertex(unsigned long long key)
 
 __device__ inline int32_t far_level(unsigned long long key) { return (int32_t)(key >> 32); }
 
-// With dist from a search of block b whose far end x lies `steps` levels or
-// more from its source: the vertex `steps` levels closer to the source on
-// the path back from x, each step to the lowest-index neighbour of the
-// block one level closer.
-__device__ int32_t walk_back(const int64_t* row_ptr, const int32_t* col, const int32_t* A,
-                             const int32_t* dist, int32_t b, int32_t x, int32_t steps)
+// With dist from a search whose far end x (a local id) lies `steps` levels
+// or more from its source: the vertex `steps` levels closer to the source
+// on the path back from x, each step to the neighbour one level closer with
+// the lowest input index.
+__device__ int32_t walk_back(const GraphDev& g, const int32_t* dist, int32_t x, int32_t steps)
 {
     for (int32_t t = 0; t < steps && x >= 0; ++t) {
         const int32_t want = dist[x] - 1;
-        int32_t nx = -1;
-        for (int64_t e = row_ptr[x]; e < row_ptr[(int64_t)x + 1]; ++e) {
-            const int32_t y = col[e];
-            if (A[y] == b && dist[y] == want && (nx < 0 || y < nx)) nx = y;
+        int32_t nx = -1, nin = INT32_MAX;
+        for (int64_t e = g.lrp[x]; e < g.lrp[(int64_t)x + 1]; ++e) {
+            const int32_t y = g.lcol[e];
+            if (dist[y] == want && g.mem[y] < nin) {
+                nx = y;
+                nin = g.mem[y];
+            }
         }
         x = nx;
     }
@@ -492,9 +499,13 @@ __device__ int32_t walk_back(const int64_t* row_ptr, const int32_t* col, const i
 // subgraph, so one workgroup takes one block and runs all of its searches:
 // the 4-sweep, the search from its middle vertex u, and up to three iFUB
 // rounds.  Levels are separated by workgroup barriers only: a search of any
-// length is part of one launch, and blocks proceed independently.  Each block
-// has the list of its vertices and queue space of its own size in n-sized
-// arrays (at its offset moff).
+// length is part of one launch, and blocks proceed independently.
+// The searches run on the blocks' induced subgraphs relabelled block by
+// block: local id = position in the block lists (mem), so block b holds the
+// local ids moff[b] .. moff[b] + size - 1, and its rows (lrp, lcol) hold
+// only its own edges.  Every array a search touches is then contiguous per
+// block (distances, masks, queues, rows), instead of spread over the input
+// order.  Ties still go by input index (mem of a local id).
 
 constexpr int kBfsLanes = 8;   // lanes sharing a frontier vertex
 constexpr int kDiamU = 4;      // frontier vertices a lane group holds at once
@@ -509,22 +520,24 @@ struct DiamShared {
     unsigned long long far;     // far_key of the farthest vertex reached
 };
 
-// Single-source search of block b from src, distances into d (every other
-// vertex of the block at -1 first); leaves the reached count and the
-// farthest vertex (largest level, lowest index) in sh.  kBfsLanes lanes
+// Single-source search of the block at local ids off .. off + size - 1 from
+// src, distances into d (every other vertex of the block at -1 first);
+// leaves the reached count and the farthest vertex (largest level, lowest
+// input index) in sh.  kBfsLanes lanes
 // share a frontier vertex, each taking every kBfsLanes-th entry of its row,
 // and every lane group holds kDiamU frontier vertices at once so that their
 // loads overlap; a vertex is claimed by a CAS on its distance, and a wave
 // reserves its claims' places in the next frontier with one LDS atomic.
 template <int NT>
-__device__ void bfs_block(const int64_t* row_ptr, const int32_t* col, const int32_t* A, int32_t b,
-                          const int32_t* mem, int32_t size, int32_t src, int32_t* d, int32_t* qa,
-                          int32_t* qb, DiamShared& sh)
+__device__ void bfs_block(const GraphDev& g, int32_t off, int32_t size, int32_t src, int32_t* d,
+                          int32_t* qa, int32_t* qb, DiamShared& sh)
 {
+    const int64_t* __restrict__ row_ptr = g.lrp;
+    const int32_t* __restrict__ col = g.lcol;
     constexpr int kPer = NT / kBfsLanes;
     const int tid = threadIdx.x, lane = tid % kWave;
     const unsigned long long below = (1ULL << lane) - 1ULL;
-    for (int j = tid; j < size; j += NT) d[mem[j]] = -1;
+    for (int j = tid; j < size; j += NT) d[off + j] = -1;
     __syncthreads();
     if (tid == 0) {
         d[src] = 0;
@@ -532,7 +545,7 @@ __device__ void bfs_block(const int64_t* row_ptr, const int32_t* col, const int3
         sh.cnt[0] = 1;
         sh.cnt[1] = 0;
         sh.reached = 1;
-        sh.far = far_key(0, src);
+        sh.far = far_key(0, g.mem[src]);
     }
     __syncthreads();
     int32_t* cur = qa;
@@ -567,8 +580,7 @@ __device__ void bfs_block(const int64_t* row_ptr, const int32_t* col, const int3
                     e[q] += live[q] ? kBfsLanes : 0;
                 }
 #pragma unroll
-                for (int q = 0; q < kDiamU; ++q)
-                    claim[q] = live[q] && A[v[q]] == b && d[v[q]] == -1;
+                for (int q = 0; q < kDiamU; ++q) claim[q] = live[q] && d[v[q]] == -1;
 #pragma unroll
                 for (int q = 0; q < kDiamU; ++q)
                     if (claim[q]) claim[q] = atomicCAS(&d[v[q]], -1, level + 1) == -1;
@@ -585,7 +597,7 @@ __device__ void bfs_block(const int64_t* row_ptr, const int32_t* col, const int3
                     pos = __shfl(pos, leader, kWave);
                     if (claim[q]) {
                         nxt[pos + (int)__popcll(bm & below)] = v[q];
-                        atomicMax(&sh.far, far_key(level + 1, v[q]));
+                        atomicMax(&sh.far, far_key(level + 1, g.mem[v[q]]));
                     }
                 }
             }
@@ -602,22 +614,23 @@ __device__ void bfs_block(const int64_t* row_ptr, const int32_t* col, const int3
     }
 }
 
-// Searches from up to 64 sources of block b at once (an iFUB round's fringe,
+// Searches from up to 64 sources of the block at once (an iFUB round's fringe,
 // source j with bit j): a vertex holds the sources that reached it (seen)
 // and those arriving at the current level (arr[level & 1]); it joins the next
 // frontier when the first new bit arrives.  sh.blast = the deepest level at
 // which some vertex took a new bit, the largest eccentricity of the sources.
 template <int NT>
-__device__ void mbfs_block(const int64_t* row_ptr, const int32_t* col, const int32_t* A, int32_t b,
-                           const int32_t* mem, int32_t size, const int32_t* srcs, int nsrc,
-                           unsigned long long* seen, unsigned long long* arr0,
+__device__ void mbfs_block(const GraphDev& g, int32_t off, int32_t size, const int32_t* srcs,
+                           int nsrc, unsigned long long* seen, unsigned long long* arr0,
                            unsigned long long* arr1, int32_t* qa, int32_t* qb, DiamShared& sh)
 {
+    const int64_t* __restrict__ row_ptr = g.lrp;
+    const int32_t* __restrict__ col = g.lcol;
     constexpr int kPer = NT / kBfsLanes;
     const int tid = threadIdx.x, lane = tid % kWave;
     const unsigned long long below = (1ULL << lane) - 1ULL;
     for (int j = tid; j < size; j += NT) {
-        const int32_t v = mem[j];
+        const int32_t v = off + j;
         seen[v] = 0ULL;
         arr0[v] = 0ULL;
         arr1[v] = 0ULL;
@@ -685,7 +698,7 @@ __device__ void mbfs_block(const int64_t* row_ptr, const int32_t* col, const int
                 }
 #pragma unroll
                 for (int q = 0; q < kDiamU; ++q)
-                    if (add[q]) add[q] = A[v[q]] == b ? add[q] & ~seen[v[q]] : 0ULL;
+                    if (add[q]) add[q] &= ~seen[v[q]];
 #pragma unroll
                 for (int q = 0; q < kDiamU; ++q) app[q] = add[q] && atomicOr(&na[v[q]], add[q]) == 0ULL;
 #pragma unroll
@@ -727,10 +740,8 @@ __device__ void mbfs_block(const int64_t* row_ptr, const int32_t* col, const int
 // searches must not run on a few waves).  `levels` takes the most levels
 // any block's searches ran.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_diam_first(const int64_t* row_ptr, const int32_t* col,
-                                                   const int32_t* A, GraphDev g, int32_t* dist,
-                                                   int32_t* qa_all, int32_t* qb_all,
-                                                   int32_t* levels)
+__global__ __launch_bounds__(NT) void k_diam_first(GraphDev g, int32_t* dist, int32_t* qa_all,
+                                                   int32_t* qb_all, int32_t* levels)
 {
     __shared__ DiamShared sh;
     const int32_t b = blockIdx.x;
@@ -738,12 +749,11 @@ __global__ __launch_bounds__(NT) void k_diam_first(const int64_t* row_ptr, const
     if (size == 0) return;   // reported as 0 from the size alone
     if (threadIdx.x == 0) sh.levels = 0;
     const int32_t off = g.moff[b];
-    bfs_block<NT>(row_ptr, col, A, b, g.mem + off, size, g.seed[b], dist, qa_all + off,
-                  qb_all + off, sh);
+    bfs_block<NT>(g, off, size, g.loc[g.seed[b]], dist, qa_all + off, qb_all + off, sh);
     if (threadIdx.x == 0) {
         const bool conn = sh.reached == size;
         g.conn[b] = conn ? 1 : 0;
-        g.far1[b] = far_vertex(sh.far);
+        g.far1[b] = g.loc[far_vertex(sh.far)];
         g.nlev[b] = sh.levels;
         if (conn) g.clist[atomicAdd(g.ccount, 1)] = b;
         atomicMax(levels, sh.levels);
@@ -751,10 +761,11 @@ __global__ __launch_bounds__(NT) void k_diam_first(const int64_t* row_ptr, const
 }
 
 template <int NT>
-__global__ __launch_bounds__(NT) void k_diam_rest(
-    const int64_t* row_ptr, const int32_t* col, const int32_t* A, GraphDev g, int32_t* dist,
-    int32_t* du, int32_t* qa_all, int32_t* qb_all, int32_t* fr_all, unsigned long long* seen,
-    unsigned long long* arr0, unsigned long long* arr1, int32_t* levels)
+__global__ __launch_bounds__(NT) void k_diam_rest(GraphDev g, int32_t* dist, int32_t* du,
+                                                  int32_t* qa_all, int32_t* qb_all,
+                                                  int32_t* fr_all, unsigned long long* seen,
+                                                  unsigned long long* arr0,
+                                                  unsigned long long* arr1, int32_t* levels)
 {
     __shared__ DiamShared sh;
     const int32_t b = g.clist[blockIdx.x];
@@ -762,15 +773,14 @@ __global__ __launch_bounds__(NT) void k_diam_rest(
     const int32_t size = g.size[b];
     if (tid == 0) sh.levels = g.nlev[b];
     const int32_t off = g.moff[b];
-    const int32_t* mem = g.mem + off;
     int32_t* qa = qa_all + off;
     int32_t* qb = qb_all + off;
-    auto search = [&](int32_t src, int32_t* d) {
-        bfs_block<NT>(row_ptr, col, A, b, mem, size, src, d, qa, qb, sh);
-    };
+    auto search = [&](int32_t src, int32_t* d) { bfs_block<NT>(g, off, size, src, d, qa, qb, sh); };
+    // the farthest vertex of the last search, as a local id
+    auto far = [&]() -> int32_t { return g.loc[far_vertex(sh.far)]; };
     // the vertex `steps` closer to the search's source on the path back from x
     auto back = [&](const int32_t* d, int32_t x, int32_t steps) -> int32_t {
-        if (tid == 0) sh.src = walk_back(row_ptr, col, A, d, b, x, steps);
+        if (tid == 0) sh.src = walk_back(g, d, x, steps);
         __syncthreads();
         const int32_t v = sh.src;
         __syncthreads();
@@ -778,27 +788,24 @@ __global__ __launch_bounds__(NT) void k_diam_rest(
     };
     search(g.far1[b], dist);                             // from a1
     const int32_t e1 = far_level(sh.far);
-    search(back(dist, far_vertex(sh.far), e1 - e1 / 2), dist);   // from r2
-    search(far_vertex(sh.far), dist);                    // from a2
+    search(back(dist, far(), e1 - e1 / 2), dist);        // from r2
+    search(far(), dist);                                 // from a2
     const int32_t e2 = far_level(sh.far);
     const int32_t lval = max(e1, e2);
-    search(back(dist, far_vertex(sh.far), e2 - e2 / 2), du);     // from u
+    search(back(dist, far(), e2 - e2 / 2), du);          // from u
     int32_t i = far_level(sh.far);
     int32_t lb = max(lval, i), ub = 2 * i;
     int32_t* fr = fr_all + off;   // the fringe
     for (int round = 0; round < 3 && ub > lb; ++round) {
         if (tid == 0) sh.fcount = 0;
         __syncthreads();
-        for (int j = tid; j < size; j += NT) {
-            const int32_t v = mem[j];
-            if (du[v] == i) fr[atomicAdd(&sh.fcount, 1)] = v;
-        }
+        for (int j = tid; j < size; j += NT)
+            if (du[off + j] == i) fr[atomicAdd(&sh.fcount, 1)] = off + j;
         __syncthreads();
         const int nf = sh.fcount;
         int32_t B = -1;
         for (int t0 = 0; t0 < nf; t0 += 64) {
-            mbfs_block<NT>(row_ptr, col, A, b, mem, size, fr + t0, min(64, nf - t0), seen, arr0,
-                           arr1, qa, qb, sh);
+            mbfs_block<NT>(g, off, size, fr + t0, min(64, nf - t0), seen, arr0, arr1, qa, qb, sh);
             B = max(B, sh.blast);
         }
         const int32_t m = max(lb, B);
@@ -857,7 +864,33 @@ __global__ __launch_bounds__(kBlock) void k_block_members(int64_t n, const int32
     const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (v >= n) return;
     const int32_t a = A[v];
-    g.mem[g.moff[a] + atomicAdd(&g.fill[a], 1)] = (int32_t)v;
+    const int32_t i = g.moff[a] + atomicAdd(&g.fill[a], 1);
+    g.mem[i] = (int32_t)v;
+    g.loc[v] = i;
+}
+
+// Rows of the relabelled block subgraphs: the intra-block degree of every
+// local id (gathered from the vertex pass), then, after their exclusive scan
+// into lrp, each vertex's own-block neighbours as local ids, in the order of
+// its input row.
+__global__ __launch_bounds__(kBlock) void k_local_deg(int64_t n, GraphDev g, int32_t* dl)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) dl[i] = g.ldeg[g.mem[i]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_local_fill(int64_t n, const int64_t* row_ptr,
+                                                       const int32_t* col, const int32_t* A,
+                                                       GraphDev g)
+{
+    const int64_t u = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (u >= n) return;
+    const int32_t a = A[u];
+    int64_t pos = g.lrp[g.loc[u]];
+    for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+        const int32_t w = col[e];
+        if (A[w] == a) g.lcol[pos++] = g.loc[w];
+    }
 }
 
 // Block results after the searches, and the summary (one block).
@@ -1046,6 +1079,17 @@ hipError_t launch_block_lists(int64_t n, const int32_t* A, int k, const GraphDev
     return hipGetLastError();
 }
 
+hipError_t launch_local_rows(int64_t n, const int64_t* row_ptr, const int32_t* col,
+                             const int32_t* A, const GraphDev& g, int32_t* dl, int64_t* part,
+                             hipStream_t s)
+{
+    k_local_deg<<<nblocks(n, kBlock), kBlock, 0, s>>>(n, g, dl);
+    hipError_t e = launch_sym_rows(n, 0, dl, part, g.lrp, s);
+    if (e != hipSuccess) return e;
+    k_local_fill<<<nblocks(n, kBlock), kBlock, 0, s>>>(n, row_ptr, col, A, g);
+    return hipGetLastError();
+}
+
 // Workgroup size for `blocks` workgroups: all resident at once where
 // possible (2048 threads per CU), 64 to 1024 threads each.
 static int diam_threads(int blocks)
@@ -1054,13 +1098,12 @@ static int diam_threads(int blocks)
     return per >= 1024 ? 1024 : per >= 512 ? 512 : per >= 256 ? 256 : per >= 128 ? 128 : 64;
 }
 
-hipError_t launch_diam_first(const int64_t* row_ptr, const int32_t* col, const int32_t* A, int k,
-                             const GraphDev& g, int32_t* dist, int32_t* qa, int32_t* qb,
+hipError_t launch_diam_first(int k, const GraphDev& g, int32_t* dist, int32_t* qa, int32_t* qb,
                              int32_t* levels, hipStream_t s)
 {
     switch (diam_threads(k)) {
 #define BKM_DIAM_FIRST(NT) \
-    case NT: k_diam_first<NT><<<k, NT, 0, s>>>(row_ptr, col, A, g, dist, qa, qb, levels); break;
+    case NT: k_diam_first<NT><<<k, NT, 0, s>>>(g, dist, qa, qb, levels); break;
         BKM_DIAM_FIRST(1024) BKM_DIAM_FIRST(512) BKM_DIAM_FIRST(256) BKM_DIAM_FIRST(128)
         BKM_DIAM_FIRST(64)
 #undef BKM_DIAM_FIRST
@@ -1068,8 +1111,7 @@ hipError_t launch_diam_first(const int64_t* row_ptr, const int32_t* col, const i
     return hipGetLastError();
 }
 
-hipError_t launch_diam_rest(const int64_t* row_ptr, const int32_t* col, const int32_t* A,
-                            int nconn, const GraphDev& g, int32_t* dist, int32_t* du, int32_t* qa,
+hipError_t launch_diam_rest(int nconn, const GraphDev& g, int32_t* dist, int32_t* du, int32_t* qa,
                             int32_t* qb, int32_t* fr, unsigned long long* seen,
                             unsigned long long* arr0, unsigned long long* arr1, int32_t* levels,
                             hipStream_t s)
@@ -1078,8 +1120,7 @@ hipError_t launch_diam_rest(const int64_t* row_ptr, const int32_t* col, const in
     switch (diam_threads(nconn)) {
 #define BKM_DIAM_REST(NT)                                                                   \
     case NT:                                                                                \
-        k_diam_rest<NT><<<nconn, NT, 0, s>>>(row_ptr, col, A, g, dist, du, qa, qb, fr, seen, \
-                                             arr0, arr1, levels);                          \
+        k_diam_rest<NT><<<nconn, NT, 0, s>>>(g, dist, du, qa, qb, fr, seen, arr0, arr1, levels); \
         break;
         BKM_DIAM_REST(1024) BKM_DIAM_REST(512) BKM_DIAM_REST(256) BKM_DIAM_REST(128)
         BKM_DIAM_REST(64)

@@ -544,6 +544,11 @@ struct GraphDev {
     int32_t* nlev;            // [k] levels of the first search
     int32_t* clist;           // [k] connected blocks, in the order found
     int* ccount;              // [1] their count
+    // the blocks' induced subgraphs relabelled: local id = position in mem
+    int32_t* ldeg;            // [n] own-block neighbours of each vertex (input index)
+    int32_t* loc;             // [n] local id of each vertex
+    int64_t* lrp;             // [n+1] rows by local id
+    int32_t* lcol;            // [<= nnz] own-block neighbours as local ids
 };
 
 hipError_t launch_bbox(const RunDev& r, int hilbert_order, hipStream_t s);
@@ -595,11 +600,12 @@ hipError_t launch_gm_vertex(int64_t n, int64_t nnz, const int64_t* row_ptr, cons
 // diameter bounds: every block's vertex list (offsets, then members), then
 // the first search of every block and the rest for the connected ones
 hipError_t launch_block_lists(int64_t n, const int32_t* A, int k, const GraphDev& g, hipStream_t s);
-hipError_t launch_diam_first(const int64_t* row_ptr, const int32_t* col, const int32_t* A, int k,
-                             const GraphDev& g, int32_t* dist, int32_t* qa, int32_t* qb,
+hipError_t launch_local_rows(int64_t n, const int64_t* row_ptr, const int32_t* col,
+                             const int32_t* A, const GraphDev& g, int32_t* dl, int64_t* part,
+                             hipStream_t s);
+hipError_t launch_diam_first(int k, const GraphDev& g, int32_t* dist, int32_t* qa, int32_t* qb,
                              int32_t* levels, hipStream_t s);
-hipError_t launch_diam_rest(const int64_t* row_ptr, const int32_t* col, const int32_t* A,
-                            int nconn, const GraphDev& g, int32_t* dist, int32_t* du, int32_t* qa,
+hipError_t launch_diam_rest(int nconn, const GraphDev& g, int32_t* dist, int32_t* du, int32_t* qa,
                             int32_t* qb, int32_t* fr, unsigned long long* seen,
                             unsigned long long* arr0, unsigned long long* arr1, int32_t* levels,
                             hipStream_t s);
