@@ -1082,7 +1082,8 @@ int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int3
     z.add<long long>(4);
     z.add<int>(16);
     z.add<double>(8);
-    for (int i = 0; i < 8; ++i) z.add<int32_t>((size_t)n);
+    for (int i = 0; i < 7; ++i) z.add<int32_t>((size_t)n);
+    z.add<int2>((size_t)n);
     for (int i = 0; i < 3; ++i) z.add<unsigned long long>((size_t)n);
     z.add<int64_t>((size_t)n + 1);
     z.add<int32_t>((size_t)std::max<int64_t>(nnz, 1));
@@ -1126,7 +1127,7 @@ int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int3
     unsigned long long* arr0 = a.take<unsigned long long>((size_t)n);
     unsigned long long* arr1 = a.take<unsigned long long>((size_t)n);
     g.ldeg = a.take<int32_t>((size_t)n);
-    g.loc = a.take<int32_t>((size_t)n);
+    g.al = a.take<int2>((size_t)n);
     g.lrp = a.take<int64_t>((size_t)n + 1);
     g.lcol = a.take<int32_t>((size_t)std::max<int64_t>(nnz, 1));
     int64_t* part = a.take<int64_t>((size_t)scan_parts(n));

@@ -749,11 +749,11 @@ __global__ __launch_bounds__(NT) void k_diam_first(GraphDev g, int32_t* dist, in
     if (size == 0) return;   // reported as 0 from the size alone
     if (threadIdx.x == 0) sh.levels = 0;
     const int32_t off = g.moff[b];
-    bfs_block<NT>(g, off, size, g.loc[g.seed[b]], dist, qa_all + off, qb_all + off, sh);
+    bfs_block<NT>(g, off, size, g.al[g.seed[b]].y, dist, qa_all + off, qb_all + off, sh);
     if (threadIdx.x == 0) {
         const bool conn = sh.reached == size;
         g.conn[b] = conn ? 1 : 0;
-        g.far1[b] = g.loc[far_vertex(sh.far)];
+        g.far1[b] = g.al[far_vertex(sh.far)].y;
         g.nlev[b] = sh.levels;
         if (conn) g.clist[atomicAdd(g.ccount, 1)] = b;
         atomicMax(levels, sh.levels);
@@ -777,7 +777,7 @@ __global__ __launch_bounds__(NT) void k_diam_rest(GraphDev g, int32_t* dist, int
     int32_t* qb = qb_all + off;
     auto search = [&](int32_t src, int32_t* d) { bfs_block<NT>(g, off, size, src, d, qa, qb, sh); };
     // the farthest vertex of the last search, as a local id
-    auto far = [&]() -> int32_t { return g.loc[far_vertex(sh.far)]; };
+    auto far = [&]() -> int32_t { return g.al[far_vertex(sh.far)].y; };
     // the vertex `steps` closer to the search's source on the path back from x
     auto back = [&](const int32_t* d, int32_t x, int32_t steps) -> int32_t {
         if (tid == 0) sh.src = walk_back(g, d, x, steps);
@@ -866,7 +866,7 @@ __global__ __launch_bounds__(kBlock) void k_block_members(int64_t n, const int32
     const int32_t a = A[v];
     const int32_t i = g.moff[a] + atomicAdd(&g.fill[a], 1);
     g.mem[i] = (int32_t)v;
-    g.loc[v] = i;
+    g.al[v] = make_int2(a, i);
 }
 
 // Rows of the relabelled block subgraphs: the intra-block degree of every
@@ -880,16 +880,15 @@ __global__ __launch_bounds__(kBlock) void k_local_deg(int64_t n, GraphDev g, int
 }
 
 __global__ __launch_bounds__(kBlock) void k_local_fill(int64_t n, const int64_t* row_ptr,
-                                                       const int32_t* col, const int32_t* A,
-                                                       GraphDev g)
+                                                       const int32_t* col, GraphDev g)
 {
     const int64_t u = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (u >= n) return;
-    const int32_t a = A[u];
-    int64_t pos = g.lrp[g.loc[u]];
+    const int2 au = g.al[u];
+    int64_t pos = g.lrp[au.y];
     for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
-        const int32_t w = col[e];
-        if (A[w] == a) g.lcol[pos++] = g.loc[w];
+        const int2 aw = g.al[col[e]];   // one 8-byte read: block and local id
+        if (aw.x == au.x) g.lcol[pos++] = aw.y;
     }
 }
 
@@ -1086,7 +1085,7 @@ hipError_t launch_local_rows(int64_t n, const int64_t* row_ptr, const int32_t* c
     k_local_deg<<<nblocks(n, kBlock), kBlock, 0, s>>>(n, g, dl);
     hipError_t e = launch_sym_rows(n, 0, dl, part, g.lrp, s);
     if (e != hipSuccess) return e;
-    k_local_fill<<<nblocks(n, kBlock), kBlock, 0, s>>>(n, row_ptr, col, A, g);
+    k_local_fill<<<nblocks(n, kBlock), kBlock, 0, s>>>(n, row_ptr, col, g);
     return hipGetLastError();
 }
 

@@ -546,7 +546,7 @@ struct GraphDev {
     int* ccount;              // [1] their count
     // the blocks' induced subgraphs relabelled: local id = position in mem
     int32_t* ldeg;            // [n] own-block neighbours of each vertex (input index)
-    int32_t* loc;             // [n] local id of each vertex
+    int2* al;                 // [n] block and local id of each vertex
     int64_t* lrp;             // [n+1] rows by local id
     int32_t* lcol;            // [<= nnz] own-block neighbours as local ids
 };
