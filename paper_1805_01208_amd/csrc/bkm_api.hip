@@ -1029,6 +1029,8 @@ int bkm_knn_graph(int64_t n, int32_t knn, const int32_t* nbr, const int32_t* ord
     z.add<int32_t>((size_t)n);
     z.add<int64_t>((size_t)scan_parts(n));
     z.add<int>(1);
+    const size_t nmiss = (size_t)((n * knn + kWave - 1) / kWave);
+    z.add<unsigned long long>(nmiss);
     Arena a;
     a.s = s;
     HIPCHK(hipMallocAsync((void**)&a.base, z.total, s));
@@ -1037,6 +1039,7 @@ int bkm_knn_graph(int64_t n, int32_t knn, const int32_t* nbr, const int32_t* ord
     int32_t* cursor = a.take<int32_t>((size_t)n);
     int64_t* part = a.take<int64_t>((size_t)scan_parts(n));
     int* bad = a.take<int>(1);
+    unsigned long long* miss = a.take<unsigned long long>(nmiss);   // written whole by the count
     HIPCHK(hipMemsetAsync(extra, 0, (size_t)n * sizeof(int32_t), s));
     HIPCHK(hipMemsetAsync(cursor, 0, (size_t)n * sizeof(int32_t), s));
     HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), s));
@@ -1048,12 +1051,12 @@ int bkm_knn_graph(int64_t n, int32_t knn, const int32_t* nbr, const int32_t* ord
         HIPCHK(hipStreamSynchronize(s));
         if (hb) return fail(BKM_EINVAL, "order is not a permutation of 0..n-1");
     }
-    HIPCHK(launch_sym_count(n, knn, nbr, order, extra, bad, s));
+    HIPCHK(launch_sym_count(n, knn, nbr, order, extra, miss, bad, s));
     HIPCHK(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (hb) return fail(BKM_EINVAL, "neighbour entry outside [0, n) or pointing to its own row");
     HIPCHK(launch_sym_rows(n, knn, extra, part, row_ptr_out, s));
-    HIPCHK(launch_sym_fill(n, knn, nbr, order, row_ptr_out, cursor, col_out, s));
+    HIPCHK(launch_sym_fill(n, knn, nbr, order, miss, row_ptr_out, cursor, col_out, s));
     int64_t nnz = 0;
     HIPCHK(hipMemcpyAsync(&nnz, row_ptr_out + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));

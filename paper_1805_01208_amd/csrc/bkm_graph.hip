@@ -283,22 +283,30 @@ __global__ __launch_bounds__(kBlock) void k_order_check(int64_t n, int32_t* mark
 }
 
 // Directed entries p -> q (q = nbr[p][j]) without the partner q -> p: one
-// more slot in q's row.  Out-of-range neighbours set *bad.
+// more slot in q's row, and bit e of `miss` set (e = the entry's index in
+// the pass, one 64-bit word per wave).  Out-of-range neighbours set *bad.
 __global__ __launch_bounds__(kBlock) void k_sym_count(int64_t n, int K, const int32_t* nbr,
                                                       const int32_t* order, int32_t* extra,
-                                                      int* bad)
+                                                      unsigned long long* miss, int* bad)
 {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= n * K) return;
-    const int64_t p = vertex_at(order, e / K);
-    const int32_t q = nbr[p * K + e % K];
-    if (q < 0 || q >= n || q == p) {
-        atomicOr(bad, 1);
-        return;
+    bool missing = false;
+    if (e < n * K) {
+        const int64_t p = vertex_at(order, e / K);
+        const int32_t q = nbr[p * K + e % K];
+        if (q < 0 || q >= n || q == p) {
+            atomicOr(bad, 1);
+        } else {
+            bool back = false;
+            for (int i = 0; i < K; ++i) back |= nbr[(int64_t)q * K + i] == (int32_t)p;
+            if (!back) {
+                atomicAdd(&extra[q], 1);
+                missing = true;
+            }
+        }
     }
-    bool back = false;
-    for (int i = 0; i < K; ++i) back |= nbr[(int64_t)q * K + i] == (int32_t)p;
-    if (!back) atomicAdd(&extra[q], 1);
+    const unsigned long long b = __ballot(missing);
+    if (threadIdx.x % kWave == 0 && e < n * K) miss[e / kWave] = b;
 }
 
 // Exclusive scan of the row lengths K + extra[p] into row_ptr (n + 1
@@ -378,21 +386,30 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_rows(int64_t n, int K, cons
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_sym_fill(int64_t n, int K, const int32_t* nbr,
-                                                     const int32_t* order, const int64_t* row_ptr,
-                                                     int32_t* cursor, int32_t* col)
+// The lists themselves at the head of their rows, in input order (the
+// reads and writes of neighbouring threads are adjacent).
+__global__ __launch_bounds__(kBlock) void k_sym_copy(int64_t n, int K, const int32_t* nbr,
+                                                     const int64_t* row_ptr, int32_t* col)
 {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= n * K) return;
+    col[row_ptr[e / K] + e % K] = nbr[e];
+}
+
+// The missing partners (bit e of `miss`, in the counting pass's order): p
+// into q's row after its own list.
+__global__ __launch_bounds__(kBlock) void k_sym_fill(int64_t n, int K, const int32_t* nbr,
+                                                     const int32_t* order,
+                                                     const unsigned long long* miss,
+                                                     const int64_t* row_ptr, int32_t* cursor,
+                                                     int32_t* col)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= n * K || !((miss[e / kWave] >> (e % kWave)) & 1ULL)) return;
     const int64_t p = vertex_at(order, e / K);
     const int32_t q = nbr[p * K + e % K];
-    col[row_ptr[p] + e % K] = q;
-    bool back = false;
-    for (int i = 0; i < K; ++i) back |= nbr[(int64_t)q * K + i] == (int32_t)p;
-    if (!back) {
-        const int slot = atomicAdd(&cursor[q], 1);
-        col[row_ptr[q] + K + slot] = (int32_t)p;
-    }
+    const int slot = atomicAdd(&cursor[q], 1);
+    col[row_ptr[q] + K + slot] = (int32_t)p;
 }
 
 __global__ __launch_bounds__(kBlock) void k_sym_sort(int64_t n, const int64_t* row_ptr,
@@ -1031,9 +1048,9 @@ hipError_t launch_order_check(int64_t n, const int32_t* order, int32_t* mark, in
 }
 
 hipError_t launch_sym_count(int64_t n, int K, const int32_t* nbr, const int32_t* order,
-                            int32_t* extra, int* bad, hipStream_t s)
+                            int32_t* extra, unsigned long long* miss, int* bad, hipStream_t s)
 {
-    k_sym_count<<<nblocks(n * K, kBlock), kBlock, 0, s>>>(n, K, nbr, order, extra, bad);
+    k_sym_count<<<nblocks(n * K, kBlock), kBlock, 0, s>>>(n, K, nbr, order, extra, miss, bad);
     return hipGetLastError();
 }
 
@@ -1051,9 +1068,12 @@ hipError_t launch_sym_rows(int64_t n, int K, const int32_t* extra, int64_t* part
 }
 
 hipError_t launch_sym_fill(int64_t n, int K, const int32_t* nbr, const int32_t* order,
-                           const int64_t* row_ptr, int32_t* cursor, int32_t* col, hipStream_t s)
+                           const unsigned long long* miss, const int64_t* row_ptr,
+                           int32_t* cursor, int32_t* col, hipStream_t s)
 {
-    k_sym_fill<<<nblocks(n * K, kBlock), kBlock, 0, s>>>(n, K, nbr, order, row_ptr, cursor, col);
+    k_sym_copy<<<nblocks(n * K, kBlock), kBlock, 0, s>>>(n, K, nbr, row_ptr, col);
+    k_sym_fill<<<nblocks(n * K, kBlock), kBlock, 0, s>>>(n, K, nbr, order, miss, row_ptr, cursor,
+                                                         col);
     k_sym_sort<<<nblocks(n, kBlock), kBlock, 0, s>>>(n, row_ptr, col);
     return hipGetLastError();
 }

@@ -587,13 +587,16 @@ hipError_t launch_knn(const RunDev& r, const KnnPts& P, int K, int32_t* nbr,
 // entry passes of the symmetrisation; NULL = input order
 hipError_t launch_order_check(int64_t n, const int32_t* order, int32_t* mark, int* bad,
                               hipStream_t s);
+// entries whose partner is missing: one bit each in miss (n*K bits, in the
+// counting pass's order), read back by the fill
 hipError_t launch_sym_count(int64_t n, int K, const int32_t* nbr, const int32_t* order,
-                            int32_t* extra, int* bad, hipStream_t s);
+                            int32_t* extra, unsigned long long* miss, int* bad, hipStream_t s);
 int64_t scan_parts(int64_t n);
 hipError_t launch_sym_rows(int64_t n, int K, const int32_t* extra, int64_t* part,
                            int64_t* row_ptr, hipStream_t s);
 hipError_t launch_sym_fill(int64_t n, int K, const int32_t* nbr, const int32_t* order,
-                           const int64_t* row_ptr, int32_t* cursor, int32_t* col, hipStream_t s);
+                           const unsigned long long* miss, const int64_t* row_ptr,
+                           int32_t* cursor, int32_t* col, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_gm_vertex(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
                             const int32_t* A, int k, const GraphDev& g, hipStream_t s);
