@@ -329,7 +329,9 @@ int bkm_partition_stats_noalloc(const bkm_points* pts, const int32_t* assignment
  * ------------------------------------------------------------------------- */
 
 typedef struct {
-    int64_t group_visits;     /* (64-point group, 64-point group) pairs compared */
+    int64_t group_visits;     /* point pairs compared / (64 * 64): a query group of 64
+                                 points against 64 partners (visits of 8-point parts
+                                 count 1/8, rounded down over the call) */
     double layout_ms;         /* device time of the Hilbert tile layout it searches */
     double search_ms;         /* device time of the neighbour search kernel */
 } bkm_knn_info;

@@ -993,6 +993,21 @@ int bkm_knn(const bkm_points* pts, int32_t knn, int32_t* nbr_out, int32_t* order
     } else {
         for (int j = 0; j < r.d; ++j) P.x[j] = r.xs64[j];
     }
+    // boxes of the groups' 8-point parts
+    Arena parts;
+    {
+        parts.s = s;
+        const size_t bytes = (size_t)r.ngroups * kKnnParts * 2 * r.d * sizeof(double);
+        hipError_t e = hipMallocAsync((void**)&parts.base, bytes, s);
+        if (e != hipSuccess) {
+            parts.base = nullptr;
+            return fail(e == hipErrorOutOfMemory ? BKM_ENOMEM : BKM_EHIP,
+                        "hipMallocAsync(%zu bytes): %s", bytes, hipGetErrorString(e));
+        }
+        double* pb = reinterpret_cast<double*>(parts.base);
+        HIPCHK(launch_knn_partbox(r, P, pb, s));
+        P.pbox = pb;
+    }
     unsigned long long* visits = reinterpret_cast<unsigned long long*>(r.red);
     HIPCHK(hipMemsetAsync(visits, 0, sizeof(unsigned long long), s));
     if (info) HIPCHK(hipEventRecord(ev[1], s));
@@ -1008,7 +1023,7 @@ int bkm_knn(const bkm_points* pts, int32_t knn, int32_t* nbr_out, int32_t* order
         float t01 = 0.f, t12 = 0.f;
         HIPCHK(hipEventElapsedTime(&t01, ev[0], ev[1]));
         HIPCHK(hipEventElapsedTime(&t12, ev[1], ev[2]));
-        info->group_visits = (int64_t)hv;
+        info->group_visits = (int64_t)(hv / kKnnParts);   // counted in 8-point parts
         info->layout_ms = t01;
         info->search_ms = t12;
     }

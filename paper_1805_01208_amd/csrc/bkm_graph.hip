@@ -8,27 +8,29 @@
 //     point in registers.  The wave first scans its own group and the two
 //     curve neighbours, takes the largest K-th distance over its lanes as the
 //     search radius, and then walks the hyper-tile / super-tile / tile /
-//     group box hierarchy, visiting only groups whose box lies within the
-//     radius (which shrinks as the lists fill).  A visited group's points
+//     group box hierarchy, visiting only boxes within the radius (which
+//     shrinks as the lists fill); within a tile the test goes down to 8-point
+//     parts of the groups, each with its own box.  A visited part's points
 //     are the same for every lane: they arrive by scalar loads and enter the
-//     arithmetic as SGPR operands.  Four partners at a time are screened
-//     with a fused squared distance against a slightly widened K-th
-//     distance; the wave computes exact distances and inserts only when a
-//     lane passes.  Exact squared distances are FP64 ((dx*dx + dy*dy) +
-//     dz*dz, no contraction) and the box distance is the same expression
-//     over per-axis gaps, so by monotone rounding a group holding a point
-//     within the radius is never pruned: the lists are the exact ones.
+//     arithmetic as SGPR operands.  Four partners at a time are screened with
+//     a fused squared distance against a slightly widened K-th distance; the
+//     wave computes exact distances and inserts only when a lane passes.
+//     Exact squared distances are FP64 ((dx*dx + dy*dy) + dz*dz, no
+//     contraction) and the box distance is the same expression over per-axis
+//     gaps, so by monotone rounding a box holding a point within the radius
+//     is never pruned: the lists are the exact ones.
 //   * symmetrisation: a directed entry p -> q that has no partner q -> p adds
 //     p to q's row; rows are then sorted by index.
 //   * metrics: one thread per vertex for cut and communication volume.  The
 //     diameter bound (Sec. 5.2, Metrics: the first 3 rounds of iFUB, from a
-//     4-sweep) runs every block at once: blocks are disjoint, so one
-//     level-synchronous frontier serves them all.  The 4-sweep and the
-//     search from its middle vertex u are five single-source searches per
-//     block; a round's fringe (the vertices at distance i from u) is searched
-//     bit-parallel, 64 sources per block and pass, each vertex holding a
-//     64-bit mask of the sources that reached it, and the deepest level any
-//     source reaches is the largest eccentricity of the fringe.
+//     4-sweep) takes one workgroup per block on the block's induced subgraph,
+//     relabelled so that its data is contiguous: every block's first search
+//     in one launch, the other searches of the connected blocks in a second.
+//     The 4-sweep and the search from its middle vertex u are five
+//     single-source searches; a round's fringe (the vertices at distance i
+//     from u) is searched bit-parallel, 64 sources per pass, each vertex
+//     holding a 64-bit mask of the sources that reached it, and the deepest
+//     level any source reaches is the largest eccentricity of the fringe.
 #include <climits>
 
 #include <algorithm>
@@ -65,6 +67,7 @@ typedef const __attribute__((address_space(4))) double* ScalarD;
 typedef const __attribute__((address_space(4))) int32_t* ScalarI;
 
 constexpr int kKnnChunk = 4;   // partners screened per wave-wide test
+constexpr int kKnnSub = kWave / kKnnParts;   // points per part of a group
 
 template <int D, int K>
 struct KnnLane {
@@ -124,11 +127,12 @@ struct KnnLane {
     // and insert.  A partner failing the screen fails the exact test too:
     // the limit only shrinks.  Padding slots hold copies of a real point and
     // are dropped by their index (-1).
-    __device__ inline void visit(const double* const* x, const int32_t* perm, int64_t h)
+    __device__ inline void visit(const double* const* x, const int32_t* perm, int64_t h, int c0 = 0,
+                                 int c1 = kWave)
     {
         const int64_t base = h * kWave;
         double lim = screen_limit();
-        for (int c = 0; c < kWave; c += kKnnChunk) {
+        for (int c = c0; c < c1; c += kKnnChunk) {
             unsigned long long hit = 0;
 #pragma unroll
             for (int u = 0; u < kKnnChunk; ++u) {
@@ -159,6 +163,34 @@ struct KnnLane {
     // active lanes (infinite while some list is not full).
     __device__ inline double radius2() const { return wave_max_d(active ? kd[K - 1] : 0.0); }
 };
+
+// Boxes of the 8-point parts of every group (the search prunes at that
+// granularity): one wave per group, min and max over each part.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_knn_partbox(RunDev r, KnnPts P, double* hb)
+{
+    const int lane = threadIdx.x % kWave;
+    const int64_t g = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (g >= r.ngroups) return;
+    double mn[D], mx[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) mn[j] = mx[j] = P.x[j][g * kWave + lane];
+    for (int o = kKnnSub / 2; o > 0; o >>= 1) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            mn[j] = fmin(mn[j], __shfl_xor(mn[j], o, kWave));
+            mx[j] = fmax(mx[j], __shfl_xor(mx[j], o, kWave));
+        }
+    }
+    if (lane % kKnnSub == 0) {
+        double* out = hb + (g * kKnnParts + lane / kKnnSub) * 2 * D;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            out[j] = mn[j];
+            out[D + j] = mx[j];
+        }
+    }
+}
 
 // FP64 copy of an FP32 layout (axis j at x + j * npad) for the search.
 __global__ __launch_bounds__(kBlock) void k_knn_widen(RunDev r, double* x)
@@ -193,16 +225,16 @@ __global__ __launch_bounds__(kBlock) void k_knn(RunDev r, KnnPts P, int32_t* nbr
 #pragma unroll
     for (int j = 0; j < 2 * D; ++j) gb[j] = r.gbox[g * 2 * D + j];
 
-    long long nvis = 0;
+    long long nvis = 0;   // in 8-point parts
     L.visit(P.x, r.perm, g);
-    ++nvis;
+    nvis += kKnnParts;
     if (g > 0) {
         L.visit(P.x, r.perm, g - 1);
-        ++nvis;
+        nvis += kKnnParts;
     }
     if (g + 1 < r.ngroups) {
         L.visit(P.x, r.perm, g + 1);
-        ++nvis;
+        nvis += kKnnParts;
     }
     double R2 = L.radius2();
 
@@ -228,18 +260,22 @@ __global__ __launch_bounds__(kBlock) void k_knn(RunDev r, KnnPts P, int32_t* nbr
                 while (mt) {
                     const int ti = si * r.super_tiles + __builtin_ctzll(mt);
                     mt &= mt - 1;
-                    const int64_t gg = (int64_t)ti * gpt + lane;
-                    const bool okg = lane < gpt && gg < r.ngroups &&
+                    // the tile's 8-point parts within the radius (one lane
+                    // each: at most 64 per tile), then the radius again
+                    const int64_t hg = (int64_t)ti * gpt * kKnnParts + lane;
+                    const int64_t gg = hg / kKnnParts;
+                    const bool okg = lane < kKnnParts * gpt && gg < r.ngroups &&
                                      (gg < g - 1 || gg > g + 1) &&
-                                     box_gap2<D>(gb, r.gbox + gg * 2 * D) <= R2;
+                                     box_gap2<D>(gb, P.pbox + hg * 2 * D) <= R2;
                     unsigned long long mg = __ballot(okg);
                     while (mg) {
-                        const int64_t gi = (int64_t)ti * gpt + __builtin_ctzll(mg);
+                        const int64_t hi = (int64_t)ti * gpt * kKnnParts + __builtin_ctzll(mg);
                         mg &= mg - 1;
-                        L.visit(P.x, r.perm, gi);
+                        const int c0 = (int)(hi % kKnnParts) * kKnnSub;
+                        L.visit(P.x, r.perm, hi / kKnnParts, c0, c0 + kKnnSub);
                         ++nvis;
-                        R2 = L.radius2();
                     }
+                    R2 = L.radius2();
                 }
             }
         }
@@ -1029,8 +1065,18 @@ hipError_t launch_knn_d(const RunDev& r, const KnnPts& P, int K, int32_t* nbr,
 hipError_t launch_knn(const RunDev& r, const KnnPts& P, int K, int32_t* nbr,
                       unsigned long long* visits, hipStream_t s)
 {
+    // a tile's parts are tested one per lane
+    if (r.T / kWave * kKnnParts > kWave || !P.pbox) return hipErrorInvalidValue;
     return r.d == 2 ? launch_knn_d<2>(r, P, K, nbr, visits, s)
                     : launch_knn_d<3>(r, P, K, nbr, visits, s);
+}
+
+hipError_t launch_knn_partbox(const RunDev& r, const KnnPts& P, double* hb, hipStream_t s)
+{
+    const unsigned grid = nblocks(r.ngroups, kBlock / kWave);
+    if (r.d == 2) k_knn_partbox<2><<<grid, kBlock, 0, s>>>(r, P, hb);
+    else k_knn_partbox<3><<<grid, kBlock, 0, s>>>(r, P, hb);
+    return hipGetLastError();
 }
 
 hipError_t launch_knn_widen(const RunDev& r, double* x, hipStream_t s)

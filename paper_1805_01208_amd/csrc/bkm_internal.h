@@ -579,8 +579,11 @@ hipError_t launch_iota(int32_t* v, int64_t n, hipStream_t s);
 // layout, one array per axis.
 struct KnnPts {
     const double* x[3];
+    const double* pbox;       // [8 ngroups][2d] boxes of the groups' 8-point parts
 };
+constexpr int kKnnParts = 8;  // parts per 64-point group
 hipError_t launch_knn_widen(const RunDev& r, double* x, hipStream_t s);
+hipError_t launch_knn_partbox(const RunDev& r, const KnnPts& P, double* hb, hipStream_t s);
 hipError_t launch_knn(const RunDev& r, const KnnPts& P, int K, int32_t* nbr,
                       unsigned long long* visits, hipStream_t s);
 // an optional vertex order (a permutation of 0..n-1, checked first) for the
