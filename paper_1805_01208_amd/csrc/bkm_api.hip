@@ -19,6 +19,7 @@
 #include <string>
 #include <vector>
 
+#include "bkm_graph_internal.h"
 #include "bkm_internal.h"
 
 using namespace bkm;

@@ -35,6 +35,7 @@
 
 #include <algorithm>
 
+#include "bkm_graph_internal.h"
 #include "bkm_internal.h"
 
 namespace bkm {
