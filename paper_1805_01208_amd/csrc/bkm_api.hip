@@ -1161,13 +1161,13 @@ int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int3
     HIPCHK(hipMemcpyAsync(&hb, g.bad, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (hb) return fail(BKM_EINVAL, "assignment outside [0, k), or row_ptr/col outside the graph");
-    // the diameter bounds: the block lists and the relabelled block subgraphs
-    // (qb holds the local degrees until the searches), the first search of
-    // every block, then the rest of the searches for the connected blocks,
-    // workgroups sized to their count
+    // the diameter bounds: the block lists, the first search of every block
+    // (on the input graph), the relabelled subgraphs of the connected blocks
+    // (fr holds the local degrees until the searches), then the rest of their
+    // searches, workgroups sized to their count
     HIPCHK(launch_block_lists(n, assignment, k, g, s));
-    HIPCHK(launch_local_rows(n, row_ptr, col, assignment, g, qb, part, s));
-    HIPCHK(launch_diam_first(k, g, dist, qa, qb, nlevels, s));
+    HIPCHK(launch_diam_first(row_ptr, col, assignment, k, g, dist, qa, qb, nlevels, s));
+    HIPCHK(launch_local_rows(n, row_ptr, col, assignment, g, fr, part, s));
     int nconn = 0;
     HIPCHK(hipMemcpyAsync(&nconn, g.ccount, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));

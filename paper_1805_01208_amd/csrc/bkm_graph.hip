@@ -23,9 +23,10 @@
 //     p to q's row; rows are then sorted by index.
 //   * metrics: one thread per vertex for cut and communication volume.  The
 //     diameter bound (Sec. 5.2, Metrics: the first 3 rounds of iFUB, from a
-//     4-sweep) takes one workgroup per block on the block's induced subgraph,
-//     relabelled so that its data is contiguous: every block's first search
-//     in one launch, the other searches of the connected blocks in a second.
+//     4-sweep) takes one workgroup per block: every block's first search in
+//     one launch on the input graph, the other searches of the connected
+//     blocks in a second, on their induced subgraphs relabelled so that
+//     their data is contiguous.
 //     The 4-sweep and the search from its middle vertex u are five
 //     single-source searches; a round's fringe (the vertices at distance i
 //     from u) is searched bit-parallel, 64 sources per pass, each vertex
@@ -554,12 +555,13 @@ __device__ int32_t walk_back(const GraphDev& g, const int32_t* dist, int32_t x, 
 // the 4-sweep, the search from its middle vertex u, and up to three iFUB
 // rounds.  Levels are separated by workgroup barriers only: a search of any
 // length is part of one launch, and blocks proceed independently.
-// The searches run on the blocks' induced subgraphs relabelled block by
-// block: local id = position in the block lists (mem), so block b holds the
-// local ids moff[b] .. moff[b] + size - 1, and its rows (lrp, lcol) hold
-// only its own edges.  Every array a search touches is then contiguous per
-// block (distances, masks, queues, rows), instead of spread over the input
-// order.  Ties still go by input index (mem of a local id).
+// After the first search, the connected blocks' induced subgraphs are
+// relabelled block by block: local id = position in the block lists (mem),
+// so block b holds the local ids moff[b] .. moff[b] + size - 1, and its rows
+// (lrp, lcol) hold only its own edges.  Every array the later searches
+// touch is then contiguous per block (distances, masks, queues, rows),
+// instead of spread over the input order.  Ties still go by input index
+// (mem of a local id).
 
 constexpr int kBfsLanes = 8;   // lanes sharing a frontier vertex
 constexpr int kDiamU = 4;      // frontier vertices a lane group holds at once
@@ -574,24 +576,47 @@ struct DiamShared {
     unsigned long long far;     // far_key of the farthest vertex reached
 };
 
-// Single-source search of the block at local ids off .. off + size - 1 from
-// src, distances into d (every other vertex of the block at -1 first);
+// The graph a search walks.  InputView: the input graph restricted to block
+// b (vertices by input index; a neighbour counts when it lies in b; the
+// block's vertices listed in mem at off).  LocalView: a relabelled block
+// (vertices by local id off .. off + size - 1; rows hold only own edges).
+struct InputView {
+    const int64_t* rp;
+    const int32_t* col;
+    const int32_t* A;
+    const int32_t* mem;
+    int32_t b;
+    __device__ int32_t vertex(int32_t off, int32_t j) const { return mem[off + j]; }
+    __device__ bool own(int32_t v) const { return A[v] == b; }
+    __device__ int32_t input(int32_t v) const { return v; }
+};
+struct LocalView {
+    const int64_t* rp;
+    const int32_t* col;
+    const int32_t* mem;
+    __device__ int32_t vertex(int32_t off, int32_t j) const { return off + j; }
+    __device__ bool own(int32_t) const { return true; }
+    __device__ int32_t input(int32_t v) const { return mem[v]; }
+};
+
+// Single-source search of a block (off, size: its place in the block lists)
+// from src, distances into d (every other vertex of the block at -1 first);
 // leaves the reached count and the farthest vertex (largest level, lowest
 // input index) in sh.  kBfsLanes lanes
 // share a frontier vertex, each taking every kBfsLanes-th entry of its row,
 // and every lane group holds kDiamU frontier vertices at once so that their
 // loads overlap; a vertex is claimed by a CAS on its distance, and a wave
 // reserves its claims' places in the next frontier with one LDS atomic.
-template <int NT>
-__device__ void bfs_block(const GraphDev& g, int32_t off, int32_t size, int32_t src, int32_t* d,
+template <int NT, typename View>
+__device__ void bfs_block(const View& gv, int32_t off, int32_t size, int32_t src, int32_t* d,
                           int32_t* qa, int32_t* qb, DiamShared& sh)
 {
-    const int64_t* __restrict__ row_ptr = g.lrp;
-    const int32_t* __restrict__ col = g.lcol;
+    const int64_t* __restrict__ row_ptr = gv.rp;
+    const int32_t* __restrict__ col = gv.col;
     constexpr int kPer = NT / kBfsLanes;
     const int tid = threadIdx.x, lane = tid % kWave;
     const unsigned long long below = (1ULL << lane) - 1ULL;
-    for (int j = tid; j < size; j += NT) d[off + j] = -1;
+    for (int j = tid; j < size; j += NT) d[gv.vertex(off, j)] = -1;
     __syncthreads();
     if (tid == 0) {
         d[src] = 0;
@@ -599,7 +624,7 @@ __device__ void bfs_block(const GraphDev& g, int32_t off, int32_t size, int32_t 
         sh.cnt[0] = 1;
         sh.cnt[1] = 0;
         sh.reached = 1;
-        sh.far = far_key(0, g.mem[src]);
+        sh.far = far_key(0, gv.input(src));
     }
     __syncthreads();
     int32_t* cur = qa;
@@ -634,7 +659,8 @@ __device__ void bfs_block(const GraphDev& g, int32_t off, int32_t size, int32_t 
                     e[q] += live[q] ? kBfsLanes : 0;
                 }
 #pragma unroll
-                for (int q = 0; q < kDiamU; ++q) claim[q] = live[q] && d[v[q]] == -1;
+                for (int q = 0; q < kDiamU; ++q)
+                    claim[q] = live[q] && gv.own(v[q]) && d[v[q]] == -1;
 #pragma unroll
                 for (int q = 0; q < kDiamU; ++q)
                     if (claim[q]) claim[q] = atomicCAS(&d[v[q]], -1, level + 1) == -1;
@@ -651,7 +677,7 @@ __device__ void bfs_block(const GraphDev& g, int32_t off, int32_t size, int32_t 
                     pos = __shfl(pos, leader, kWave);
                     if (claim[q]) {
                         nxt[pos + (int)__popcll(bm & below)] = v[q];
-                        atomicMax(&sh.far, far_key(level + 1, g.mem[v[q]]));
+                        atomicMax(&sh.far, far_key(level + 1, gv.input(v[q])));
                     }
                 }
             }
@@ -794,8 +820,10 @@ __device__ void mbfs_block(const GraphDev& g, int32_t off, int32_t size, const i
 // searches must not run on a few waves).  `levels` takes the most levels
 // any block's searches ran.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_diam_first(GraphDev g, int32_t* dist, int32_t* qa_all,
-                                                   int32_t* qb_all, int32_t* levels)
+__global__ __launch_bounds__(NT) void k_diam_first(const int64_t* row_ptr, const int32_t* col,
+                                                   const int32_t* A, GraphDev g, int32_t* dist,
+                                                   int32_t* qa_all, int32_t* qb_all,
+                                                   int32_t* levels)
 {
     __shared__ DiamShared sh;
     const int32_t b = blockIdx.x;
@@ -803,7 +831,8 @@ __global__ __launch_bounds__(NT) void k_diam_first(GraphDev g, int32_t* dist, in
     if (size == 0) return;   // reported as 0 from the size alone
     if (threadIdx.x == 0) sh.levels = 0;
     const int32_t off = g.moff[b];
-    bfs_block<NT>(g, off, size, g.al[g.seed[b]].y, dist, qa_all + off, qb_all + off, sh);
+    const InputView gv{row_ptr, col, A, g.mem, b};
+    bfs_block<NT>(gv, off, size, g.seed[b], dist, qa_all + off, qb_all + off, sh);
     if (threadIdx.x == 0) {
         const bool conn = sh.reached == size;
         g.conn[b] = conn ? 1 : 0;
@@ -829,7 +858,8 @@ __global__ __launch_bounds__(NT) void k_diam_rest(GraphDev g, int32_t* dist, int
     const int32_t off = g.moff[b];
     int32_t* qa = qa_all + off;
     int32_t* qb = qb_all + off;
-    auto search = [&](int32_t src, int32_t* d) { bfs_block<NT>(g, off, size, src, d, qa, qb, sh); };
+    const LocalView gv{g.lrp, g.lcol, g.mem};
+    auto search = [&](int32_t src, int32_t* d) { bfs_block<NT>(gv, off, size, src, d, qa, qb, sh); };
     // the farthest vertex of the last search, as a local id
     auto far = [&]() -> int32_t { return g.al[far_vertex(sh.far)].y; };
     // the vertex `steps` closer to the search's source on the path back from x
@@ -923,14 +953,17 @@ __global__ __launch_bounds__(kBlock) void k_block_members(int64_t n, const int32
     g.al[v] = make_int2(a, i);
 }
 
-// Rows of the relabelled block subgraphs: the intra-block degree of every
-// local id (gathered from the vertex pass), then, after their exclusive scan
+// Rows of the relabelled subgraphs of the connected blocks (the others need
+// no more searches): the intra-block degree of every local id (from the
+// vertex pass; 0 in a disconnected block), then, after their exclusive scan
 // into lrp, each vertex's own-block neighbours as local ids, in the order of
 // its input row.
 __global__ __launch_bounds__(kBlock) void k_local_deg(int64_t n, GraphDev g, int32_t* dl)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) dl[i] = g.ldeg[g.mem[i]];
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= n) return;
+    const int2 av = g.al[v];
+    dl[av.y] = g.conn[av.x] ? g.ldeg[v] : 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_local_fill(int64_t n, const int64_t* row_ptr,
@@ -939,6 +972,7 @@ __global__ __launch_bounds__(kBlock) void k_local_fill(int64_t n, const int64_t*
     const int64_t u = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (u >= n) return;
     const int2 au = g.al[u];
+    if (!g.conn[au.x]) return;
     int64_t pos = g.lrp[au.y];
     for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
         const int2 aw = g.al[col[e]];   // one 8-byte read: block and local id
@@ -1164,12 +1198,13 @@ static int diam_threads(int blocks)
     return per >= 1024 ? 1024 : per >= 512 ? 512 : per >= 256 ? 256 : per >= 128 ? 128 : 64;
 }
 
-hipError_t launch_diam_first(int k, const GraphDev& g, int32_t* dist, int32_t* qa, int32_t* qb,
+hipError_t launch_diam_first(const int64_t* row_ptr, const int32_t* col, const int32_t* A, int k,
+                             const GraphDev& g, int32_t* dist, int32_t* qa, int32_t* qb,
                              int32_t* levels, hipStream_t s)
 {
     switch (diam_threads(k)) {
 #define BKM_DIAM_FIRST(NT) \
-    case NT: k_diam_first<NT><<<k, NT, 0, s>>>(g, dist, qa, qb, levels); break;
+    case NT: k_diam_first<NT><<<k, NT, 0, s>>>(row_ptr, col, A, g, dist, qa, qb, levels); break;
         BKM_DIAM_FIRST(1024) BKM_DIAM_FIRST(512) BKM_DIAM_FIRST(256) BKM_DIAM_FIRST(128)
         BKM_DIAM_FIRST(64)
 #undef BKM_DIAM_FIRST

@@ -70,7 +70,8 @@ hipError_t launch_block_lists(int64_t n, const int32_t* A, int k, const GraphDev
 hipError_t launch_local_rows(int64_t n, const int64_t* row_ptr, const int32_t* col,
                              const int32_t* A, const GraphDev& g, int32_t* dl, int64_t* part,
                              hipStream_t s);
-hipError_t launch_diam_first(int k, const GraphDev& g, int32_t* dist, int32_t* qa, int32_t* qb,
+hipError_t launch_diam_first(const int64_t* row_ptr, const int32_t* col, const int32_t* A, int k,
+                             const GraphDev& g, int32_t* dist, int32_t* qa, int32_t* qb,
                              int32_t* levels, hipStream_t s);
 hipError_t launch_diam_rest(int nconn, const GraphDev& g, int32_t* dist, int32_t* du, int32_t* qa,
                             int32_t* qb, int32_t* fr, unsigned long long* seen,
