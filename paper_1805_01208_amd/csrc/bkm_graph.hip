@@ -83,21 +83,24 @@ struct KnnLane {
     // the list is not full), below zero for a padding lane.
     __device__ inline double limit() const { return active ? kd[K - 1] : -1.0; }
 
-    // Insertion into the sorted list without branches: every slot compares
-    // with the new pair at once, then takes its own, its upper neighbour's
-    // or the new entry.
+    // Insertion into the sorted list: the new pair replaces the K-th entry
+    // and moves up while it comes before its upper neighbour; the wave stops
+    // as soon as no lane moves (late insertions land near the end).
     __device__ inline void insert(double s, int32_t pi)
     {
-        bool c[K];
-#pragma unroll
-        for (int m = 0; m < K; ++m) c[m] = nb_before(s, pi, kd[m], ki[m]);
+        kd[K - 1] = s;
+        ki[K - 1] = pi;
 #pragma unroll
         for (int m = K - 1; m > 0; --m) {
-            kd[m] = c[m - 1] ? kd[m - 1] : (c[m] ? s : kd[m]);
-            ki[m] = c[m - 1] ? ki[m - 1] : (c[m] ? pi : ki[m]);
+            const bool c = nb_before(kd[m], ki[m], kd[m - 1], ki[m - 1]);
+            if (__ballot(c) == 0ULL) break;
+            const double td = kd[m - 1];
+            const int32_t ti = ki[m - 1];
+            kd[m - 1] = c ? kd[m] : td;
+            ki[m - 1] = c ? ki[m] : ti;
+            kd[m] = c ? td : kd[m];
+            ki[m] = c ? ti : ki[m];
         }
-        kd[0] = c[0] ? s : kd[0];
-        ki[0] = c[0] ? pi : ki[0];
     }
 
     // Screening limit: the limit widened by 2^-50 relative and 2^-1060
