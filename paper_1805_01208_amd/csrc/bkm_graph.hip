@@ -125,8 +125,8 @@ struct KnnLane {
         return d2;
     }
 
-    // All 64 points of group h against this lane's point.  Four partners at
-    // a time are screened by a fused squared distance against the lane's
+    // Points c0 .. c1 - 1 of group h (all 64 by default) against this lane's
+    // point.  Four partners at a time are screened by a fused squared distance against the lane's
     // widened limit; only when some lane passes does the wave compute the
     // exact distances, test (squared distance, index) against the K-th entry
     // and insert.  A partner failing the screen fails the exact test too:
