@@ -1173,6 +1173,28 @@ int bkm_graph_metrics(int64_t n, int64_t nnz, const int64_t* row_ptr, const int3
     HIPCHK(hipStreamSynchronize(s));
     if (nconn < 0 || nconn > k)
         return fail(BKM_EHIP, "connected block count %d outside [0, %d]", nconn, k);
+    // with more connected blocks than CUs, the shortest first (by the levels
+    // of their first search): a CU's second workgroup is then one of the
+    // longest, next to one of the shortest
+    int dev = 0, ncu = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    if (nconn > ncu) {
+        std::vector<int32_t> cl((size_t)nconn), lv((size_t)k);
+        HIPCHK(hipMemcpyAsync(cl.data(), g.clist, (size_t)nconn * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(lv.data(), g.nlev, (size_t)k * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int32_t b : cl)
+            if (b < 0 || b >= k) return fail(BKM_EHIP, "connected block %d outside [0, %d)", b, k);
+        std::sort(cl.begin(), cl.end(), [&](int32_t x, int32_t y) {
+            return lv[x] < lv[y] || (lv[x] == lv[y] && x < y);
+        });
+        HIPCHK(hipMemcpyAsync(g.clist, cl.data(), (size_t)nconn * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
     HIPCHK(launch_diam_rest(nconn, g, dist, du, qa, qb, fr, seen, arr0, arr1, nlevels, s));
     int levels = 0;
     HIPCHK(hipMemcpyAsync(&levels, nlevels, sizeof(levels), hipMemcpyDeviceToHost, s));

@@ -119,6 +119,20 @@ def test_metrics_of_partitions_match_oracle():
     _metrics_both(rp, col, torch.zeros(25000, dtype=torch.int32).cuda(), 1, "one block")
 
 
+def test_metrics_with_more_connected_blocks_than_cus():
+    """More connected blocks than compute units: the second launch of the
+    diameter searches then takes them in the order of their first search's
+    length.  Results identical to the oracle's."""
+    from paper_1805_01208_amd import bkm
+    X = workloads.uniform(96000, 2, 76)
+    Xd = cuda(X)
+    nbr, info = bkm.knn(Xd, 6, order=True)
+    rp, col = bkm.knn_graph(nbr, info["order"])
+    part = bkm.balanced_kmeans(Xd, 480, max_iter=20)
+    g = _metrics_both(rp, col, part["A"], 480, "480 blocks")
+    assert 480 - g["disconnected_blocks"] > torch.cuda.get_device_properties(0).multi_processor_count
+
+
 def test_metrics_on_a_grid_graph():
     """The 4-neighbour grid in strips: closed forms on both sides."""
     w, s, b = 6, 5, 9
